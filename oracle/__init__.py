@@ -1,0 +1,23 @@
+"""Plain CPU FP64 oracle for the mode-optimized DMRG hot path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+its Python binding) may import, call or execute anything under ``oracle/``;
+only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` use it.
+
+The oracle is deliberately slow and literal:
+
+* ``integrals``  -- Eq. (1)-(3) and the mode transformation of Sec. II.B,
+  written out as dense FP64 arrays (lattice, momentum basis, rotation).
+* ``ed``         -- exact diagonalisation in a fixed particle-number sector
+  (Fock bitstrings, Jordan-Wigner signs), used to pin everything else.
+* ``dmrg``       -- a two-site DMRG (Sec. II.A) whose renormalised blocks are
+  kept as *explicit* Fock-space basis vectors, so that the effective
+  Hamiltonian product is the plain projection  P^T H P psi.  It shares no
+  code with, and uses none of the operator bookkeeping of, the GPU path.
+* ``davidson``   -- a textbook Davidson eigensolver (Sec. II.A names Lanczos
+  or Davidson; the variant used is the reading recorded in the design notes).
+
+Pins (closed forms, brute force on tiny inputs, basis invariance) live in
+``tests/test_oracle_*.py``.
+"""
