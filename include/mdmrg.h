@@ -1,0 +1,209 @@
+/*
+ * mdmrg -- MI355X (gfx950) hot path of mode-optimized ab initio DMRG.
+ *
+ * C ABI of libmdmrg.so.  Every entry point returns an int status (0 = OK,
+ * negative = error, see MDMRG_E*) and never throws across the boundary; the
+ * text of the last error of a context is returned by mdmrg_last_error().
+ * Host arrays passed in are copied (the caller keeps ownership).  Device
+ * pointers passed in (x, y, diagonal buffers) are caller-owned allocations on
+ * the context's device, laid out as reported by mdmrg_psi_layout().
+ * All device work runs on the context's stream; calls that return host
+ * scalars synchronise that stream.  A context is used by one host thread at a
+ * time.
+ *
+ * Model (Eq. (1), Sec. II.A):
+ *     H = sum_pq T[p,q] a+_p a_q + sum_pqrs V[p,q,r,s] a+_p a+_q a_r a_s
+ * literal sums, no implied 1/2, real FP64 parameters, p a spin-orbital index.
+ * Spinless fermions: one spin-orbital per site, U(1) particle number.
+ * Spin-1/2 fermions: spin-orbital p = 2*site + sigma (sigma 0 = up,
+ * 1 = down), local basis {0, up, down, up+down} encoded as bitmask
+ * s = n_up | (n_down << 1) (Eq. (4)), U(1) x U(1) (N_up, N_down).
+ *
+ * Exchange format of matrix product states (Eq. (4)):
+ *   bond i (0..n) sits left of site i; its sectors carry the quantum numbers
+ *   of sites [0, i): (N, 0) spinless or (N_up, N_down), listed in ascending
+ *   lexicographic order.  Bond 0 is {(0,0): 1}; bond n is {target: 1}.
+ *   Site tensor i has one dense block per (l, s, r) with
+ *   Q_r = Q_l + q(s), l a sector of bond i, r of bond i+1, of shape
+ *   m_l x m_r, row-major; blocks are concatenated site by site in
+ *   lexicographic (l, s, r) order.
+ *   The two-site wave function at bond (l, l+1) has one block per
+ *   (a, s1, s2, b), a a sector of bond l, b of bond l+2,
+ *   Q_a + q(s1) + q(s2) = Q_b, shape m_a x m_b row-major, packed in
+ *   lexicographic (a, s1, s2, b) order without padding.  The basis state of
+ *   element (a,i; s1; s2; b,j) is |a,i>|s1>|s2>|b,j> with the creation
+ *   operators of the left block leftmost (Jordan-Wigner chain order).
+ */
+#ifndef MDMRG_H
+#define MDMRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mdmrg_ctx_s *mdmrg_ctx;
+
+enum {
+  MDMRG_OK = 0,
+  MDMRG_EINVAL = -1,   /* bad argument, shape or non-Hermitian input       */
+  MDMRG_ENOMEM = -2,   /* device or host allocation failed                  */
+  MDMRG_EDEVICE = -3,  /* HIP / rocSOLVER error, or NaN detected on device  */
+  MDMRG_ESTATE = -4,   /* call out of order (no Hamiltonian, no MPS, ...)   */
+  MDMRG_ENOCONV = -5,  /* Davidson reached max_iter; best estimate returned */
+  MDMRG_EUNSUP = -6    /* valid request this build does not implement       */
+};
+
+enum { MDMRG_MODEL_SPINLESS = 0, MDMRG_MODEL_HUBBARD = 1 };
+enum { MDMRG_BASIS_REAL = 0, MDMRG_BASIS_MOMENTUM = 1 };
+enum { MDMRG_FP64 = 0, MDMRG_FP32 = 1, MDMRG_BF16X3 = 2 };
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` with its own (default-priority)
+ * stream.  *out receives the handle; on failure *out is NULL. */
+int mdmrg_create(mdmrg_ctx *out, int device);
+/* Release every device and host resource of the context.  NULL is a no-op. */
+void mdmrg_destroy(mdmrg_ctx ctx);
+/* Context-owned, NUL-terminated text of the last error ("" if none). */
+const char *mdmrg_last_error(mdmrg_ctx ctx);
+/* Library version string (static storage). */
+const char *mdmrg_version(void);
+
+/* ----------------------------------------------- model parameters (host) */
+
+/* Number of spin-orbitals of a model on an Lx x Ly torus. */
+int mdmrg_lattice_nso(int model, int Lx, int Ly);
+
+/* Eq. (2) (model HUBBARD, u = U) or Eq. (3) with t' = 0 (model SPINLESS,
+ * u = V) on an Lx x Ly torus (Sec. II.A).  Hopping enters as -t.
+ * basis REAL: sites in row-major snake order, bonds (x,y)-(x+1,y) and
+ * (x,y)-(x,y+1) with periodic wrap, each once.  basis MOMENTUM: plane-wave
+ * modes k = 2 pi (a/Lx, b/Ly) ordered by eps_k = -2t(cos kx + cos ky)
+ * ascending, ties by label b*Lx+a; spinless V[k1,k2,k3,k4] =
+ * (u/N)(cos qx + cos qy) delta(k1+k2=k3+k4), q = k3-k2; Hubbard
+ * V[(k1 up),(k2 dn),(k3 dn),(k4 up)] = (u/N) delta(k1+k2=k3+k4).
+ * T (nso*nso) and V (nso^4), row-major, caller-allocated, overwritten. */
+int mdmrg_build_lattice(int model, int basis, int Lx, int Ly, double t, double u,
+                        double *T, double *V);
+
+/* Mode transformation on the parameters (Sec. II.B): old modes
+ * c_a = sum_i R[a,i] d_i, R real orthogonal n_modes x n_modes row-major.
+ * T <- R^T T R, V[i,j,k,l] <- sum R[a,i]R[b,j]R[c,k]R[d,l] V[a,b,c,d].
+ * spin_half != 0 applies R to both spin components (p = 2*mode + sigma).
+ * T and V are updated in place.  EINVAL if R is not orthogonal (1e-10). */
+int mdmrg_rotate_modes(int n_modes, int spin_half, const double *R, double *T, double *V);
+
+/* ------------------------------------------------------------- Hamiltonian */
+
+/* Set Eq. (1) on n_sites sites.  spin_half selects the local dimension
+ * (2 or 4) and the symmetry (U(1) or U(1)xU(1)); T is nso x nso, V nso^4
+ * dense row-major (nso = n_sites or 2*n_sites).  target = (N, 0) or
+ * (N_up, N_down).  EINVAL if T != T^T or V[p,q,r,s] != V[s,r,q,p] beyond
+ * 1e-12 * max|.|, or if the target is unreachable.  Invalidates the MPS. */
+int mdmrg_set_hamiltonian(mdmrg_ctx ctx, int n_sites, int spin_half, const double *T,
+                          const double *V, int target_a, int target_b);
+
+/* Same with V in coordinate form: nnz entries (p,q,r,s) = ijkl[4*e..4*e+3],
+ * value val[e]; repeated entries add up. */
+int mdmrg_set_hamiltonian_coo(mdmrg_ctx ctx, int n_sites, int spin_half, const double *T,
+                              int64_t nnz, const int32_t *ijkl, const double *val,
+                              int target_a, int target_b);
+
+/* Number of operator terms of the canonical (antisymmetrised) Hamiltonian. */
+int mdmrg_n_terms(mdmrg_ctx ctx, int64_t *n_one_body, int64_t *n_two_body);
+
+/* ------------------------------------------------------------------- MPS */
+
+/* Load an MPS in the exchange format above.  n_sect[n+1] sector counts per
+ * bond; sect_qn[2*S] and sect_dim[S] for all S sectors of all bonds in bond
+ * order; data = site tensors (n_data doubles).  Sites left of the bond later
+ * prepared are used as left isometries, sites right of it as right
+ * isometries. */
+int mdmrg_set_mps(mdmrg_ctx ctx, const int32_t *n_sect, const int32_t *sect_qn,
+                  const int32_t *sect_dim, const double *data, int64_t n_data);
+
+/* Sector list of bond i: query with qn = dim = NULL to get *n_sect. */
+int mdmrg_get_bond(mdmrg_ctx ctx, int bond, int32_t *n_sect, int32_t *qn, int32_t *dim);
+
+/* ------------------------------------------------------------------- bond */
+
+/* Make bond (l, l+1) current: build (on the device) the renormalised
+ * operators of the left block (sites < l) and the right block
+ * (sites > l+1) from the MPS by repeated renormalisation (Sec. II.A), then
+ * the "Tables" of the step: sector lists, the wave-function layout and the
+ * task lists of the effective Hamiltonian. */
+int mdmrg_prepare_bond(mdmrg_ctx ctx, int l);
+
+/* Layout of the current two-site vector.  *n_elem = total doubles,
+ * *n_blk = number of blocks; if desc != NULL it receives 8 int32 per block:
+ * (a, s1, s2, b, m_a, m_b, offset_lo, offset_hi). */
+int mdmrg_psi_layout(mdmrg_ctx ctx, int64_t *n_elem, int32_t *n_blk, int32_t *desc);
+
+/* y = H_eff x at the current bond (x, y: caller-owned device buffers of
+ * n_elem doubles, must not alias).  prec MDMRG_FP64 is the plain form. */
+int mdmrg_heff_apply(mdmrg_ctx ctx, int prec, const double *x, double *y);
+
+/* Diagonal of H_eff at the current bond into device buffer d. */
+int mdmrg_heff_diag(mdmrg_ctx ctx, double *d);
+
+/* Cost of one H_eff x at the current bond: algorithmic FLOP (sum over GEMM
+ * tasks of 2mnk in the chosen order, no padding, identity products not
+ * counted), algorithmic bytes (each distinct operand block read once, each
+ * output block written once, intermediates written and read once), the
+ * number of operator products (terms) and of GEMM segments.  Any output
+ * pointer may be NULL. */
+int mdmrg_heff_cost(mdmrg_ctx ctx, double *flop, double *bytes, int64_t *n_terms, int64_t *n_gemm);
+
+/* Davidson for the lowest eigenpair of H_eff (Sec. II.A), FP64 on device.
+ * x (device, n_elem) holds the start vector on entry (normalised inside; if
+ * zero, a seeded random vector is used) and the eigenvector on exit.
+ * Stops at ||H x - theta x||_2 <= tol with ||x|| = 1.  Returns ENOCONV
+ * after max_iter matrix-vector products with the best estimate in
+ * *energy / x.  m_max: subspace size before a thick restart to 2 vectors. */
+int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max,
+                   double *energy, double *resid, int *n_matvec);
+
+/* Reduced-density-matrix truncation of the two-site vector x (Diag_D):
+ * direction +1 replaces site l by a left isometry and bond l+1 by the kept
+ * states of the left enlarged block; -1 replaces site l+1 by a right
+ * isometry.  Keeps min(D, available) states ranked by eigenvalue.  Outputs
+ * truncation error, von Neumann and half-Renyi entropies (any may be NULL). */
+int mdmrg_decimate(mdmrg_ctx ctx, const double *x, int D, int direction, double *trunc_err,
+                   double *s_vn, double *s_half);
+
+/* Renormalisation (Ren_l / Ren_r): after mdmrg_decimate(direction) at bond
+ * (l, l+1), build on the device every operator of the grown block (left
+ * block of sites <= l for +1, right block of sites >= l+1 for -1) from the
+ * new isometry, then make bond (l+direction, l+direction+1) current
+ * (as mdmrg_prepare_bond).  ESTATE if the last call at this bond was not
+ * mdmrg_decimate with the same direction. */
+int mdmrg_renormalize(mdmrg_ctx ctx, int direction);
+
+/* Start vector of the new current bond (StVec): x_new (n_elem of the new
+ * layout) = the two-site vector x_old of the previous bond (its layout)
+ * written in the new basis,  psi' = P'^T P psi.  Valid right after
+ * mdmrg_renormalize; x_old and x_new are caller-owned device buffers. */
+int mdmrg_stvec(mdmrg_ctx ctx, const double *x_old, double *x_new);
+
+/* Finite two-site sweeps from the current MPS (a right then a left
+ * half-sweep per sweep), bond dimension D_schedule[min(k, n_sched-1)] in
+ * sweep k, Davidson tolerance tol.  energies receives the final energy of
+ * each sweep (n_sweeps doubles, may be NULL). */
+int mdmrg_sweep(mdmrg_ctx ctx, int n_sweeps, const int *D_schedule, int n_sched, double tol,
+                double *energies);
+
+/* Wall seconds per step category (Diag_H, Ren, Tables, Diag_D, StVec,
+ * Other) accumulated since creation, the algorithmic FLOP of all H_eff
+ * products, and HIP-event timings of the grouped-GEMM launches on the
+ * context stream; out must hold 14 doubles:
+ * [diag_h, ren, tables, diag_d, stvec, other, heff_flop, n_matvec,
+ *  heff_gemm_ms, heff_gemm_launches, heff_gemm_flop,
+ *  ren_gemm_ms, ren_gemm_launches, ren_gemm_flop]. */
+int mdmrg_get_stats(mdmrg_ctx ctx, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDMRG_H */

@@ -1,0 +1,48 @@
+"""Build libmdmrg.so in-tree for gfx950 with hipcc.
+
+Usage: python -m paper_2311_14106_amd.build   (or build() from Python)
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, 'csrc')
+OUT = os.path.join(HERE, 'libmdmrg.so')
+HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
+CXX = os.environ.get('CXX', 'g++')
+
+SOURCES = ['device.hip', 'model.cpp', 'engine.cpp', 'capi.cpp']
+COMMON = ['-O3', '-fPIC', '-std=c++17', '-Wall', '-Wno-unused-result']
+HIP_FLAGS = ['-x', 'hip', '--offload-arch=gfx950',
+             '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops']
+
+
+def build(verbose=False):
+    objdir = os.path.join(HERE, '_build')
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        path = os.path.join(CSRC, src)
+        obj = os.path.join(objdir, src + '.o')
+        if src.endswith('.hip'):
+            cmd = [HIPCC] + COMMON + HIP_FLAGS
+        else:
+            cmd = [CXX] + COMMON
+        cmd += ['-I', os.path.join(HERE, '..', 'include'), '-c', path, '-o', obj]
+        if verbose:
+            print(' '.join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(obj)
+    tmp = OUT + '.tmp'
+    cmd = [HIPCC, '-shared', '-fPIC', '--offload-arch=gfx950', '-o', tmp] + objs + \
+          ['-L/opt/rocm/lib', '-lrocsolver', '-lrocblas', '-Wl,-rpath,/opt/rocm/lib']
+    if verbose:
+        print(' '.join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, OUT)
+    return OUT
+
+
+if __name__ == '__main__':
+    print(build(verbose='-v' in sys.argv))

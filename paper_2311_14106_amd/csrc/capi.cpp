@@ -1,0 +1,309 @@
+// extern "C" boundary of libmdmrg: argument checks, exception -> status.
+#include <cmath>
+
+#include "../../include/mdmrg.h"
+#include "engine.h"
+
+using namespace mdmrg;
+
+struct mdmrg_ctx_s {
+  Context c;
+};
+
+template <class F>
+static int guarded(mdmrg_ctx ctx, F &&f) {
+  try {
+    if (ctx) ctx->c.err.clear();
+    return f();
+  } catch (const Error &e) {
+    if (ctx) ctx->c.err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    if (ctx) ctx->c.err = "host allocation failed";
+    return MDMRG_ENOMEM;
+  } catch (const std::exception &e) {
+    if (ctx) ctx->c.err = e.what();
+    return MDMRG_EDEVICE;
+  }
+}
+
+static thread_local std::string g_err;
+
+extern "C" {
+
+const char *mdmrg_version(void) { return "mdmrg 0.1 (gfx950)"; }
+
+int mdmrg_create(mdmrg_ctx *out, int device) {
+  if (!out) return MDMRG_EINVAL;
+  *out = nullptr;
+  try {
+    auto *c = new mdmrg_ctx_s();
+    c->c.dev = dev_create(device);
+    dev_timing_enable(c->c.dev, true);
+    *out = c;
+    return MDMRG_OK;
+  } catch (const Error &e) {
+    g_err = e.what();
+    return e.code;
+  } catch (...) {
+    return MDMRG_EDEVICE;
+  }
+}
+
+void mdmrg_destroy(mdmrg_ctx ctx) { delete ctx; }
+
+const char *mdmrg_last_error(mdmrg_ctx ctx) { return ctx ? ctx->c.err.c_str() : g_err.c_str(); }
+
+int mdmrg_lattice_nso(int model, int Lx, int Ly) {
+  if (Lx < 1 || Ly < 1 || (model != 0 && model != 1)) return MDMRG_EINVAL;
+  return lattice_nso(model, Lx, Ly);
+}
+
+int mdmrg_build_lattice(int model, int basis, int Lx, int Ly, double t, double u, double *T, double *V) {
+  if (!T || !V) return MDMRG_EINVAL;
+  return guarded(nullptr, [&] {
+    build_lattice(model, basis, Lx, Ly, t, u, T, V);
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_rotate_modes(int n_modes, int spin_half, const double *R, double *T, double *V) {
+  if (!R || !T || !V || n_modes < 1) return MDMRG_EINVAL;
+  return guarded(nullptr, [&] {
+    rotate_modes(n_modes, spin_half, R, T, V);
+    return MDMRG_OK;
+  });
+}
+
+static int set_ham(mdmrg_ctx ctx, int n_sites, int spin_half, const double *T, const double *V,
+                   const int32_t *ijkl, const double *val, int64_t nnz, int ta, int tb) {
+  if (!ctx) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    MDMRG_REQUIRE(n_sites >= 2 && T, MDMRG_EINVAL, "set_hamiltonian: bad arguments");
+    Context &c = ctx->c;
+    c.reset_envs();
+    c.have_mps = false;
+    c.ham.build(n_sites, spin_half, T, V, ijkl, val, nnz, QN(ta, spin_half ? tb : 0));
+    c.have_ham = true;
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_set_hamiltonian(mdmrg_ctx ctx, int n_sites, int spin_half, const double *T, const double *V,
+                          int target_a, int target_b) {
+  if (!V) return MDMRG_EINVAL;
+  return set_ham(ctx, n_sites, spin_half, T, V, nullptr, nullptr, 0, target_a, target_b);
+}
+
+int mdmrg_set_hamiltonian_coo(mdmrg_ctx ctx, int n_sites, int spin_half, const double *T, int64_t nnz,
+                              const int32_t *ijkl, const double *val, int target_a, int target_b) {
+  if (nnz < 0 || (nnz > 0 && (!ijkl || !val))) return MDMRG_EINVAL;
+  return set_ham(ctx, n_sites, spin_half, T, nullptr, ijkl, val, nnz, target_a, target_b);
+}
+
+int mdmrg_n_terms(mdmrg_ctx ctx, int64_t *n1, int64_t *n2) {
+  if (!ctx) return MDMRG_EINVAL;
+  if (!ctx->c.have_ham) return MDMRG_ESTATE;
+  if (n1) *n1 = ctx->c.ham.n1;
+  if (n2) *n2 = ctx->c.ham.n2;
+  return MDMRG_OK;
+}
+
+int mdmrg_set_mps(mdmrg_ctx ctx, const int32_t *n_sect, const int32_t *sect_qn, const int32_t *sect_dim,
+                  const double *data, int64_t n_data) {
+  if (!ctx || !n_sect || !sect_qn || !sect_dim || (!data && n_data)) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    Context &c = ctx->c;
+    MDMRG_REQUIRE(c.have_ham, MDMRG_ESTATE, "set_mps: set the Hamiltonian first");
+    const int n = c.ham.n, d = c.ham.d;
+    c.reset_envs();
+    for (auto &t : c.A)
+      if (t.data) dev_free(c.dev, t.data);
+    c.A.clear();
+    c.bonds.assign(n + 1, Bond());
+    int64_t s = 0;
+    for (int i = 0; i <= n; ++i) {
+      MDMRG_REQUIRE(n_sect[i] >= 1, MDMRG_EINVAL, "set_mps: every bond needs a sector");
+      for (int k = 0; k < n_sect[i]; ++k, ++s) {
+        const QN q(sect_qn[2 * s], sect_qn[2 * s + 1]);
+        MDMRG_REQUIRE(sect_dim[s] >= 1, MDMRG_EINVAL, "set_mps: sector dimensions must be positive");
+        if (!c.bonds[i].qn.empty())
+          MDMRG_REQUIRE(c.bonds[i].qn.back() < q, MDMRG_EINVAL, "set_mps: sectors must be strictly ascending");
+        c.bonds[i].qn.push_back(q);
+        c.bonds[i].dim.push_back(sect_dim[s]);
+      }
+      c.bonds[i].rebuild_index();
+    }
+    MDMRG_REQUIRE(c.bonds[0].qn.size() == 1 && c.bonds[0].qn[0] == QN() && c.bonds[0].dim[0] == 1,
+                  MDMRG_EINVAL, "set_mps: bond 0 must be the vacuum");
+    MDMRG_REQUIRE(c.bonds[n].qn.size() == 1 && c.bonds[n].qn[0] == c.ham.target && c.bonds[n].dim[0] == 1,
+                  MDMRG_EINVAL, "set_mps: last bond must be the target sector");
+    int64_t pos = 0;
+    c.A.resize(n);
+    for (int i = 0; i < n; ++i) {
+      SiteTensor &T = c.A[i];
+      const Bond &L = c.bonds[i], &R = c.bonds[i + 1];
+      for (size_t l = 0; l < L.qn.size(); ++l)
+        for (int st = 0; st < d; ++st) {
+          const int r = R.find(L.qn[l] + c.ham.q_of_state(st));
+          if (r < 0) continue;
+          T.add(int(l), st, r, int64_t(L.dim[l]) * R.dim[r]);
+        }
+      MDMRG_REQUIRE(pos + T.size <= n_data, MDMRG_EINVAL, "set_mps: data shorter than the sector layout");
+      T.data = (double *)dev_alloc(c.dev, sizeof(double) * std::max<int64_t>(1, T.size));
+      dev_h2d(c.dev, T.data, data + pos, sizeof(double) * T.size);
+      pos += T.size;
+    }
+    MDMRG_REQUIRE(pos == n_data, MDMRG_EINVAL, "set_mps: data longer than the sector layout");
+    c.have_mps = true;
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_get_bond(mdmrg_ctx ctx, int bond, int32_t *n_sect, int32_t *qn, int32_t *dim) {
+  if (!ctx || !n_sect) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    Context &c = ctx->c;
+    MDMRG_REQUIRE(c.have_mps, MDMRG_ESTATE, "get_bond: no MPS");
+    MDMRG_REQUIRE(bond >= 0 && bond <= c.ham.n, MDMRG_EINVAL, "get_bond: bond out of range");
+    const Bond &b = c.bonds[bond];
+    *n_sect = int32_t(b.qn.size());
+    for (size_t i = 0; i < b.qn.size(); ++i) {
+      if (qn) {
+        qn[2 * i] = b.qn[i].a;
+        qn[2 * i + 1] = b.qn[i].b;
+      }
+      if (dim) dim[i] = b.dim[i];
+    }
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_prepare_bond(mdmrg_ctx ctx, int l) {
+  if (!ctx) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    ctx->c.prepare(l);
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_psi_layout(mdmrg_ctx ctx, int64_t *n_elem, int32_t *n_blk, int32_t *desc) {
+  if (!ctx) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    Context &c = ctx->c;
+    MDMRG_REQUIRE(c.cur >= 0, MDMRG_ESTATE, "psi_layout: no current bond");
+    if (n_elem) *n_elem = c.psi.n_elem;
+    if (n_blk) *n_blk = int32_t(c.psi.blk.size());
+    if (desc)
+      for (size_t i = 0; i < c.psi.blk.size(); ++i) {
+        const PsiBlk &b = c.psi.blk[i];
+        int32_t *o = desc + 8 * i;
+        o[0] = b.a;
+        o[1] = b.s1;
+        o[2] = b.s2;
+        o[3] = b.b;
+        o[4] = b.m;
+        o[5] = b.n;
+        o[6] = int32_t(b.off & 0xffffffff);
+        o[7] = int32_t(b.off >> 32);
+      }
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_heff_apply(mdmrg_ctx ctx, int prec, const double *x, double *y) {
+  if (!ctx || !x || !y || x == y) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    MDMRG_REQUIRE(prec == MDMRG_FP64, MDMRG_EUNSUP, "heff_apply: only the FP64 form is built");
+    ctx->c.heff_apply(x, y);
+    dev_sync(ctx->c.dev);
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_heff_diag(mdmrg_ctx ctx, double *d) {
+  if (!ctx || !d) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    ctx->c.heff_diag(d);
+    dev_sync(ctx->c.dev);
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_heff_cost(mdmrg_ctx ctx, double *flop, double *bytes, int64_t *n_terms, int64_t *n_gemm) {
+  if (!ctx) return MDMRG_EINVAL;
+  if (ctx->c.cur < 0) return MDMRG_ESTATE;
+  if (flop) *flop = ctx->c.heff.flop;
+  if (bytes) *bytes = ctx->c.heff.bytes;
+  if (n_terms) *n_terms = ctx->c.heff_terms;
+  if (n_gemm) *n_gemm = ctx->c.heff.n_gemm;
+  return MDMRG_OK;
+}
+
+int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max, double *energy, double *resid,
+                   int *n_matvec) {
+  if (!ctx || !x || !(tol > 0) || max_iter < 1) return MDMRG_EINVAL;
+  return guarded(ctx, [&] { return ctx->c.davidson(x, tol, max_iter, m_max, energy, resid, n_matvec); });
+}
+
+int mdmrg_decimate(mdmrg_ctx ctx, const double *x, int D, int direction, double *trunc_err, double *s_vn,
+                   double *s_half) {
+  if (!ctx || !x) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    ctx->c.decimate(x, D, direction, trunc_err, s_vn, s_half);
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_renormalize(mdmrg_ctx ctx, int direction) {
+  if (!ctx) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    ctx->c.renormalize(direction);
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_stvec(mdmrg_ctx ctx, const double *x_old, double *x_new) {
+  if (!ctx || !x_old || !x_new || x_old == x_new) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    Context &c = ctx->c;
+    MDMRG_REQUIRE(c.prev_l >= 0 && c.cur == c.prev_l + c.prev_dir, MDMRG_ESTATE,
+                  "stvec: call renormalize first");
+    c.stvec(x_old, c.prev_l, c.prev_dir, c.prev_psi, x_new, c.psi);
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_sweep(mdmrg_ctx ctx, int n_sweeps, const int *D_schedule, int n_sched, double tol, double *energies) {
+  if (!ctx || !D_schedule) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    ctx->c.sweep(n_sweeps, D_schedule, n_sched, tol, energies);
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
+  if (!ctx || !out) return MDMRG_EINVAL;
+  const Stats &s = ctx->c.stats;
+  out[0] = s.t_diag_h;
+  out[1] = s.t_ren;
+  out[2] = s.t_tables;
+  out[3] = s.t_diag_d;
+  out[4] = s.t_stvec;
+  out[5] = s.t_other;
+  out[6] = s.heff_flop;
+  out[7] = s.n_matvec;
+  return guarded(ctx, [&] {
+    double ms[kTags], ln[kTags], fl[kTags];
+    dev_timing_collect(ctx->c.dev, ms, ln, fl);
+    out[8] = ms[1];
+    out[9] = ln[1];
+    out[10] = fl[1];
+    out[11] = ms[2];
+    out[12] = ln[2];
+    out[13] = fl[2];
+    return MDMRG_OK;
+  });
+}
+
+}  // extern "C"

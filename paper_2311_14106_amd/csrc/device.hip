@@ -1,0 +1,577 @@
+// Device layer of libmdmrg for gfx950 (CDNA4): memory, the grouped
+// sector-block GEMM (FP64 MFMA) that carries the effective-Hamiltonian
+// product, renormalisation, density matrices and operator combinations, the
+// diagonal of H_eff, deterministic FP64 vector reductions, a counter-based
+// Gaussian generator and the symmetric eigensolver (rocSOLVER).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+#include "internal.h"
+
+namespace mdmrg {
+
+#define HIP_CHECK(x)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      throw Error(-3, std::string("HIP error: ") + hipGetErrorString(e_) + " at " #x);  \
+  } while (0)
+
+struct Device {
+  int id = 0;
+  hipStream_t stream = nullptr;
+  rocblas_handle blas = nullptr;
+  double *red = nullptr;       // reduction partials
+  double *red_out = nullptr;   // reduction results (device)
+  double *host_red = nullptr;  // pinned host mirror
+  int *info = nullptr;
+  double *syevd_work = nullptr;
+  size_t syevd_work_n = 0;
+  // launch timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending {
+    int tag;
+    hipEvent_t a, b;
+    double flop;
+  };
+  std::vector<Pending> pending;
+  double ms[kTags] = {}, launches[kTags] = {}, flop[kTags] = {};
+};
+
+static hipEvent_t ev_get(Device *d) {
+  if (!d->ev_pool.empty()) {
+    hipEvent_t e = d->ev_pool.back();
+    d->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_CHECK(hipEventCreate(&e));
+  return e;
+}
+
+static void timing_drain(Device *d) {
+  if (d->pending.empty()) return;
+  HIP_CHECK(hipEventSynchronize(d->pending.back().b));
+  for (auto &p : d->pending) {
+    float t = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&t, p.a, p.b));
+    d->ms[p.tag] += t;
+    d->launches[p.tag] += 1;
+    d->flop[p.tag] += p.flop;
+    d->ev_pool.push_back(p.a);
+    d->ev_pool.push_back(p.b);
+  }
+  d->pending.clear();
+}
+
+void dev_timing_enable(Device *d, bool on) { d->timing = on; }
+void dev_timing_collect(Device *d, double *ms, double *launches, double *flop) {
+  timing_drain(d);
+  for (int i = 0; i < kTags; ++i) {
+    ms[i] = d->ms[i];
+    launches[i] = d->launches[i];
+    flop[i] = d->flop[i];
+  }
+}
+
+double wall_seconds() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr int kRedBlocks = 256;
+constexpr int kMaxDot = 64;
+
+Device *dev_create(int device) {
+  auto *d = new Device();
+  d->id = device;
+  HIP_CHECK(hipSetDevice(device));
+  // blocking stream: ordered with work that callers queue on the legacy default stream
+  HIP_CHECK(hipStreamCreate(&d->stream));
+  if (rocblas_create_handle(&d->blas) != rocblas_status_success) throw Error(-3, "rocblas_create_handle failed");
+  rocblas_set_stream(d->blas, d->stream);
+  HIP_CHECK(hipMalloc(&d->red, sizeof(double) * kRedBlocks * kMaxDot));
+  HIP_CHECK(hipMalloc(&d->red_out, sizeof(double) * kMaxDot));
+  HIP_CHECK(hipHostMalloc(&d->host_red, sizeof(double) * kMaxDot));
+  HIP_CHECK(hipMalloc(&d->info, sizeof(int)));
+  return d;
+}
+
+void dev_destroy(Device *d) {
+  if (!d) return;
+  (void)hipSetDevice(d->id);
+  (void)hipStreamSynchronize(d->stream);
+  for (auto &p : d->pending) {
+    d->ev_pool.push_back(p.a);
+    d->ev_pool.push_back(p.b);
+  }
+  for (auto e : d->ev_pool) (void)hipEventDestroy(e);
+  (void)hipFree(d->red);
+  (void)hipFree(d->red_out);
+  (void)hipHostFree(d->host_red);
+  (void)hipFree(d->info);
+  if (d->syevd_work) (void)hipFree(d->syevd_work);
+  if (d->blas) rocblas_destroy_handle(d->blas);
+  (void)hipStreamDestroy(d->stream);
+  delete d;
+}
+
+void *dev_alloc(Device *d, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void *p = nullptr;
+  hipError_t e = hipMallocAsync(&p, bytes, d->stream);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error(-2, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return p;
+}
+void dev_free(Device *d, void *p) {
+  if (p) HIP_CHECK(hipFreeAsync(p, d->stream));
+}
+void dev_h2d(Device *d, void *dst, const void *src, size_t b) {
+  if (b) HIP_CHECK(hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, d->stream));
+  HIP_CHECK(hipStreamSynchronize(d->stream));
+}
+void dev_d2h(Device *d, void *dst, const void *src, size_t b) {
+  if (b) HIP_CHECK(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToHost, d->stream));
+  HIP_CHECK(hipStreamSynchronize(d->stream));
+}
+void dev_d2d(Device *d, void *dst, const void *src, size_t b) {
+  if (b) HIP_CHECK(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, d->stream));
+}
+void dev_sync(Device *d) { HIP_CHECK(hipStreamSynchronize(d->stream)); }
+size_t dev_free_bytes(Device *d) {
+  size_t f = 0, t = 0;
+  HIP_CHECK(hipMemGetInfo(&f, &t));
+  return f;
+}
+
+// ------------------------------------------------------------------ zero
+__global__ void k_zero(double *x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0;
+}
+void dev_zero(Device *d, void *dst, size_t bytes) {
+  // a fill kernel (not a memset node) so that callers may capture it
+  int64_t n = int64_t(bytes / 8);
+  if (n > 0) {
+    int grid = int(std::min<int64_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, d->stream, (double *)dst, n);
+    HIP_CHECK(hipGetLastError());
+  }
+  if (bytes % 8) HIP_CHECK(hipMemsetAsync((char *)dst + n * 8, 0, bytes % 8, d->stream));
+}
+
+// ----------------------------------------------------- grouped GEMM (FP64)
+// Workgroup = 4 waves = 64x64 output tile; wave (wm, wn) owns a 32x32
+// quadrant as 2x2 MFMA 16x16x4 accumulators.  K is staged through LDS in
+// steps of 16.  Operand layout of v_mfma_f64_16x16x4f64: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; accumulator element r of lane l is
+// C[l/16 + 4r][l%16] (checked against a host reference on gfx950).
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int TM = 64, TN = 64, TK = 16, LDP = TM + 2;
+
+__global__ __launch_bounds__(256) void k_gemm_f64(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
+                                                  const GSeg *__restrict__ segs, Bases bases) {
+  __shared__ double As[TK][LDP];
+  __shared__ double Bs[TK][LDP];
+  const GTile tl = tiles[blockIdx.x];
+  const GOut o = outs[tl.out];
+  const int row0 = int(tl.ti) * TM, col0 = int(tl.tj) * TN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  for (int si = 0; si < o.seg_count; ++si) {
+    const GSeg sg = segs[o.seg_begin + si];
+    const double *A = bases.p[sg.a_slot] + sg.a_off;
+    const double *B = bases.p[sg.b_slot] + sg.b_off;
+    const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB, idA = sg.flags & SEG_AID;
+    const double alpha = sg.alpha;
+    for (int k0 = 0; k0 < sg.k; k0 += TK) {
+      // stage op(A)[row0 + i][k0 + kk] (scaled by alpha)
+#pragma unroll
+      for (int it = 0; it < (TM * TK) / 256; ++it) {
+        const int e = tid + it * 256;
+        int i, kk;
+        if (!tA) {
+          i = e / TK;
+          kk = e % TK;
+        } else {
+          kk = e / TM;
+          i = e % TM;
+        }
+        const int gi = row0 + i, gk = k0 + kk;
+        double v = 0.0;
+        if (gi < o.m && gk < sg.k) {
+          if (idA)
+            v = (gi == gk) ? alpha : 0.0;
+          else
+            v = alpha * (tA ? A[(int64_t)gk * sg.lda + gi] : A[(int64_t)gi * sg.lda + gk]);
+        }
+        As[kk][i] = v;
+      }
+      // stage op(B)[k0 + kk][col0 + j]
+#pragma unroll
+      for (int it = 0; it < (TN * TK) / 256; ++it) {
+        const int e = tid + it * 256;
+        int j, kk;
+        if (!tB) {
+          kk = e / TN;
+          j = e % TN;
+        } else {
+          j = e / TK;
+          kk = e % TK;
+        }
+        const int gj = col0 + j, gk = k0 + kk;
+        double v = 0.0;
+        if (gj < o.n && gk < sg.k) v = tB ? B[(int64_t)gj * sg.ldb + gk] : B[(int64_t)gk * sg.ldb + gj];
+        Bs[kk][j] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 4) {
+        double a0 = As[kk + lk][wm + lr];
+        double a1 = As[kk + lk][wm + 16 + lr];
+        double b0 = Bs[kk + lk][wn + lr];
+        double b1 = Bs[kk + lk][wn + 16 + lr];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  double *C = bases.p[o.c_slot] + o.c_off;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = row0 + wm + mi * 16 + lk + 4 * r;
+        const int gj = col0 + wn + ni * 16 + lr;
+        if (gi < o.m && gj < o.n) {
+          double *p = C + (int64_t)gi * o.ldc + gj;
+          const double v = acc[mi][ni][r];
+          *p = o.accumulate ? (*p + v) : v;
+        }
+      }
+}
+
+DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
+  auto *dp = new DevPlan();
+  dp->n_outs = int64_t(plan.outs.size());
+  dp->n_segs = int64_t(plan.segs.size());
+  dp->flop = plan.flop;
+  // tiles, largest outputs first (longest-processing-time order)
+  std::vector<std::pair<double, int32_t>> work(plan.outs.size());
+  for (size_t i = 0; i < plan.outs.size(); ++i) {
+    const GOut &o = plan.outs[i];
+    double kk = 0;
+    for (int s = 0; s < o.seg_count; ++s) kk += plan.segs[o.seg_begin + s].k;
+    work[i] = {-(kk + 16.0) * o.m * o.n, int32_t(i)};
+  }
+  std::stable_sort(work.begin(), work.end());
+  std::vector<GTile> tiles;
+  for (auto &w : work) {
+    const GOut &o = plan.outs[w.second];
+    const int nti = (o.m + TM - 1) / TM, ntj = (o.n + TN - 1) / TN;
+    for (int i = 0; i < nti; ++i)
+      for (int j = 0; j < ntj; ++j) tiles.push_back(GTile{w.second, int16_t(i), int16_t(j)});
+  }
+  MDMRG_REQUIRE(tiles.size() < (size_t(1) << 31), -6, "grouped GEMM plan has too many tiles");
+  dp->n_tiles = int64_t(tiles.size());
+  if (dp->n_tiles) {
+    dp->segs = (GSeg *)dev_alloc(d, sizeof(GSeg) * std::max<size_t>(1, plan.segs.size()));
+    dp->outs = (GOut *)dev_alloc(d, sizeof(GOut) * plan.outs.size());
+    dp->tiles = (GTile *)dev_alloc(d, sizeof(GTile) * tiles.size());
+    if (!plan.segs.empty()) dev_h2d(d, dp->segs, plan.segs.data(), sizeof(GSeg) * plan.segs.size());
+    dev_h2d(d, dp->outs, plan.outs.data(), sizeof(GOut) * plan.outs.size());
+    dev_h2d(d, dp->tiles, tiles.data(), sizeof(GTile) * tiles.size());
+  }
+  return dp;
+}
+
+void dev_plan_free(Device *d, DevPlan *p) {
+  if (!p) return;
+  dev_free(d, p->segs);
+  dev_free(d, p->outs);
+  dev_free(d, p->tiles);
+  delete p;
+}
+
+void dev_gemm_run(Device *d, const DevPlan *p, const Bases &b, int tag) {
+  if (!p || p->n_tiles == 0) return;
+  const bool timed = d->timing && tag > 0 && tag < kTags;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    if (d->pending.size() > 512) timing_drain(d);
+    e0 = ev_get(d);
+    e1 = ev_get(d);
+    HIP_CHECK(hipEventRecord(e0, d->stream));
+  }
+  hipLaunchKernelGGL(k_gemm_f64, dim3(unsigned(p->n_tiles)), dim3(256), 0, d->stream, p->tiles, p->outs, p->segs,
+                     b);
+  HIP_CHECK(hipGetLastError());
+  if (timed) {
+    HIP_CHECK(hipEventRecord(e1, d->stream));
+    d->pending.push_back(Device::Pending{tag, e0, e1, p->flop});
+  }
+}
+
+// ------------------------------------------------------- diagonal of H_eff
+__global__ void k_diag(const DiagTask *__restrict__ tasks, const int32_t *__restrict__ beg,
+                       const int64_t *__restrict__ off, const int32_t *__restrict__ bm,
+                       const int32_t *__restrict__ bn, Bases bases, double *__restrict__ d) {
+  const int b = blockIdx.x;
+  const int m = bm[b], n = bn[b];
+  double *D = d + off[b];
+  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    double s = 0.0;
+    for (int t = beg[b]; t < beg[b + 1]; ++t) {
+      const DiagTask tk = tasks[t];
+      const double l = tk.l_id ? 1.0 : bases.p[tk.l_slot][tk.l_off + (int64_t)i * tk.ls];
+      const double r = tk.r_id ? 1.0 : bases.p[tk.r_slot][tk.r_off + (int64_t)j * tk.rs];
+      s += tk.alpha * l * r;
+    }
+    D[e] = s;
+  }
+}
+
+DevDiag *dev_diag_upload(Device *d, const std::vector<DiagTask> &tasks, const std::vector<int64_t> &blk_off,
+                         const std::vector<int32_t> &blk_m, const std::vector<int32_t> &blk_n) {
+  // tasks must be grouped by output block (d_off order matches blk_off)
+  auto *dd = new DevDiag();
+  const int64_t nb = int64_t(blk_off.size());
+  std::vector<int32_t> beg(nb + 1, 0);
+  std::unordered_map<int64_t, int> bidx;
+  for (int64_t i = 0; i < nb; ++i) bidx[blk_off[i]] = int(i);
+  std::vector<std::vector<DiagTask>> per(nb);
+  for (auto &t : tasks) per[bidx.at(t.d_off)].push_back(t);
+  std::vector<DiagTask> flat;
+  for (int64_t i = 0; i < nb; ++i) {
+    beg[i] = int32_t(flat.size());
+    flat.insert(flat.end(), per[i].begin(), per[i].end());
+  }
+  beg[nb] = int32_t(flat.size());
+  dd->n_tasks = int64_t(flat.size());
+  dd->n_blk = nb;
+  dd->tasks = (DiagTask *)dev_alloc(d, sizeof(DiagTask) * std::max<size_t>(1, flat.size()));
+  dd->blk_begin = (int32_t *)dev_alloc(d, sizeof(int32_t) * (nb + 1));
+  dd->blk_off = (int64_t *)dev_alloc(d, sizeof(int64_t) * std::max<int64_t>(1, nb));
+  dd->blk_m = (int32_t *)dev_alloc(d, sizeof(int32_t) * std::max<int64_t>(1, nb));
+  dd->blk_n = (int32_t *)dev_alloc(d, sizeof(int32_t) * std::max<int64_t>(1, nb));
+  if (!flat.empty()) dev_h2d(d, dd->tasks, flat.data(), sizeof(DiagTask) * flat.size());
+  dev_h2d(d, dd->blk_begin, beg.data(), sizeof(int32_t) * (nb + 1));
+  if (nb) {
+    dev_h2d(d, dd->blk_off, blk_off.data(), sizeof(int64_t) * nb);
+    dev_h2d(d, dd->blk_m, blk_m.data(), sizeof(int32_t) * nb);
+    dev_h2d(d, dd->blk_n, blk_n.data(), sizeof(int32_t) * nb);
+  }
+  return dd;
+}
+
+void dev_diag_free(Device *d, DevDiag *p) {
+  if (!p) return;
+  dev_free(d, p->tasks);
+  dev_free(d, p->blk_begin);
+  dev_free(d, p->blk_off);
+  dev_free(d, p->blk_m);
+  dev_free(d, p->blk_n);
+  delete p;
+}
+
+void dev_diag_run(Device *d, const DevDiag *p, const Bases &b, double *out) {
+  if (!p || p->n_blk == 0) return;
+  hipLaunchKernelGGL(k_diag, dim3(unsigned(p->n_blk)), dim3(256), 0, d->stream, p->tasks, p->blk_begin, p->blk_off,
+                     p->blk_m, p->blk_n, b, out);
+  HIP_CHECK(hipGetLastError());
+}
+
+// -------------------------------------------------- FP64 vector primitives
+__device__ inline double block_sum(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_multidot_partial(const double *__restrict__ V, int64_t ldv,
+                                                          const double *__restrict__ x, int64_t n,
+                                                          double *__restrict__ part) {
+  __shared__ double sh[256];
+  const int y = blockIdx.y;
+  const double *v = V + (int64_t)y * ldv;
+  double s = 0.0;
+  for (int64_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) s += v[k] * x[k];
+  const double r = block_sum(s, sh);
+  if (threadIdx.x == 0) part[y * gridDim.x + blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(256) void k_multidot_final(const double *__restrict__ part, int nb,
+                                                        double *__restrict__ out) {
+  __shared__ double sh[256];
+  const int y = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += part[y * nb + i];
+  const double r = block_sum(s, sh);
+  if (threadIdx.x == 0) out[y] = r;
+}
+
+void dev_multidot(Device *d, const double *V, int64_t ldv, int m, const double *x, int64_t n, double *out_host) {
+  MDMRG_REQUIRE(m >= 0 && m <= kMaxDot, -1, "multidot: too many vectors");
+  if (m == 0) return;
+  hipLaunchKernelGGL(k_multidot_partial, dim3(kRedBlocks, m), dim3(256), 0, d->stream, V, ldv, x, n, d->red);
+  hipLaunchKernelGGL(k_multidot_final, dim3(m), dim3(256), 0, d->stream, d->red, kRedBlocks, d->red_out);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipMemcpyAsync(d->host_red, d->red_out, sizeof(double) * m, hipMemcpyDeviceToHost, d->stream));
+  HIP_CHECK(hipStreamSynchronize(d->stream));
+  std::memcpy(out_host, d->host_red, sizeof(double) * m);
+}
+
+struct Coefs {
+  double c[kMaxDot];
+};
+__global__ void k_lincomb(const double *__restrict__ V, int64_t ldv, int m, Coefs c, double beta,
+                          double *__restrict__ y, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    double s = (beta == 0.0) ? 0.0 : beta * y[k];
+    for (int i = 0; i < m; ++i) s += c.c[i] * V[(int64_t)i * ldv + k];
+    y[k] = s;
+  }
+}
+void dev_lincomb(Device *d, const double *V, int64_t ldv, int m, const double *c_host, double beta, double *y,
+                 int64_t n) {
+  MDMRG_REQUIRE(m >= 0 && m <= kMaxDot, -1, "lincomb: too many vectors");
+  Coefs c{};
+  for (int i = 0; i < m; ++i) c.c[i] = c_host[i];
+  int grid = int(std::min<int64_t>((n + 255) / 256, 8192));
+  if (grid < 1) return;
+  hipLaunchKernelGGL(k_lincomb, dim3(grid), dim3(256), 0, d->stream, V, ldv, m, c, beta, y, n);
+  HIP_CHECK(hipGetLastError());
+}
+
+__global__ void k_axpy(double a, const double *__restrict__ x, double *__restrict__ y, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    y[k] += a * x[k];
+}
+void dev_axpy(Device *d, double a, const double *x, double *y, int64_t n) {
+  int grid = int(std::min<int64_t>((n + 255) / 256, 8192));
+  if (grid < 1) return;
+  hipLaunchKernelGGL(k_axpy, dim3(grid), dim3(256), 0, d->stream, a, x, y, n);
+  HIP_CHECK(hipGetLastError());
+}
+__global__ void k_scale(double a, double *__restrict__ x, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    x[k] *= a;
+}
+void dev_scale(Device *d, double a, double *x, int64_t n) {
+  int grid = int(std::min<int64_t>((n + 255) / 256, 8192));
+  if (grid < 1) return;
+  hipLaunchKernelGGL(k_scale, dim3(grid), dim3(256), 0, d->stream, a, x, n);
+  HIP_CHECK(hipGetLastError());
+}
+__global__ void k_precond(const double *__restrict__ r, const double *__restrict__ dg, double theta, double eps,
+                          double *__restrict__ t, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    double den = theta - dg[k];
+    if (fabs(den) < eps) den = (den < 0.0) ? -eps : eps;
+    t[k] = r[k] / den;
+  }
+}
+void dev_precond(Device *d, const double *r, const double *dg, double theta, double eps, double *t, int64_t n) {
+  int grid = int(std::min<int64_t>((n + 255) / 256, 8192));
+  if (grid < 1) return;
+  hipLaunchKernelGGL(k_precond, dim3(grid), dim3(256), 0, d->stream, r, dg, theta, eps, t, n);
+  HIP_CHECK(hipGetLastError());
+}
+
+// splitmix64 (Steele, Lea, Flood 2014) as a counter-based generator,
+// Box-Muller to N(0,1).
+__device__ inline uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void k_randn(double *x, int64_t n, uint64_t seed) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t base = seed * 0x2545F4914F6CDD1Dull + 2 * (uint64_t)k;
+    const double u1 = ((splitmix64(base) >> 11) + 1) * (1.0 / 9007199254740993.0);
+    const double u2 = (splitmix64(base + 1) >> 11) * (1.0 / 9007199254740992.0);
+    x[k] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+}
+void dev_randn(Device *d, double *x, int64_t n, uint64_t seed) {
+  int grid = int(std::min<int64_t>((n + 255) / 256, 8192));
+  if (grid < 1) return;
+  hipLaunchKernelGGL(k_randn, dim3(grid), dim3(256), 0, d->stream, x, n, seed);
+  HIP_CHECK(hipGetLastError());
+}
+
+// ------------------------------------------------------------- eigensolver
+void dev_syevd(Device *d, double *A, int n, double *w) {
+  if (n <= 0) return;
+  if (d->syevd_work_n < size_t(n)) {
+    if (d->syevd_work) HIP_CHECK(hipFree(d->syevd_work));
+    HIP_CHECK(hipMalloc(&d->syevd_work, sizeof(double) * n));
+    d->syevd_work_n = size_t(n);
+  }
+  rocblas_status st = rocsolver_dsyevd(d->blas, rocblas_evect_original, rocblas_fill_upper, n, A, n, w,
+                                       d->syevd_work, d->info);
+  MDMRG_REQUIRE(st == rocblas_status_success, -3, "rocsolver_dsyevd failed");
+  int info = 0;
+  HIP_CHECK(hipMemcpyAsync(&info, d->info, sizeof(int), hipMemcpyDeviceToHost, d->stream));
+  HIP_CHECK(hipStreamSynchronize(d->stream));
+  MDMRG_REQUIRE(info == 0, -3, "rocsolver_dsyevd did not converge (info " + std::to_string(info) + ")");
+}
+
+// ------------------------------------------------------------------ gather
+__global__ void k_gather(const GatherBlk *__restrict__ blks, const int32_t *__restrict__ cols,
+                         const double *__restrict__ E, double *__restrict__ out, int transpose_out) {
+  const GatherBlk g = blks[blockIdx.x];
+  const int total = g.rows * g.ncol;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int i = e / g.ncol, j = e % g.ncol;
+    const double v = E[g.e_off + (int64_t)cols[g.col_begin + j] * g.ldE + g.row0 + i];
+    if (transpose_out)
+      out[g.out_off + (int64_t)j * g.rows + i] = v;
+    else
+      out[g.out_off + (int64_t)i * g.ncol + j] = v;
+  }
+}
+void dev_gather(Device *d, const std::vector<GatherBlk> &blks, const std::vector<int32_t> &cols, const double *E,
+                double *out, bool transpose_out) {
+  if (blks.empty()) return;
+  auto *db = (GatherBlk *)dev_alloc(d, sizeof(GatherBlk) * blks.size());
+  auto *dc = (int32_t *)dev_alloc(d, sizeof(int32_t) * std::max<size_t>(1, cols.size()));
+  dev_h2d(d, db, blks.data(), sizeof(GatherBlk) * blks.size());
+  if (!cols.empty()) dev_h2d(d, dc, cols.data(), sizeof(int32_t) * cols.size());
+  hipLaunchKernelGGL(k_gather, dim3(unsigned(blks.size())), dim3(256), 0, d->stream, db, dc, E, out,
+                     transpose_out ? 1 : 0);
+  HIP_CHECK(hipGetLastError());
+  dev_free(d, db);
+  dev_free(d, dc);
+}
+
+}  // namespace mdmrg

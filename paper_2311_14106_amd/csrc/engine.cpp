@@ -1,0 +1,1755 @@
+// DMRG engine: block operators, normal/complementary partition of Eq. (1)
+// at every bond, renormalisation, the task lists of the effective
+// Hamiltonian, Davidson, density-matrix decimation, start vectors, sweeps.
+//
+// Notation: a term of Eq. (1) is an index-ordered product of elementary
+// operators.  At a bond the chain is split into the left block L (sites < l),
+// the two explicit sites S1 = l, S2 = l+1 and the right block R (sites > l+1).
+// Each term is written as (L part)(S1 part)(S2 part)(R part) and routed to
+// exactly one product  X_L (x) O_S (x) X_R  of stored or on-the-fly block
+// operators (normal operators on L, complementary operators on R, plus the
+// few complementary operators of L that the sums need), so that the number
+// of products is O(n^2) and every product is a pair of dense sector GEMMs.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "engine.h"
+
+namespace mdmrg {
+
+uint64_t make_key(int kind, const int *e, int n) {
+  uint64_t k = uint64_t(kind) | (uint64_t(n) << 4);
+  for (int i = 0; i < n; ++i) k |= uint64_t(e[i] + 1) << (8 + 13 * i);
+  return k;
+}
+static int key_kind(uint64_t k) { return int(k & 15); }
+static int key_n(uint64_t k) { return int((k >> 4) & 15); }
+static int key_parity(uint64_t k) {
+  const int kd = key_kind(k);
+  if (kd == K_H || kd == K_I) return 0;
+  return key_n(k) & 1;
+}
+static int parity_of_state(int s) { return __builtin_popcount(unsigned(s)) & 1; }
+
+// ------------------------------------------------------------------ OpSet
+void OpSet::add(uint64_t key, QN delta) {
+  if (ops.count(key)) return;
+  auto it = gidx.find(delta.key());
+  int g;
+  if (it == gidx.end()) {
+    g = int(groups.size());
+    gidx[delta.key()] = g;
+    groups.emplace_back();
+    groups.back().delta = delta;
+  } else {
+    g = it->second;
+  }
+  ops[key] = {g, groups[g].n_ops++};
+  order.push_back(key);
+}
+
+void OpSet::layout(Device *dev) {
+  int64_t base = 0;
+  const int nsec = int(bond->qn.size());
+  for (auto &G : groups) {
+    G.pair_of_col.assign(nsec, -1);
+    G.row.clear();
+    G.col.clear();
+    G.poff.clear();
+    G.size = 0;
+    for (int c = 0; c < nsec; ++c) {
+      const int r = bond->find(bond->qn[c] + G.delta);
+      if (r < 0) continue;
+      G.pair_of_col[c] = int(G.row.size());
+      G.row.push_back(r);
+      G.col.push_back(c);
+      G.poff.push_back(G.size);
+      G.size += int64_t(bond->dim[r]) * bond->dim[c];
+    }
+    G.base = base;
+    base += (G.size * G.n_ops + 31) / 32 * 32;
+  }
+  arena_size = base;
+  arena = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, arena_size));
+  dev_zero(dev, arena, sizeof(double) * std::max<int64_t>(1, arena_size));
+  laid_out = true;
+}
+
+void OpSet::release(Device *dev) {
+  if (arena) dev_free(dev, arena);
+  arena = nullptr;
+}
+
+int64_t OpSet::block(uint64_t key, int c, int *row) const {
+  auto it = ops.find(key);
+  if (it == ops.end()) return -1;
+  const Group &G = groups[it->second.first];
+  if (c < 0 || c >= int(G.pair_of_col.size())) return -1;
+  const int p = G.pair_of_col[c];
+  if (p < 0) return -1;
+  if (row) *row = G.row[p];
+  return G.base + int64_t(it->second.second) * G.size + G.poff[p];
+}
+
+// ------------------------------------------------------------------ helpers
+struct Parts {
+  int k[4] = {0, 0, 0, 0};
+  int e[4][4];
+};
+// part 0: sites < s1, 1: site s1, 2: site s1+1, 3: sites > s1+1
+static void split(const Hamiltonian &H, const Term &t, int s1, Parts &p) {
+  for (int i = 0; i < t.n; ++i) {
+    const int site = H.site_of(t.e[i]);
+    const int part = site < s1 ? 0 : site == s1 ? 1 : site == s1 + 1 ? 2 : 3;
+    p.e[part][p.k[part]++] = t.e[i];
+  }
+}
+static QN q_sum(const Hamiltonian &H, const int *e, int n) {
+  QN q;
+  for (int i = 0; i < n; ++i) q = q + H.q_of_op(e[i]);
+  return q;
+}
+
+// d x d site matrix list accumulated per (source operator)
+struct SiteItem {
+  std::vector<double> M;
+  int parity = 0;
+};
+
+// ------------------------------------------------------------------ needs
+static void need_left(const Hamiltonian &H, int bond, OpSet &S) {
+  S.add(make_key(K_H, nullptr, 0), QN());
+  for (int p = 0; p < H.ns * bond; ++p)
+    for (int dag = 1; dag >= 0; --dag) {
+      const int e = 2 * p + dag;
+      S.add(make_key(K_N, &e, 1), H.q_of_op(e));
+    }
+  for (const Term &t : H.terms) {
+    int in[4], out[4], ki = 0, ko = 0;
+    for (int i = 0; i < t.n; ++i) {
+      if (H.site_of(t.e[i]) < bond)
+        in[ki++] = t.e[i];
+      else
+        out[ko++] = t.e[i];
+    }
+    if (ki == 2) S.add(make_key(K_N, in, 2), q_sum(H, in, 2));
+    if (t.n == 4 && ki == 3) S.add(make_key(K_C, out, 1), QN() - q_sum(H, out, 1));
+  }
+}
+
+static void need_right(const Hamiltonian &H, int bond, OpSet &S) {
+  S.add(make_key(K_H, nullptr, 0), QN());
+  for (int p = H.ns * bond; p < H.nso; ++p)
+    for (int dag = 1; dag >= 0; --dag) {
+      const int e = 2 * p + dag;
+      S.add(make_key(K_N, &e, 1), QN() - H.q_of_op(e));
+    }
+  for (const Term &t : H.terms) {
+    int in[4], out[4], ki = 0, ko = 0;
+    for (int i = 0; i < t.n; ++i) {
+      if (H.site_of(t.e[i]) >= bond)
+        in[ki++] = t.e[i];
+      else
+        out[ko++] = t.e[i];
+    }
+    if (ki >= 1 && (ko == 1 || ko == 2)) S.add(make_key(K_C, out, ko), q_sum(H, out, ko));
+  }
+}
+
+// content of on-the-fly complementary operators of a block: combo key ->
+// list of (normal operator key, coefficient).  Left: terms with
+// ext_L(t) = K and k_L >= 1, except the three-operator two-body part (kept
+// as a stored operator).  Right: terms with ext_R(t) = K, k_R == 1 (|K|=3).
+using Content = std::map<uint64_t, std::map<uint64_t, double>>;
+static void combo_content(const Hamiltonian &H, bool left, int bond, const std::set<uint64_t> &wanted,
+                          Content &out) {
+  if (wanted.empty()) return;
+  for (const Term &t : H.terms) {
+    int in[4], ext[4], ki = 0, ko = 0;
+    for (int i = 0; i < t.n; ++i) {
+      const bool inside = left ? (H.site_of(t.e[i]) < bond) : (H.site_of(t.e[i]) >= bond);
+      if (inside)
+        in[ki++] = t.e[i];
+      else
+        ext[ko++] = t.e[i];
+    }
+    if (ki == 0 || ko == 0) continue;
+    if (left && t.n == 4 && ki == 3) continue;
+    if (!left && ki != 1) continue;
+    const uint64_t k = make_key(K_X, ext, ko);
+    if (!wanted.count(k)) continue;
+    out[k][make_key(K_N, in, ki)] += t.c;
+  }
+}
+
+static QN combo_delta(const Hamiltonian &H, bool left, uint64_t key) {
+  // decode external list
+  int e[4];
+  const int n = key_n(key);
+  for (int i = 0; i < n; ++i) e[i] = int((key >> (8 + 13 * i)) & 8191) - 1;
+  const QN qe = q_sum(H, e, n);
+  return left ? QN() - qe : qe;
+}
+
+// Materialise combos X (already laid out) from the stored operators of env.
+static void materialize(Device *dev, OpSet &X, const OpSet &env, const Content &content) {
+  for (size_t g = 0; g < X.groups.size(); ++g) {
+    const Group &GX = X.groups[g];
+    if (GX.size == 0 || GX.n_ops == 0) continue;
+    auto ge = env.gidx.find(GX.delta.key());
+    if (ge == env.gidx.end()) continue;
+    const Group &GE = env.groups[ge->second];
+    MDMRG_REQUIRE(GE.size == GX.size, -4, "materialize: layout mismatch");
+    std::vector<double> C(size_t(GX.n_ops) * GE.n_ops, 0.0);
+    bool any = false;
+    for (auto &kv : X.ops) {
+      if (kv.second.first != int(g)) continue;
+      auto ct = content.find(kv.first);
+      if (ct == content.end()) continue;
+      for (auto &src : ct->second) {
+        auto se = env.ops.find(src.first);
+        if (se == env.ops.end()) continue;
+        MDMRG_REQUIRE(se->second.first == ge->second, -4, "materialize: source in wrong group");
+        C[size_t(kv.second.second) * GE.n_ops + se->second.second] += src.second;
+        any = true;
+      }
+    }
+    if (!any) continue;
+    double *dC = (double *)dev_alloc(dev, sizeof(double) * C.size());
+    dev_h2d(dev, dC, C.data(), sizeof(double) * C.size());
+    GemmPlan plan;
+    GSeg s{};
+    s.a_off = 0;
+    s.b_off = GE.base;
+    s.alpha = 1.0;
+    s.k = GE.n_ops;
+    s.lda = GE.n_ops;
+    s.ldb = int32_t(GE.size);
+    MDMRG_REQUIRE(GE.size < (int64_t(1) << 31), -6, "operator too large for int32 leading dimension");
+    s.a_slot = 0;
+    s.b_slot = 2;
+    s.flags = 0;
+    plan.segs.push_back(s);
+    GOut o{};
+    o.c_off = GX.base;
+    o.m = GX.n_ops;
+    o.n = int32_t(GX.size);
+    o.ldc = int32_t(GX.size);
+    o.seg_begin = 0;
+    o.seg_count = 1;
+    o.c_slot = 1;
+    o.accumulate = 0;
+    plan.outs.push_back(o);
+    DevPlan *dp = dev_plan_upload(dev, plan);
+    Bases b{};
+    b.p[0] = dC;
+    b.p[1] = X.arena;
+    b.p[2] = env.arena;
+    for (int i = 3; i < kSlots; ++i) b.p[i] = dC;
+    dev_gemm_run(dev, dp, b);
+    dev_plan_free(dev, dp);
+    dev_free(dev, dC);
+  }
+}
+
+// ------------------------------------------------------- two-phase planner
+static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutBlk> &outs, int64_t limit,
+                            TwoPhasePlan &plan, Device *dev) {
+  std::stable_sort(tasks.begin(), tasks.end(), [](const PairTask &a, const PairTask &b) { return a.out < b.out; });
+  plan.scratch = 0;
+  {
+    // algorithmic bytes: every distinct operand block read once, every
+    // output block written once
+    std::set<std::pair<int, int64_t>> seen;
+    double elems = 0.0;
+    for (const PairTask &t : tasks) {
+      if (!t.idA && seen.insert({t.A.slot, t.A.off}).second) elems += double(t.m) * t.k1;
+      if (seen.insert({t.X.slot, t.X.off}).second) elems += double(t.k1) * t.k2;
+      if (!t.idB && seen.insert({t.B.slot, t.B.off}).second) elems += double(t.k2) * t.n;
+    }
+    std::set<int32_t> so;
+    for (const PairTask &t : tasks)
+      if (so.insert(t.out).second) elems += double(outs[t.out].m) * outs[t.out].n;
+    plan.bytes += 8.0 * elems;
+  }
+  struct TKey {
+    int order;
+    int xs;
+    int64_t xo;
+    int os;
+    int64_t oo;
+    int tr;
+    bool operator<(const TKey &o) const {
+      return std::tie(order, xs, xo, os, oo, tr) < std::tie(o.order, o.xs, o.xo, o.os, o.oo, o.tr);
+    }
+  };
+  size_t i = 0;
+  while (i < tasks.size()) {
+    GemmPlan p1, p2;
+    std::map<TKey, int64_t> tmap;
+    int64_t used = 0;
+    std::vector<std::vector<GSeg>> per_out;
+    std::vector<int32_t> out_ids;
+    int cur_out = -1;
+    size_t j = i;
+    for (; j < tasks.size(); ++j) {
+      const PairTask &t = tasks[j];
+      // chunk boundary only between outputs
+      if (t.out != cur_out && used > limit && !out_ids.empty()) break;
+      if (t.out != cur_out) {
+        cur_out = t.out;
+        out_ids.push_back(t.out);
+        per_out.emplace_back();
+      }
+      std::vector<GSeg> &segs = per_out.back();
+      GSeg s{};
+      s.alpha = t.alpha;
+      auto refA = [&](GSeg &g, const Ref &r, bool tr) {
+        g.a_slot = uint8_t(r.slot);
+        g.a_off = r.off;
+        g.lda = r.ld;
+        if (tr) g.flags |= SEG_TA;
+      };
+      auto refB = [&](GSeg &g, const Ref &r, bool tr) {
+        g.b_slot = uint8_t(r.slot);
+        g.b_off = r.off;
+        g.ldb = r.ld;
+        if (tr) g.flags |= SEG_TB;
+      };
+      if (t.idA && t.idB) {
+        s.flags = SEG_AID;
+        s.a_slot = 0;
+        s.a_off = 0;
+        s.lda = 0;
+        refB(s, t.X, false);
+        s.k = t.k1;
+        segs.push_back(s);
+        continue;
+      }
+      if (t.idA) {
+        refA(s, t.X, false);
+        refB(s, t.B, t.tB);
+        s.k = t.k2;
+        p2.flop += 2.0 * t.m * t.n * t.k2;
+        segs.push_back(s);
+        continue;
+      }
+      if (t.idB) {
+        refA(s, t.A, t.tA);
+        refB(s, t.X, false);
+        s.k = t.k1;
+        p2.flop += 2.0 * t.m * t.n * t.k1;
+        segs.push_back(s);
+        continue;
+      }
+      const double c_lr = double(t.m) * t.k1 * t.k2 + double(t.m) * t.k2 * t.n;  // (A X) B
+      const double c_rl = double(t.k1) * t.k2 * t.n + double(t.m) * t.k1 * t.n;  // A (X B)
+      if (c_rl <= c_lr) {
+        TKey key{1, t.X.slot, t.X.off, t.B.slot, t.B.off, int(t.tB)};
+        auto it = tmap.find(key);
+        int64_t toff;
+        if (it == tmap.end()) {
+          toff = used;
+          used += (int64_t(t.k1) * t.n + 7) / 8 * 8;
+          tmap[key] = toff;
+          GSeg s1{};
+          s1.alpha = 1.0;
+          refA(s1, t.X, false);
+          refB(s1, t.B, t.tB);
+          s1.k = t.k2;
+          GOut o{};
+          o.c_off = toff;
+          o.m = t.k1;
+          o.n = t.n;
+          o.ldc = t.n;
+          o.seg_begin = int32_t(p1.segs.size());
+          o.seg_count = 1;
+          o.c_slot = 2;
+          o.accumulate = 0;
+          p1.segs.push_back(s1);
+          p1.outs.push_back(o);
+          p1.flop += 2.0 * t.k1 * t.n * t.k2;
+        } else {
+          toff = it->second;
+        }
+        refA(s, t.A, t.tA);
+        refB(s, Ref{2, toff, t.n}, false);
+        s.k = t.k1;
+        p2.flop += 2.0 * t.m * t.n * t.k1;
+      } else {
+        TKey key{0, t.X.slot, t.X.off, t.A.slot, t.A.off, int(t.tA)};
+        auto it = tmap.find(key);
+        int64_t toff;
+        if (it == tmap.end()) {
+          toff = used;
+          used += (int64_t(t.m) * t.k2 + 7) / 8 * 8;
+          tmap[key] = toff;
+          GSeg s1{};
+          s1.alpha = 1.0;
+          refA(s1, t.A, t.tA);
+          refB(s1, t.X, false);
+          s1.k = t.k1;
+          GOut o{};
+          o.c_off = toff;
+          o.m = t.m;
+          o.n = t.k2;
+          o.ldc = t.k2;
+          o.seg_begin = int32_t(p1.segs.size());
+          o.seg_count = 1;
+          o.c_slot = 2;
+          o.accumulate = 0;
+          p1.segs.push_back(s1);
+          p1.outs.push_back(o);
+          p1.flop += 2.0 * t.m * t.k2 * t.k1;
+        } else {
+          toff = it->second;
+        }
+        refA(s, Ref{2, toff, t.k2}, false);
+        refB(s, t.B, t.tB);
+        s.k = t.k2;
+        p2.flop += 2.0 * t.m * t.n * t.k2;
+      }
+      segs.push_back(s);
+    }
+    for (size_t q = 0; q < out_ids.size(); ++q) {
+      const OutBlk &ob = outs[out_ids[q]];
+      GOut o{};
+      o.c_off = ob.off;
+      o.m = ob.m;
+      o.n = ob.n;
+      o.ldc = ob.ld;
+      o.seg_begin = int32_t(p2.segs.size());
+      o.seg_count = int32_t(per_out[q].size());
+      o.c_slot = uint8_t(ob.slot);
+      o.accumulate = 1;
+      p2.segs.insert(p2.segs.end(), per_out[q].begin(), per_out[q].end());
+      p2.outs.push_back(o);
+    }
+    plan.n_gemm += int64_t(p1.segs.size() + p2.segs.size());
+    plan.flop += p1.flop + p2.flop;
+    plan.bytes += 16.0 * double(used);  // intermediates written and read back
+    plan.scratch = std::max(plan.scratch, used);
+    Chunk ch;
+    ch.p1 = p1.outs.empty() ? nullptr : dev_plan_upload(dev, p1);
+    ch.p2 = p2.outs.empty() ? nullptr : dev_plan_upload(dev, p2);
+    plan.chunks.push_back(ch);
+    i = j;
+  }
+}
+
+void Context::ensure_scratch(int64_t n) {
+  if (n <= T_scratch_n) return;
+  if (T_scratch) dev_free(dev, T_scratch);
+  T_scratch = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(n, 1));
+  T_scratch_n = n;
+}
+
+void Context::run_plan(const TwoPhasePlan &p, Bases &b, int tag) {
+  b.p[2] = T_scratch;
+  for (auto &c : p.chunks) {
+    if (c.p1) dev_gemm_run(dev, c.p1, b, tag);
+    if (c.p2) dev_gemm_run(dev, c.p2, b, tag);
+  }
+}
+
+// ------------------------------------------------------------- boundaries
+std::unique_ptr<OpSet> Context::env_boundary(bool left, int bond) {
+  auto S = std::make_unique<OpSet>();
+  S->bond = &bonds[bond];
+  if (left)
+    need_left(ham, bond, *S);
+  else
+    need_right(ham, bond, *S);
+  S->layout(dev);  // all zero: empty block, H = 0, no operators act
+  return S;
+}
+
+// Renormalise recipes (items per new operator) into the new OpSet.
+// left: new(a'',c'') += sum alpha A(a,s,a'')^T X(a,c) A(c,t,c'')
+// right: new(b'',c'') += sum alpha B(b'',s,b) X(b,c) B(c'',t,c)^T
+struct Recipe {
+  std::map<OpRef, SiteItem> items;
+};
+
+static void add_item(Recipe &r, OpRef ref, const std::vector<double> &M, int parity, double scale) {
+  auto it = r.items.find(ref);
+  if (it == r.items.end()) {
+    SiteItem si;
+    si.M.assign(M.size(), 0.0);
+    si.parity = parity;
+    it = r.items.emplace(ref, si).first;
+  }
+  for (size_t i = 0; i < M.size(); ++i) it->second.M[i] += scale * M[i];
+}
+
+static void renorm_execute(Context &C, bool left, int site, OpSet &Bp, const OpSet &env, const OpSet *combo,
+                           const std::unordered_map<uint64_t, Recipe> &recipes) {
+  const Hamiltonian &H = C.ham;
+  const int d = H.d;
+  const Bond &bo = C.bonds[left ? site : site + 1];  // old block bond
+  const Bond &bn = C.bonds[left ? site + 1 : site];  // new block bond
+  const SiteTensor &T = C.A[site];
+  std::vector<PairTask> tasks;
+  std::vector<OutBlk> outs;
+  GemmPlan direct;  // identity X: Y += alpha op(A) op(B), one GEMM each
+  for (uint64_t key : Bp.order) {
+    auto rit = recipes.find(key);
+    if (rit == recipes.end()) continue;
+    const auto [g, idx] = Bp.ops.at(key);
+    const Group &G = Bp.groups[g];
+    for (size_t p = 0; p < G.row.size(); ++p) {
+      const int rn = G.row[p], cn = G.col[p];
+      const int64_t yoff = G.base + int64_t(idx) * G.size + G.poff[p];
+      const int out_id = int(outs.size());
+      bool used = false;
+      std::vector<GSeg> dsegs;
+      for (auto &it : rit->second.items) {
+        const OpRef &ref = it.first;
+        const SiteItem &si = it.second;
+        const OpSet *src = ref.src == 1 ? &env : ref.src == 2 ? combo : nullptr;
+        if (ref.src && (!src || !src->has(ref.key))) continue;
+        const int pX = ref.src == 0 ? 0 : key_parity(ref.key);
+        for (int s = 0; s < d; ++s)
+          for (int t = 0; t < d; ++t) {
+            const double m = si.M[s * d + t];
+            if (m == 0.0) continue;
+            int ro, co, ia, ic;
+            if (left) {
+              ro = bo.find(bn.qn[rn] - H.q_of_state(s));
+              co = bo.find(bn.qn[cn] - H.q_of_state(t));
+              if (ro < 0 || co < 0) continue;
+              ia = T.find(ro, s, rn);
+              ic = T.find(co, t, cn);
+            } else {
+              ro = bo.find(bn.qn[rn] + H.q_of_state(s));
+              co = bo.find(bn.qn[cn] + H.q_of_state(t));
+              if (ro < 0 || co < 0) continue;
+              ia = T.find(rn, s, ro);
+              ic = T.find(cn, t, co);
+            }
+            if (ia < 0 || ic < 0) continue;
+            int64_t xoff = -1;
+            if (ref.src == 0) {
+              if (ro != co) continue;
+            } else {
+              int row = -1;
+              xoff = src->block(ref.key, co, &row);
+              if (xoff < 0 || row != ro) continue;
+            }
+            double sign = 1.0;
+            if (left) {
+              if ((si.parity & 1) && bo.qn[co].parity()) sign = -1.0;
+            } else {
+              if ((pX & 1) && parity_of_state(t)) sign = -1.0;
+            }
+            const int mro = bo.dim[ro], mco = bo.dim[co], mrn = bn.dim[rn], mcn = bn.dim[cn];
+            Ref Ar, Br;
+            bool tA, tB;
+            if (left) {  // A(ro,s,rn)^T [mrn x mro], B = A(co,t,cn) [mco x mcn]
+              Ar = Ref{6, T.off[ia], mrn};
+              tA = true;
+              Br = Ref{6, T.off[ic], mcn};
+              tB = false;
+            } else {  // B(rn,s,ro) [mrn x mro], B(cn,t,co)^T [mco x mcn]
+              Ar = Ref{6, T.off[ia], mro};
+              tA = false;
+              Br = Ref{6, T.off[ic], mco};
+              tB = true;
+            }
+            used = true;
+            if (ref.src == 0) {
+              GSeg s1{};
+              s1.alpha = m * sign;
+              s1.a_slot = 6;
+              s1.a_off = Ar.off;
+              s1.lda = Ar.ld;
+              s1.b_slot = 6;
+              s1.b_off = Br.off;
+              s1.ldb = Br.ld;
+              s1.flags = uint8_t((tA ? SEG_TA : 0) | (tB ? SEG_TB : 0));
+              s1.k = mro;
+              dsegs.push_back(s1);
+              direct.flop += 2.0 * mrn * mcn * mro;
+              continue;
+            }
+            PairTask pt{};
+            pt.out = out_id;
+            pt.alpha = m * sign;
+            pt.A = Ar;
+            pt.tA = tA;
+            pt.B = Br;
+            pt.tB = tB;
+            pt.X = Ref{ref.src == 1 ? 3 : 5, xoff, mco};
+            pt.m = mrn;
+            pt.k1 = mro;
+            pt.k2 = mco;
+            pt.n = mcn;
+            tasks.push_back(pt);
+          }
+      }
+      if (!used) continue;
+      outs.push_back(OutBlk{1, yoff, bn.dim[rn], bn.dim[cn], bn.dim[cn]});
+      if (!dsegs.empty()) {
+        GOut o{};
+        o.c_off = yoff;
+        o.m = bn.dim[rn];
+        o.n = bn.dim[cn];
+        o.ldc = o.n;
+        o.c_slot = 1;
+        o.accumulate = 1;
+        o.seg_begin = int32_t(direct.segs.size());
+        o.seg_count = int32_t(dsegs.size());
+        direct.segs.insert(direct.segs.end(), dsegs.begin(), dsegs.end());
+        direct.outs.push_back(o);
+      }
+    }
+  }
+  TwoPhasePlan plan;
+  build_two_phase(tasks, outs, C.scratch_limit, plan, C.dev);
+  if (!direct.outs.empty()) {
+    Chunk ch;
+    ch.p2 = dev_plan_upload(C.dev, direct);
+    plan.chunks.push_back(ch);
+    plan.flop += direct.flop;
+  }
+  C.ensure_scratch(plan.scratch);
+  Bases b{};
+  for (int i = 0; i < kSlots; ++i) b.p[i] = Bp.arena;
+  b.p[1] = Bp.arena;
+  b.p[3] = env.arena;
+  b.p[5] = combo && combo->arena ? combo->arena : Bp.arena;
+  b.p[6] = T.data;
+  C.run_plan(plan, b, 2);
+  plan.release(C.dev);
+}
+
+// L(bond site) + site -> L(bond site+1), with A[site] a left isometry
+std::unique_ptr<OpSet> Context::renorm_left(const OpSet &L, int site) {
+  const Hamiltonian &H = ham;
+  const int d = H.d;
+  auto Lp = std::make_unique<OpSet>();
+  Lp->bond = &bonds[site + 1];
+  need_left(H, site + 1, *Lp);
+  Lp->layout(dev);
+  std::unordered_map<uint64_t, Recipe> rec;
+  std::set<uint64_t> wanted;
+  std::vector<double> I(d * d, 0.0);
+  for (int s = 0; s < d; ++s) I[s * d + s] = 1.0;
+  const uint64_t kH = make_key(K_H, nullptr, 0);
+  const OpRef ident{0, ident_key()};
+  // H_{L'}
+  add_item(rec[kH], OpRef{1, kH}, I, 0, 1.0);
+  std::set<std::pair<OpRef, uint64_t>> seen;  // (source, site-op list) pairs already added
+  auto add_set = [&](uint64_t newkey, OpRef src, const int *es, int ks) {
+    const uint64_t sk = make_key(K_N, es, ks);
+    if (!seen.insert({src, sk ^ (newkey * 0x9E3779B97F4A7C15ull)}).second) return;
+    add_item(rec[newkey], src, H.site_matrix(site, es, ks), ks & 1, 1.0);
+    if (src.src == 2) wanted.insert(src.key);
+  };
+  for (const Term &t : H.terms) {
+    Parts p;
+    split(H, t, site, p);  // 0: L, 1: site, 2,3: outside
+    const int kout = p.k[2] + p.k[3];
+    int ext[4], ke = 0;
+    for (int i = 0; i < p.k[2]; ++i) ext[ke++] = p.e[2][i];
+    for (int i = 0; i < p.k[3]; ++i) ext[ke++] = p.e[3][i];
+    if (kout == 0 && p.k[1] >= 1) {
+      if (p.k[0] == 0) {
+        add_item(rec[kH], ident, H.site_matrix(site, p.e[1], p.k[1]), 0, t.c);
+      } else {
+        const uint64_t kk = (t.n == 4 && p.k[0] == 3) ? make_key(K_C, p.e[1], p.k[1]) : make_key(K_X, p.e[1], p.k[1]);
+        add_set(kH, OpRef{(t.n == 4 && p.k[0] == 3) ? 1 : 2, kk}, p.e[1], p.k[1]);
+      }
+    }
+    // S^{L'}_y: two-body terms with three operators in L' and one outside
+    if (t.n == 4 && kout == 1 && p.k[0] + p.k[1] == 3) {
+      const uint64_t nk = make_key(K_C, ext, 1);
+      if (!Lp->has(nk)) continue;
+      if (p.k[0] == 3) {
+        add_set(nk, OpRef{1, nk}, nullptr, 0);
+      } else if (p.k[0] >= 1) {
+        int K[4], kk = 0;
+        for (int i = 0; i < p.k[1]; ++i) K[kk++] = p.e[1][i];
+        K[kk++] = ext[0];
+        add_set(nk, OpRef{2, make_key(K_X, K, kk)}, p.e[1], p.k[1]);
+      } else {
+        add_item(rec[nk], ident, H.site_matrix(site, p.e[1], p.k[1]), p.k[1] & 1, t.c);
+      }
+    }
+  }
+  // normal operators
+  for (uint64_t key : Lp->order) {
+    if (key_kind(key) != K_N) continue;
+    const int n = key_n(key);
+    int e[4];
+    for (int i = 0; i < n; ++i) e[i] = int((key >> (8 + 13 * i)) & 8191) - 1;
+    int kin = 0;
+    while (kin < n && H.site_of(e[kin]) < site) ++kin;
+    if (kin == n) {
+      add_item(rec[key], OpRef{1, key}, I, 0, 1.0);
+    } else if (kin == 0) {
+      add_item(rec[key], ident, H.site_matrix(site, e, n), n & 1, 1.0);
+    } else {
+      add_item(rec[key], OpRef{1, make_key(K_N, e, kin)}, H.site_matrix(site, e + kin, n - kin), (n - kin) & 1, 1.0);
+    }
+  }
+  // combos of L needed by the recipes
+  std::unique_ptr<OpSet> X;
+  if (!wanted.empty()) {
+    X = std::make_unique<OpSet>();
+    X->bond = L.bond;
+    for (uint64_t k : wanted) X->add(k, combo_delta(H, true, k));
+    X->layout(dev);
+    Content content;
+    combo_content(H, true, site, wanted, content);
+    materialize(dev, *X, L, content);
+  }
+  renorm_execute(*this, true, site, *Lp, L, X.get(), rec);
+  if (X) X->release(dev);
+  return Lp;
+}
+
+// R(bond site+1) + site -> R(bond site), with A[site] a right isometry
+std::unique_ptr<OpSet> Context::renorm_right(const OpSet &R, int site) {
+  const Hamiltonian &H = ham;
+  const int d = H.d;
+  auto Rp = std::make_unique<OpSet>();
+  Rp->bond = &bonds[site];
+  need_right(H, site, *Rp);
+  Rp->layout(dev);
+  std::unordered_map<uint64_t, Recipe> rec;
+  std::set<uint64_t> wanted;
+  std::vector<double> I(d * d, 0.0);
+  for (int s = 0; s < d; ++s) I[s * d + s] = 1.0;
+  const uint64_t kH = make_key(K_H, nullptr, 0);
+  const OpRef ident{0, ident_key()};
+  add_item(rec[kH], OpRef{1, kH}, I, 0, 1.0);
+  std::set<std::pair<OpRef, uint64_t>> seen;
+  auto add_set = [&](uint64_t newkey, OpRef src, const int *es, int ks) {
+    const uint64_t sk = make_key(K_N, es, ks);
+    if (!seen.insert({src, sk ^ (newkey * 0x9E3779B97F4A7C15ull)}).second) return;
+    add_item(rec[newkey], src, H.site_matrix(site, es, ks), ks & 1, 1.0);
+    if (src.src == 2) wanted.insert(src.key);
+  };
+  for (const Term &t : H.terms) {
+    // parts relative to the new block: outside (< site), site, R (> site)
+    int out[4], sp[4], rr[4], ko = 0, ks = 0, kr = 0;
+    for (int i = 0; i < t.n; ++i) {
+      const int st = H.site_of(t.e[i]);
+      if (st < site)
+        out[ko++] = t.e[i];
+      else if (st == site)
+        sp[ks++] = t.e[i];
+      else
+        rr[kr++] = t.e[i];
+    }
+    if (ks + kr == 0) continue;
+    if (ko == 0) {  // H_{R'}
+      if (ks == 0) continue;  // in H_R
+      if (kr == 0) {
+        add_item(rec[kH], ident, H.site_matrix(site, sp, ks), 0, t.c);
+      } else {
+        const bool stored = ks <= 2;
+        add_set(kH, OpRef{stored ? 1 : 2, make_key(stored ? K_C : K_X, sp, ks)}, sp, ks);
+      }
+      continue;
+    }
+    if (ko > 2) continue;
+    const uint64_t nk = make_key(K_C, out, ko);
+    if (!Rp->has(nk)) continue;
+    if (kr == 0) {
+      add_item(rec[nk], ident, H.site_matrix(site, sp, ks), ks & 1, t.c);
+      continue;
+    }
+    int K[4], kk = 0;
+    for (int i = 0; i < ko; ++i) K[kk++] = out[i];
+    for (int i = 0; i < ks; ++i) K[kk++] = sp[i];
+    const bool stored = kk <= 2;
+    add_set(nk, OpRef{stored ? 1 : 2, make_key(stored ? K_C : K_X, K, kk)}, sp, ks);
+  }
+  for (uint64_t key : Rp->order) {
+    if (key_kind(key) != K_N) continue;
+    int e = int((key >> 8) & 8191) - 1;
+    if (H.site_of(e) == site)
+      add_item(rec[key], ident, H.site_matrix(site, &e, 1), 1, 1.0);
+    else
+      add_item(rec[key], OpRef{1, key}, I, 0, 1.0);
+  }
+  std::unique_ptr<OpSet> X;
+  if (!wanted.empty()) {
+    X = std::make_unique<OpSet>();
+    X->bond = R.bond;
+    for (uint64_t k : wanted) X->add(k, combo_delta(H, false, k));
+    X->layout(dev);
+    Content content;
+    combo_content(H, false, site + 1, wanted, content);
+    materialize(dev, *X, R, content);
+  }
+  renorm_execute(*this, false, site, *Rp, R, X.get(), rec);
+  if (X) X->release(dev);
+  return Rp;
+}
+
+// ------------------------------------------------------------- layout
+PsiLayout Context::make_layout(int l) const {
+  PsiLayout L;
+  const Bond &ba = bonds[l], &bb = bonds[l + 2];
+  const int d = ham.d;
+  for (size_t a = 0; a < ba.qn.size(); ++a)
+    for (int s1 = 0; s1 < d; ++s1)
+      for (int s2 = 0; s2 < d; ++s2) {
+        const QN q = ba.qn[a] + ham.q_of_state(s1) + ham.q_of_state(s2);
+        const int b = bb.find(q);
+        if (b < 0 || ba.dim[a] == 0 || bb.dim[b] == 0) continue;
+        PsiBlk pb{int(a), s1, s2, b, ba.dim[a], bb.dim[b], L.n_elem};
+        L.idx[PsiLayout::key(int(a), s1, s2, b)] = int(L.blk.size());
+        L.blk.push_back(pb);
+        L.n_elem += int64_t(pb.m) * pb.n;
+      }
+  return L;
+}
+
+// ------------------------------------------------------------- prepare
+void Context::release_bond() {
+  heff.release(dev);
+  if (diag) dev_diag_free(dev, diag);
+  diag = nullptr;
+  if (Lx) Lx->release(dev);
+  if (Rx) Rx->release(dev);
+  Lx.reset();
+  Rx.reset();
+  cur = -1;
+}
+
+void Context::reset_envs() {
+  release_bond();
+  for (auto &e : Lenv)
+    if (e) e->release(dev);
+  for (auto &e : Renv)
+    if (e) e->release(dev);
+  Lenv.clear();
+  Renv.clear();
+}
+
+Context::~Context() {
+  if (!dev) return;
+  try {
+    reset_envs();
+    for (auto &t : A)
+      if (t.data) dev_free(dev, t.data);
+    if (T_scratch) dev_free(dev, T_scratch);
+    dev_sync(dev);
+  } catch (...) {
+  }
+  dev_destroy(dev);
+}
+
+void Context::prepare(int l) {
+  MDMRG_REQUIRE(have_ham && have_mps, -4, "prepare_bond: Hamiltonian and MPS required");
+  const int n = ham.n;
+  MDMRG_REQUIRE(l >= 0 && l + 1 < n, -1, "prepare_bond: bond out of range");
+  double t0 = wall_seconds();
+  if (int(Lenv.size()) != n + 1) {
+    Lenv.resize(n + 1);
+    Renv.resize(n + 1);
+  }
+  if (!Lenv[0]) Lenv[0] = env_boundary(true, 0);
+  for (int i = 0; i < l; ++i)
+    if (!Lenv[i + 1]) Lenv[i + 1] = renorm_left(*Lenv[i], i);
+  if (!Renv[n]) Renv[n] = env_boundary(false, n);
+  for (int i = n - 1; i >= l + 2; --i)
+    if (!Renv[i]) Renv[i] = renorm_right(*Renv[i + 1], i);
+  dev_sync(dev);
+  stats.t_ren += wall_seconds() - t0;
+  build_heff(l);
+}
+
+// ------------------------------------------------------------- H_eff
+void Context::build_heff(int l) {
+  double t0 = wall_seconds();
+  release_bond();
+  last_decimated = 0;
+  const Hamiltonian &H = ham;
+  const int d = H.d, d2 = d * d;
+  const OpSet &L = *Lenv[l];
+  const OpSet &R = *Renv[l + 2];
+  psi = make_layout(l);
+  struct Item {
+    std::vector<double> O;
+    int parity = 0;
+  };
+  std::map<std::pair<OpRef, OpRef>, Item> items;
+  std::set<std::tuple<OpRef, OpRef, uint64_t, uint64_t>> seen;
+  std::set<uint64_t> wantL, wantR;
+  auto two_site = [&](const int *e1, int k1, const int *e2, int k2) {
+    std::vector<double> X1 = H.site_matrix(l, e1, k1), X2 = H.site_matrix(l + 1, e2, k2);
+    std::vector<double> O(d2 * d2, 0.0);
+    for (int a1 = 0; a1 < d; ++a1)
+      for (int b1 = 0; b1 < d; ++b1) {
+        if (X1[a1 * d + b1] == 0.0) continue;
+        const double sg = ((k2 & 1) && parity_of_state(b1)) ? -1.0 : 1.0;
+        for (int a2 = 0; a2 < d; ++a2)
+          for (int b2 = 0; b2 < d; ++b2)
+            O[(a1 * d + a2) * d2 + b1 * d + b2] += sg * X1[a1 * d + b1] * X2[a2 * d + b2];
+      }
+    return O;
+  };
+  auto add_item2 = [&](OpRef lr, OpRef rr, const std::vector<double> &O, int par, double c) {
+    auto &it = items[{lr, rr}];
+    if (it.O.empty()) it.O.assign(d2 * d2, 0.0);
+    it.parity = par;
+    for (int i = 0; i < d2 * d2; ++i) it.O[i] += c * O[i];
+  };
+  auto add_set = [&](OpRef lr, OpRef rr, const int *e1, int k1, const int *e2, int k2) {
+    const auto key = std::make_tuple(lr, rr, make_key(K_N, e1, k1), make_key(K_N, e2, k2));
+    if (!seen.insert(key).second) return;
+    add_item2(lr, rr, two_site(e1, k1, e2, k2), (k1 + k2) & 1, 1.0);
+    if (lr.src == 2) wantL.insert(lr.key);
+    if (rr.src == 2) wantR.insert(rr.key);
+  };
+  const uint64_t kH = make_key(K_H, nullptr, 0);
+  const OpRef ident{0, ident_key()};
+  {
+    std::vector<double> Id(d2 * d2, 0.0);
+    for (int i = 0; i < d2; ++i) Id[i * d2 + i] = 1.0;
+    add_item2(OpRef{1, kH}, ident, Id, 0, 1.0);
+    add_item2(ident, OpRef{1, kH}, Id, 0, 1.0);
+  }
+  for (const Term &t : H.terms) {
+    Parts p;
+    split(H, t, l, p);
+    const int kL = p.k[0], kS = p.k[1] + p.k[2], kR = p.k[3];
+    if (kL == t.n || kR == t.n) continue;
+    if (kL == 0 && kR == 0) {
+      add_item2(ident, ident, two_site(p.e[1], p.k[1], p.e[2], p.k[2]), 0, t.c);
+      continue;
+    }
+    if (kR >= 1 && t.n - kR <= 2) {
+      int K[4], kk = 0;
+      for (int q = 0; q < 3; ++q)
+        for (int i = 0; i < p.k[q]; ++i) K[kk++] = p.e[q][i];
+      OpRef lr = kL == 0 ? ident : OpRef{1, make_key(K_N, p.e[0], kL)};
+      add_set(lr, OpRef{1, make_key(K_C, K, kk)}, p.e[1], p.k[1], p.e[2], p.k[2]);
+      continue;
+    }
+    if (kR >= 1) {  // kR == 1, three operators outside R
+      if (kL == 3) {
+        add_set(OpRef{1, make_key(K_C, p.e[3], 1)}, OpRef{1, make_key(K_N, p.e[3], 1)}, nullptr, 0, nullptr, 0);
+      } else if (kL == 2) {
+        int K[4], kk = 0;
+        for (int q = 1; q < 4; ++q)
+          for (int i = 0; i < p.k[q]; ++i) K[kk++] = p.e[q][i];
+        add_set(OpRef{2, make_key(K_X, K, kk)}, OpRef{1, make_key(K_N, p.e[3], 1)}, p.e[1], p.k[1], p.e[2],
+                p.k[2]);
+      } else {
+        int K[4], kk = 0;
+        for (int q = 0; q < 3; ++q)
+          for (int i = 0; i < p.k[q]; ++i) K[kk++] = p.e[q][i];
+        OpRef lr = kL == 0 ? ident : OpRef{1, make_key(K_N, p.e[0], kL)};
+        add_set(lr, OpRef{2, make_key(K_X, K, kk)}, p.e[1], p.k[1], p.e[2], p.k[2]);
+      }
+      continue;
+    }
+    // kR == 0, kL >= 1, kS >= 1
+    int K[4], kk = 0;
+    for (int q = 1; q < 3; ++q)
+      for (int i = 0; i < p.k[q]; ++i) K[kk++] = p.e[q][i];
+    const bool stored = (t.n == 4 && kL == 3);
+    add_set(OpRef{stored ? 1 : 2, make_key(stored ? K_C : K_X, K, kk)}, ident, p.e[1], p.k[1], p.e[2], p.k[2]);
+    (void)kS;
+  }
+  // on-the-fly complementary operators
+  if (!wantL.empty()) {
+    Lx = std::make_unique<OpSet>();
+    Lx->bond = L.bond;
+    for (uint64_t k : wantL) Lx->add(k, combo_delta(H, true, k));
+    Lx->layout(dev);
+    Content c;
+    combo_content(H, true, l, wantL, c);
+    materialize(dev, *Lx, L, c);
+  }
+  if (!wantR.empty()) {
+    Rx = std::make_unique<OpSet>();
+    Rx->bond = R.bond;
+    for (uint64_t k : wantR) Rx->add(k, combo_delta(H, false, k));
+    Rx->layout(dev);
+    Content c;
+    combo_content(H, false, l + 2, wantR, c);
+    materialize(dev, *Rx, R, c);
+  }
+  // GEMM tasks
+  const Bond &ba = bonds[l], &bb = bonds[l + 2];
+  std::vector<PairTask> tasks;
+  std::vector<OutBlk> outs(psi.blk.size());
+  for (size_t i = 0; i < psi.blk.size(); ++i) {
+    const PsiBlk &pb = psi.blk[i];
+    outs[i] = OutBlk{1, pb.off, pb.m, pb.n, pb.n};
+  }
+  std::vector<DiagTask> dtasks;
+  heff_terms = int64_t(items.size());
+  for (auto &kv : items) {
+    const OpRef &lr = kv.first.first, &rr = kv.first.second;
+    const Item &it = kv.second;
+    const OpSet *Ls = lr.src == 1 ? &L : lr.src == 2 ? Lx.get() : nullptr;
+    const OpSet *Rs = rr.src == 1 ? &R : rr.src == 2 ? Rx.get() : nullptr;
+    if ((lr.src && !Ls->has(lr.key)) || (rr.src && !Rs->has(rr.key))) continue;  // zero operator
+    const int pR = rr.src ? key_parity(rr.key) : 0;
+    const int pS = it.parity;
+    for (const PsiBlk &pb : psi.blk) {
+      // L block a -> a'
+      int ap = pb.a, bp = pb.b;
+      int64_t loff = -1, roff = -1;
+      if (lr.src) {
+        loff = Ls->block(lr.key, pb.a, &ap);
+        if (loff < 0) continue;
+      }
+      if (rr.src) {
+        roff = Rs->block(rr.key, pb.b, &bp);
+        if (roff < 0) continue;
+      }
+      const int pa = ba.qn[pb.a].parity();
+      const int col = pb.s1 * d + pb.s2;
+      for (int s1p = 0; s1p < d; ++s1p)
+        for (int s2p = 0; s2p < d; ++s2p) {
+          const double o = it.O[(s1p * d + s2p) * d2 + col];
+          if (o == 0.0) continue;
+          const int oi = psi.find(ap, s1p, s2p, bp);
+          if (oi < 0) continue;
+          const int ex = pR * (pa + parity_of_state(pb.s1) + parity_of_state(pb.s2)) + pS * pa;
+          const double alpha = o * ((ex & 1) ? -1.0 : 1.0);
+          PairTask t{};
+          t.out = oi;
+          t.m = ba.dim[ap];
+          t.k1 = pb.m;
+          t.k2 = pb.n;
+          t.n = bb.dim[bp];
+          t.alpha = alpha;
+          t.X = Ref{0, pb.off, pb.n};
+          if (lr.src)
+            t.A = Ref{lr.src == 1 ? 3 : 5, loff, pb.m};
+          else
+            t.idA = true;
+          if (rr.src) {
+            t.B = Ref{rr.src == 1 ? 4 : 6, roff, pb.n};
+            t.tB = true;
+          } else {
+            t.idB = true;
+          }
+          tasks.push_back(t);
+          // diagonal contribution
+          if (oi == int(&pb - &psi.blk[0]) && ap == pb.a && bp == pb.b) {
+            DiagTask dt{};
+            dt.d_off = pb.off;
+            dt.alpha = alpha;
+            dt.m = pb.m;
+            dt.n = pb.n;
+            dt.l_id = lr.src ? 0 : 1;
+            dt.r_id = rr.src ? 0 : 1;
+            dt.l_slot = uint8_t(lr.src == 1 ? 3 : 5);
+            dt.r_slot = uint8_t(rr.src == 1 ? 4 : 6);
+            dt.l_off = loff;
+            dt.r_off = roff;
+            dt.ls = pb.m + 1;
+            dt.rs = pb.n + 1;
+            dtasks.push_back(dt);
+          }
+        }
+    }
+  }
+  build_two_phase(tasks, outs, scratch_limit, heff, dev);
+  ensure_scratch(heff.scratch);
+  std::vector<int64_t> boff;
+  std::vector<int32_t> bm, bn;
+  for (auto &pb : psi.blk) {
+    boff.push_back(pb.off);
+    bm.push_back(pb.m);
+    bn.push_back(pb.n);
+  }
+  diag = dev_diag_upload(dev, dtasks, boff, bm, bn);
+  cur = l;
+  dev_sync(dev);
+  stats.t_tables += wall_seconds() - t0;
+}
+
+void Context::heff_apply(const double *x, double *y) {
+  MDMRG_REQUIRE(cur >= 0, -4, "heff_apply: no current bond");
+  dev_zero(dev, y, sizeof(double) * psi.n_elem);
+  Bases b{};
+  b.p[0] = const_cast<double *>(x);
+  b.p[1] = y;
+  b.p[3] = Lenv[cur]->arena;
+  b.p[4] = Renv[cur + 2]->arena;
+  b.p[5] = Lx ? Lx->arena : b.p[3];
+  b.p[6] = Rx ? Rx->arena : b.p[4];
+  b.p[7] = y;
+  run_plan(heff, b, 1);
+  stats.heff_flop += heff.flop;
+  stats.n_matvec += 1;
+}
+
+void Context::heff_diag(double *dd) {
+  MDMRG_REQUIRE(cur >= 0, -4, "heff_diag: no current bond");
+  dev_zero(dev, dd, sizeof(double) * psi.n_elem);
+  Bases b{};
+  b.p[0] = dd;
+  b.p[1] = dd;
+  b.p[2] = dd;
+  b.p[3] = Lenv[cur]->arena;
+  b.p[4] = Renv[cur + 2]->arena;
+  b.p[5] = Lx ? Lx->arena : b.p[3];
+  b.p[6] = Rx ? Rx->arena : b.p[4];
+  b.p[7] = dd;
+  dev_diag_run(dev, diag, b, dd);
+}
+
+// ------------------------------------------------------------- Davidson
+// cyclic Jacobi eigen-decomposition of a small symmetric matrix (row-major)
+static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w, std::vector<double> &V) {
+  V.assign(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+    if (off < 1e-300) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return A[a * n + a] < A[b * n + b]; });
+  w.resize(n);
+  std::vector<double> V2(size_t(n) * n);
+  for (int j = 0; j < n; ++j) {
+    w[j] = A[idx[j] * n + idx[j]];
+    for (int k = 0; k < n; ++k) V2[k * n + j] = V[k * n + idx[j]];
+  }
+  V = V2;
+}
+
+int Context::davidson(double *x, double tol, int max_iter, int m_max, double *energy, double *resid,
+                      int *n_mv) {
+  MDMRG_REQUIRE(cur >= 0, -4, "davidson: no current bond");
+  MDMRG_REQUIRE(m_max >= 3 && m_max <= 60, -1, "davidson: m_max must be in [3, 60]");
+  const int64_t N = psi.n_elem;
+  double t0 = wall_seconds();
+  double *V = (double *)dev_alloc(dev, sizeof(double) * N * m_max);
+  double *AV = (double *)dev_alloc(dev, sizeof(double) * N * m_max);
+  double *dg = (double *)dev_alloc(dev, sizeof(double) * N);
+  double *r = (double *)dev_alloc(dev, sizeof(double) * N);
+  double *ax = (double *)dev_alloc(dev, sizeof(double) * N);
+  heff_diag(dg);
+  // start vector
+  double nrm;
+  dev_multidot(dev, x, 0, 1, x, N, &nrm);
+  if (!(nrm > 1e-300)) {
+    dev_randn(dev, x, N, 3);
+    dev_multidot(dev, x, 0, 1, x, N, &nrm);
+  }
+  MDMRG_REQUIRE(std::isfinite(nrm), -3, "davidson: start vector is not finite");
+  dev_d2d(dev, V, x, sizeof(double) * N);
+  dev_scale(dev, 1.0 / std::sqrt(nrm), V, N);
+  heff_apply(V, AV);
+  int nmv = 1, nv = 1;
+  std::vector<double> Hs(size_t(m_max) * m_max, 0.0);
+  {
+    double h;
+    dev_multidot(dev, V, 0, 1, AV, N, &h);
+    Hs[0] = h;
+  }
+  double theta = Hs[0], rn = 1e300;
+  int status = 0;
+  std::vector<double> w, Y;
+  while (true) {
+    std::vector<double> S(size_t(nv) * nv);
+    for (int i = 0; i < nv; ++i)
+      for (int j = 0; j < nv; ++j) S[i * nv + j] = 0.5 * (Hs[i * m_max + j] + Hs[j * m_max + i]);
+    jacobi_eig(nv, S, w, Y);
+    theta = w[0];
+    std::vector<double> y(nv);
+    for (int i = 0; i < nv; ++i) y[i] = Y[i * nv + 0];
+    dev_lincomb(dev, V, N, nv, y.data(), 0.0, x, N);
+    dev_lincomb(dev, AV, N, nv, y.data(), 0.0, ax, N);
+    dev_d2d(dev, r, ax, sizeof(double) * N);
+    dev_axpy(dev, -theta, x, r, N);
+    double r2;
+    dev_multidot(dev, r, 0, 1, r, N, &r2);
+    MDMRG_REQUIRE(std::isfinite(r2) && std::isfinite(theta), -3, "davidson: NaN in residual");
+    rn = std::sqrt(r2);
+    if (rn <= tol) break;
+    if (nmv >= max_iter) {
+      status = -5;
+      break;
+    }
+    if (nv == m_max) {
+      // thick restart to the two lowest Ritz vectors
+      std::vector<double> y1(nv);
+      for (int i = 0; i < nv; ++i) y1[i] = Y[i * nv + 1];
+      double *tv = r;  // reuse r as temporary after saving
+      double *tav = (double *)dev_alloc(dev, sizeof(double) * N);
+      dev_lincomb(dev, V, N, nv, y1.data(), 0.0, tv, N);
+      dev_lincomb(dev, AV, N, nv, y1.data(), 0.0, tav, N);
+      dev_d2d(dev, V, x, sizeof(double) * N);
+      dev_d2d(dev, AV, ax, sizeof(double) * N);
+      dev_d2d(dev, V + N, tv, sizeof(double) * N);
+      dev_d2d(dev, AV + N, tav, sizeof(double) * N);
+      dev_free(dev, tav);
+      std::fill(Hs.begin(), Hs.end(), 0.0);
+      double h[2];
+      dev_multidot(dev, V, N, 2, AV, N, h);
+      Hs[0] = h[0];
+      dev_multidot(dev, V, N, 2, AV + N, N, h);
+      Hs[1] = h[0];
+      Hs[m_max + 1] = h[1];
+      Hs[m_max] = h[0];
+      nv = 2;
+      // recompute residual of x
+      dev_d2d(dev, r, ax, sizeof(double) * N);
+      dev_axpy(dev, -theta, x, r, N);
+    }
+    // correction vector
+    double *t = V + int64_t(nv) * N;
+    dev_precond(dev, r, dg, theta, 1e-8, t, N);
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<double> c(nv);
+      dev_multidot(dev, V, N, nv, t, N, c.data());
+      for (auto &v : c) v = -v;
+      dev_lincomb(dev, V, N, nv, c.data(), 1.0, t, N);
+    }
+    double tn;
+    dev_multidot(dev, t, 0, 1, t, N, &tn);
+    if (!(tn > 1e-28)) {
+      // preconditioned residual collapsed into the subspace: use r itself
+      dev_d2d(dev, t, r, sizeof(double) * N);
+      for (int pass = 0; pass < 2; ++pass) {
+        std::vector<double> c(nv);
+        dev_multidot(dev, V, N, nv, t, N, c.data());
+        for (auto &v : c) v = -v;
+        dev_lincomb(dev, V, N, nv, c.data(), 1.0, t, N);
+      }
+      dev_multidot(dev, t, 0, 1, t, N, &tn);
+      if (!(tn > 1e-28)) break;
+    }
+    dev_scale(dev, 1.0 / std::sqrt(tn), t, N);
+    heff_apply(t, AV + int64_t(nv) * N);
+    ++nmv;
+    std::vector<double> col(nv + 1);
+    dev_multidot(dev, V, N, nv + 1, AV + int64_t(nv) * N, N, col.data());
+    for (int i = 0; i <= nv; ++i) {
+      Hs[i * m_max + nv] = col[i];
+      Hs[nv * m_max + i] = col[i];
+    }
+    ++nv;
+  }
+  // normalise the returned vector
+  double xn;
+  dev_multidot(dev, x, 0, 1, x, N, &xn);
+  dev_scale(dev, 1.0 / std::sqrt(xn), x, N);
+  dev_free(dev, V);
+  dev_free(dev, AV);
+  dev_free(dev, dg);
+  dev_free(dev, r);
+  dev_free(dev, ax);
+  dev_sync(dev);
+  if (energy) *energy = theta;
+  if (resid) *resid = rn;
+  if (n_mv) *n_mv = nmv;
+  stats.t_diag_h += wall_seconds() - t0;
+  return status;
+}
+
+// ------------------------------------------------------------- decimation
+void Context::decimate(const double *x, int D, int dir, double *trunc, double *svn, double *shalf) {
+  MDMRG_REQUIRE(cur >= 0, -4, "decimate: no current bond");
+  MDMRG_REQUIRE(D >= 1, -1, "decimate: D must be positive");
+  MDMRG_REQUIRE(dir == 1 || dir == -1, -1, "decimate: direction must be +1 or -1");
+  double t0 = wall_seconds();
+  const int l = cur, d = ham.d;
+  const Bond &ba = bonds[l], &bb = bonds[l + 2];
+  // enlarged-block sectors and their row lists
+  struct Sec {
+    QN q;
+    std::vector<std::pair<int, int>> rows;  // (sector, local state) for dir +1 : (a,s1); dir -1: (s2,b)
+    std::vector<int> roff;
+    int M = 0;
+    int64_t base = 0;
+  };
+  std::map<int64_t, int> sidx;
+  std::vector<Sec> secs;
+  auto sec_of = [&](QN q) {
+    auto it = sidx.find(q.key());
+    if (it != sidx.end()) return it->second;
+    sidx[q.key()] = int(secs.size());
+    secs.push_back(Sec{q, {}, {}, 0, 0});
+    return int(secs.size()) - 1;
+  };
+  std::map<int64_t, std::pair<int, int>> rowpos;  // (sector idx, row idx) per (x, s)
+  auto rkey = [](int a, int s) { return int64_t(a) * 64 + s; };
+  if (dir > 0) {
+    for (size_t a = 0; a < ba.qn.size(); ++a)
+      for (int s1 = 0; s1 < d; ++s1) {
+        bool any = false;
+        for (int s2 = 0; s2 < d && !any; ++s2)
+          for (size_t b = 0; b < bb.qn.size() && !any; ++b) any = psi.find(int(a), s1, s2, int(b)) >= 0;
+        if (!any) continue;
+        const int si = sec_of(ba.qn[a] + ham.q_of_state(s1));
+        rowpos[rkey(int(a), s1)] = {si, int(secs[si].rows.size())};
+        secs[si].rows.push_back({int(a), s1});
+      }
+  } else {
+    for (int s2 = 0; s2 < d; ++s2)
+      for (size_t b = 0; b < bb.qn.size(); ++b) {
+        bool any = false;
+        for (size_t a = 0; a < ba.qn.size() && !any; ++a)
+          for (int s1 = 0; s1 < d && !any; ++s1) any = psi.find(int(a), s1, s2, int(b)) >= 0;
+        if (!any) continue;
+        const int si = sec_of(bb.qn[b] - ham.q_of_state(s2));
+        rowpos[rkey(int(b), s2)] = {si, int(secs[si].rows.size())};
+        secs[si].rows.push_back({s2, int(b)});
+      }
+  }
+  // sort sectors by quantum number for a deterministic order
+  std::vector<int> sorder(secs.size());
+  std::iota(sorder.begin(), sorder.end(), 0);
+  std::sort(sorder.begin(), sorder.end(), [&](int i, int j) { return secs[i].q < secs[j].q; });
+  int64_t tot = 0;
+  for (auto &s : secs) {
+    s.roff.resize(s.rows.size());
+    int off = 0;
+    for (size_t r = 0; r < s.rows.size(); ++r) {
+      s.roff[r] = off;
+      off += dir > 0 ? ba.dim[s.rows[r].first] : bb.dim[s.rows[r].second];
+    }
+    s.M = off;
+    s.base = tot;
+    tot += int64_t(off) * off;
+  }
+  double *rho = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, tot));
+  dev_zero(dev, rho, sizeof(double) * std::max<int64_t>(1, tot));
+  // rho blocks as grouped GEMM (psi in slot 0, rho in slot 1)
+  GemmPlan gp;
+  for (auto &s : secs) {
+    for (size_t i = 0; i < s.rows.size(); ++i)
+      for (size_t j = 0; j < s.rows.size(); ++j) {
+        GOut o{};
+        o.c_slot = 1;
+        o.accumulate = 0;
+        o.seg_begin = int32_t(gp.segs.size());
+        if (dir > 0) {
+          const int a = s.rows[i].first, s1 = s.rows[i].second, a2 = s.rows[j].first, s1b = s.rows[j].second;
+          o.c_off = s.base + int64_t(s.roff[i]) * s.M + s.roff[j];
+          o.m = ba.dim[a];
+          o.n = ba.dim[a2];
+          o.ldc = s.M;
+          for (int s2 = 0; s2 < d; ++s2)
+            for (size_t b = 0; b < bb.qn.size(); ++b) {
+              const int p1 = psi.find(a, s1, s2, int(b)), p2 = psi.find(a2, s1b, s2, int(b));
+              if (p1 < 0 || p2 < 0) continue;
+              GSeg g{};
+              g.alpha = 1.0;
+              g.a_slot = 0;
+              g.a_off = psi.blk[p1].off;
+              g.lda = psi.blk[p1].n;
+              g.b_slot = 0;
+              g.b_off = psi.blk[p2].off;
+              g.ldb = psi.blk[p2].n;
+              g.flags = SEG_TB;
+              g.k = psi.blk[p1].n;
+              gp.segs.push_back(g);
+            }
+        } else {
+          const int s2 = s.rows[i].first, b = s.rows[i].second, s2b = s.rows[j].first, b2 = s.rows[j].second;
+          o.c_off = s.base + int64_t(s.roff[i]) * s.M + s.roff[j];
+          o.m = bb.dim[b];
+          o.n = bb.dim[b2];
+          o.ldc = s.M;
+          for (size_t a = 0; a < ba.qn.size(); ++a)
+            for (int s1 = 0; s1 < d; ++s1) {
+              const int p1 = psi.find(int(a), s1, s2, b), p2 = psi.find(int(a), s1, s2b, b2);
+              if (p1 < 0 || p2 < 0) continue;
+              GSeg g{};
+              g.alpha = 1.0;
+              g.a_slot = 0;
+              g.a_off = psi.blk[p1].off;
+              g.lda = psi.blk[p1].n;
+              g.b_slot = 0;
+              g.b_off = psi.blk[p2].off;
+              g.ldb = psi.blk[p2].n;
+              g.flags = SEG_TA;
+              g.k = psi.blk[p1].m;
+              gp.segs.push_back(g);
+            }
+        }
+        o.seg_count = int32_t(gp.segs.size()) - o.seg_begin;
+        if (o.seg_count > 0) gp.outs.push_back(o);
+      }
+  }
+  {
+    DevPlan *dp = dev_plan_upload(dev, gp);
+    Bases b{};
+    for (int i = 0; i < kSlots; ++i) b.p[i] = rho;
+    b.p[0] = const_cast<double *>(x);
+    b.p[1] = rho;
+    dev_gemm_run(dev, dp, b);
+    dev_plan_free(dev, dp);
+  }
+  // eigen-decomposition per sector
+  double *wdev = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, tot > 0 ? tot : 1));
+  std::vector<std::vector<double>> evals(secs.size());
+  int64_t woff = 0;
+  std::vector<int64_t> wbase(secs.size());
+  for (size_t i = 0; i < secs.size(); ++i) {
+    wbase[i] = woff;
+    woff += secs[i].M;
+  }
+  double *wv = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, woff));
+  for (size_t i = 0; i < secs.size(); ++i) dev_syevd(dev, rho + secs[i].base, secs[i].M, wv + wbase[i]);
+  std::vector<double> wall(std::max<int64_t>(1, woff));
+  dev_d2h(dev, wall.data(), wv, sizeof(double) * woff);
+  dev_free(dev, wdev);
+  dev_free(dev, wv);
+  // global selection: (-lambda, sector qn, index)
+  struct Cand {
+    double lam;
+    int sec;
+    int k;
+  };
+  std::vector<Cand> cand;
+  for (size_t i = 0; i < secs.size(); ++i)
+    for (int k = 0; k < secs[i].M; ++k) cand.push_back(Cand{wall[wbase[i] + k], int(i), k});
+  std::sort(cand.begin(), cand.end(), [&](const Cand &a, const Cand &b) {
+    if (a.lam != b.lam) return a.lam > b.lam;
+    if (secs[a.sec].q != secs[b.sec].q) return secs[a.sec].q < secs[b.sec].q;
+    return a.k > b.k;
+  });
+  const int keep = std::min<int>(D, int(cand.size()));
+  double kept = 0.0, sv = 0.0, sh = 0.0;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    const double p = std::max(0.0, cand[i].lam);
+    if (int(i) < keep) kept += p;
+    if (p > 1e-300) {
+      sv -= p * std::log(p);
+      sh += std::sqrt(p);
+    }
+  }
+  if (trunc) *trunc = std::max(0.0, 1.0 - kept);
+  if (svn) *svn = sv;
+  if (shalf) *shalf = 2.0 * std::log(std::max(sh, 1e-300));
+  // kept columns per sector (descending eigenvalue = descending index)
+  std::vector<std::vector<int32_t>> kcols(secs.size());
+  for (int i = 0; i < keep; ++i) kcols[cand[i].sec].push_back(cand[i].k);
+  for (auto &v : kcols) std::sort(v.begin(), v.end(), std::greater<int32_t>());
+  // new bond
+  Bond nb;
+  for (int si : sorder)
+    if (!kcols[si].empty()) {
+      nb.qn.push_back(secs[si].q);
+      nb.dim.push_back(int(kcols[si].size()));
+    }
+  nb.rebuild_index();
+  // new site tensor
+  SiteTensor T;
+  std::vector<GatherBlk> gb;
+  std::vector<int32_t> cols;
+  for (int si : sorder) {
+    if (kcols[si].empty()) continue;
+    const int ni = nb.find(secs[si].q);
+    const int cb = int(cols.size());
+    cols.insert(cols.end(), kcols[si].begin(), kcols[si].end());
+    const Sec &s = secs[si];
+    for (size_t r = 0; r < s.rows.size(); ++r) {
+      GatherBlk g{};
+      g.e_off = s.base;
+      g.ldE = s.M;
+      g.row0 = s.roff[r];
+      g.ncol = int32_t(kcols[si].size());
+      g.col_begin = cb;
+      if (dir > 0) {
+        const int a = s.rows[r].first, s1 = s.rows[r].second;
+        g.rows = ba.dim[a];
+        T.add(a, s1, ni, int64_t(ba.dim[a]) * nb.dim[ni]);
+        g.out_off = T.off.back();
+      } else {
+        const int s2 = s.rows[r].first, b = s.rows[r].second;
+        g.rows = bb.dim[b];
+        T.add(ni, s2, b, int64_t(nb.dim[ni]) * bb.dim[b]);
+        g.out_off = T.off.back();
+      }
+      gb.push_back(g);
+    }
+  }
+  T.data = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, T.size));
+  dev_gather(dev, gb, cols, rho, T.data, dir < 0);
+  dev_free(dev, rho);
+  // install
+  const int site = dir > 0 ? l : l + 1;
+  if (A[site].data) dev_free(dev, A[site].data);
+  A[site] = std::move(T);
+  bonds[l + 1] = nb;
+  last_decimated = dir;
+  // environments that depended on the replaced site / bond are stale
+  for (int i = l + 1; i <= ham.n; ++i)
+    if (dir > 0 && Lenv[i]) {
+      Lenv[i]->release(dev);
+      Lenv[i].reset();
+    }
+  for (int i = 0; i <= l + 1; ++i)
+    if (dir < 0 && Renv[i]) {
+      Renv[i]->release(dev);
+      Renv[i].reset();
+    }
+  dev_sync(dev);
+  stats.t_diag_d += wall_seconds() - t0;
+}
+
+// ------------------------------------------------------------- StVec
+// dir +1: x_old at bond (l, l+1) with A[l] now a left isometry onto bond
+//         l+1; new vector at bond (l+1, l+2) uses A[l+2] (right isometry).
+// dir -1: A[l+1] now a right isometry; new vector at bond (l-1, l) uses
+//         A[l-1] (left isometry).
+void Context::stvec(const double *x_old, int l, int dir, const PsiLayout &ol, double *x_new,
+                    const PsiLayout &nl) {
+  double t0 = wall_seconds();
+  const int d = ham.d;
+  // intermediate blocks: dir +1: T[n, s2, b] (bond l+1 sector n, bond l+2 sector b)
+  //                      dir -1: T[a, s1, n] (bond l sector a, bond l+1 sector n)
+  std::map<std::tuple<int, int, int>, std::pair<int64_t, std::pair<int, int>>> tb;
+  int64_t toff = 0;
+  GemmPlan p1, p2;
+  const Bond &b0 = bonds[l], &b1 = bonds[l + 1], &b2 = bonds[l + 2];
+  if (dir > 0) {
+    const SiteTensor &Al = A[l];
+    for (size_t nsec = 0; nsec < b1.qn.size(); ++nsec)
+      for (int s2 = 0; s2 < d; ++s2)
+        for (size_t b = 0; b < b2.qn.size(); ++b) {
+          GOut o{};
+          o.seg_begin = int32_t(p1.segs.size());
+          for (size_t a = 0; a < b0.qn.size(); ++a)
+            for (int s1 = 0; s1 < d; ++s1) {
+              const int ia = Al.find(int(a), s1, int(nsec));
+              const int ip = ol.find(int(a), s1, s2, int(b));
+              if (ia < 0 || ip < 0) continue;
+              GSeg g{};
+              g.alpha = 1.0;
+              g.a_slot = 6;
+              g.a_off = Al.off[ia];
+              g.lda = b1.dim[nsec];
+              g.flags = SEG_TA;
+              g.b_slot = 0;
+              g.b_off = ol.blk[ip].off;
+              g.ldb = ol.blk[ip].n;
+              g.k = b0.dim[a];
+              p1.segs.push_back(g);
+              p1.flop += 2.0 * b1.dim[nsec] * b2.dim[b] * b0.dim[a];
+            }
+          o.seg_count = int32_t(p1.segs.size()) - o.seg_begin;
+          if (!o.seg_count) continue;
+          o.c_slot = 2;
+          o.c_off = toff;
+          o.m = b1.dim[nsec];
+          o.n = b2.dim[b];
+          o.ldc = o.n;
+          tb[{int(nsec), s2, int(b)}] = {toff, {o.m, o.n}};
+          toff += int64_t(o.m) * o.n;
+          p1.outs.push_back(o);
+        }
+    const SiteTensor &B2 = A[l + 2];
+    for (const PsiBlk &pb : nl.blk) {  // (n, s2, s3, c)
+      GOut o{};
+      o.seg_begin = int32_t(p2.segs.size());
+      for (size_t b = 0; b < b2.qn.size(); ++b) {
+        auto it = tb.find({pb.a, pb.s1, int(b)});
+        const int ib = B2.find(int(b), pb.s2, pb.b);
+        if (it == tb.end() || ib < 0) continue;
+        GSeg g{};
+        g.alpha = 1.0;
+        g.a_slot = 2;
+        g.a_off = it->second.first;
+        g.lda = b2.dim[b];
+        g.b_slot = 7;
+        g.b_off = B2.off[ib];
+        g.ldb = pb.n;
+        g.k = b2.dim[b];
+        p2.segs.push_back(g);
+        p2.flop += 2.0 * pb.m * pb.n * b2.dim[b];
+      }
+      o.seg_count = int32_t(p2.segs.size()) - o.seg_begin;
+      o.c_slot = 1;
+      o.c_off = pb.off;
+      o.m = pb.m;
+      o.n = pb.n;
+      o.ldc = pb.n;
+      o.accumulate = 0;
+      p2.outs.push_back(o);
+    }
+  } else {
+    const SiteTensor &Bn = A[l + 1];
+    for (size_t a = 0; a < b0.qn.size(); ++a)
+      for (int s1 = 0; s1 < d; ++s1)
+        for (size_t nsec = 0; nsec < b1.qn.size(); ++nsec) {
+          GOut o{};
+          o.seg_begin = int32_t(p1.segs.size());
+          for (int s2 = 0; s2 < d; ++s2)
+            for (size_t b = 0; b < b2.qn.size(); ++b) {
+              const int ib = Bn.find(int(nsec), s2, int(b));
+              const int ip = ol.find(int(a), s1, s2, int(b));
+              if (ib < 0 || ip < 0) continue;
+              GSeg g{};
+              g.alpha = 1.0;
+              g.a_slot = 0;
+              g.a_off = ol.blk[ip].off;
+              g.lda = ol.blk[ip].n;
+              g.b_slot = 6;
+              g.b_off = Bn.off[ib];
+              g.ldb = b2.dim[b];
+              g.flags = SEG_TB;
+              g.k = b2.dim[b];
+              p1.segs.push_back(g);
+              p1.flop += 2.0 * b0.dim[a] * b1.dim[nsec] * b2.dim[b];
+            }
+          o.seg_count = int32_t(p1.segs.size()) - o.seg_begin;
+          if (!o.seg_count) continue;
+          o.c_slot = 2;
+          o.c_off = toff;
+          o.m = b0.dim[a];
+          o.n = b1.dim[nsec];
+          o.ldc = o.n;
+          tb[{int(a), s1, int(nsec)}] = {toff, {o.m, o.n}};
+          toff += int64_t(o.m) * o.n;
+          p1.outs.push_back(o);
+        }
+    const SiteTensor &Am = A[l - 1];
+    const Bond &bm = bonds[l - 1];
+    for (const PsiBlk &pb : nl.blk) {  // (a0, s0, s1, n)
+      GOut o{};
+      o.seg_begin = int32_t(p2.segs.size());
+      for (size_t a = 0; a < b0.qn.size(); ++a) {
+        auto it = tb.find({int(a), pb.s2, pb.b});
+        const int ia = Am.find(pb.a, pb.s1, int(a));
+        if (it == tb.end() || ia < 0) continue;
+        GSeg g{};
+        g.alpha = 1.0;
+        g.a_slot = 7;
+        g.a_off = Am.off[ia];
+        g.lda = b0.dim[a];
+        g.b_slot = 2;
+        g.b_off = it->second.first;
+        g.ldb = pb.n;
+        g.k = b0.dim[a];
+        p2.segs.push_back(g);
+        p2.flop += 2.0 * pb.m * pb.n * b0.dim[a];
+      }
+      (void)bm;
+      o.seg_count = int32_t(p2.segs.size()) - o.seg_begin;
+      o.c_slot = 1;
+      o.c_off = pb.off;
+      o.m = pb.m;
+      o.n = pb.n;
+      o.ldc = pb.n;
+      o.accumulate = 0;
+      p2.outs.push_back(o);
+    }
+  }
+  ensure_scratch(toff);
+  dev_zero(dev, x_new, sizeof(double) * nl.n_elem);
+  Bases b{};
+  for (int i = 0; i < kSlots; ++i) b.p[i] = x_new;
+  b.p[0] = const_cast<double *>(x_old);
+  b.p[1] = x_new;
+  b.p[2] = T_scratch;
+  b.p[6] = dir > 0 ? A[l].data : A[l + 1].data;
+  b.p[7] = dir > 0 ? A[l + 2].data : A[l - 1].data;
+  DevPlan *d1 = dev_plan_upload(dev, p1);
+  DevPlan *d2 = dev_plan_upload(dev, p2);
+  dev_gemm_run(dev, d1, b);
+  dev_gemm_run(dev, d2, b);
+  dev_plan_free(dev, d1);
+  dev_plan_free(dev, d2);
+  dev_sync(dev);
+  stats.t_stvec += wall_seconds() - t0;
+}
+
+void Context::renormalize(int dir) {
+  MDMRG_REQUIRE(cur >= 0 && last_decimated == dir && (dir == 1 || dir == -1), -4,
+                "renormalize: call decimate at the current bond with the same direction first");
+  const int l = cur, n = ham.n;
+  const int nl = l + dir;
+  MDMRG_REQUIRE(nl >= 0 && nl + 1 < n, -1, "renormalize: no bond beyond the chain end");
+  double t0 = wall_seconds();
+  if (dir > 0) {
+    if (!Lenv[l + 1]) Lenv[l + 1] = renorm_left(*Lenv[l], l);
+  } else {
+    if (!Renv[l + 1]) Renv[l + 1] = renorm_right(*Renv[l + 2], l + 1);
+  }
+  dev_sync(dev);
+  stats.t_ren += wall_seconds() - t0;
+  prev_psi = psi;
+  prev_l = l;
+  prev_dir = dir;
+  prepare(nl);
+  last_decimated = 0;
+}
+
+// ------------------------------------------------------------- sweeps
+void Context::sweep(int n_sweeps, const int *Ds, int n_sched, double tol, double *energies) {
+  MDMRG_REQUIRE(have_ham && have_mps, -4, "sweep: Hamiltonian and MPS required");
+  MDMRG_REQUIRE(n_sweeps >= 1 && n_sched >= 1, -1, "sweep: bad schedule");
+  const int n = ham.n;
+  MDMRG_REQUIRE(n >= 3, -1, "sweep: need at least 3 sites");
+  // start at bond (0, 1)
+  prepare(0);
+  double *x = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, psi.n_elem));
+  dev_randn(dev, x, psi.n_elem, 1);
+  double e = 0.0;
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    const int D = Ds[std::min(sw, n_sched - 1)];
+    for (int dir : {1, -1}) {
+      const int lo = 0, hi = n - 2;
+      int l = dir > 0 ? lo : hi;
+      while (true) {
+        double res;
+        int nmv;
+        davidson(x, tol, 200, 24, &e, &res, &nmv);
+        const bool last = dir > 0 ? (l == hi - 1) : (l == lo + 1);
+        decimate(x, D, dir, nullptr, nullptr, nullptr);
+        renormalize(dir);
+        double *xn = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, psi.n_elem));
+        stvec(x, prev_l, dir, prev_psi, xn, psi);
+        dev_free(dev, x);
+        x = xn;
+        l = cur;
+        if (last) {
+          // the turning bond is optimised at the start of the next half-sweep
+          break;
+        }
+      }
+    }
+    if (energies) energies[sw] = e;
+  }
+  dev_free(dev, x);
+  dev_sync(dev);
+}
+
+}  // namespace mdmrg

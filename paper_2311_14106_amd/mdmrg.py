@@ -1,0 +1,248 @@
+"""Thin ctypes binding of libmdmrg.so (argument marshalling only).
+
+Every computation happens in the C++/HIP library; this module only converts
+numpy arrays / torch device tensors into the plain pointers and sizes of the
+C ABI declared in include/mdmrg.h, and turns negative status codes into
+exceptions.  Device buffers are torch tensors on the context's device (torch
+is used for device memory and streams only).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_LIB = os.path.join(HERE, 'libmdmrg.so')
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOCONV, EUNSUP = 0, -1, -2, -3, -4, -5, -6
+SPINLESS, HUBBARD = 0, 1
+REAL, MOMENTUM = 0, 1
+FP64, FP32, BF16X3 = 0, 1, 2
+
+_c_dbl_p = ctypes.POINTER(ctypes.c_double)
+_c_i32_p = ctypes.POINTER(ctypes.c_int32)
+_c_i64_p = ctypes.POINTER(ctypes.c_int64)
+
+EXPORTS = {
+    'mdmrg_version': (ctypes.c_char_p, []),
+    'mdmrg_create': (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
+    'mdmrg_destroy': (None, [ctypes.c_void_p]),
+    'mdmrg_last_error': (ctypes.c_char_p, [ctypes.c_void_p]),
+    'mdmrg_lattice_nso': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    'mdmrg_build_lattice': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_double, ctypes.c_double, _c_dbl_p, _c_dbl_p]),
+    'mdmrg_rotate_modes': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
+    'mdmrg_set_hamiltonian': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_dbl_p, _c_dbl_p,
+                                             ctypes.c_int, ctypes.c_int]),
+    'mdmrg_set_hamiltonian_coo': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_dbl_p,
+                                                 ctypes.c_int64, _c_i32_p, _c_dbl_p, ctypes.c_int, ctypes.c_int]),
+    'mdmrg_n_terms': (ctypes.c_int, [ctypes.c_void_p, _c_i64_p, _c_i64_p]),
+    'mdmrg_set_mps': (ctypes.c_int, [ctypes.c_void_p, _c_i32_p, _c_i32_p, _c_i32_p, _c_dbl_p, ctypes.c_int64]),
+    'mdmrg_get_bond': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i32_p, _c_i32_p, _c_i32_p]),
+    'mdmrg_prepare_bond': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    'mdmrg_psi_layout': (ctypes.c_int, [ctypes.c_void_p, _c_i64_p, _c_i32_p, _c_i32_p]),
+    'mdmrg_heff_apply': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    'mdmrg_heff_diag': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    'mdmrg_heff_cost': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_i64_p, _c_i64_p]),
+    'mdmrg_davidson': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_int, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_int)]),
+    'mdmrg_decimate': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                      _c_dbl_p, _c_dbl_p, _c_dbl_p]),
+    'mdmrg_renormalize': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    'mdmrg_stvec': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    'mdmrg_sweep': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i32_p, ctypes.c_int, ctypes.c_double,
+                                   _c_dbl_p]),
+    'mdmrg_get_stats': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p]),
+}
+
+
+class MdmrgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f'mdmrg status {code}: {msg}')
+        self.code = code
+
+
+def load(path=None):
+    """Load the library and declare the C signatures.  Raises if missing."""
+    path = path or DEFAULT_LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f'libmdmrg not built: {path} is missing (run paper_2311_14106_amd.build)')
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB
+
+
+def _dp(a):
+    return a.ctypes.data_as(_c_dbl_p)
+
+
+def _ip(a):
+    return a.ctypes.data_as(_c_i32_p)
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or a raw integer address)."""
+    if isinstance(t, int):
+        return ctypes.c_void_p(t)
+    if isinstance(t, np.ndarray):
+        return ctypes.c_void_p(t.ctypes.data)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def build_lattice(model, basis, Lx, Ly, t, u, L=None):
+    L = L or lib()
+    nso = L.mdmrg_lattice_nso(model, Lx, Ly)
+    T = np.zeros((nso, nso))
+    V = np.zeros((nso,) * 4)
+    st = L.mdmrg_build_lattice(model, basis, Lx, Ly, t, u, _dp(T), _dp(V))
+    if st:
+        raise MdmrgError(st, L.mdmrg_last_error(None).decode())
+    return T, V
+
+
+def rotate_modes(R, T, V, spin_half, L=None):
+    L = L or lib()
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    T = np.array(T, dtype=np.float64, order='C')
+    V = np.array(V, dtype=np.float64, order='C')
+    st = L.mdmrg_rotate_modes(R.shape[0], int(spin_half), _dp(R), _dp(T), _dp(V))
+    if st:
+        raise MdmrgError(st, L.mdmrg_last_error(None).decode())
+    return T, V
+
+
+class Context:
+    """One library context on one HIP device."""
+
+    def __init__(self, device=0, path=None):
+        self.lib = load(path) if path else lib()
+        h = ctypes.c_void_p()
+        st = self.lib.mdmrg_create(ctypes.byref(h), device)
+        if st:
+            raise MdmrgError(st, self.lib.mdmrg_last_error(None).decode())
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self.lib.mdmrg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st, allow=()):
+        if st and st not in allow:
+            raise MdmrgError(st, self.lib.mdmrg_last_error(self.h).decode())
+        return st
+
+    # ---------------------------------------------------------------- model
+    def set_hamiltonian(self, n_sites, spin_half, T, V, target):
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        self._chk(self.lib.mdmrg_set_hamiltonian(self.h, n_sites, int(spin_half), _dp(T), _dp(V),
+                                                 int(target[0]), int(target[1])))
+
+    def set_hamiltonian_coo(self, n_sites, spin_half, T, ijkl, val, target):
+        T = np.ascontiguousarray(T, dtype=np.float64)
+        ijkl = np.ascontiguousarray(ijkl, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        self._chk(self.lib.mdmrg_set_hamiltonian_coo(self.h, n_sites, int(spin_half), _dp(T), len(val),
+                                                     _ip(ijkl), _dp(val), int(target[0]), int(target[1])))
+
+    def n_terms(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        self._chk(self.lib.mdmrg_n_terms(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    # ------------------------------------------------------------------ MPS
+    def set_mps(self, n_sect, sect_qn, sect_dim, data):
+        n_sect = np.ascontiguousarray(n_sect, dtype=np.int32)
+        sect_qn = np.ascontiguousarray(sect_qn, dtype=np.int32)
+        sect_dim = np.ascontiguousarray(sect_dim, dtype=np.int32)
+        data = np.ascontiguousarray(data, dtype=np.float64)
+        self._chk(self.lib.mdmrg_set_mps(self.h, _ip(n_sect), _ip(sect_qn), _ip(sect_dim), _dp(data),
+                                         len(data)))
+
+    def get_bond(self, i):
+        n = ctypes.c_int32()
+        self._chk(self.lib.mdmrg_get_bond(self.h, i, ctypes.byref(n), None, None))
+        qn = np.zeros(2 * n.value, dtype=np.int32)
+        dim = np.zeros(n.value, dtype=np.int32)
+        self._chk(self.lib.mdmrg_get_bond(self.h, i, ctypes.byref(n), _ip(qn), _ip(dim)))
+        return [((int(qn[2 * k]), int(qn[2 * k + 1])), int(dim[k])) for k in range(n.value)]
+
+    # ----------------------------------------------------------------- bond
+    def prepare_bond(self, l):
+        self._chk(self.lib.mdmrg_prepare_bond(self.h, l))
+
+    def psi_layout(self):
+        ne, nb = ctypes.c_int64(), ctypes.c_int32()
+        self._chk(self.lib.mdmrg_psi_layout(self.h, ctypes.byref(ne), ctypes.byref(nb), None))
+        desc = np.zeros(8 * nb.value, dtype=np.int32)
+        self._chk(self.lib.mdmrg_psi_layout(self.h, ctypes.byref(ne), ctypes.byref(nb), _ip(desc)))
+        d = desc.reshape(-1, 8).astype(np.int64)
+        off = (d[:, 6] & 0xffffffff) | (d[:, 7] << 32)
+        blocks = [(int(a), int(s1), int(s2), int(b), int(o), int(m), int(n))
+                  for (a, s1, s2, b, m, n), o in zip(d[:, :6], off)]
+        return blocks, ne.value
+
+    def heff_apply(self, x, y, prec=FP64):
+        self._chk(self.lib.mdmrg_heff_apply(self.h, prec, _ptr(x), _ptr(y)))
+
+    def heff_diag(self, d):
+        self._chk(self.lib.mdmrg_heff_diag(self.h, _ptr(d)))
+
+    def heff_cost(self):
+        f, b, t, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        self._chk(self.lib.mdmrg_heff_cost(self.h, ctypes.byref(f), ctypes.byref(b), ctypes.byref(t),
+                                           ctypes.byref(g)))
+        return {'flop': f.value, 'bytes': b.value, 'n_terms': t.value, 'n_gemm': g.value}
+
+    def davidson(self, x, tol=1e-8, max_iter=200, m_max=24):
+        e, r, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        st = self._chk(self.lib.mdmrg_davidson(self.h, _ptr(x), tol, max_iter, m_max, ctypes.byref(e),
+                                               ctypes.byref(r), ctypes.byref(n)), allow=(ENOCONV,))
+        return e.value, r.value, n.value, st == OK
+
+    def decimate(self, x, D, direction):
+        t, s, h = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.mdmrg_decimate(self.h, _ptr(x), D, direction, ctypes.byref(t), ctypes.byref(s),
+                                          ctypes.byref(h)))
+        return t.value, s.value, h.value
+
+    def renormalize(self, direction):
+        self._chk(self.lib.mdmrg_renormalize(self.h, direction))
+
+    def stvec(self, x_old, x_new):
+        self._chk(self.lib.mdmrg_stvec(self.h, _ptr(x_old), _ptr(x_new)))
+
+    def sweep(self, n_sweeps, D_schedule, tol=1e-8):
+        Ds = np.ascontiguousarray(D_schedule, dtype=np.int32)
+        E = np.zeros(n_sweeps)
+        self._chk(self.lib.mdmrg_sweep(self.h, n_sweeps, _ip(Ds), len(Ds), tol, _dp(E)))
+        return E
+
+    def stats(self):
+        out = np.zeros(14)
+        self._chk(self.lib.mdmrg_get_stats(self.h, _dp(out)))
+        keys = ['diag_h_s', 'ren_s', 'tables_s', 'diag_d_s', 'stvec_s', 'other_s', 'heff_flop', 'n_matvec',
+                'heff_gemm_ms', 'heff_gemm_launches', 'heff_gemm_flop',
+                'ren_gemm_ms', 'ren_gemm_launches', 'ren_gemm_flop']
+        return dict(zip(keys, out.tolist()))

@@ -101,6 +101,60 @@ def bond_profile(n_sites, spinful, target, D, weight_power=1.0):
     return [sorted(b.items()) for b in bonds]
 
 
+def _consistent(bonds, n_sites, spinful):
+    """Shrink dimensions until every site tensor can be left and right
+    isometric (rows >= columns both ways)."""
+    d = 4 if spinful else 2
+    changed = True
+    while changed:
+        changed = False
+        for i in range(n_sites):
+            L, R = bonds[i], bonds[i + 1]
+            for Qr in list(R):
+                avail = sum(L.get((Qr[0] - local_qn(s, spinful)[0], Qr[1] - local_qn(s, spinful)[1]), 0)
+                            for s in range(d))
+                if R[Qr] > avail:
+                    R[Qr] = avail
+                    changed = True
+                if R[Qr] == 0:
+                    del R[Qr]
+        for i in range(n_sites - 1, -1, -1):
+            L, R = bonds[i], bonds[i + 1]
+            for Ql in list(L):
+                avail = sum(R.get((Ql[0] + local_qn(s, spinful)[0], Ql[1] + local_qn(s, spinful)[1]), 0)
+                            for s in range(d))
+                if L[Ql] > avail:
+                    L[Ql] = avail
+                    changed = True
+                if L[Ql] == 0:
+                    del L[Ql]
+    return [sorted(b.items()) for b in bonds]
+
+
+def scale_profile(bonds_small, n_sites, spinful, target, D):
+    """Scale a recorded sector-dimension profile (list of [(qn, dim)] per
+    bond, e.g. from a short low-D run) to bond dimension D: every sector
+    keeps its share of the bond, capped by the largest possible dimension
+    (the smaller Fock count of the two sides), then made consistent."""
+    target = tuple(target)
+    out = []
+    for i, b in enumerate(bonds_small):
+        tot = sum(m for _, m in b)
+        nb = {}
+        for Q, m in b:
+            right = (target[0] - Q[0], target[1] - Q[1])
+            cap = min(_count_left(i, Q, spinful), _count_left(n_sites - i, right, spinful))
+            nb[tuple(Q)] = max(1, min(cap, int(round(m * D / max(tot, 1)))))
+        # trim to D (largest first keeps the shape)
+        while sum(nb.values()) > D:
+            Q = max(nb, key=lambda q: (nb[q], q))
+            nb[Q] -= 1
+            if nb[Q] == 0:
+                del nb[Q]
+        out.append(nb)
+    return _consistent(out, n_sites, spinful)
+
+
 def random_mps(bonds, spinful, seed, center):
     """Random MPS: sites < center left-isometric, sites > center+1
     right-isometric, sites center and center+1 random Gaussian.
