@@ -305,7 +305,9 @@ def decimate(mps, l, x, D, direction, tie_tol=1e-10):
     lam_all = np.array([-e[0] for e in evals])
     lam_keep = np.array([-e[0] for e in keep])
     trunc = max(0.0, 1.0 - lam_keep.sum())
-    p = lam_all[lam_all > 1e-300]
+    # entropies over the numerical rank: eigenvalues at the rounding level
+    # (|lambda| <~ 1e-16) would enter sqrt() as ~1e-8 noise
+    p = lam_all[lam_all > 1e-14]
     s_vn = float(-(p * np.log(p)).sum())
     s_half = float(2.0 * np.log(np.sqrt(p).sum()))
     count = {}

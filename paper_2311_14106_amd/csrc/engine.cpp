@@ -1449,7 +1449,7 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
   for (size_t i = 0; i < cand.size(); ++i) {
     const double p = std::max(0.0, cand[i].lam);
     if (int(i) < keep) kept += p;
-    if (p > 1e-300) {
+    if (p > 1e-14) {  // numerical rank: rounding-level eigenvalues excluded
       sv -= p * std::log(p);
       sh += std::sqrt(p);
     }
