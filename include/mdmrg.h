@@ -142,7 +142,10 @@ int mdmrg_prepare_bond(mdmrg_ctx ctx, int l);
 int mdmrg_psi_layout(mdmrg_ctx ctx, int64_t *n_elem, int32_t *n_blk, int32_t *desc);
 
 /* y = H_eff x at the current bond (x, y: caller-owned device buffers of
- * n_elem doubles, must not alias).  prec MDMRG_FP64 is the plain form. */
+ * n_elem doubles, must not alias).  prec MDMRG_FP64 is the plain form;
+ * MDMRG_FP32 (split form) runs every GEMM on FP32 shadows of the operators
+ * and of x with FP32 MFMA accumulation, y returned in FP64; MDMRG_BF16X3
+ * returns EUNSUP in this build. */
 int mdmrg_heff_apply(mdmrg_ctx ctx, int prec, const double *x, double *y);
 
 /* Diagonal of H_eff at the current bond into device buffer d. */
@@ -164,6 +167,15 @@ int mdmrg_heff_cost(mdmrg_ctx ctx, double *flop, double *bytes, int64_t *n_terms
  * *energy / x.  m_max: subspace size before a thick restart to 2 vectors. */
 int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max,
                    double *energy, double *resid, int *n_matvec);
+
+/* Mixed-precision Davidson: a Davidson solve whose products use the split
+ * form prec_split (MDMRG_FP32) until its residual reaches tol_split or
+ * stops decreasing (noise floor of the split operator), then an FP64
+ * Davidson from that vector until the FP64 residual <= tol.  *n_mv64 and
+ * *n_mv_split count the products of each kind. */
+int mdmrg_davidson_mixed(mdmrg_ctx ctx, double *x, double tol, int prec_split, double tol_split,
+                         int max_iter, int m_max, double *energy, double *resid, int *n_mv64,
+                         int *n_mv_split);
 
 /* Reduced-density-matrix truncation of the two-site vector x (Diag_D):
  * direction +1 replaces site l by a left isometry and bond l+1 by the kept
@@ -194,13 +206,30 @@ int mdmrg_stvec(mdmrg_ctx ctx, const double *x_old, double *x_new);
 int mdmrg_sweep(mdmrg_ctx ctx, int n_sweeps, const int *D_schedule, int n_sched, double tol,
                 double *energies);
 
+/* The grouped sector-block GEMM that carries every dense contraction of the
+ * path (H_eff products, renormalisation, density matrices), exposed for
+ * direct use.  For each output o (8 int64 per output:
+ * slot, offset, m, n, ldc, seg_begin, seg_count, accumulate):
+ *   C_o = (accumulate ? C_o : 0) + sum_{s in segments of o} alpha[s] op(A_s) op(B_s)
+ * with segment s given by 8 int64: a_slot, a_offset, lda, b_slot, b_offset,
+ * ldb, k, flags (1 = A transposed, 2 = B transposed, 4 = A is the identity).
+ * All matrices are FP64 row-major inside caller-owned device buffers
+ * bases[0..n_bases-1] (n_bases <= 8) of base_len[i] doubles; offsets are in
+ * elements.  Every access range is checked on the host first (EINVAL).
+ * Outputs must not overlap each other or any operand of the call. */
+int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, const int64_t *base_len,
+                       int64_t n_out, const int64_t *out_desc, int64_t n_seg, const int64_t *seg_desc,
+                       const double *alpha);
+
 /* Wall seconds per step category (Diag_H, Ren, Tables, Diag_D, StVec,
  * Other) accumulated since creation, the algorithmic FLOP of all H_eff
  * products, and HIP-event timings of the grouped-GEMM launches on the
- * context stream; out must hold 14 doubles:
+ * context stream; out must hold 19 doubles:
  * [diag_h, ren, tables, diag_d, stvec, other, heff_flop, n_matvec,
  *  heff_gemm_ms, heff_gemm_launches, heff_gemm_flop,
- *  ren_gemm_ms, ren_gemm_launches, ren_gemm_flop]. */
+ *  ren_gemm_ms, ren_gemm_launches, ren_gemm_flop,
+ *  heff_flop_split, n_matvec_split,
+ *  split_gemm_ms, split_gemm_launches, split_gemm_flop]. */
 int mdmrg_get_stats(mdmrg_ctx ctx, double *out);
 
 #ifdef __cplusplus

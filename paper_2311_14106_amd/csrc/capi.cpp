@@ -214,8 +214,9 @@ int mdmrg_psi_layout(mdmrg_ctx ctx, int64_t *n_elem, int32_t *n_blk, int32_t *de
 int mdmrg_heff_apply(mdmrg_ctx ctx, int prec, const double *x, double *y) {
   if (!ctx || !x || !y || x == y) return MDMRG_EINVAL;
   return guarded(ctx, [&] {
-    MDMRG_REQUIRE(prec == MDMRG_FP64, MDMRG_EUNSUP, "heff_apply: only the FP64 form is built");
-    ctx->c.heff_apply(x, y);
+    MDMRG_REQUIRE(prec == MDMRG_FP64 || prec == MDMRG_FP32, MDMRG_EUNSUP,
+                  "heff_apply: precision form not built (FP64 and FP32 are)");
+    ctx->c.heff_apply(x, y, prec);
     dev_sync(ctx->c.dev);
     return MDMRG_OK;
   });
@@ -244,6 +245,15 @@ int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max
                    int *n_matvec) {
   if (!ctx || !x || !(tol > 0) || max_iter < 1) return MDMRG_EINVAL;
   return guarded(ctx, [&] { return ctx->c.davidson(x, tol, max_iter, m_max, energy, resid, n_matvec); });
+}
+
+int mdmrg_davidson_mixed(mdmrg_ctx ctx, double *x, double tol, int prec_split, double tol_split, int max_iter,
+                         int m_max, double *energy, double *resid, int *n_mv64, int *n_mv_split) {
+  if (!ctx || !x || !(tol > 0) || !(tol_split > 0) || max_iter < 1) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    return ctx->c.davidson_mixed(x, tol, prec_split, tol_split, max_iter, m_max, energy, resid, n_mv64,
+                                 n_mv_split);
+  });
 }
 
 int mdmrg_decimate(mdmrg_ctx ctx, const double *x, int D, int direction, double *trunc_err, double *s_vn,
@@ -282,6 +292,76 @@ int mdmrg_sweep(mdmrg_ctx ctx, int n_sweeps, const int *D_schedule, int n_sched,
   });
 }
 
+int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, const int64_t *base_len,
+                       int64_t n_out, const int64_t *out_desc, int64_t n_seg, const int64_t *seg_desc,
+                       const double *alpha) {
+  if (!ctx || n_bases < 1 || n_bases > kSlots || !bases || !base_len || n_out < 0 || n_seg < 0 ||
+      (n_out && !out_desc) || (n_seg && (!seg_desc || !alpha)))
+    return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    GemmPlan plan;
+    auto in_range = [&](int slot, int64_t off, int64_t last) {
+      return slot >= 0 && slot < n_bases && off >= 0 && last >= 0 && off + last < base_len[slot];
+    };
+    for (int64_t e = 0; e < n_seg; ++e) {
+      const int64_t *d = seg_desc + 8 * e;
+      GSeg g{};
+      g.a_slot = uint8_t(d[0]);
+      g.a_off = d[1];
+      g.lda = int32_t(d[2]);
+      g.b_slot = uint8_t(d[3]);
+      g.b_off = d[4];
+      g.ldb = int32_t(d[5]);
+      g.k = int32_t(d[6]);
+      g.flags = uint8_t(d[7] & 7);
+      g.alpha = alpha[e];
+      MDMRG_REQUIRE(d[6] >= 0 && d[6] < (int64_t(1) << 31) && d[2] >= 0 && d[5] >= 0 && d[0] < kSlots &&
+                        d[3] < kSlots && d[0] >= 0 && d[3] >= 0,
+                    MDMRG_EINVAL, "gemm_grouped: bad segment descriptor");
+      plan.segs.push_back(g);
+    }
+    for (int64_t o = 0; o < n_out; ++o) {
+      const int64_t *d = out_desc + 8 * o;
+      GOut g{};
+      g.c_slot = uint8_t(d[0]);
+      g.c_off = d[1];
+      g.m = int32_t(d[2]);
+      g.n = int32_t(d[3]);
+      g.ldc = int32_t(d[4]);
+      g.seg_begin = int32_t(d[5]);
+      g.seg_count = int32_t(d[6]);
+      g.accumulate = uint8_t(d[7] != 0);
+      MDMRG_REQUIRE(d[2] >= 1 && d[3] >= 1 && d[4] >= d[3] && d[2] < (1 << 20) && d[3] < (1 << 20) &&
+                        d[5] >= 0 && d[6] >= 0 && d[5] + d[6] <= n_seg,
+                    MDMRG_EINVAL, "gemm_grouped: bad output descriptor");
+      MDMRG_REQUIRE(in_range(int(d[0]), d[1], (d[2] - 1) * d[4] + d[3] - 1), MDMRG_EINVAL,
+                    "gemm_grouped: output block outside its buffer");
+      for (int64_t q = d[5]; q < d[5] + d[6]; ++q) {
+        const GSeg &sg = plan.segs[q];
+        const int64_t m = d[2], n = d[3], k = sg.k;
+        if (k == 0) continue;
+        if (!(sg.flags & SEG_AID)) {
+          const int64_t last = (sg.flags & SEG_TA) ? (k - 1) * sg.lda + m - 1 : (m - 1) * sg.lda + k - 1;
+          MDMRG_REQUIRE(in_range(sg.a_slot, sg.a_off, last) && sg.lda >= ((sg.flags & SEG_TA) ? m : k),
+                        MDMRG_EINVAL, "gemm_grouped: A operand outside its buffer");
+        }
+        const int64_t lastb = (sg.flags & SEG_TB) ? (n - 1) * sg.ldb + k - 1 : (k - 1) * sg.ldb + n - 1;
+        MDMRG_REQUIRE(in_range(sg.b_slot, sg.b_off, lastb) && sg.ldb >= ((sg.flags & SEG_TB) ? k : n),
+                      MDMRG_EINVAL, "gemm_grouped: B operand outside its buffer");
+        if (!(sg.flags & SEG_AID)) plan.flop += 2.0 * m * n * k;
+      }
+      plan.outs.push_back(g);
+    }
+    Bases b{};
+    for (int i = 0; i < kSlots; ++i) b.p[i] = const_cast<double *>(bases[i < n_bases ? i : 0]);
+    DevPlan *dp = dev_plan_upload(ctx->c.dev, plan);
+    dev_gemm_run(ctx->c.dev, dp, b, 3);
+    dev_plan_free(ctx->c.dev, dp);
+    dev_sync(ctx->c.dev);
+    return MDMRG_OK;
+  });
+}
+
 int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
   if (!ctx || !out) return MDMRG_EINVAL;
   const Stats &s = ctx->c.stats;
@@ -302,6 +382,11 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
     out[11] = ms[2];
     out[12] = ln[2];
     out[13] = fl[2];
+    out[14] = s.heff_flop_split;
+    out[15] = s.n_matvec_split;
+    out[16] = ms[4];
+    out[17] = ln[4];
+    out[18] = fl[4];
     return MDMRG_OK;
   });
 }

@@ -175,32 +175,59 @@ void dev_zero(Device *d, void *dst, size_t bytes) {
 // quadrant as 2x2 MFMA 16x16x4 accumulators.  K is staged through LDS in
 // steps of 16.  Operand layout of v_mfma_f64_16x16x4f64: lane l supplies
 // A[l%16][l/16] and B[l/16][l%16]; accumulator element r of lane l is
-// C[l/16 + 4r][l%16] (checked against a host reference on gfx950).
+// C[l/16 + 4r][l%16] for FP64 and C[4(l/16) + r][l%16] for FP32.
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int TM = 64, TN = 64, TK = 16, LDP = TM + 2;
 
-__global__ __launch_bounds__(256) void k_gemm_f64(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
-                                                  const GSeg *__restrict__ segs, Bases bases) {
-  __shared__ double As[TK][LDP];
-  __shared__ double Bs[TK][LDP];
+// one MFMA 16x16x4 step in the element type of the kernel: FP64
+// (v_mfma_f64_16x16x4f64) or FP32 (v_mfma_f32_16x16x4f32), same operand
+// layout
+template <class T>
+struct Mfma;
+// accumulator element r of lane l holds C[row(l/16, r)][l%16]; the FP64 and
+// FP32 instructions differ (both checked on gfx950 against host references)
+template <>
+struct Mfma<double> {
+  typedef v4d acc_t;
+  static __device__ inline int row(int lk, int r) { return lk + 4 * r; }
+  static __device__ inline acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef v4f acc_t;
+  static __device__ inline int row(int lk, int r) { return 4 * lk + r; }
+  static __device__ inline acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <class T>
+__global__ __launch_bounds__(256) void k_gemm(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
+                                              const GSeg *__restrict__ segs, Bases bases) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T As[TK][LDP];
+  __shared__ T Bs[TK][LDP];
   const GTile tl = tiles[blockIdx.x];
   const GOut o = outs[tl.out];
   const int row0 = int(tl.ti) * TM, col0 = int(tl.tj) * TN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
-  v4d acc[2][2];
+  acc_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   for (int si = 0; si < o.seg_count; ++si) {
     const GSeg sg = segs[o.seg_begin + si];
-    const double *A = bases.p[sg.a_slot] + sg.a_off;
-    const double *B = bases.p[sg.b_slot] + sg.b_off;
+    const T *A = reinterpret_cast<const T *>(bases.p[sg.a_slot]) + sg.a_off;
+    const T *B = reinterpret_cast<const T *>(bases.p[sg.b_slot]) + sg.b_off;
     const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB, idA = sg.flags & SEG_AID;
-    const double alpha = sg.alpha;
+    const T alpha = T(sg.alpha);
     for (int k0 = 0; k0 < sg.k; k0 += TK) {
       // stage op(A)[row0 + i][k0 + kk] (scaled by alpha)
 #pragma unroll
@@ -215,10 +242,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GTile *__restrict__ tile
           i = e % TM;
         }
         const int gi = row0 + i, gk = k0 + kk;
-        double v = 0.0;
+        T v = T(0);
         if (gi < o.m && gk < sg.k) {
           if (idA)
-            v = (gi == gk) ? alpha : 0.0;
+            v = (gi == gk) ? alpha : T(0);
           else
             v = alpha * (tA ? A[(int64_t)gk * sg.lda + gi] : A[(int64_t)gi * sg.lda + gk]);
         }
@@ -237,40 +264,130 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GTile *__restrict__ tile
           kk = e % TK;
         }
         const int gj = col0 + j, gk = k0 + kk;
-        double v = 0.0;
+        T v = T(0);
         if (gj < o.n && gk < sg.k) v = tB ? B[(int64_t)gj * sg.ldb + gk] : B[(int64_t)gk * sg.ldb + gj];
         Bs[kk][j] = v;
       }
       __syncthreads();
 #pragma unroll
       for (int kk = 0; kk < TK; kk += 4) {
-        double a0 = As[kk + lk][wm + lr];
-        double a1 = As[kk + lk][wm + 16 + lr];
-        double b0 = Bs[kk + lk][wn + lr];
-        double b1 = Bs[kk + lk][wn + 16 + lr];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        const T a0 = As[kk + lk][wm + lr];
+        const T a1 = As[kk + lk][wm + 16 + lr];
+        const T b0 = Bs[kk + lk][wn + lr];
+        const T b1 = Bs[kk + lk][wn + 16 + lr];
+        acc[0][0] = Mfma<T>::step(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<T>::step(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<T>::step(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<T>::step(a1, b1, acc[1][1]);
       }
       __syncthreads();
     }
   }
-  double *C = bases.p[o.c_slot] + o.c_off;
+  T *C = reinterpret_cast<T *>(bases.p[o.c_slot]) + o.c_off;
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gi = row0 + wm + mi * 16 + lk + 4 * r;
+        const int gi = row0 + wm + mi * 16 + Mfma<T>::row(lk, r);
         const int gj = col0 + wn + ni * 16 + lr;
         if (gi < o.m && gj < o.n) {
-          double *p = C + (int64_t)gi * o.ldc + gj;
-          const double v = acc[mi][ni][r];
+          T *p = C + (int64_t)gi * o.ldc + gj;
+          const T v = acc[mi][ni][r];
           *p = o.accumulate ? (*p + v) : v;
         }
       }
+}
+
+// Wave-tile variant for small sector blocks: each wave owns an independent
+// 32x32 output tile (2x2 MFMA 16x16x4; the second row / column of MFMA
+// blocks is skipped when the tile has <= 16 rows / columns).  Fragments are
+// loaded straight from global memory (K unrolled by 16), no LDS, no
+// workgroup barrier, so four unrelated small tiles share one workgroup.
+constexpr int WT = 32;
+template <class T>
+__global__ __launch_bounds__(256) void k_gemm_wave(const GTile *__restrict__ tiles, int64_t n_tiles,
+                                                   const GOut *__restrict__ outs,
+                                                   const GSeg *__restrict__ segs, Bases bases) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t t = int64_t(blockIdx.x) * 4 + wave;
+  if (t >= n_tiles) return;  // wave-uniform exit; the kernel has no barrier
+  const GTile tl = tiles[t];
+  const GOut o = outs[tl.out];
+  const int row0 = int(tl.ti) * WT, col0 = int(tl.tj) * WT;
+  const int lr = lane & 15, lk = lane >> 4;
+  const bool m2 = (o.m - row0) > 16, n2 = (o.n - col0) > 16;  // wave-uniform
+  const int gi0 = row0 + lr, gi1 = row0 + 16 + lr, gj0 = col0 + lr, gj1 = col0 + 16 + lr;
+  const bool vi0 = gi0 < o.m, vi1 = m2 && gi1 < o.m, vj0 = gj0 < o.n, vj1 = n2 && gj1 < o.n;
+  acc_t acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  for (int si = 0; si < o.seg_count; ++si) {
+    const GSeg sg = segs[o.seg_begin + si];
+    const T *A = reinterpret_cast<const T *>(bases.p[sg.a_slot]) + sg.a_off;
+    const T *B = reinterpret_cast<const T *>(bases.p[sg.b_slot]) + sg.b_off;
+    const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB, idA = sg.flags & SEG_AID;
+    const T alpha = T(sg.alpha);
+    const int64_t lda = sg.lda, ldb = sg.ldb;
+    for (int k0 = 0; k0 < sg.k; k0 += 16) {
+      T a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gk = k0 + 4 * u + lk;
+        const bool vk = gk < sg.k;
+        T x0 = T(0), x1 = T(0), y0 = T(0), y1 = T(0);
+        if (vk) {
+          if (idA) {
+            x0 = (vi0 && gi0 == gk) ? T(1) : T(0);
+            x1 = (vi1 && gi1 == gk) ? T(1) : T(0);
+          } else if (tA) {
+            if (vi0) x0 = A[gk * lda + gi0];
+            if (vi1) x1 = A[gk * lda + gi1];
+          } else {
+            if (vi0) x0 = A[gi0 * lda + gk];
+            if (vi1) x1 = A[gi1 * lda + gk];
+          }
+          if (tB) {
+            if (vj0) y0 = B[gj0 * ldb + gk];
+            if (vj1) y1 = B[gj1 * ldb + gk];
+          } else {
+            if (vj0) y0 = B[gk * ldb + gj0];
+            if (vj1) y1 = B[gk * ldb + gj1];
+          }
+        }
+        a0[u] = alpha * x0;
+        a1[u] = alpha * x1;
+        b0[u] = y0;
+        b1[u] = y1;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc00 = Mfma<T>::step(a0[u], b0[u], acc00);
+        if (n2) acc01 = Mfma<T>::step(a0[u], b1[u], acc01);
+        if (m2) {
+          acc10 = Mfma<T>::step(a1[u], b0[u], acc10);
+          if (n2) acc11 = Mfma<T>::step(a1[u], b1[u], acc11);
+        }
+      }
+    }
+  }
+  T *C = reinterpret_cast<T *>(bases.p[o.c_slot]) + o.c_off;
+  const acc_t *accs[4] = {&acc00, &acc01, &acc10, &acc11};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int mi = q >> 1, ni = q & 1;
+    if ((mi && !m2) || (ni && !n2)) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gi = row0 + mi * 16 + Mfma<T>::row(lk, r);
+      const int gj = col0 + ni * 16 + lr;
+      if (gi < o.m && gj < o.n) {
+        T *pc = C + (int64_t)gi * o.ldc + gj;
+        const T v = (*accs[q])[r];
+        *pc = o.accumulate ? (*pc + v) : v;
+      }
+    }
+  }
 }
 
 DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
@@ -287,13 +404,24 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
     work[i] = {-(kk + 16.0) * o.m * o.n, int32_t(i)};
   }
   std::stable_sort(work.begin(), work.end());
-  std::vector<GTile> tiles;
+  // outputs with both sides >= 48 use 64x64 workgroup tiles, the rest
+  // 32x32 wave tiles
+  std::vector<GTile> tiles, small;
   for (auto &w : work) {
     const GOut &o = plan.outs[w.second];
-    const int nti = (o.m + TM - 1) / TM, ntj = (o.n + TN - 1) / TN;
-    for (int i = 0; i < nti; ++i)
-      for (int j = 0; j < ntj; ++j) tiles.push_back(GTile{w.second, int16_t(i), int16_t(j)});
+    if (o.m >= 48 && o.n >= 48) {
+      const int nti = (o.m + TM - 1) / TM, ntj = (o.n + TN - 1) / TN;
+      for (int i = 0; i < nti; ++i)
+        for (int j = 0; j < ntj; ++j) tiles.push_back(GTile{w.second, int16_t(i), int16_t(j)});
+    } else {
+      const int nti = (o.m + WT - 1) / WT, ntj = (o.n + WT - 1) / WT;
+      for (int i = 0; i < nti; ++i)
+        for (int j = 0; j < ntj; ++j) small.push_back(GTile{w.second, int16_t(i), int16_t(j)});
+    }
   }
+  dp->n_big = int64_t(tiles.size());
+  dp->n_small = int64_t(small.size());
+  tiles.insert(tiles.end(), small.begin(), small.end());
   MDMRG_REQUIRE(tiles.size() < (size_t(1) << 31), -6, "grouped GEMM plan has too many tiles");
   dp->n_tiles = int64_t(tiles.size());
   if (dp->n_tiles) {
@@ -315,7 +443,7 @@ void dev_plan_free(Device *d, DevPlan *p) {
   delete p;
 }
 
-void dev_gemm_run(Device *d, const DevPlan *p, const Bases &b, int tag) {
+void dev_gemm_run(Device *d, const DevPlan *p, const Bases &b, int tag, int prec) {
   if (!p || p->n_tiles == 0) return;
   const bool timed = d->timing && tag > 0 && tag < kTags;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -325,13 +453,48 @@ void dev_gemm_run(Device *d, const DevPlan *p, const Bases &b, int tag) {
     e1 = ev_get(d);
     HIP_CHECK(hipEventRecord(e0, d->stream));
   }
-  hipLaunchKernelGGL(k_gemm_f64, dim3(unsigned(p->n_tiles)), dim3(256), 0, d->stream, p->tiles, p->outs, p->segs,
-                     b);
+  if (prec == 0) {
+    if (p->n_big)
+      hipLaunchKernelGGL(k_gemm<double>, dim3(unsigned(p->n_big)), dim3(256), 0, d->stream, p->tiles, p->outs,
+                         p->segs, b);
+    if (p->n_small)
+      hipLaunchKernelGGL(k_gemm_wave<double>, dim3(unsigned((p->n_small + 3) / 4)), dim3(256), 0, d->stream,
+                         p->tiles + p->n_big, p->n_small, p->outs, p->segs, b);
+  } else {
+    if (p->n_big)
+      hipLaunchKernelGGL(k_gemm<float>, dim3(unsigned(p->n_big)), dim3(256), 0, d->stream, p->tiles, p->outs,
+                         p->segs, b);
+    if (p->n_small)
+      hipLaunchKernelGGL(k_gemm_wave<float>, dim3(unsigned((p->n_small + 3) / 4)), dim3(256), 0, d->stream,
+                         p->tiles + p->n_big, p->n_small, p->outs, p->segs, b);
+  }
   HIP_CHECK(hipGetLastError());
   if (timed) {
     HIP_CHECK(hipEventRecord(e1, d->stream));
     d->pending.push_back(Device::Pending{tag, e0, e1, p->flop});
   }
+}
+
+// --------------------------------------------------------- precision casts
+__global__ void k_d2f(const double *__restrict__ x, float *__restrict__ y, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    y[k] = float(x[k]);
+}
+__global__ void k_f2d(const float *__restrict__ x, double *__restrict__ y, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    y[k] = double(x[k]);
+}
+void dev_d2f(Device *d, const double *x, float *y, int64_t n) {
+  int grid = int(std::min<int64_t>((n + 255) / 256, 8192));
+  if (grid < 1) return;
+  hipLaunchKernelGGL(k_d2f, dim3(grid), dim3(256), 0, d->stream, x, y, n);
+  HIP_CHECK(hipGetLastError());
+}
+void dev_f2d(Device *d, const float *x, double *y, int64_t n) {
+  int grid = int(std::min<int64_t>((n + 255) / 256, 8192));
+  if (grid < 1) return;
+  hipLaunchKernelGGL(k_f2d, dim3(grid), dim3(256), 0, d->stream, x, y, n);
+  HIP_CHECK(hipGetLastError());
 }
 
 // ------------------------------------------------------- diagonal of H_eff

@@ -445,11 +445,11 @@ void Context::ensure_scratch(int64_t n) {
   T_scratch_n = n;
 }
 
-void Context::run_plan(const TwoPhasePlan &p, Bases &b, int tag) {
+void Context::run_plan(const TwoPhasePlan &p, Bases &b, int tag, int prec) {
   b.p[2] = T_scratch;
   for (auto &c : p.chunks) {
-    if (c.p1) dev_gemm_run(dev, c.p1, b, tag);
-    if (c.p2) dev_gemm_run(dev, c.p2, b, tag);
+    if (c.p1) dev_gemm_run(dev, c.p1, b, tag, prec);
+    if (c.p2) dev_gemm_run(dev, c.p2, b, tag, prec);
   }
 }
 
@@ -812,6 +812,10 @@ PsiLayout Context::make_layout(int l) const {
 
 // ------------------------------------------------------------- prepare
 void Context::release_bond() {
+  for (float **p : {&L32, &R32, &Lx32, &Rx32, &x32, &y32}) {
+    if (*p) dev_free(dev, *p);
+    *p = nullptr;
+  }
   heff.release(dev);
   if (diag) dev_diag_free(dev, diag);
   diag = nullptr;
@@ -1072,8 +1076,43 @@ void Context::build_heff(int l) {
   stats.t_tables += wall_seconds() - t0;
 }
 
-void Context::heff_apply(const double *x, double *y) {
+void Context::ensure_fp32() {
+  if (x32) return;
+  auto shadow = [&](const OpSet *S) -> float * {
+    if (!S || !S->arena) return nullptr;
+    float *f = (float *)dev_alloc(dev, sizeof(float) * std::max<int64_t>(1, S->arena_size));
+    dev_d2f(dev, S->arena, f, S->arena_size);
+    return f;
+  };
+  L32 = shadow(Lenv[cur].get());
+  R32 = shadow(Renv[cur + 2].get());
+  Lx32 = shadow(Lx.get());
+  Rx32 = shadow(Rx.get());
+  x32 = (float *)dev_alloc(dev, sizeof(float) * std::max<int64_t>(1, psi.n_elem));
+  y32 = (float *)dev_alloc(dev, sizeof(float) * std::max<int64_t>(1, psi.n_elem));
+}
+
+void Context::heff_apply(const double *x, double *y, int prec) {
   MDMRG_REQUIRE(cur >= 0, -4, "heff_apply: no current bond");
+  MDMRG_REQUIRE(prec == 0 || prec == 1, -6, "heff_apply: precision form not built");
+  if (prec == 1) {
+    ensure_fp32();
+    dev_d2f(dev, x, x32, psi.n_elem);
+    dev_zero(dev, y32, sizeof(float) * psi.n_elem);
+    Bases b{};
+    b.p[0] = reinterpret_cast<double *>(x32);
+    b.p[1] = reinterpret_cast<double *>(y32);
+    b.p[3] = reinterpret_cast<double *>(L32);
+    b.p[4] = reinterpret_cast<double *>(R32);
+    b.p[5] = Lx32 ? reinterpret_cast<double *>(Lx32) : b.p[3];
+    b.p[6] = Rx32 ? reinterpret_cast<double *>(Rx32) : b.p[4];
+    b.p[7] = b.p[1];
+    run_plan(heff, b, 4, 1);
+    dev_f2d(dev, y32, y, psi.n_elem);
+    stats.heff_flop_split += heff.flop;
+    stats.n_matvec_split += 1;
+    return;
+  }
   dev_zero(dev, y, sizeof(double) * psi.n_elem);
   Bases b{};
   b.p[0] = const_cast<double *>(x);
@@ -1150,7 +1189,7 @@ static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w, std
 }
 
 int Context::davidson(double *x, double tol, int max_iter, int m_max, double *energy, double *resid,
-                      int *n_mv) {
+                      int *n_mv, int prec, bool stall) {
   MDMRG_REQUIRE(cur >= 0, -4, "davidson: no current bond");
   MDMRG_REQUIRE(m_max >= 3 && m_max <= 60, -1, "davidson: m_max must be in [3, 60]");
   const int64_t N = psi.n_elem;
@@ -1171,8 +1210,10 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
   MDMRG_REQUIRE(std::isfinite(nrm), -3, "davidson: start vector is not finite");
   dev_d2d(dev, V, x, sizeof(double) * N);
   dev_scale(dev, 1.0 / std::sqrt(nrm), V, N);
-  heff_apply(V, AV);
+  heff_apply(V, AV, prec);
   int nmv = 1, nv = 1;
+  double best_r = 1e300;
+  int best_at = 0;
   std::vector<double> Hs(size_t(m_max) * m_max, 0.0);
   {
     double h;
@@ -1202,6 +1243,16 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
     if (nmv >= max_iter) {
       status = -5;
       break;
+    }
+    if (stall) {
+      // the split-precision operator has a noise floor: stop once the
+      // residual has not halved over the last 16 products
+      if (rn < 0.5 * best_r) {
+        best_r = rn;
+        best_at = nmv;
+      } else if (nmv - best_at >= 16) {
+        break;
+      }
     }
     if (nv == m_max) {
       // thick restart to the two lowest Ritz vectors
@@ -1253,7 +1304,7 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
       if (!(tn > 1e-28)) break;
     }
     dev_scale(dev, 1.0 / std::sqrt(tn), t, N);
-    heff_apply(t, AV + int64_t(nv) * N);
+    heff_apply(t, AV + int64_t(nv) * N, prec);
     ++nmv;
     std::vector<double> col(nv + 1);
     dev_multidot(dev, V, N, nv + 1, AV + int64_t(nv) * N, N, col.data());
@@ -1278,6 +1329,20 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
   if (n_mv) *n_mv = nmv;
   stats.t_diag_h += wall_seconds() - t0;
   return status;
+}
+
+int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_split, int max_iter, int m_max,
+                            double *energy, double *resid, int *n_mv64, int *n_mv_split) {
+  MDMRG_REQUIRE(prec_split == 1, -6, "davidson_mixed: only the FP32 split form is built");
+  double e = 0.0, r = 0.0;
+  int ns = 0, n64 = 0;
+  davidson(x, std::max(tol, tol_split), max_iter, m_max, &e, &r, &ns, prec_split, true);
+  const int st = davidson(x, tol, max_iter, m_max, &e, &r, &n64, 0, false);
+  if (energy) *energy = e;
+  if (resid) *resid = r;
+  if (n_mv64) *n_mv64 = n64;
+  if (n_mv_split) *n_mv_split = ns;
+  return st;
 }
 
 // ------------------------------------------------------------- decimation

@@ -135,6 +135,7 @@ struct PsiLayout {
 struct Stats {
   double t_diag_h = 0, t_ren = 0, t_tables = 0, t_diag_d = 0, t_stvec = 0, t_other = 0;
   double heff_flop = 0, n_matvec = 0;
+  double heff_flop_split = 0, n_matvec_split = 0;
 };
 
 // ------------------------------------------------------------- context
@@ -168,9 +169,18 @@ struct Context {
   std::unique_ptr<OpSet> renorm_right(const OpSet &R, int site);  // R(bond site+1) -> R(bond site)
   void prepare(int l);
   void build_heff(int l);
-  void heff_apply(const double *x, double *y);
+  void heff_apply(const double *x, double *y, int prec = 0);
   void heff_diag(double *d);
-  int davidson(double *x, double tol, int max_iter, int m_max, double *energy, double *resid, int *n_mv);
+  // prec: matrix-vector precision (0 FP64, 1 FP32 split form); stall: stop
+  // when the residual stops decreasing (used for the split-precision phase)
+  int davidson(double *x, double tol, int max_iter, int m_max, double *energy, double *resid, int *n_mv,
+               int prec = 0, bool stall = false);
+  // split-precision Davidson to tol_split, then FP64 Davidson to tol
+  int davidson_mixed(double *x, double tol, int prec_split, double tol_split, int max_iter, int m_max,
+                     double *energy, double *resid, int *n_mv64, int *n_mv_split);
+  // FP32 shadows of the current bond's operators and vectors
+  float *L32 = nullptr, *R32 = nullptr, *Lx32 = nullptr, *Rx32 = nullptr, *x32 = nullptr, *y32 = nullptr;
+  void ensure_fp32();
   void decimate(const double *x, int D, int dir, double *trunc, double *svn, double *shalf);
   void stvec(const double *x_old, int l_old, int dir, const PsiLayout &old_layout, double *x_new,
              const PsiLayout &new_layout);
@@ -182,7 +192,7 @@ struct Context {
   PsiLayout make_layout(int l) const;
   void sweep(int n_sweeps, const int *D, int n_sched, double tol, double *energies);
   void ensure_scratch(int64_t n);
-  void run_plan(const TwoPhasePlan &p, Bases &b, int tag = 0);
+  void run_plan(const TwoPhasePlan &p, Bases &b, int tag = 0, int prec = 0);
 };
 
 }  // namespace mdmrg

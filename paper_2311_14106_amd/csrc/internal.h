@@ -123,11 +123,17 @@ struct DevPlan {
   GOut *outs = nullptr;
   GTile *tiles = nullptr;
   int64_t n_tiles = 0, n_outs = 0, n_segs = 0;
+  int64_t n_big = 0, n_small = 0;  // 64x64 workgroup tiles first, then 32x32 wave tiles
   double flop = 0.0;
 };
 DevPlan *dev_plan_upload(Device *, const GemmPlan &);
 void dev_plan_free(Device *, DevPlan *);
-void dev_gemm_run(Device *, const DevPlan *, const Bases &, int tag = 0);
+// prec 0: FP64 operands and results; prec 1: FP32 operands, FP32 MFMA
+// accumulation and FP32 results (base pointers then address float arrays
+// with the same element offsets)
+void dev_gemm_run(Device *, const DevPlan *, const Bases &, int tag = 0, int prec = 0);
+void dev_d2f(Device *, const double *x, float *y, int64_t n);
+void dev_f2d(Device *, const float *x, double *y, int64_t n);
 // HIP-event timing of tagged grouped-GEMM launches (tag 1..7): elapsed
 // milliseconds, launch count and algorithmic FLOP per tag since creation.
 constexpr int kTags = 8;

@@ -46,12 +46,18 @@ EXPORTS = {
     'mdmrg_heff_cost': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_i64_p, _c_i64_p]),
     'mdmrg_davidson': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
                                       ctypes.c_int, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_int)]),
+    'mdmrg_davidson_mixed': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_double, ctypes.c_int, ctypes.c_int, _c_dbl_p, _c_dbl_p,
+                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     'mdmrg_decimate': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                       _c_dbl_p, _c_dbl_p, _c_dbl_p]),
     'mdmrg_renormalize': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     'mdmrg_stvec': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     'mdmrg_sweep': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i32_p, ctypes.c_int, ctypes.c_double,
                                    _c_dbl_p]),
+    'mdmrg_gemm_grouped': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                          _c_i64_p, ctypes.c_int64, _c_i64_p, ctypes.c_int64, _c_i64_p,
+                                          _c_dbl_p]),
     'mdmrg_get_stats': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p]),
 }
 
@@ -221,6 +227,14 @@ class Context:
                                                ctypes.byref(r), ctypes.byref(n)), allow=(ENOCONV,))
         return e.value, r.value, n.value, st == OK
 
+    def davidson_mixed(self, x, tol=1e-8, tol_split=1e-5, prec_split=FP32, max_iter=200, m_max=24):
+        e, r = ctypes.c_double(), ctypes.c_double()
+        n64, ns = ctypes.c_int(), ctypes.c_int()
+        st = self._chk(self.lib.mdmrg_davidson_mixed(self.h, _ptr(x), tol, prec_split, tol_split, max_iter, m_max,
+                                                     ctypes.byref(e), ctypes.byref(r), ctypes.byref(n64),
+                                                     ctypes.byref(ns)), allow=(ENOCONV,))
+        return e.value, r.value, n64.value, ns.value, st == OK
+
     def decimate(self, x, D, direction):
         t, s, h = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         self._chk(self.lib.mdmrg_decimate(self.h, _ptr(x), D, direction, ctypes.byref(t), ctypes.byref(s),
@@ -239,10 +253,25 @@ class Context:
         self._chk(self.lib.mdmrg_sweep(self.h, n_sweeps, _ip(Ds), len(Ds), tol, _dp(E)))
         return E
 
+    def gemm_grouped(self, buffers, out_desc, seg_desc, alpha):
+        """buffers: list of device tensors (float64); descriptors: int64 arrays
+        of shape (n_out, 8) and (n_seg, 8); alpha: float64 (n_seg,)."""
+        nb = len(buffers)
+        ptrs = (ctypes.c_void_p * nb)(*[_ptr(b).value for b in buffers])
+        lens = np.array([b.numel() if hasattr(b, 'numel') else b.size for b in buffers], dtype=np.int64)
+        od = np.ascontiguousarray(out_desc, dtype=np.int64).reshape(-1, 8)
+        sd = np.ascontiguousarray(seg_desc, dtype=np.int64).reshape(-1, 8)
+        al = np.ascontiguousarray(alpha, dtype=np.float64)
+        self._chk(self.lib.mdmrg_gemm_grouped(self.h, nb, ptrs, lens.ctypes.data_as(_c_i64_p), len(od),
+                                              od.ctypes.data_as(_c_i64_p), len(sd),
+                                              sd.ctypes.data_as(_c_i64_p), _dp(al)))
+
     def stats(self):
-        out = np.zeros(14)
+        out = np.zeros(19)
         self._chk(self.lib.mdmrg_get_stats(self.h, _dp(out)))
         keys = ['diag_h_s', 'ren_s', 'tables_s', 'diag_d_s', 'stvec_s', 'other_s', 'heff_flop', 'n_matvec',
                 'heff_gemm_ms', 'heff_gemm_launches', 'heff_gemm_flop',
-                'ren_gemm_ms', 'ren_gemm_launches', 'ren_gemm_flop']
+                'ren_gemm_ms', 'ren_gemm_launches', 'ren_gemm_flop',
+                'heff_flop_split', 'n_matvec_split', 'split_gemm_ms', 'split_gemm_launches',
+                'split_gemm_flop']
         return dict(zip(keys, out.tolist()))

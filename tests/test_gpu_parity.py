@@ -199,3 +199,35 @@ def test_decimation_matches_oracle():
             assert abs(trunc - t2) <= 1e-12 and abs(svn - s2) <= 1e-12 and abs(shalf - h2) <= 1e-12
             if not tie:
                 assert ctx.get_bond(l + 1) == nb      # kept sector dimensions: exact
+
+
+def test_split_precision_heff_and_mixed_davidson():
+    """FP32 split form: every product error is bounded by FP32 rounding of
+    the same task list (|y32 - y| <= 1e-5 max|y|), and the mixed-precision
+    Davidson (FP32 products, then FP64 refinement) reaches the lowest FP64
+    eigenvalue of the oracle's H_eff to 1e-12 relative."""
+    mdmrg = _gpu()
+    T, W = I.hubbard_momentum(3, 3, 1.0, 4.0)
+    n, spin, target, l = 9, True, (4, 4), 3
+    ch = dmrg.Chain(T, W, n, spin, target)
+    bonds = si.bond_profile(n, spin, target, 64)
+    tens = si.random_mps(bonds, spin, 3, l)
+    prob = dmrg.TwoSiteProblem(dmrg.MPS(ch, bonds, tens), l)
+    e_ref, _ = prob.lowest(v0=si.random_vector(prob.dim, 1))
+    ctx = mdmrg.Context(0)
+    ctx.set_hamiltonian(n, spin, T, W, target)
+    ctx.set_mps(*si.flatten_mps(bonds, tens, spin))
+    ctx.prepare_bond(l)
+    _, ne = ctx.psi_layout()
+    x = si.random_vector(ne, 5)
+    y_ref = prob.matvec(x)
+    yd = torch.zeros(ne, dtype=torch.float64, device='cuda:0')
+    ctx.heff_apply(to_dev(x), yd, prec=mdmrg.FP32)
+    err = np.abs(yd.cpu().numpy() - y_ref).max() / np.abs(y_ref).max()
+    log(f'[split] FP32 H_eff rel err {err:.2e}')
+    assert 0 < err <= 1e-5
+    xd = to_dev(si.random_vector(ne, 2))
+    e, r, n64, nsp, conv = ctx.davidson_mixed(xd, tol=1e-9, tol_split=1e-5)
+    log(f'[split] mixed Davidson: FP64 products {n64}, FP32 products {nsp}, E={e:.14f}')
+    assert conv and nsp > 0 and r <= 1e-9
+    assert abs(e - e_ref) <= 1e-12 * abs(e_ref)
