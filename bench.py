@@ -146,9 +146,9 @@ def main():
     s1 = ctx.stats()
     d = {k: s1[k] - s0[k] for k in s1}
     heff_flop = d['heff_flop']
-    gemm_ms = d['heff_gemm_ms']
-    gemm_flop = d['heff_gemm_flop']
-    launches = max(1.0, d['heff_gemm_launches'])
+    gemm_ms = d['heff_gemm_ms'] + d['heff_p1_ms']
+    gemm_flop = d['heff_gemm_flop'] + d['heff_p1_flop']
+    launches = max(1.0, d['heff_gemm_launches'] + d['heff_p1_launches'])
     # algorithmic bytes of the timed products (per-bond cost x products)
     nmv_total = d['n_matvec']
     bytes_per_mv = float(np.mean([c['bytes'] for c in costs]))
@@ -166,7 +166,10 @@ def main():
     roof.update({'kernel': 'k_gemm_f64 (H_eff psi grouped sector GEMM)',
                  'launches': int(launches), 'avg_launch_ms': gemm_ms / launches,
                  'flop_per_launch': gemm_flop / launches, 'intensity_flop_per_byte': intensity,
-                 'kernel_tflops': achieved_tf})
+                 'kernel_tflops': achieved_tf,
+                 'phase1_ms': d['heff_p1_ms'], 'phase2_ms': d['heff_gemm_ms'],
+                 'phase1_tflops': d['heff_p1_flop'] / max(d['heff_p1_ms'], 1e-9) / 1e9,
+                 'phase2_tflops': d['heff_gemm_flop'] / max(d['heff_gemm_ms'], 1e-9) / 1e9})
     out = {
         'metric': 'H_eff·ψ TFLOP/s and Davidson s/step, FP64 vs split-precision at fixed ΔE',
         'value': heff_flop / wall / 1e12,

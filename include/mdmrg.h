@@ -224,12 +224,16 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
 /* Wall seconds per step category (Diag_H, Ren, Tables, Diag_D, StVec,
  * Other) accumulated since creation, the algorithmic FLOP of all H_eff
  * products, and HIP-event timings of the grouped-GEMM launches on the
- * context stream; out must hold 19 doubles:
+ * context stream; out must hold 25 doubles:
  * [diag_h, ren, tables, diag_d, stvec, other, heff_flop, n_matvec,
  *  heff_gemm_ms, heff_gemm_launches, heff_gemm_flop,
  *  ren_gemm_ms, ren_gemm_launches, ren_gemm_flop,
  *  heff_flop_split, n_matvec_split,
- *  split_gemm_ms, split_gemm_launches, split_gemm_flop]. */
+ *  split_gemm_ms, split_gemm_launches, split_gemm_flop,
+ *  heff_phase1_ms, heff_phase1_launches, heff_phase1_flop,
+ *  grouped_ms, grouped_launches, grouped_flop (mdmrg_gemm_grouped calls)].
+ * heff_gemm_* covers the accumulation (second) phase of the FP64 H_eff
+ * products and heff_phase1_* their intermediate (first) phase. */
 int mdmrg_get_stats(mdmrg_ctx ctx, double *out);
 
 #ifdef __cplusplus

@@ -387,6 +387,12 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
     out[16] = ms[4];
     out[17] = ln[4];
     out[18] = fl[4];
+    out[19] = ms[5];
+    out[20] = ln[5];
+    out[21] = fl[5];
+    out[22] = ms[3];
+    out[23] = ln[3];
+    out[24] = fl[3];
     return MDMRG_OK;
   });
 }

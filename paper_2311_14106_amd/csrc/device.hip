@@ -207,9 +207,12 @@ struct Mfma<float> {
 template <class T>
 __global__ __launch_bounds__(256) void k_gemm(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
                                               const GSeg *__restrict__ segs, Bases bases) {
+  // Double-buffered: while the MFMAs consume LDS buffer `cur`, the next
+  // K step (possibly of the next segment) is fetched into registers, then
+  // written to the other buffer; one barrier per K step.
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T As[TK][LDP];
-  __shared__ T Bs[TK][LDP];
+  __shared__ T As[2][TK][LDP];
+  __shared__ T Bs[2][TK][LDP];
   const GTile tl = tiles[blockIdx.x];
   const GOut o = outs[tl.out];
   const int row0 = int(tl.ti) * TM, col0 = int(tl.tj) * TN;
@@ -222,65 +225,81 @@ __global__ __launch_bounds__(256) void k_gemm(const GTile *__restrict__ tiles, c
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  for (int si = 0; si < o.seg_count; ++si) {
-    const GSeg sg = segs[o.seg_begin + si];
+  T ra[4], rb[4];
+  bool st_tA = false, st_tB = false;
+  // fetch op(A)[row0 + i][k0 + kk] * alpha and op(B)[k0 + kk][col0 + j]
+  auto gload = [&](const GSeg &sg, int k0) {
     const T *A = reinterpret_cast<const T *>(bases.p[sg.a_slot]) + sg.a_off;
     const T *B = reinterpret_cast<const T *>(bases.p[sg.b_slot]) + sg.b_off;
     const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB, idA = sg.flags & SEG_AID;
     const T alpha = T(sg.alpha);
-    for (int k0 = 0; k0 < sg.k; k0 += TK) {
-      // stage op(A)[row0 + i][k0 + kk] (scaled by alpha)
+    st_tA = tA;
+    st_tB = tB;
 #pragma unroll
-      for (int it = 0; it < (TM * TK) / 256; ++it) {
-        const int e = tid + it * 256;
-        int i, kk;
-        if (!tA) {
-          i = e / TK;
-          kk = e % TK;
-        } else {
-          kk = e / TM;
-          i = e % TM;
-        }
-        const int gi = row0 + i, gk = k0 + kk;
-        T v = T(0);
-        if (gi < o.m && gk < sg.k) {
-          if (idA)
-            v = (gi == gk) ? alpha : T(0);
-          else
-            v = alpha * (tA ? A[(int64_t)gk * sg.lda + gi] : A[(int64_t)gi * sg.lda + gk]);
-        }
-        As[kk][i] = v;
+    for (int it = 0; it < 4; ++it) {
+      const int e = tid + it * 256;
+      const int i = tA ? (e % TM) : (e / TK), kk = tA ? (e / TM) : (e % TK);
+      const int gi = row0 + i, gk = k0 + kk;
+      T v = T(0);
+      if (gi < o.m && gk < sg.k) {
+        if (idA)
+          v = (gi == gk) ? alpha : T(0);
+        else
+          v = alpha * (tA ? A[(int64_t)gk * sg.lda + gi] : A[(int64_t)gi * sg.lda + gk]);
       }
-      // stage op(B)[k0 + kk][col0 + j]
+      ra[it] = v;
+      const int j = tB ? (e / TK) : (e % TN), kb = tB ? (e % TK) : (e / TN);
+      const int gj = col0 + j, gkb = k0 + kb;
+      T w = T(0);
+      if (gj < o.n && gkb < sg.k) w = tB ? B[(int64_t)gj * sg.ldb + gkb] : B[(int64_t)gkb * sg.ldb + gj];
+      rb[it] = w;
+    }
+  };
+  auto lstore = [&](int buf) {
 #pragma unroll
-      for (int it = 0; it < (TN * TK) / 256; ++it) {
-        const int e = tid + it * 256;
-        int j, kk;
-        if (!tB) {
-          kk = e / TN;
-          j = e % TN;
-        } else {
-          j = e / TK;
-          kk = e % TK;
-        }
-        const int gj = col0 + j, gk = k0 + kk;
-        T v = T(0);
-        if (gj < o.n && gk < sg.k) v = tB ? B[(int64_t)gj * sg.ldb + gk] : B[(int64_t)gk * sg.ldb + gj];
-        Bs[kk][j] = v;
+    for (int it = 0; it < 4; ++it) {
+      const int e = tid + it * 256;
+      const int i = st_tA ? (e % TM) : (e / TK), kk = st_tA ? (e / TM) : (e % TK);
+      As[buf][kk][i] = ra[it];
+      const int j = st_tB ? (e / TK) : (e % TN), kb = st_tB ? (e % TK) : (e / TN);
+      Bs[buf][kb][j] = rb[it];
+    }
+  };
+
+  if (o.seg_count > 0) {
+    int si = 0, k0 = 0, cur = 0;
+    GSeg sg = segs[o.seg_begin];
+    gload(sg, 0);
+    lstore(0);
+    __syncthreads();
+    while (true) {
+      int nk0 = k0 + TK, nsi = si;
+      GSeg nsg = sg;
+      if (nk0 >= sg.k) {
+        nsi = si + 1;
+        nk0 = 0;
+        if (nsi < o.seg_count) nsg = segs[o.seg_begin + nsi];
       }
-      __syncthreads();
+      const bool has_next = nsi < o.seg_count;
+      if (has_next) gload(nsg, nk0);
 #pragma unroll
       for (int kk = 0; kk < TK; kk += 4) {
-        const T a0 = As[kk + lk][wm + lr];
-        const T a1 = As[kk + lk][wm + 16 + lr];
-        const T b0 = Bs[kk + lk][wn + lr];
-        const T b1 = Bs[kk + lk][wn + 16 + lr];
+        const T a0 = As[cur][kk + lk][wm + lr];
+        const T a1 = As[cur][kk + lk][wm + 16 + lr];
+        const T b0 = Bs[cur][kk + lk][wn + lr];
+        const T b1 = Bs[cur][kk + lk][wn + 16 + lr];
         acc[0][0] = Mfma<T>::step(a0, b0, acc[0][0]);
         acc[0][1] = Mfma<T>::step(a0, b1, acc[0][1]);
         acc[1][0] = Mfma<T>::step(a1, b0, acc[1][0]);
         acc[1][1] = Mfma<T>::step(a1, b1, acc[1][1]);
       }
+      if (!has_next) break;
+      lstore(cur ^ 1);
       __syncthreads();
+      cur ^= 1;
+      si = nsi;
+      k0 = nk0;
+      sg = nsg;
     }
   }
   T *C = reinterpret_cast<T *>(bases.p[o.c_slot]) + o.c_off;
@@ -473,6 +492,52 @@ void dev_gemm_run(Device *d, const DevPlan *p, const Bases &b, int tag, int prec
     HIP_CHECK(hipEventRecord(e1, d->stream));
     d->pending.push_back(Device::Pending{tag, e0, e1, p->flop});
   }
+}
+
+// ------------------------------------------------------ split-K reduction
+template <class T>
+__global__ void k_reduce(const int64_t *__restrict__ off, const int32_t *__restrict__ len, int n_split,
+                         int64_t stride, const T *__restrict__ P, T *__restrict__ y) {
+  const int64_t o = off[blockIdx.y];
+  const int n = len[blockIdx.y];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    T s = y[o + i];
+    for (int q = 0; q < n_split; ++q) s += P[q * stride + o + i];
+    y[o + i] = s;
+  }
+}
+DevReduce *dev_reduce_upload(Device *d, const std::vector<int64_t> &off, const std::vector<int32_t> &len,
+                             int n_split, int64_t stride) {
+  auto *r = new DevReduce();
+  r->n_blk = int64_t(off.size());
+  r->n_split = n_split;
+  r->stride = stride;
+  for (int32_t l : len) r->max_len = std::max<int64_t>(r->max_len, l);
+  if (r->n_blk) {
+    r->off = (int64_t *)dev_alloc(d, sizeof(int64_t) * off.size());
+    r->len = (int32_t *)dev_alloc(d, sizeof(int32_t) * len.size());
+    dev_h2d(d, r->off, off.data(), sizeof(int64_t) * off.size());
+    dev_h2d(d, r->len, len.data(), sizeof(int32_t) * len.size());
+  }
+  return r;
+}
+void dev_reduce_free(Device *d, DevReduce *r) {
+  if (!r) return;
+  dev_free(d, r->off);
+  dev_free(d, r->len);
+  delete r;
+}
+void dev_reduce_run(Device *d, const DevReduce *r, const double *P, double *y, int prec) {
+  if (!r || r->n_blk == 0) return;
+  MDMRG_REQUIRE(r->n_blk < 65536, -6, "split-K reduction: too many blocks for one launch");
+  const unsigned gx = unsigned(std::min<int64_t>((r->max_len + 255) / 256, 64));
+  if (prec == 0)
+    hipLaunchKernelGGL(k_reduce<double>, dim3(gx, unsigned(r->n_blk)), dim3(256), 0, d->stream, r->off, r->len,
+                       r->n_split, r->stride, P, y);
+  else
+    hipLaunchKernelGGL(k_reduce<float>, dim3(gx, unsigned(r->n_blk)), dim3(256), 0, d->stream, r->off, r->len,
+                       r->n_split, r->stride, reinterpret_cast<const float *>(P), reinterpret_cast<float *>(y));
+  HIP_CHECK(hipGetLastError());
 }
 
 // --------------------------------------------------------- precision casts

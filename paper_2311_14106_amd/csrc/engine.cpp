@@ -12,6 +12,8 @@
 // of products is O(n^2) and every product is a pair of dense sector GEMMs.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 #include "engine.h"
@@ -146,10 +148,10 @@ static void need_right(const Hamiltonian &H, int bond, OpSet &S) {
       S.add(make_key(K_N, &e, 1), QN() - H.q_of_op(e));
     }
   for (const Term &t : H.terms) {
-    int in[4], out[4], ki = 0, ko = 0;
+    int out[4], ki = 0, ko = 0;
     for (int i = 0; i < t.n; ++i) {
       if (H.site_of(t.e[i]) >= bond)
-        in[ki++] = t.e[i];
+        ++ki;
       else
         out[ko++] = t.e[i];
     }
@@ -254,8 +256,12 @@ static void materialize(Device *dev, OpSet &X, const OpSet &env, const Content &
 }
 
 // ------------------------------------------------------- two-phase planner
+// split_stride > 0 enables split-K of the accumulation phase: outputs are
+// the blocks of one buffer of split_stride elements; their K-concatenated
+// segment lists are cut into plan.n_split contiguous groups written to
+// partial copies (slot 7) and summed by a fixed-order reduction.
 static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutBlk> &outs, int64_t limit,
-                            TwoPhasePlan &plan, Device *dev) {
+                            TwoPhasePlan &plan, Device *dev, int64_t split_stride = 0) {
   std::stable_sort(tasks.begin(), tasks.end(), [](const PairTask &a, const PairTask &b) { return a.out < b.out; });
   plan.scratch = 0;
   {
@@ -412,19 +418,67 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
       }
       segs.push_back(s);
     }
+    // split-K factor: enough workgroup tiles to fill the chip
+    int S = 1;
+    if (split_stride > 0) {
+      int64_t tiles = 0;
+      size_t maxseg = 0;
+      for (size_t q = 0; q < out_ids.size(); ++q) {
+        const OutBlk &ob = outs[out_ids[q]];
+        tiles += (ob.m >= 48 && ob.n >= 48) ? int64_t((ob.m + 63) / 64) * ((ob.n + 63) / 64)
+                                            : int64_t((ob.m + 31) / 32) * ((ob.n + 31) / 32) / 4 + 1;
+        maxseg = std::max(maxseg, per_out[q].size());
+      }
+      S = int(std::min<int64_t>(std::max<int64_t>(1, 4096 / std::max<int64_t>(tiles, 1)), 32));
+      S = int(std::min<size_t>(size_t(S), std::max<size_t>(maxseg, 1)));
+      plan.n_split = std::max(plan.n_split, S);
+    }
+    std::vector<int64_t> roff;
+    std::vector<int32_t> rlen;
     for (size_t q = 0; q < out_ids.size(); ++q) {
       const OutBlk &ob = outs[out_ids[q]];
-      GOut o{};
-      o.c_off = ob.off;
-      o.m = ob.m;
-      o.n = ob.n;
-      o.ldc = ob.ld;
-      o.seg_begin = int32_t(p2.segs.size());
-      o.seg_count = int32_t(per_out[q].size());
-      o.c_slot = uint8_t(ob.slot);
-      o.accumulate = 1;
-      p2.segs.insert(p2.segs.end(), per_out[q].begin(), per_out[q].end());
-      p2.outs.push_back(o);
+      const std::vector<GSeg> &sv = per_out[q];
+      if (S == 1) {
+        GOut o{};
+        o.c_off = ob.off;
+        o.m = ob.m;
+        o.n = ob.n;
+        o.ldc = ob.ld;
+        o.seg_begin = int32_t(p2.segs.size());
+        o.seg_count = int32_t(sv.size());
+        o.c_slot = uint8_t(ob.slot);
+        o.accumulate = 1;
+        p2.segs.insert(p2.segs.end(), sv.begin(), sv.end());
+        p2.outs.push_back(o);
+        continue;
+      }
+      // contiguous groups balanced by K; every (block, group) is written
+      // (empty groups write zeros) so no stale partial survives a chunk
+      double ktot = 0.0;
+      for (const GSeg &g : sv) ktot += g.k + 4.0;
+      size_t pos = 0;
+      double acc = 0.0;
+      for (int q2 = 0; q2 < S; ++q2) {
+        const double goal = ktot * (q2 + 1) / S;
+        GOut o{};
+        o.c_off = int64_t(q2) * split_stride + ob.off;
+        o.m = ob.m;
+        o.n = ob.n;
+        o.ldc = ob.ld;
+        o.seg_begin = int32_t(p2.segs.size());
+        o.c_slot = 7;
+        o.accumulate = 0;
+        while (pos < sv.size() && (acc < goal - 1e-9 || q2 == S - 1)) {
+          p2.segs.push_back(sv[pos]);
+          acc += sv[pos].k + 4.0;
+          ++pos;
+        }
+        o.seg_count = int32_t(p2.segs.size()) - o.seg_begin;
+        p2.outs.push_back(o);
+      }
+      MDMRG_REQUIRE(ob.ld == ob.n, -4, "split-K needs packed output blocks");
+      roff.push_back(ob.off);
+      rlen.push_back(ob.m * ob.n);
     }
     plan.n_gemm += int64_t(p1.segs.size() + p2.segs.size());
     plan.flop += p1.flop + p2.flop;
@@ -433,6 +487,7 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
     Chunk ch;
     ch.p1 = p1.outs.empty() ? nullptr : dev_plan_upload(dev, p1);
     ch.p2 = p2.outs.empty() ? nullptr : dev_plan_upload(dev, p2);
+    if (S > 1) ch.red = dev_reduce_upload(dev, roff, rlen, S, split_stride);
     plan.chunks.push_back(ch);
     i = j;
   }
@@ -446,10 +501,13 @@ void Context::ensure_scratch(int64_t n) {
 }
 
 void Context::run_plan(const TwoPhasePlan &p, Bases &b, int tag, int prec) {
+  // phase-1 launches of an H_eff product are timed under tag 5
   b.p[2] = T_scratch;
+  if (p.n_split > 1) b.p[7] = P_scratch;
   for (auto &c : p.chunks) {
-    if (c.p1) dev_gemm_run(dev, c.p1, b, tag, prec);
+    if (c.p1) dev_gemm_run(dev, c.p1, b, tag == 1 ? 5 : tag, prec);
     if (c.p2) dev_gemm_run(dev, c.p2, b, tag, prec);
+    if (c.red) dev_reduce_run(dev, c.red, P_scratch, b.p[1], prec);
   }
 }
 
@@ -734,7 +792,7 @@ std::unique_ptr<OpSet> Context::renorm_right(const OpSet &R, int site) {
   };
   for (const Term &t : H.terms) {
     // parts relative to the new block: outside (< site), site, R (> site)
-    int out[4], sp[4], rr[4], ko = 0, ks = 0, kr = 0;
+    int out[4], sp[4], ko = 0, ks = 0, kr = 0;
     for (int i = 0; i < t.n; ++i) {
       const int st = H.site_of(t.e[i]);
       if (st < site)
@@ -742,7 +800,7 @@ std::unique_ptr<OpSet> Context::renorm_right(const OpSet &R, int site) {
       else if (st == site)
         sp[ks++] = t.e[i];
       else
-        rr[kr++] = t.e[i];
+        ++kr;
     }
     if (ks + kr == 0) continue;
     if (ko == 0) {  // H_{R'}
@@ -843,6 +901,7 @@ Context::~Context() {
     for (auto &t : A)
       if (t.data) dev_free(dev, t.data);
     if (T_scratch) dev_free(dev, T_scratch);
+    if (P_scratch) dev_free(dev, P_scratch);
     dev_sync(dev);
   } catch (...) {
   }
@@ -1061,7 +1120,49 @@ void Context::build_heff(int l) {
         }
     }
   }
-  build_two_phase(tasks, outs, scratch_limit, heff, dev);
+  if (std::getenv("MDMRG_VERBOSE")) {
+    // flop-weighted histogram of the largest GEMM dimension
+    const int edges[] = {8, 16, 32, 64, 128, 256, 512, 1 << 30};
+    double hist[8] = {0};
+    for (const PairTask &t : tasks) {
+      const int mx = std::max(std::max(t.m, t.n), std::max(t.k1, t.k2));
+      int bin = 0;
+      while (mx > edges[bin]) ++bin;
+      hist[bin] += 2.0 * t.m * t.k1 * t.k2 + 2.0 * t.m * t.k2 * t.n;
+    }
+    double tot = 0;
+    for (double h : hist) tot += h;
+    fprintf(stderr, "[mdmrg] bond %d: psi %lld elems in %zu blocks, %zu products, %zu pair tasks; flop share by max dim",
+            l, (long long)psi.n_elem, psi.blk.size(), items.size(), tasks.size());
+    for (int i = 0; i < 8; ++i) fprintf(stderr, " <=%d:%.2f", edges[i], tot > 0 ? hist[i] / tot : 0.0);
+    fprintf(stderr, "\n");
+  }
+  build_two_phase(tasks, outs, scratch_limit, heff, dev, psi.n_elem);
+  if (heff.n_split > 1 && P_scratch_n < heff.n_split * psi.n_elem) {
+    if (P_scratch) dev_free(dev, P_scratch);
+    P_scratch_n = heff.n_split * psi.n_elem;
+    P_scratch = (double *)dev_alloc(dev, sizeof(double) * P_scratch_n);
+  }
+  if (std::getenv("MDMRG_VERBOSE")) {
+    int64_t big = 0, small = 0, s1 = 0, s2 = 0, o2 = 0;
+    for (auto &c : heff.chunks) {
+      for (DevPlan *p : {c.p1, c.p2})
+        if (p) {
+          big += p->n_big;
+          small += p->n_small;
+        }
+      if (c.p1) s1 += c.p1->n_segs;
+      if (c.p2) {
+        s2 += c.p2->n_segs;
+        o2 += c.p2->n_outs;
+      }
+    }
+    fprintf(stderr,
+            "[mdmrg] bond %d: %zu chunks, scratch %.2f GB, flop %.3e, bytes %.3e, phase-1 outputs %lld, phase-2 "
+            "outputs %lld with %lld segments (split-K %d), tiles big %lld small %lld\n",
+            l, heff.chunks.size(), heff.scratch * 8e-9, heff.flop, heff.bytes, (long long)s1, (long long)o2,
+            (long long)s2, heff.n_split, (long long)big, (long long)small);
+  }
   ensure_scratch(heff.scratch);
   std::vector<int64_t> boff;
   std::vector<int32_t> bm, bn;

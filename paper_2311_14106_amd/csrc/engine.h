@@ -98,6 +98,9 @@ struct OutBlk {
 };
 struct Chunk {
   DevPlan *p1 = nullptr, *p2 = nullptr;
+  // split-K: phase 2 wrote n_split partial copies (slot 7, stride = output
+  // buffer length); reduce them, in a fixed order, into these blocks
+  DevReduce *red = nullptr;
 };
 struct TwoPhasePlan {
   std::vector<Chunk> chunks;
@@ -105,12 +108,19 @@ struct TwoPhasePlan {
   double flop = 0.0;
   double bytes = 0.0;  // algorithmic HBM bytes: operands once, outputs once, intermediates twice
   int64_t n_gemm = 0;
+  int n_split = 1;
   void release(Device *d) {
     for (auto &c : chunks) {
       dev_plan_free(d, c.p1);
       dev_plan_free(d, c.p2);
+      dev_reduce_free(d, c.red);
     }
     chunks.clear();
+    scratch = 0;
+    flop = 0.0;
+    bytes = 0.0;
+    n_gemm = 0;
+    n_split = 1;
   }
 };
 
@@ -156,9 +166,11 @@ struct Context {
   DevDiag *diag = nullptr;
   double *T_scratch = nullptr;
   int64_t T_scratch_n = 0;
+  double *P_scratch = nullptr;  // split-K partial outputs
+  int64_t P_scratch_n = 0;
   int64_t heff_terms = 0;
   Stats stats;
-  int64_t scratch_limit = int64_t(192) << 20;  // doubles of phase-1 scratch
+  int64_t scratch_limit = int64_t(1) << 30;  // doubles of phase-1 scratch (8 GB)
 
   ~Context();
   void reset_envs();

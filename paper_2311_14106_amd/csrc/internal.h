@@ -140,6 +140,21 @@ constexpr int kTags = 8;
 void dev_timing_enable(Device *, bool on);
 void dev_timing_collect(Device *, double *ms, double *launches, double *flop);
 
+// Deterministic split-K reduction: y[off+i] += sum_{s<S} P[s*stride + off+i]
+// over a list of blocks (off, len), s ascending.
+struct DevReduce {
+  int64_t *off = nullptr;
+  int32_t *len = nullptr;
+  int64_t n_blk = 0;
+  int64_t max_len = 0;
+  int n_split = 1;
+  int64_t stride = 0;
+};
+DevReduce *dev_reduce_upload(Device *, const std::vector<int64_t> &off, const std::vector<int32_t> &len,
+                             int n_split, int64_t stride);
+void dev_reduce_free(Device *, DevReduce *);
+void dev_reduce_run(Device *, const DevReduce *, const double *P, double *y, int prec);
+
 struct DevDiag {
   DiagTask *tasks = nullptr;
   int32_t *blk_begin = nullptr;  // CSR over output blocks

@@ -267,11 +267,12 @@ class Context:
                                               sd.ctypes.data_as(_c_i64_p), _dp(al)))
 
     def stats(self):
-        out = np.zeros(19)
+        out = np.zeros(25)
         self._chk(self.lib.mdmrg_get_stats(self.h, _dp(out)))
         keys = ['diag_h_s', 'ren_s', 'tables_s', 'diag_d_s', 'stvec_s', 'other_s', 'heff_flop', 'n_matvec',
                 'heff_gemm_ms', 'heff_gemm_launches', 'heff_gemm_flop',
                 'ren_gemm_ms', 'ren_gemm_launches', 'ren_gemm_flop',
                 'heff_flop_split', 'n_matvec_split', 'split_gemm_ms', 'split_gemm_launches',
-                'split_gemm_flop']
+                'split_gemm_flop', 'heff_p1_ms', 'heff_p1_launches', 'heff_p1_flop',
+                'grouped_ms', 'grouped_launches', 'grouped_flop']
         return dict(zip(keys, out.tolist()))
