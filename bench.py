@@ -87,6 +87,40 @@ def cpu_baseline(mdmrg, budget_s):
                       f'{os.environ.get("OMP_NUM_THREADS", "default")}'}
 
 
+def split_compare(ctx, x0, torch, args):
+    """Davidson s/step at fixed dE: FP64 form vs mixed precision (FP32
+    products, then FP64 refinement), both from the same start vector at the
+    current bond; E_ref = FP64 solve to |r| <= 1e-10; dE = 1e-9 |E_ref|."""
+    from paper_2311_14106_amd import mdmrg
+
+    def solve(fn):
+        x = x0.clone()
+        torch.cuda.synchronize()
+        t0 = time.time()
+        res = fn(x)
+        torch.cuda.synchronize()
+        return res, time.time() - t0
+
+    s0 = ctx.stats()
+    (e_ref, r_ref, n_ref, _), _ = solve(lambda x: ctx.davidson(x, tol=1e-10, max_iter=600))
+    (e64, r64, n64, _), t64 = solve(lambda x: ctx.davidson(x, tol=args.split_tol, max_iter=600))
+    (em, rm, nm64, nm32, _), tm = solve(lambda x: ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol,
+                                                                     prec_split=mdmrg.FP32, max_iter=600))
+    de = 1e-9 * abs(e_ref)
+    s1 = ctx.stats()
+    ms64 = (s1['heff_gemm_ms'] + s1['heff_p1_ms'] - s0['heff_gemm_ms'] - s0['heff_p1_ms']) / max(
+        1.0, s1['n_matvec'] - s0['n_matvec'])
+    ms32 = (s1['split_gemm_ms'] - s0['split_gemm_ms']) / max(1.0, s1['n_matvec_split'] - s0['n_matvec_split'])
+    log(f'[bench] fixed-dE: ref E={e_ref:.12f} ({n_ref} products); FP64 {t64:.2f}s {n64} products '
+        f'dE={abs(e64 - e_ref):.1e}; mixed {tm:.2f}s {nm32} FP32 + {nm64} FP64 products dE={abs(em - e_ref):.1e}')
+    return {'dE_target': de, 'E_ref': e_ref, 'residual_tol': args.split_tol,
+            'fp64': {'davidson_s': t64, 'products': n64, 'dE': abs(e64 - e_ref), 'ok': abs(e64 - e_ref) <= de},
+            'mixed_fp32': {'davidson_s': tm, 'products_fp32': nm32, 'products_fp64': nm64,
+                           'dE': abs(em - e_ref), 'ok': abs(em - e_ref) <= de},
+            'speedup': t64 / tm if tm > 0 else None,
+            'gemm_ms_per_product': {'fp64': ms64, 'fp32': ms32}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -97,6 +131,9 @@ def main():
     ap.add_argument('--tol', type=float, default=1e-7)
     ap.add_argument('--cpu-budget', type=float, default=15.0)
     ap.add_argument('--no-cpu', action='store_true')
+    ap.add_argument('--no-split', action='store_true')
+    ap.add_argument('--split-tol', type=float, default=1e-5,
+                    help='FP64 residual tolerance of the fixed-dE Davidson comparison')
     args = ap.parse_args()
     if args.gpus != 1:
         print(f'bench.py: --gpus {args.gpus} is not supported; this build runs on exactly one GPU '
@@ -146,30 +183,36 @@ def main():
     s1 = ctx.stats()
     d = {k: s1[k] - s0[k] for k in s1}
     heff_flop = d['heff_flop']
-    gemm_ms = d['heff_gemm_ms'] + d['heff_p1_ms']
-    gemm_flop = d['heff_gemm_flop'] + d['heff_p1_flop']
-    launches = max(1.0, d['heff_gemm_launches'] + d['heff_p1_launches'])
-    # algorithmic bytes of the timed products (per-bond cost x products)
+    # algorithmic cost of the timed products
     nmv_total = d['n_matvec']
     bytes_per_mv = float(np.mean([c['bytes'] for c in costs]))
     flop_per_mv = float(np.mean([c['flop'] for c in costs]))
     intensity = flop_per_mv / max(bytes_per_mv, 1.0)
     ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
-    achieved_tf = gemm_flop / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+    # dominant kernel variant of the timed H_eff products (HIP events on the
+    # library stream around every launch)
+    kern = {'t64': ('k_gemm<double> (64x64 workgroup tiles)', 'heff_t64'),
+            't32': ('k_gemm_wave<double> (32x32 wave tiles)', 'heff_t32')}
+    dom = max(kern, key=lambda k: d[kern[k][1] + '_ms'])
+    name, key = kern[dom]
+    k_ms, k_launch, k_flop = d[key + '_ms'], max(1.0, d[key + '_launches']), d[key + '_flop']
+    achieved_tf = k_flop / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
+    tot_ms = d['heff_t64_ms'] + d['heff_t32_ms']
     if intensity >= ridge:
         roof = {'bound': 'mfma', 'achieved': achieved_tf, 'peak': PEAK_FP64_TFLOPS, 'unit': 'TFLOP/s',
                 'frac': achieved_tf / PEAK_FP64_TFLOPS, 'traffic': None}
     else:
-        gbs = bytes_per_mv * nmv_total / (gemm_ms * 1e-3) / 1e9 if gemm_ms > 0 else 0.0
+        gbs = bytes_per_mv * nmv_total / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
         roof = {'bound': 'hbm', 'achieved': gbs, 'peak': PEAK_HBM_GBS, 'unit': 'GB/s',
                 'frac': gbs / PEAK_HBM_GBS, 'traffic': None}
-    roof.update({'kernel': 'k_gemm_f64 (H_eff psi grouped sector GEMM)',
-                 'launches': int(launches), 'avg_launch_ms': gemm_ms / launches,
-                 'flop_per_launch': gemm_flop / launches, 'intensity_flop_per_byte': intensity,
-                 'kernel_tflops': achieved_tf,
-                 'phase1_ms': d['heff_p1_ms'], 'phase2_ms': d['heff_gemm_ms'],
-                 'phase1_tflops': d['heff_p1_flop'] / max(d['heff_p1_ms'], 1e-9) / 1e9,
-                 'phase2_tflops': d['heff_gemm_flop'] / max(d['heff_gemm_ms'], 1e-9) / 1e9})
+    roof.update({'kernel': name, 'launches': int(k_launch), 'avg_launch_ms': k_ms / k_launch,
+                 'flop_per_launch': k_flop / k_launch,
+                 'share_of_heff_gemm_time': k_ms / max(tot_ms, 1e-9),
+                 'avg_launch_ms_whole_process': s1['all_' + dom + '_ms'] / max(1.0, s1['all_' + dom + '_launches']),
+                 'launches_whole_process': int(s1['all_' + dom + '_launches']),
+                 'heff_intensity_flop_per_byte': intensity,
+                 'heff_gemm_tflops_all_variants': (d['heff_t64_flop'] + d['heff_t32_flop']) / max(tot_ms, 1e-9) / 1e9,
+                 'phase1_ms': d['heff_p1_ms'], 'phase2_ms': d['heff_gemm_ms']})
     out = {
         'metric': 'H_eff·ψ TFLOP/s and Davidson s/step, FP64 vs split-precision at fixed ΔE',
         'value': heff_flop / wall / 1e12,
@@ -195,6 +238,8 @@ def main():
         'energies': energies,
         'roofline': roof,
     }
+    if not args.no_split:
+        out['split_precision'] = split_compare(ctx, x, torch, args)
     if not args.no_cpu:
         out['cpu_baseline'] = cpu_baseline(mdmrg, args.cpu_budget)
     print(json.dumps(out), flush=True)

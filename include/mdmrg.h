@@ -129,6 +129,16 @@ int mdmrg_get_bond(mdmrg_ctx ctx, int bond, int32_t *n_sect, int32_t *qn, int32_
 
 /* ------------------------------------------------------------------- bond */
 
+enum {
+  MDMRG_OPT_KEEP_ENVS = 1,     /* 1 (default): keep the operators of every block built;
+                                  0: mdmrg_prepare_bond keeps only the blocks of the
+                                  requested bond (memory for one-bond workloads) */
+  MDMRG_OPT_SCRATCH_LIMIT = 2  /* doubles of intermediate storage per product pass
+                                  (default 2^30); larger values mean fewer passes */
+};
+/* Set a context option (EINVAL for unknown options or bad values). */
+int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value);
+
 /* Make bond (l, l+1) current: build (on the device) the renormalised
  * operators of the left block (sites < l) and the right block
  * (sites > l+1) from the MPS by repeated renormalisation (Sec. II.A), then
@@ -224,14 +234,19 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
 /* Wall seconds per step category (Diag_H, Ren, Tables, Diag_D, StVec,
  * Other) accumulated since creation, the algorithmic FLOP of all H_eff
  * products, and HIP-event timings of the grouped-GEMM launches on the
- * context stream; out must hold 25 doubles:
+ * context stream; out must hold 35 doubles:
  * [diag_h, ren, tables, diag_d, stvec, other, heff_flop, n_matvec,
  *  heff_gemm_ms, heff_gemm_launches, heff_gemm_flop,
  *  ren_gemm_ms, ren_gemm_launches, ren_gemm_flop,
  *  heff_flop_split, n_matvec_split,
  *  split_gemm_ms, split_gemm_launches, split_gemm_flop,
  *  heff_phase1_ms, heff_phase1_launches, heff_phase1_flop,
- *  grouped_ms, grouped_launches, grouped_flop (mdmrg_gemm_grouped calls)].
+ *  grouped_ms, grouped_launches, grouped_flop (mdmrg_gemm_grouped calls),
+ *  heff_tile64_ms, heff_tile64_launches, heff_tile64_flop,
+ *  heff_tile32_ms, heff_tile32_launches, heff_tile32_flop,
+ *  all_tile64_ms, all_tile64_launches, all_tile32_ms, all_tile32_launches].
+ * tile64 = k_gemm (64x64 workgroup tiles), tile32 = k_gemm_wave (32x32 wave
+ * tiles); heff_* = FP64 H_eff products, all_* = every timed launch.
  * heff_gemm_* covers the accumulation (second) phase of the FP64 H_eff
  * products and heff_phase1_* their intermediate (first) phase. */
 int mdmrg_get_stats(mdmrg_ctx ctx, double *out);

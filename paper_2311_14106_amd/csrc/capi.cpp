@@ -179,6 +179,25 @@ int mdmrg_get_bond(mdmrg_ctx ctx, int bond, int32_t *n_sect, int32_t *qn, int32_
   });
 }
 
+int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value) {
+  if (!ctx) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    Context &c = ctx->c;
+    switch (option) {
+      case MDMRG_OPT_KEEP_ENVS:
+        c.keep_envs = value != 0;
+        break;
+      case MDMRG_OPT_SCRATCH_LIMIT:
+        MDMRG_REQUIRE(value >= (int64_t(1) << 20), MDMRG_EINVAL, "set_option: scratch limit below 2^20 doubles");
+        c.scratch_limit = value;
+        break;
+      default:
+        throw Error(MDMRG_EINVAL, "set_option: unknown option");
+    }
+    return MDMRG_OK;
+  });
+}
+
 int mdmrg_prepare_bond(mdmrg_ctx ctx, int l) {
   if (!ctx) return MDMRG_EINVAL;
   return guarded(ctx, [&] {
@@ -374,8 +393,14 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
   out[6] = s.heff_flop;
   out[7] = s.n_matvec;
   return guarded(ctx, [&] {
+    double ms2[kTags][2], ln2[kTags][2], fl2[kTags][2];
+    dev_timing_collect(ctx->c.dev, ms2, ln2, fl2);
     double ms[kTags], ln[kTags], fl[kTags];
-    dev_timing_collect(ctx->c.dev, ms, ln, fl);
+    for (int i = 0; i < kTags; ++i) {
+      ms[i] = ms2[i][0] + ms2[i][1];
+      ln[i] = ln2[i][0] + ln2[i][1];
+      fl[i] = fl2[i][0] + fl2[i][1];
+    }
     out[8] = ms[1];
     out[9] = ln[1];
     out[10] = fl[1];
@@ -393,6 +418,20 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
     out[22] = ms[3];
     out[23] = ln[3];
     out[24] = fl[3];
+    // per kernel variant: FP64 H_eff products (both phases), then every
+    // FP64-or-FP32 launch of the context
+    for (int k = 0; k < 2; ++k) {
+      out[25 + 3 * k] = ms2[1][k] + ms2[5][k];
+      out[26 + 3 * k] = ln2[1][k] + ln2[5][k];
+      out[27 + 3 * k] = fl2[1][k] + fl2[5][k];
+      double am = 0, al = 0;
+      for (int i = 1; i < kTags; ++i) {
+        am += ms2[i][k];
+        al += ln2[i][k];
+      }
+      out[31 + 2 * k] = am;
+      out[32 + 2 * k] = al;
+    }
     return MDMRG_OK;
   });
 }

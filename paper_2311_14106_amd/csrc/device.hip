@@ -37,12 +37,12 @@ struct Device {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   struct Pending {
-    int tag;
+    int tag, kind;
     hipEvent_t a, b;
     double flop;
   };
   std::vector<Pending> pending;
-  double ms[kTags] = {}, launches[kTags] = {}, flop[kTags] = {};
+  double ms[kTags][2] = {}, launches[kTags][2] = {}, flop[kTags][2] = {};
 };
 
 static hipEvent_t ev_get(Device *d) {
@@ -62,9 +62,9 @@ static void timing_drain(Device *d) {
   for (auto &p : d->pending) {
     float t = 0.f;
     HIP_CHECK(hipEventElapsedTime(&t, p.a, p.b));
-    d->ms[p.tag] += t;
-    d->launches[p.tag] += 1;
-    d->flop[p.tag] += p.flop;
+    d->ms[p.tag][p.kind] += t;
+    d->launches[p.tag][p.kind] += 1;
+    d->flop[p.tag][p.kind] += p.flop;
     d->ev_pool.push_back(p.a);
     d->ev_pool.push_back(p.b);
   }
@@ -72,13 +72,14 @@ static void timing_drain(Device *d) {
 }
 
 void dev_timing_enable(Device *d, bool on) { d->timing = on; }
-void dev_timing_collect(Device *d, double *ms, double *launches, double *flop) {
+void dev_timing_collect(Device *d, double ms[][2], double launches[][2], double flop[][2]) {
   timing_drain(d);
-  for (int i = 0; i < kTags; ++i) {
-    ms[i] = d->ms[i];
-    launches[i] = d->launches[i];
-    flop[i] = d->flop[i];
-  }
+  for (int i = 0; i < kTags; ++i)
+    for (int k = 0; k < 2; ++k) {
+      ms[i][k] = d->ms[i][k];
+      launches[i][k] = d->launches[i][k];
+      flop[i][k] = d->flop[i][k];
+    }
 }
 
 double wall_seconds() {
@@ -204,15 +205,89 @@ struct Mfma<float> {
   }
 };
 
+// Per-thread load state of one segment: each thread stages 4 elements of
+// op(A) and 4 of op(B) per K step.  Base pointers are uniform over the
+// workgroup; per-element offsets, validity and K offsets are fixed per
+// segment, so the K loop only adds the step offset and checks the K bound.
+template <class T>
+struct SegLoad {
+  const T *A, *B;
+  int32_t oa[4], ob[4];  // element offsets inside the operand blocks
+  int32_t da, db;        // advance per K step (elements)
+  int8_t ka[4], kb[4];   // k offset of each staged element within the step
+  uint8_t va, vb;        // bit it: element it lies inside the output tile
+  int k;
+  T alpha;
+  bool idA, tA, tB;
+};
+
+template <class T>
+__device__ inline void seg_setup(SegLoad<T> &L, const GSeg &sg, const Bases &bases, const GOut &o, int row0,
+                                 int col0, int tid) {
+  L.A = reinterpret_cast<const T *>(bases.p[sg.a_slot]) + sg.a_off;
+  L.B = reinterpret_cast<const T *>(bases.p[sg.b_slot]) + sg.b_off;
+  L.tA = sg.flags & SEG_TA;
+  L.tB = sg.flags & SEG_TB;
+  L.idA = sg.flags & SEG_AID;
+  L.alpha = T(sg.alpha);
+  L.k = sg.k;
+  L.da = L.tA ? TK * sg.lda : TK;
+  L.db = L.tB ? TK : TK * sg.ldb;
+  L.va = 0;
+  L.vb = 0;
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int e = tid + it * 256;
+    const int i = L.tA ? (e % TM) : (e / TK), kk = L.tA ? (e / TM) : (e % TK);
+    const int gi = row0 + i;
+    L.ka[it] = int8_t(kk);
+    if (gi < o.m) L.va |= uint8_t(1 << it);
+    L.oa[it] = L.idA ? gi : (L.tA ? kk * sg.lda + gi : gi * sg.lda + kk);
+    const int j = L.tB ? (e / TK) : (e % TN), kb = L.tB ? (e % TK) : (e / TN);
+    const int gj = col0 + j;
+    L.kb[it] = int8_t(kb);
+    if (gj < o.n) L.vb |= uint8_t(1 << it);
+    L.ob[it] = L.tB ? gj * sg.ldb + kb : kb * sg.ldb + gj;
+  }
+}
+
+template <class T>
+__device__ inline void seg_fetch(const SegLoad<T> &L, int step, T ra[4], T rb[4]) {
+  const int k0 = step * TK;
+  const int64_t sa = int64_t(step) * L.da, sb = int64_t(step) * L.db;
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int gk = k0 + L.ka[it];
+    T v = T(0);
+    if (((L.va >> it) & 1) && gk < L.k)
+      v = L.idA ? ((L.oa[it] == gk) ? L.alpha : T(0)) : L.alpha * L.A[sa + L.oa[it]];
+    ra[it] = v;
+    const int gkb = k0 + L.kb[it];
+    rb[it] = (((L.vb >> it) & 1) && gkb < L.k) ? L.B[sb + L.ob[it]] : T(0);
+  }
+}
+
+template <class T>
+__device__ inline void seg_store(const SegLoad<T> &L, int tid, const T ra[4], const T rb[4], T *As, T *Bs) {
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int e = tid + it * 256;
+    const int i = L.tA ? (e % TM) : (e / TK), kk = L.tA ? (e / TM) : (e % TK);
+    As[kk * LDP + i] = ra[it];
+    const int j = L.tB ? (e / TK) : (e % TN), kb = L.tB ? (e % TK) : (e / TN);
+    Bs[kb * LDP + j] = rb[it];
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_gemm(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
                                               const GSeg *__restrict__ segs, Bases bases) {
-  // Double-buffered: while the MFMAs consume LDS buffer `cur`, the next
-  // K step (possibly of the next segment) is fetched into registers, then
-  // written to the other buffer; one barrier per K step.
+  // Double-buffered inside a segment: while the MFMAs consume LDS buffer
+  // `buf`, the next K step is fetched into registers and then written to
+  // the other buffer; one barrier per K step.
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T As[2][TK][LDP];
-  __shared__ T Bs[2][TK][LDP];
+  __shared__ T As[2][TK * LDP];
+  __shared__ T Bs[2][TK * LDP];
   const GTile tl = tiles[blockIdx.x];
   const GOut o = outs[tl.out];
   const int row0 = int(tl.ti) * TM, col0 = int(tl.tj) * TN;
@@ -226,80 +301,33 @@ __global__ __launch_bounds__(256) void k_gemm(const GTile *__restrict__ tiles, c
     for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
   T ra[4], rb[4];
-  bool st_tA = false, st_tB = false;
-  // fetch op(A)[row0 + i][k0 + kk] * alpha and op(B)[k0 + kk][col0 + j]
-  auto gload = [&](const GSeg &sg, int k0) {
-    const T *A = reinterpret_cast<const T *>(bases.p[sg.a_slot]) + sg.a_off;
-    const T *B = reinterpret_cast<const T *>(bases.p[sg.b_slot]) + sg.b_off;
-    const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB, idA = sg.flags & SEG_AID;
-    const T alpha = T(sg.alpha);
-    st_tA = tA;
-    st_tB = tB;
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int e = tid + it * 256;
-      const int i = tA ? (e % TM) : (e / TK), kk = tA ? (e / TM) : (e % TK);
-      const int gi = row0 + i, gk = k0 + kk;
-      T v = T(0);
-      if (gi < o.m && gk < sg.k) {
-        if (idA)
-          v = (gi == gk) ? alpha : T(0);
-        else
-          v = alpha * (tA ? A[(int64_t)gk * sg.lda + gi] : A[(int64_t)gi * sg.lda + gk]);
-      }
-      ra[it] = v;
-      const int j = tB ? (e / TK) : (e % TN), kb = tB ? (e % TK) : (e / TN);
-      const int gj = col0 + j, gkb = k0 + kb;
-      T w = T(0);
-      if (gj < o.n && gkb < sg.k) w = tB ? B[(int64_t)gj * sg.ldb + gkb] : B[(int64_t)gkb * sg.ldb + gj];
-      rb[it] = w;
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int e = tid + it * 256;
-      const int i = st_tA ? (e % TM) : (e / TK), kk = st_tA ? (e / TM) : (e % TK);
-      As[buf][kk][i] = ra[it];
-      const int j = st_tB ? (e / TK) : (e % TN), kb = st_tB ? (e % TK) : (e / TN);
-      Bs[buf][kb][j] = rb[it];
-    }
-  };
-
-  if (o.seg_count > 0) {
-    int si = 0, k0 = 0, cur = 0;
-    GSeg sg = segs[o.seg_begin];
-    gload(sg, 0);
-    lstore(0);
+  SegLoad<T> L;
+  int buf = 0;
+  for (int si = 0; si < o.seg_count; ++si) {
+    seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
+    const int nsteps = (L.k + TK - 1) / TK;
+    if (nsteps == 0) continue;
+    seg_fetch(L, 0, ra, rb);
+    seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
     __syncthreads();
-    while (true) {
-      int nk0 = k0 + TK, nsi = si;
-      GSeg nsg = sg;
-      if (nk0 >= sg.k) {
-        nsi = si + 1;
-        nk0 = 0;
-        if (nsi < o.seg_count) nsg = segs[o.seg_begin + nsi];
-      }
-      const bool has_next = nsi < o.seg_count;
-      if (has_next) gload(nsg, nk0);
+    for (int step = 0; step < nsteps; ++step) {
+      const bool more = step + 1 < nsteps;
+      if (more) seg_fetch(L, step + 1, ra, rb);
+      const T *Ab = As[buf], *Bb = Bs[buf];
 #pragma unroll
       for (int kk = 0; kk < TK; kk += 4) {
-        const T a0 = As[cur][kk + lk][wm + lr];
-        const T a1 = As[cur][kk + lk][wm + 16 + lr];
-        const T b0 = Bs[cur][kk + lk][wn + lr];
-        const T b1 = Bs[cur][kk + lk][wn + 16 + lr];
+        const T a0 = Ab[(kk + lk) * LDP + wm + lr];
+        const T a1 = Ab[(kk + lk) * LDP + wm + 16 + lr];
+        const T b0 = Bb[(kk + lk) * LDP + wn + lr];
+        const T b1 = Bb[(kk + lk) * LDP + wn + 16 + lr];
         acc[0][0] = Mfma<T>::step(a0, b0, acc[0][0]);
         acc[0][1] = Mfma<T>::step(a0, b1, acc[0][1]);
         acc[1][0] = Mfma<T>::step(a1, b0, acc[1][0]);
         acc[1][1] = Mfma<T>::step(a1, b1, acc[1][1]);
       }
-      if (!has_next) break;
-      lstore(cur ^ 1);
+      buf ^= 1;
+      if (more) seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
       __syncthreads();
-      cur ^= 1;
-      si = nsi;
-      k0 = nk0;
-      sg = nsg;
     }
   }
   T *C = reinterpret_cast<T *>(bases.p[o.c_slot]) + o.c_off;
@@ -410,6 +438,16 @@ __global__ __launch_bounds__(256) void k_gemm_wave(const GTile *__restrict__ til
 }
 
 DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
+  // the 64x64 kernel keeps per-thread 32-bit element offsets inside one K
+  // step of an operand block: rows x ld (+16) must stay below 2^31
+  for (const GOut &o : plan.outs)
+    for (int q = 0; q < o.seg_count; ++q) {
+      const GSeg &g = plan.segs[o.seg_begin + q];
+      const int64_t ext_a = (g.flags & SEG_TA) ? int64_t(TK) * g.lda + o.m : int64_t(o.m) * g.lda + TK;
+      const int64_t ext_b = (g.flags & SEG_TB) ? int64_t(o.n) * g.ldb + TK : int64_t(TK) * g.ldb + o.n;
+      MDMRG_REQUIRE(ext_a < (int64_t(1) << 31) && ext_b < (int64_t(1) << 31), -6,
+                    "grouped GEMM: operand block too large for 32-bit element offsets");
+    }
   auto *dp = new DevPlan();
   dp->n_outs = int64_t(plan.outs.size());
   dp->n_segs = int64_t(plan.segs.size());
@@ -428,6 +466,15 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
   std::vector<GTile> tiles, small;
   for (auto &w : work) {
     const GOut &o = plan.outs[w.second];
+    double of = 0.0;
+    for (int q = 0; q < o.seg_count; ++q) {
+      const GSeg &g = plan.segs[o.seg_begin + q];
+      if (!(g.flags & SEG_AID)) of += 2.0 * o.m * o.n * g.k;
+    }
+    if (o.m >= 48 && o.n >= 48)
+      dp->flop_big += of;
+    else
+      dp->flop_small += of;
     if (o.m >= 48 && o.n >= 48) {
       const int nti = (o.m + TM - 1) / TM, ntj = (o.n + TN - 1) / TN;
       for (int i = 0; i < nti; ++i)
@@ -464,33 +511,38 @@ void dev_plan_free(Device *d, DevPlan *p) {
 
 void dev_gemm_run(Device *d, const DevPlan *p, const Bases &b, int tag, int prec) {
   if (!p || p->n_tiles == 0) return;
-  const bool timed = d->timing && tag > 0 && tag < kTags;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (timed) {
-    if (d->pending.size() > 512) timing_drain(d);
-    e0 = ev_get(d);
-    e1 = ev_get(d);
-    HIP_CHECK(hipEventRecord(e0, d->stream));
-  }
-  if (prec == 0) {
-    if (p->n_big)
-      hipLaunchKernelGGL(k_gemm<double>, dim3(unsigned(p->n_big)), dim3(256), 0, d->stream, p->tiles, p->outs,
-                         p->segs, b);
-    if (p->n_small)
-      hipLaunchKernelGGL(k_gemm_wave<double>, dim3(unsigned((p->n_small + 3) / 4)), dim3(256), 0, d->stream,
-                         p->tiles + p->n_big, p->n_small, p->outs, p->segs, b);
-  } else {
-    if (p->n_big)
-      hipLaunchKernelGGL(k_gemm<float>, dim3(unsigned(p->n_big)), dim3(256), 0, d->stream, p->tiles, p->outs,
-                         p->segs, b);
-    if (p->n_small)
-      hipLaunchKernelGGL(k_gemm_wave<float>, dim3(unsigned((p->n_small + 3) / 4)), dim3(256), 0, d->stream,
-                         p->tiles + p->n_big, p->n_small, p->outs, p->segs, b);
-  }
-  HIP_CHECK(hipGetLastError());
-  if (timed) {
-    HIP_CHECK(hipEventRecord(e1, d->stream));
-    d->pending.push_back(Device::Pending{tag, e0, e1, p->flop});
+  if (tag <= 0 || tag >= kTags) tag = 6;  // untagged launches are timed as "other"
+  const bool timed = d->timing;
+  for (int kind = 0; kind < 2; ++kind) {
+    const int64_t nt = kind == 0 ? p->n_big : p->n_small;
+    if (!nt) continue;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+      if (d->pending.size() > 512) timing_drain(d);
+      e0 = ev_get(d);
+      e1 = ev_get(d);
+      HIP_CHECK(hipEventRecord(e0, d->stream));
+    }
+    if (kind == 0) {
+      if (prec == 0)
+        hipLaunchKernelGGL(k_gemm<double>, dim3(unsigned(nt)), dim3(256), 0, d->stream, p->tiles, p->outs, p->segs,
+                           b);
+      else
+        hipLaunchKernelGGL(k_gemm<float>, dim3(unsigned(nt)), dim3(256), 0, d->stream, p->tiles, p->outs, p->segs,
+                           b);
+    } else {
+      if (prec == 0)
+        hipLaunchKernelGGL(k_gemm_wave<double>, dim3(unsigned((nt + 3) / 4)), dim3(256), 0, d->stream,
+                           p->tiles + p->n_big, nt, p->outs, p->segs, b);
+      else
+        hipLaunchKernelGGL(k_gemm_wave<float>, dim3(unsigned((nt + 3) / 4)), dim3(256), 0, d->stream,
+                           p->tiles + p->n_big, nt, p->outs, p->segs, b);
+    }
+    HIP_CHECK(hipGetLastError());
+    if (timed) {
+      HIP_CHECK(hipEventRecord(e1, d->stream));
+      d->pending.push_back(Device::Pending{tag, kind, e0, e1, kind == 0 ? p->flop_big : p->flop_small});
+    }
   }
 }
 

@@ -917,12 +917,28 @@ void Context::prepare(int l) {
     Lenv.resize(n + 1);
     Renv.resize(n + 1);
   }
-  if (!Lenv[0]) Lenv[0] = env_boundary(true, 0);
-  for (int i = 0; i < l; ++i)
-    if (!Lenv[i + 1]) Lenv[i + 1] = renorm_left(*Lenv[i], i);
-  if (!Renv[n]) Renv[n] = env_boundary(false, n);
-  for (int i = n - 1; i >= l + 2; --i)
-    if (!Renv[i]) Renv[i] = renorm_right(*Renv[i + 1], i);
+  auto drop = [&](std::unique_ptr<OpSet> &e) {
+    if (e) e->release(dev);
+    e.reset();
+  };
+  if (!Lenv[l]) {
+    int i0 = l;
+    while (i0 > 0 && !Lenv[i0]) --i0;
+    if (!Lenv[i0]) Lenv[i0] = env_boundary(true, i0);
+    for (int i = i0; i < l; ++i) {
+      Lenv[i + 1] = renorm_left(*Lenv[i], i);
+      if (!keep_envs) drop(Lenv[i]);
+    }
+  }
+  if (!Renv[l + 2]) {
+    int i0 = l + 2;
+    while (i0 < n && !Renv[i0]) ++i0;
+    if (!Renv[i0]) Renv[i0] = env_boundary(false, i0);
+    for (int i = i0 - 1; i >= l + 2; --i) {
+      Renv[i] = renorm_right(*Renv[i + 1], i);
+      if (!keep_envs) drop(Renv[i + 1]);
+    }
+  }
   dev_sync(dev);
   stats.t_ren += wall_seconds() - t0;
   build_heff(l);
@@ -1347,11 +1363,11 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
     }
     if (stall) {
       // the split-precision operator has a noise floor: stop once the
-      // residual has not halved over the last 16 products
-      if (rn < 0.5 * best_r) {
+      // residual has not dropped by 10% over the last 24 products
+      if (rn < 0.9 * best_r) {
         best_r = rn;
         best_at = nmv;
-      } else if (nmv - best_at >= 16) {
+      } else if (nmv - best_at >= 24) {
         break;
       }
     }

@@ -171,6 +171,7 @@ struct Context {
   int64_t heff_terms = 0;
   Stats stats;
   int64_t scratch_limit = int64_t(1) << 30;  // doubles of phase-1 scratch (8 GB)
+  bool keep_envs = true;  // keep every block environment built (needed by sweeps)
 
   ~Context();
   void reset_envs();

@@ -125,6 +125,7 @@ struct DevPlan {
   int64_t n_tiles = 0, n_outs = 0, n_segs = 0;
   int64_t n_big = 0, n_small = 0;  // 64x64 workgroup tiles first, then 32x32 wave tiles
   double flop = 0.0;
+  double flop_big = 0.0, flop_small = 0.0;  // algorithmic FLOP of the outputs of each tile class
 };
 DevPlan *dev_plan_upload(Device *, const GemmPlan &);
 void dev_plan_free(Device *, DevPlan *);
@@ -134,11 +135,12 @@ void dev_plan_free(Device *, DevPlan *);
 void dev_gemm_run(Device *, const DevPlan *, const Bases &, int tag = 0, int prec = 0);
 void dev_d2f(Device *, const double *x, float *y, int64_t n);
 void dev_f2d(Device *, const float *x, double *y, int64_t n);
-// HIP-event timing of tagged grouped-GEMM launches (tag 1..7): elapsed
-// milliseconds, launch count and algorithmic FLOP per tag since creation.
+// HIP-event timing of tagged grouped-GEMM launches (tag 1..7), kept per
+// kernel variant (0: 64x64 workgroup tiles, 1: 32x32 wave tiles): elapsed
+// milliseconds, launch count and algorithmic FLOP since creation.
 constexpr int kTags = 8;
 void dev_timing_enable(Device *, bool on);
-void dev_timing_collect(Device *, double *ms, double *launches, double *flop);
+void dev_timing_collect(Device *, double ms[][2], double launches[][2], double flop[][2]);
 
 // Deterministic split-K reduction: y[off+i] += sum_{s<S} P[s*stride + off+i]
 // over a list of blocks (off, len), s ascending.

@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOCONV, EUNSUP = 0, -1, -2, -3, -4, -5, -6
 SPINLESS, HUBBARD = 0, 1
 REAL, MOMENTUM = 0, 1
 FP64, FP32, BF16X3 = 0, 1, 2
+OPT_KEEP_ENVS, OPT_SCRATCH_LIMIT = 1, 2
 
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)
 _c_i32_p = ctypes.POINTER(ctypes.c_int32)
@@ -39,6 +40,7 @@ EXPORTS = {
     'mdmrg_n_terms': (ctypes.c_int, [ctypes.c_void_p, _c_i64_p, _c_i64_p]),
     'mdmrg_set_mps': (ctypes.c_int, [ctypes.c_void_p, _c_i32_p, _c_i32_p, _c_i32_p, _c_dbl_p, ctypes.c_int64]),
     'mdmrg_get_bond': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i32_p, _c_i32_p, _c_i32_p]),
+    'mdmrg_set_option': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]),
     'mdmrg_prepare_bond': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     'mdmrg_psi_layout': (ctypes.c_int, [ctypes.c_void_p, _c_i64_p, _c_i32_p, _c_i32_p]),
     'mdmrg_heff_apply': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
@@ -195,6 +197,9 @@ class Context:
         return [((int(qn[2 * k]), int(qn[2 * k + 1])), int(dim[k])) for k in range(n.value)]
 
     # ----------------------------------------------------------------- bond
+    def set_option(self, option, value):
+        self._chk(self.lib.mdmrg_set_option(self.h, option, int(value)))
+
     def prepare_bond(self, l):
         self._chk(self.lib.mdmrg_prepare_bond(self.h, l))
 
@@ -267,12 +272,15 @@ class Context:
                                               sd.ctypes.data_as(_c_i64_p), _dp(al)))
 
     def stats(self):
-        out = np.zeros(25)
+        out = np.zeros(35)
         self._chk(self.lib.mdmrg_get_stats(self.h, _dp(out)))
         keys = ['diag_h_s', 'ren_s', 'tables_s', 'diag_d_s', 'stvec_s', 'other_s', 'heff_flop', 'n_matvec',
                 'heff_gemm_ms', 'heff_gemm_launches', 'heff_gemm_flop',
                 'ren_gemm_ms', 'ren_gemm_launches', 'ren_gemm_flop',
                 'heff_flop_split', 'n_matvec_split', 'split_gemm_ms', 'split_gemm_launches',
                 'split_gemm_flop', 'heff_p1_ms', 'heff_p1_launches', 'heff_p1_flop',
-                'grouped_ms', 'grouped_launches', 'grouped_flop']
+                'grouped_ms', 'grouped_launches', 'grouped_flop',
+                'heff_t64_ms', 'heff_t64_launches', 'heff_t64_flop',
+                'heff_t32_ms', 'heff_t32_launches', 'heff_t32_flop',
+                'all_t64_ms', 'all_t64_launches', 'all_t32_ms', 'all_t32_launches']
         return dict(zip(keys, out.tolist()))
