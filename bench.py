@@ -12,6 +12,10 @@ the sector-dimension profile of every bond; it is scaled to D and filled with
 seeded random isometries (seed 1); the operators of both blocks are then
 renormalised on the GPU.  Inputs are resident in HBM before timing starts.
 
+--workload spinless8x8 selects the spinless 8x8 torus (t=1, V=2, N=32,
+momentum basis rotated inside degenerate shells, dense two-body integrals)
+instead; --keep-envs 0 keeps only the block environments in use (large D).
+
 Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
 this build runs on one GPU.
 """
@@ -28,28 +32,58 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 MFMA
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+# HBM traffic per launch of the dominant kernel, from FETCH_SIZE / WRITE_SIZE
+# counter passes over this same command (paper_2311_14106_amd/traffic.py)
+TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'k_gemm_traffic_hubbard6x6_D1024.txt')
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel_key, D):
+    """HBM bytes per launch recorded for this kernel and bond dimension, or
+    None when absent or taken on other kernel / planner sources."""
+    from paper_2311_14106_amd import traffic
+    try:
+        with open(TRAFFIC_FILE) as f:
+            txt = f.read()
+        rec = json.loads(txt[txt.index('{'):txt.rindex('}') + 1])
+    except (OSError, ValueError):
+        return None
+    if (rec.get('sources_sha256') != traffic.sources_digest() or rec.get('kernel_key') != kernel_key
+            or rec.get('D') != D):
+        return None
+    return rec.get('hbm_bytes_per_launch')
+
+
+WORKLOADS = {
+    'hubbard6x6': 'Hubbard 6x6 torus t=1 U=4 momentum basis, 18up+18dn, U(1)xU(1)',
+    'spinless8x8': 'spinless 8x8 torus t=1 V=2 momentum basis rotated within degenerate shells '
+                   '(seed 0, angle 0.1), dense V, N=32, U(1)',
+}
+
+
 def make_workload(mdmrg, ctx, args):
+    """Hamiltonian of the workload and the sector profile of every bond: a
+    short real two-site run at low bond dimension, scaled to D."""
     import seeded_inputs as si
-    Lx = Ly = 6
-    n = Lx * Ly
-    target = (18, 18)
-    T, V = mdmrg.build_lattice(mdmrg.HUBBARD, mdmrg.MOMENTUM, Lx, Ly, 1.0, 4.0)
-    ctx.set_hamiltonian(n, True, T, V, target)
-    # profile from a short real run at low D
-    b0 = si.bond_profile(n, True, target, 16)
-    ctx.set_mps(*si.flatten_mps(b0, si.random_mps(b0, True, 1, 0), True))
+    if args.workload == 'hubbard6x6':
+        n, spin, target = 36, True, (18, 18)
+        T, V = mdmrg.build_lattice(mdmrg.HUBBARD, mdmrg.MOMENTUM, 6, 6, 1.0, 4.0)
+    else:
+        n, spin, target = 64, False, (32, 0)
+        T, V = mdmrg.build_lattice(mdmrg.SPINLESS, mdmrg.MOMENTUM, 8, 8, 1.0, 2.0)
+        T, V = mdmrg.rotate_modes(si.shell_rotation(np.diag(T), 0), T, V, False)
+    ctx.set_hamiltonian(n, spin, T, V, target)
+    b0 = si.bond_profile(n, spin, target, 16)
+    ctx.set_mps(*si.flatten_mps(b0, si.random_mps(b0, spin, 1, 0), spin))
     t0 = time.time()
     ctx.sweep(1, [args.profile_D], 1e-6)
     small = [ctx.get_bond(i) for i in range(n + 1)]
     log(f'[bench] profile run D={args.profile_D}: {time.time() - t0:.1f}s')
-    bonds = si.scale_profile(small, n, True, target, args.D)
-    return n, target, bonds
+    bonds = si.scale_profile(small, n, spin, target, args.D)
+    return n, spin, target, bonds
 
 
 def cpu_baseline(mdmrg, budget_s):
@@ -126,8 +160,12 @@ def main():
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=3)
     ap.add_argument('--warmup', type=int, default=1)
+    ap.add_argument('--workload', choices=sorted(WORKLOADS), default='hubbard6x6')
     ap.add_argument('--D', type=int, default=1024)
-    ap.add_argument('--profile-D', type=int, default=128)
+    ap.add_argument('--profile-D', type=int, default=None,
+                    help='bond dimension of the profile run (default 128 Hubbard, 64 spinless 8x8)')
+    ap.add_argument('--keep-envs', type=int, default=1,
+                    help='0: keep only the block environments in use (large D)')
     ap.add_argument('--tol', type=float, default=1e-7)
     ap.add_argument('--cpu-budget', type=float, default=15.0)
     ap.add_argument('--no-cpu', action='store_true')
@@ -135,6 +173,8 @@ def main():
     ap.add_argument('--split-tol', type=float, default=1e-5,
                     help='FP64 residual tolerance of the fixed-dE Davidson comparison')
     args = ap.parse_args()
+    if args.profile_D is None:
+        args.profile_D = 128 if args.workload == 'hubbard6x6' else 64
     if args.gpus != 1:
         print(f'bench.py: --gpus {args.gpus} is not supported; this build runs on exactly one GPU '
               f'(run with --gpus 1)', file=sys.stderr)
@@ -147,10 +187,11 @@ def main():
     assert torch.cuda.is_available(), 'bench.py needs a GPU'
 
     ctx = mdmrg.Context(0)
-    n, target, bonds = make_workload(mdmrg, ctx, args)
+    n, spin, target, bonds = make_workload(mdmrg, ctx, args)
+    ctx.set_option(mdmrg.OPT_KEEP_ENVS, args.keep_envs)
     l0 = n // 2 - 1 - args.warmup - args.steps // 2
     t0 = time.time()
-    ctx.set_mps(*si.flatten_mps(bonds, si.random_mps(bonds, True, 1, l0), True))
+    ctx.set_mps(*si.flatten_mps(bonds, si.random_mps(bonds, spin, 1, l0), spin))
     ctx.prepare_bond(l0)
     log(f'[bench] environment at bond {l0} built in {time.time() - t0:.1f}s')
     _, ne = ctx.psi_layout()
@@ -173,8 +214,11 @@ def main():
     costs = []
     t0 = time.time()
     energies = []
+    hist = None
     for k in range(args.steps):
         costs.append(ctx.heff_cost())
+        h = ctx.heff_histogram()
+        hist = h if hist is None else {b: hist[b] + h[b] for b in h}
         x, e, r, nmv = step(x)
         energies.append(e)
         log(f'[bench] step {k}: E={e:.10f} |r|={r:.1e} matvecs={nmv}')
@@ -208,11 +252,13 @@ def main():
     roof.update({'kernel': name, 'launches': int(k_launch), 'avg_launch_ms': k_ms / k_launch,
                  'flop_per_launch': k_flop / k_launch,
                  'share_of_heff_gemm_time': k_ms / max(tot_ms, 1e-9),
-                 'avg_launch_ms_whole_process': s1['all_' + dom + '_ms'] / max(1.0, s1['all_' + dom + '_launches']),
-                 'launches_whole_process': int(s1['all_' + dom + '_launches']),
+                 # dispatch indices of this kernel (FP64) in the whole process
+                 'launch_window_whole_process': [int(s0['proc_f64_' + dom + '_launches']),
+                                                 int(s1['proc_f64_' + dom + '_launches'])],
                  'heff_intensity_flop_per_byte': intensity,
                  'heff_gemm_tflops_all_variants': (d['heff_t64_flop'] + d['heff_t32_flop']) / max(tot_ms, 1e-9) / 1e9,
                  'phase1_ms': d['heff_p1_ms'], 'phase2_ms': d['heff_gemm_ms']})
+    roof['traffic'] = measured_traffic(dom, args.D) if args.workload == 'hubbard6x6' else None
     out = {
         'metric': 'H_eff·ψ TFLOP/s and Davidson s/step, FP64 vs split-precision at fixed ΔE',
         'value': heff_flop / wall / 1e12,
@@ -226,13 +272,15 @@ def main():
         'vs_baseline': None,
         'dtype': 'f64',
         'data': 'synthetic',
-        'config': {'workload': f'Hubbard 6x6 torus t=1 U=4 momentum basis, 18up+18dn, U(1)xU(1), '
-                               f'D={args.D}, two-site DMRG steps from bond {l0 + args.warmup}',
+        'config': {'workload': f'{WORKLOADS[args.workload]}, D={args.D}, two-site DMRG steps from bond '
+                               f'{l0 + args.warmup}',
                    'D': args.D, 'n_sites': n, 'precision_form': 'plain FP64',
                    'davidson_tol': args.tol},
         'davidson_s_per_step': d['diag_h_s'] / args.steps,
         'matvecs_per_step': nmv_total / args.steps,
         'heff_flop_per_matvec': flop_per_mv,
+        # share of H_eff FLOP by the smaller output side of each GEMM (bin lower edges)
+        'heff_flop_share_by_min_mn': {str(b): v / max(sum(hist.values()), 1.0) for b, v in hist.items()},
         'step_breakdown_s': {k: d[k] / args.steps for k in
                              ('diag_h_s', 'ren_s', 'tables_s', 'diag_d_s', 'stvec_s')},
         'energies': energies,
@@ -242,6 +290,11 @@ def main():
         out['split_precision'] = split_compare(ctx, x, torch, args)
     if not args.no_cpu:
         out['cpu_baseline'] = cpu_baseline(mdmrg, args.cpu_budget)
+    # every launch of the kernel in this process (all contexts), for
+    # comparison with a kernel-trace profile of the same command
+    sp = ctx.stats()
+    roof['avg_launch_ms_whole_process'] = sp['proc_f64_' + dom + '_ms'] / max(1.0, sp['proc_f64_' + dom + '_launches'])
+    roof['launches_whole_process'] = int(sp['proc_f64_' + dom + '_launches'])
     print(json.dumps(out), flush=True)
 
 

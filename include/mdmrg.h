@@ -169,6 +169,13 @@ int mdmrg_heff_diag(mdmrg_ctx ctx, double *d);
  * pointer may be NULL. */
 int mdmrg_heff_cost(mdmrg_ctx ctx, double *flop, double *bytes, int64_t *n_terms, int64_t *n_gemm);
 
+/* Shape profile of one H_eff x at the current bond (the workload shape the
+ * grouped kernels see): algorithmic FLOP of its GEMMs binned by the smaller
+ * output side min(m, n), bins [1,16) [16,32) [32,48) [48,64) [64,128)
+ * [128,256) [256,512) [512,inf); flop_by_bin must hold 8 doubles.  Sums to
+ * the FLOP of mdmrg_heff_cost.  ESTATE before mdmrg_prepare_bond. */
+int mdmrg_heff_histogram(mdmrg_ctx ctx, double *flop_by_bin);
+
 /* Davidson for the lowest eigenpair of H_eff (Sec. II.A), FP64 on device.
  * x (device, n_elem) holds the start vector on entry (normalised inside; if
  * zero, a seeded random vector is used) and the eigenvector on exit.
@@ -234,7 +241,7 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
 /* Wall seconds per step category (Diag_H, Ren, Tables, Diag_D, StVec,
  * Other) accumulated since creation, the algorithmic FLOP of all H_eff
  * products, and HIP-event timings of the grouped-GEMM launches on the
- * context stream; out must hold 35 doubles:
+ * context stream; out must hold 47 doubles:
  * [diag_h, ren, tables, diag_d, stvec, other, heff_flop, n_matvec,
  *  heff_gemm_ms, heff_gemm_launches, heff_gemm_flop,
  *  ren_gemm_ms, ren_gemm_launches, ren_gemm_flop,
@@ -244,9 +251,13 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
  *  grouped_ms, grouped_launches, grouped_flop (mdmrg_gemm_grouped calls),
  *  heff_tile64_ms, heff_tile64_launches, heff_tile64_flop,
  *  heff_tile32_ms, heff_tile32_launches, heff_tile32_flop,
- *  all_tile64_ms, all_tile64_launches, all_tile32_ms, all_tile32_launches].
+ *  all_tile64_ms, all_tile64_launches, all_tile32_ms, all_tile32_launches,
+ *  proc_f64_tile64_{ms, launches, flop}, proc_f64_tile32_{ms, launches, flop},
+ *  proc_f32_tile64_{ms, launches, flop}, proc_f32_tile32_{ms, launches, flop}].
  * tile64 = k_gemm (64x64 workgroup tiles), tile32 = k_gemm_wave (32x32 wave
- * tiles); heff_* = FP64 H_eff products, all_* = every timed launch.
+ * tiles); heff_* = FP64 H_eff products, all_* = every launch of the context
+ * (FP64 and FP32), proc_* = every launch of one kernel (element type x tile
+ * variant) in the whole process, over all contexts including destroyed ones.
  * heff_gemm_* covers the accumulation (second) phase of the FP64 H_eff
  * products and heff_phase1_* their intermediate (first) phase. */
 int mdmrg_get_stats(mdmrg_ctx ctx, double *out);

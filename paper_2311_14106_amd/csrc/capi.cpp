@@ -260,6 +260,13 @@ int mdmrg_heff_cost(mdmrg_ctx ctx, double *flop, double *bytes, int64_t *n_terms
   return MDMRG_OK;
 }
 
+int mdmrg_heff_histogram(mdmrg_ctx ctx, double *flop_by_bin) {
+  if (!ctx || !flop_by_bin) return MDMRG_EINVAL;
+  if (ctx->c.cur < 0) return MDMRG_ESTATE;
+  for (int b = 0; b < TwoPhasePlan::kHistBins; ++b) flop_by_bin[b] = ctx->c.heff.hist_flop[b];
+  return MDMRG_OK;
+}
+
 int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max, double *energy, double *resid,
                    int *n_matvec) {
   if (!ctx || !x || !(tol > 0) || max_iter < 1) return MDMRG_EINVAL;
@@ -432,6 +439,14 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
       out[31 + 2 * k] = am;
       out[32 + 2 * k] = al;
     }
+    double pm[2][2], pl[2][2], pf[2][2];
+    dev_timing_process(ctx->c.dev, pm, pl, pf);
+    for (int p = 0; p < 2; ++p)
+      for (int k = 0; k < 2; ++k) {
+        out[35 + 3 * (2 * p + k)] = pm[p][k];
+        out[36 + 3 * (2 * p + k)] = pl[p][k];
+        out[37 + 3 * (2 * p + k)] = pf[p][k];
+      }
     return MDMRG_OK;
   });
 }

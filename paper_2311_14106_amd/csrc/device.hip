@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <numeric>
 
 #include "internal.h"
@@ -37,7 +38,7 @@ struct Device {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   struct Pending {
-    int tag, kind;
+    int tag, kind, prec;
     hipEvent_t a, b;
     double flop;
   };
@@ -56,19 +57,39 @@ static hipEvent_t ev_get(Device *d) {
   return e;
 }
 
+// Process-wide totals per kernel (precision x tile variant), summed over
+// every device context of the process, including destroyed ones.
+static std::mutex g_timing_mu;
+static double g_ms[2][2], g_launches[2][2], g_flop[2][2];
+
 static void timing_drain(Device *d) {
   if (d->pending.empty()) return;
   HIP_CHECK(hipEventSynchronize(d->pending.back().b));
+  std::lock_guard<std::mutex> lk(g_timing_mu);
   for (auto &p : d->pending) {
     float t = 0.f;
     HIP_CHECK(hipEventElapsedTime(&t, p.a, p.b));
     d->ms[p.tag][p.kind] += t;
     d->launches[p.tag][p.kind] += 1;
     d->flop[p.tag][p.kind] += p.flop;
+    g_ms[p.prec][p.kind] += t;
+    g_launches[p.prec][p.kind] += 1;
+    g_flop[p.prec][p.kind] += p.flop;
     d->ev_pool.push_back(p.a);
     d->ev_pool.push_back(p.b);
   }
   d->pending.clear();
+}
+
+void dev_timing_process(Device *d, double ms[2][2], double launches[2][2], double flop[2][2]) {
+  timing_drain(d);
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  for (int p = 0; p < 2; ++p)
+    for (int k = 0; k < 2; ++k) {
+      ms[p][k] = g_ms[p][k];
+      launches[p][k] = g_launches[p][k];
+      flop[p][k] = g_flop[p][k];
+    }
 }
 
 void dev_timing_enable(Device *d, bool on) { d->timing = on; }
@@ -109,6 +130,10 @@ void dev_destroy(Device *d) {
   if (!d) return;
   (void)hipSetDevice(d->id);
   (void)hipStreamSynchronize(d->stream);
+  try {
+    timing_drain(d);  // keep the process-wide totals complete
+  } catch (...) {
+  }
   for (auto &p : d->pending) {
     d->ev_pool.push_back(p.a);
     d->ev_pool.push_back(p.b);
@@ -179,7 +204,8 @@ void dev_zero(Device *d, void *dst, size_t bytes) {
 // C[l/16 + 4r][l%16] for FP64 and C[4(l/16) + r][l%16] for FP32.
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int TM = 64, TN = 64, TK = 16, LDP = TM + 2;
+constexpr int TK = 16;  // K step of the workgroup-tile kernel
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 
 // one MFMA 16x16x4 step in the element type of the kernel: FP64
 // (v_mfma_f64_16x16x4f64) or FP32 (v_mfma_f32_16x16x4f32), same operand
@@ -205,136 +231,225 @@ struct Mfma<float> {
   }
 };
 
-// Per-thread load state of one segment: each thread stages 4 elements of
-// op(A) and 4 of op(B) per K step.  Base pointers are uniform over the
-// workgroup; per-element offsets, validity and K offsets are fixed per
-// segment, so the K loop only adds the step offset and checks the K bound.
-template <class T>
+// Workgroup tile of the grouped kernel: BM x BN outputs per workgroup of
+// WY x WX waves, each wave a (BM/WY) x (BN/WX) block of 16x16 MFMA tiles;
+// K staged through LDS in steps of TK with one step of register prefetch;
+// kXSEG: the prefetch runs across segment boundaries.
+constexpr int kBM = 64, kBN = 64, kWY = 2, kWX = 4;
+constexpr bool kXSEG = false;
+constexpr int kPad = 2;  // LDS row padding (doubles) of the staged A / B tiles
+constexpr int kNT = 64 * kWY * kWX;  // threads per workgroup
+
+// Per-thread load state of one segment: each thread stages EA elements of
+// op(A) and EB of op(B) per K step.  Element `it` of a thread sits at row
+// i0 + di*it and K offset k0 + dk*it of the staged tile ((di, dk) follow
+// from the operand's transposition), so its memory offset is affine in
+// `it` too: o0 + it*dO.  Base pointers are uniform over the workgroup.
+template <class T, int BM, int BN, int NT = kNT>
 struct SegLoad {
+  static constexpr int EA = BM * TK / NT, EB = BN * TK / NT;
+  static_assert(EA >= 1 && EB >= 1 && NT % BM == 0 && NT % BN == 0 && NT % TK == 0, "tile / thread mismatch");
   const T *A, *B;
-  int32_t oa[4], ob[4];  // element offsets inside the operand blocks
-  int32_t da, db;        // advance per K step (elements)
-  int8_t ka[4], kb[4];   // k offset of each staged element within the step
-  uint8_t va, vb;        // bit it: element it lies inside the output tile
+  int32_t oa0, doa, ob0, dob;  // element offset of it = 0 and per-it increment
+  int32_t da, db;              // advance per K step (elements)
+  int32_t ka0, dka, kb0, dkb;  // K offset within the step: k0 + dk*it
+  int32_t ia0, dia;            // A: first output row and its increment (identity operands)
+  uint32_t va, vb;             // bit it: element it lies inside the output
   int k;
   T alpha;
   bool idA, tA, tB;
 };
 
-template <class T>
-__device__ inline void seg_setup(SegLoad<T> &L, const GSeg &sg, const Bases &bases, const GOut &o, int row0,
-                                 int col0, int tid) {
+template <class T, int BM, int BN>
+__device__ inline void seg_setup(SegLoad<T, BM, BN> &L, const GSeg &sg, const Bases &bases, const GOut &o,
+                                 int row0, int col0, int tid) {
   L.A = reinterpret_cast<const T *>(bases.p[sg.a_slot]) + sg.a_off;
   L.B = reinterpret_cast<const T *>(bases.p[sg.b_slot]) + sg.b_off;
-  L.tA = sg.flags & SEG_TA;
-  L.tB = sg.flags & SEG_TB;
+  const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB;
+  L.tA = tA;
+  L.tB = tB;
   L.idA = sg.flags & SEG_AID;
   L.alpha = T(sg.alpha);
   L.k = sg.k;
-  L.da = L.tA ? TK * sg.lda : TK;
-  L.db = L.tB ? TK : TK * sg.ldb;
+  L.da = tA ? TK * sg.lda : TK;
+  L.db = tB ? TK : TK * sg.ldb;
+  // A tile BM x TK: row-major source -> (i, kk) = (e / TK, e % TK);
+  // transposed source -> (e % BM, e / BM); e = tid + NT it
+  constexpr int NT = kNT;
+  const int i0 = tA ? tid % BM : tid / TK, di = tA ? 0 : NT / TK;
+  L.ka0 = tA ? tid / BM : tid % TK;
+  L.dka = tA ? NT / BM : 0;
+  L.ia0 = row0 + i0;
+  L.dia = di;
+  const int j0 = tB ? tid / TK : tid % BN, dj = tB ? NT / TK : 0;
+  // offsets are formed only for rows / columns inside the output (later
+  // elements of a thread never re-enter it), so they stay within the
+  // operand extents the host checked against 32-bit range
+  const bool a_in = row0 + i0 < o.m, b_in = col0 + j0 < o.n;
+  L.oa0 = !a_in ? 0 : (tA ? L.ka0 * sg.lda + i0 + row0 : (i0 + row0) * sg.lda + L.ka0);
+  L.doa = tA ? L.dka * sg.lda : di * sg.lda;
+  // B tile TK x BN: row-major source -> (kb, j) = (e / BN, e % BN);
+  // transposed source -> (e % TK, e / TK)
+  L.kb0 = tB ? tid % TK : tid / BN;
+  L.dkb = tB ? 0 : NT / BN;
+  L.ob0 = !b_in ? 0 : (tB ? (j0 + col0) * sg.ldb + L.kb0 : L.kb0 * sg.ldb + j0 + col0);
+  L.dob = tB ? dj * sg.ldb : L.dkb * sg.ldb;
   L.va = 0;
   L.vb = 0;
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const int e = tid + it * 256;
-    const int i = L.tA ? (e % TM) : (e / TK), kk = L.tA ? (e / TM) : (e % TK);
-    const int gi = row0 + i;
-    L.ka[it] = int8_t(kk);
-    if (gi < o.m) L.va |= uint8_t(1 << it);
-    L.oa[it] = L.idA ? gi : (L.tA ? kk * sg.lda + gi : gi * sg.lda + kk);
-    const int j = L.tB ? (e / TK) : (e % TN), kb = L.tB ? (e % TK) : (e / TN);
-    const int gj = col0 + j;
-    L.kb[it] = int8_t(kb);
-    if (gj < o.n) L.vb |= uint8_t(1 << it);
-    L.ob[it] = L.tB ? gj * sg.ldb + kb : kb * sg.ldb + gj;
-  }
+  for (int it = 0; it < L.EA; ++it)
+    if (L.ia0 + di * it < o.m) L.va |= 1u << it;
+#pragma unroll
+  for (int it = 0; it < L.EB; ++it)
+    if (col0 + j0 + dj * it < o.n) L.vb |= 1u << it;
 }
 
-template <class T>
-__device__ inline void seg_fetch(const SegLoad<T> &L, int step, T ra[4], T rb[4]) {
+template <class T, int BM, int BN>
+__device__ inline void seg_fetch(const SegLoad<T, BM, BN> &L, int step, T (&ra)[SegLoad<T, BM, BN>::EA],
+                                 T (&rb)[SegLoad<T, BM, BN>::EB]) {
   const int k0 = step * TK;
   const int64_t sa = int64_t(step) * L.da, sb = int64_t(step) * L.db;
+  const T *Ap = L.A + sa, *Bp = L.B + sb;
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const int gk = k0 + L.ka[it];
+  for (int it = 0; it < L.EA; ++it) {
+    const int gk = k0 + L.ka0 + L.dka * it;
     T v = T(0);
     if (((L.va >> it) & 1) && gk < L.k)
-      v = L.idA ? ((L.oa[it] == gk) ? L.alpha : T(0)) : L.alpha * L.A[sa + L.oa[it]];
+      v = L.idA ? ((L.ia0 + L.dia * it == gk) ? L.alpha : T(0)) : L.alpha * Ap[L.oa0 + L.doa * it];
     ra[it] = v;
-    const int gkb = k0 + L.kb[it];
-    rb[it] = (((L.vb >> it) & 1) && gkb < L.k) ? L.B[sb + L.ob[it]] : T(0);
   }
-}
-
-template <class T>
-__device__ inline void seg_store(const SegLoad<T> &L, int tid, const T ra[4], const T rb[4], T *As, T *Bs) {
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const int e = tid + it * 256;
-    const int i = L.tA ? (e % TM) : (e / TK), kk = L.tA ? (e / TM) : (e % TK);
-    As[kk * LDP + i] = ra[it];
-    const int j = L.tB ? (e / TK) : (e % TN), kb = L.tB ? (e % TK) : (e / TN);
-    Bs[kb * LDP + j] = rb[it];
+  for (int it = 0; it < L.EB; ++it) {
+    const int gkb = k0 + L.kb0 + L.dkb * it;
+    rb[it] = (((L.vb >> it) & 1) && gkb < L.k) ? Bp[L.ob0 + L.dob * it] : T(0);
+  }
+}
+
+// LDS position of element `it`: A stage [kk][BM + 2], B stage [kb][BN + 2];
+// the row / column of an element is recovered from its thread and `it`
+template <class T, int BM, int BN>
+__device__ inline void seg_store(const SegLoad<T, BM, BN> &L, int tid, const T (&ra)[SegLoad<T, BM, BN>::EA],
+                                 const T (&rb)[SegLoad<T, BM, BN>::EB], T *As, T *Bs) {
+  constexpr int NT = kNT;
+  const int i0 = L.tA ? tid % BM : tid / TK, di = L.tA ? 0 : NT / TK;
+  const int j0 = L.tB ? tid / TK : tid % BN, dj = L.tB ? NT / TK : 0;
+#pragma unroll
+  for (int it = 0; it < L.EA; ++it) As[(L.ka0 + L.dka * it) * (BM + kPad) + i0 + di * it] = ra[it];
+#pragma unroll
+  for (int it = 0; it < L.EB; ++it) Bs[(L.kb0 + L.dkb * it) * (BN + kPad) + j0 + dj * it] = rb[it];
+}
+
+// MFMAs of one K step on the LDS stage (Ab, Bb) for this wave's quadrant;
+// 16x16 blocks wholly outside the output are skipped (wave-uniform masks).
+constexpr int kMI = kBM / kWY / 16, kNI = kBN / kWX / 16;  // MFMA tiles per wave
+template <class T, int BM, int BN>
+__device__ inline void tile_mfma(const T *Ab, const T *Bb, int wm, int wn, int lr, int lk, bool full, int qm,
+                                 int qn, typename Mfma<T>::acc_t (&acc)[kMI][kNI]) {
+  constexpr int MI = kMI, NI = kNI;
+#pragma unroll
+  for (int kk = 0; kk < TK; kk += 4) {
+    T a[MI], b[NI];
+#pragma unroll
+    for (int mi = 0; mi < MI; ++mi) a[mi] = Ab[(kk + lk) * (BM + kPad) + wm + 16 * mi + lr];
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) b[ni] = Bb[(kk + lk) * (BN + kPad) + wn + 16 * ni + lr];
+#pragma unroll
+    for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < NI; ++ni)
+        if (full || (qm > 16 * mi && qn > 16 * ni)) acc[mi][ni] = Mfma<T>::step(a[mi], b[ni], acc[mi][ni]);
   }
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_gemm(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
+__global__ __launch_bounds__(kNT) void k_gemm(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
                                               const GSeg *__restrict__ segs, Bases bases) {
-  // Double-buffered inside a segment: while the MFMAs consume LDS buffer
-  // `buf`, the next K step is fetched into registers and then written to
-  // the other buffer; one barrier per K step.
+  constexpr int BM = kBM, BN = kBN, MI = kMI, NI = kNI;
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T As[2][TK * LDP];
-  __shared__ T Bs[2][TK * LDP];
+  typedef SegLoad<T, BM, BN> SL;
+  __shared__ T As[2][TK * (BM + kPad)];
+  __shared__ T Bs[2][TK * (BN + kPad)];
   const GTile tl = tiles[blockIdx.x];
+  if (tl.out < 0) return;  // queue padding; uniform over the workgroup, before any barrier
   const GOut o = outs[tl.out];
-  const int row0 = int(tl.ti) * TM, col0 = int(tl.tj) * TN;
+  const int row0 = int(tl.ti) * BM, col0 = int(tl.tj) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave / kWX) * (BM / kWY), wn = (wave % kWX) * (BN / kWX);
   const int lr = lane & 15, lk = lane >> 4;
-  acc_t acc[2][2];
+  // rows / columns of this wave's quadrant inside the output (wave-uniform)
+  const int qm = o.m - (row0 + wm), qn = o.n - (col0 + wn);
+  const bool full = qm >= BM / kWY && qn >= BN / kWX;
+  acc_t acc[MI][NI];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+    for (int j = 0; j < NI; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  T ra[4], rb[4];
-  SegLoad<T> L;
-  int buf = 0;
-  for (int si = 0; si < o.seg_count; ++si) {
-    seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
-    const int nsteps = (L.k + TK - 1) / TK;
-    if (nsteps == 0) continue;
-    seg_fetch(L, 0, ra, rb);
-    seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
-    __syncthreads();
-    for (int step = 0; step < nsteps; ++step) {
-      const bool more = step + 1 < nsteps;
-      if (more) seg_fetch(L, step + 1, ra, rb);
-      const T *Ab = As[buf], *Bb = Bs[buf];
-#pragma unroll
-      for (int kk = 0; kk < TK; kk += 4) {
-        const T a0 = Ab[(kk + lk) * LDP + wm + lr];
-        const T a1 = Ab[(kk + lk) * LDP + wm + 16 + lr];
-        const T b0 = Bb[(kk + lk) * LDP + wn + lr];
-        const T b1 = Bb[(kk + lk) * LDP + wn + 16 + lr];
-        acc[0][0] = Mfma<T>::step(a0, b0, acc[0][0]);
-        acc[0][1] = Mfma<T>::step(a0, b1, acc[0][1]);
-        acc[1][0] = Mfma<T>::step(a1, b0, acc[1][0]);
-        acc[1][1] = Mfma<T>::step(a1, b1, acc[1][1]);
-      }
-      buf ^= 1;
-      if (more) seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
+  SL L;
+  T ra[SL::EA], rb[SL::EB];
+  if (kXSEG) {
+    // one pipeline over all (segment, K step) pairs: the step after the last
+    // one of a segment is the first step of the next non-empty segment, whose
+    // load state replaces the current one (whose data already sits in LDS)
+    int si = 0;
+    while (si < o.seg_count && segs[o.seg_begin + si].k <= 0) ++si;
+    if (si < o.seg_count) {
+      seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
+      int nsteps = (L.k + TK - 1) / TK, step = 0, buf = 0;
+      seg_fetch(L, 0, ra, rb);
+      seg_store(L, tid, ra, rb, As[0], Bs[0]);
       __syncthreads();
+      for (;;) {
+        bool more = true;
+        if (step + 1 < nsteps) {
+          ++step;
+          seg_fetch(L, step, ra, rb);
+        } else {
+          int sn = si + 1;
+          while (sn < o.seg_count && segs[o.seg_begin + sn].k <= 0) ++sn;
+          if (sn < o.seg_count) {
+            si = sn;
+            seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
+            nsteps = (L.k + TK - 1) / TK;
+            step = 0;
+            seg_fetch(L, 0, ra, rb);
+          } else {
+            more = false;
+          }
+        }
+        tile_mfma<T, BM, BN>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
+        if (!more) break;
+        buf ^= 1;
+        seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
+        __syncthreads();
+      }
+    }
+  } else {
+    for (int si = 0; si < o.seg_count; ++si) {
+      seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
+      const int nsteps = (L.k + TK - 1) / TK;
+      if (nsteps == 0) continue;
+      // double-buffered LDS: while the MFMAs consume stage `buf`, the next
+      // K step is fetched into registers and then written to the other stage
+      int buf = 0;
+      seg_fetch(L, 0, ra, rb);
+      seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
+      __syncthreads();
+      for (int step = 0; step < nsteps; ++step) {
+        const bool more = step + 1 < nsteps;
+        if (more) seg_fetch(L, step + 1, ra, rb);
+        tile_mfma<T, BM, BN>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
+        buf ^= 1;
+        if (more) seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
+        __syncthreads();
+      }
     }
   }
   T *C = reinterpret_cast<T *>(bases.p[o.c_slot]) + o.c_off;
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
+    for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gi = row0 + wm + mi * 16 + Mfma<T>::row(lk, r);
@@ -362,6 +477,7 @@ __global__ __launch_bounds__(256) void k_gemm_wave(const GTile *__restrict__ til
   const int64_t t = int64_t(blockIdx.x) * 4 + wave;
   if (t >= n_tiles) return;  // wave-uniform exit; the kernel has no barrier
   const GTile tl = tiles[t];
+  if (tl.out < 0) return;  // queue padding; wave-uniform
   const GOut o = outs[tl.out];
   const int row0 = int(tl.ti) * WT, col0 = int(tl.tj) * WT;
   const int lr = lane & 15, lk = lane >> 4;
@@ -461,9 +577,17 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
     work[i] = {-(kk + 16.0) * o.m * o.n, int32_t(i)};
   }
   std::stable_sort(work.begin(), work.end());
-  // outputs with both sides >= 48 use 64x64 workgroup tiles, the rest
-  // 32x32 wave tiles
-  std::vector<GTile> tiles, small;
+  // outputs of the big class (gemm_big_tile) use kBM x kBN workgroup tiles, the rest
+  // 32x32 wave tiles (four to a workgroup).  Workgroups of one launch go to
+  // the 8 XCDs round-robin (workgroup b to XCD b mod 8) and every XCD has
+  // its own L2, so outputs are cut into chunks of whole tile rows (at most
+  // 64 tiles: a few A panels against all B panels of the output), chunks are
+  // dealt to per-XCD queues (largest first, to the queue with the least
+  // work) and the queues interleaved: the tiles of a chunk run on one XCD and
+  // share its L2.  Queues are padded with empty tiles (out = -1).
+  constexpr int kChunkTiles = 64;
+  std::vector<std::vector<GTile>> qb(kXcds), qs(kXcds);
+  double load_b[kXcds] = {}, load_s[kXcds] = {};
   for (auto &w : work) {
     const GOut &o = plan.outs[w.second];
     double of = 0.0;
@@ -471,20 +595,43 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
       const GSeg &g = plan.segs[o.seg_begin + q];
       if (!(g.flags & SEG_AID)) of += 2.0 * o.m * o.n * g.k;
     }
-    if (o.m >= 48 && o.n >= 48)
-      dp->flop_big += of;
-    else
-      dp->flop_small += of;
-    if (o.m >= 48 && o.n >= 48) {
-      const int nti = (o.m + TM - 1) / TM, ntj = (o.n + TN - 1) / TN;
-      for (int i = 0; i < nti; ++i)
-        for (int j = 0; j < ntj; ++j) tiles.push_back(GTile{w.second, int16_t(i), int16_t(j)});
-    } else {
-      const int nti = (o.m + WT - 1) / WT, ntj = (o.n + WT - 1) / WT;
-      for (int i = 0; i < nti; ++i)
-        for (int j = 0; j < ntj; ++j) small.push_back(GTile{w.second, int16_t(i), int16_t(j)});
+    const bool big = gemm_big_tile(o.m, o.n);
+    (big ? dp->flop_big : dp->flop_small) += of;
+    const int tm = big ? kBM : WT, tn = big ? kBN : WT;
+    double *load = big ? load_b : load_s;
+    const int nti = (o.m + tm - 1) / tm, ntj = (o.n + tn - 1) / tn;
+    const int rows = std::max(1, kChunkTiles / ntj);
+    for (int i0 = 0; i0 < nti; i0 += rows) {
+      const int i1 = std::min(nti, i0 + rows);
+      const int x = int(std::min_element(load, load + kXcds) - load);
+      load[x] += -w.first * double(i1 - i0) / nti;
+      auto &q = big ? qb[x] : qs[x];
+      for (int i = i0; i < i1; ++i)
+        for (int j = 0; j < ntj; ++j) q.push_back(GTile{w.second, int16_t(i), int16_t(j)});
     }
   }
+  // unit = tiles per workgroup: 1 for the workgroup-tile kernel, 4 for the
+  // wave-tile kernel; position b*unit .. b*unit+unit-1 belongs to workgroup b
+  auto interleave = [](std::vector<std::vector<GTile>> &qs_, int unit) {
+    size_t maxu = 0;
+    for (auto &q : qs_) {
+      while (q.size() % unit) q.push_back(GTile{-1, 0, 0});
+      maxu = std::max(maxu, q.size() / unit);
+    }
+    std::vector<GTile> out;
+    for (size_t u = 0; u < maxu; ++u)
+      for (auto &q : qs_)
+        for (int t = 0; t < unit; ++t) out.push_back(u * unit < q.size() ? q[u * unit + t] : GTile{-1, 0, 0});
+    // trailing empty workgroups are not launched
+    while (out.size() >= size_t(unit)) {
+      bool empty = true;
+      for (int t = 0; t < unit; ++t) empty = empty && out[out.size() - 1 - t].out < 0;
+      if (!empty) break;
+      out.resize(out.size() - unit);
+    }
+    return out;
+  };
+  std::vector<GTile> tiles = interleave(qb, 1), small = interleave(qs, 4);
   dp->n_big = int64_t(tiles.size());
   dp->n_small = int64_t(small.size());
   tiles.insert(tiles.end(), small.begin(), small.end());
@@ -525,10 +672,10 @@ void dev_gemm_run(Device *d, const DevPlan *p, const Bases &b, int tag, int prec
     }
     if (kind == 0) {
       if (prec == 0)
-        hipLaunchKernelGGL(k_gemm<double>, dim3(unsigned(nt)), dim3(256), 0, d->stream, p->tiles, p->outs, p->segs,
+        hipLaunchKernelGGL(k_gemm<double>, dim3(unsigned(nt)), dim3(kNT), 0, d->stream, p->tiles, p->outs, p->segs,
                            b);
       else
-        hipLaunchKernelGGL(k_gemm<float>, dim3(unsigned(nt)), dim3(256), 0, d->stream, p->tiles, p->outs, p->segs,
+        hipLaunchKernelGGL(k_gemm<float>, dim3(unsigned(nt)), dim3(kNT), 0, d->stream, p->tiles, p->outs, p->segs,
                            b);
     } else {
       if (prec == 0)
@@ -541,7 +688,7 @@ void dev_gemm_run(Device *d, const DevPlan *p, const Bases &b, int tag, int prec
     HIP_CHECK(hipGetLastError());
     if (timed) {
       HIP_CHECK(hipEventRecord(e1, d->stream));
-      d->pending.push_back(Device::Pending{tag, kind, e0, e1, kind == 0 ? p->flop_big : p->flop_small});
+      d->pending.push_back(Device::Pending{tag, kind, prec ? 1 : 0, e0, e1, kind == 0 ? p->flop_big : p->flop_small});
     }
   }
 }

@@ -338,6 +338,7 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
         refB(s, t.B, t.tB);
         s.k = t.k2;
         p2.flop += 2.0 * t.m * t.n * t.k2;
+        plan.hist_add(t.m, t.n, 2.0 * t.m * t.n * t.k2);
         segs.push_back(s);
         continue;
       }
@@ -346,6 +347,7 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
         refB(s, t.X, false);
         s.k = t.k1;
         p2.flop += 2.0 * t.m * t.n * t.k1;
+        plan.hist_add(t.m, t.n, 2.0 * t.m * t.n * t.k1);
         segs.push_back(s);
         continue;
       }
@@ -376,6 +378,7 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
           p1.segs.push_back(s1);
           p1.outs.push_back(o);
           p1.flop += 2.0 * t.k1 * t.n * t.k2;
+          plan.hist_add(t.k1, t.n, 2.0 * t.k1 * t.n * t.k2);
         } else {
           toff = it->second;
         }
@@ -383,6 +386,7 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
         refB(s, Ref{2, toff, t.n}, false);
         s.k = t.k1;
         p2.flop += 2.0 * t.m * t.n * t.k1;
+        plan.hist_add(t.m, t.n, 2.0 * t.m * t.n * t.k1);
       } else {
         TKey key{0, t.X.slot, t.X.off, t.A.slot, t.A.off, int(t.tA)};
         auto it = tmap.find(key);
@@ -408,6 +412,7 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
           p1.segs.push_back(s1);
           p1.outs.push_back(o);
           p1.flop += 2.0 * t.m * t.k2 * t.k1;
+          plan.hist_add(t.m, t.k2, 2.0 * t.m * t.k2 * t.k1);
         } else {
           toff = it->second;
         }
@@ -415,6 +420,7 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
         refB(s, t.B, t.tB);
         s.k = t.k2;
         p2.flop += 2.0 * t.m * t.n * t.k2;
+        plan.hist_add(t.m, t.n, 2.0 * t.m * t.n * t.k2);
       }
       segs.push_back(s);
     }
@@ -425,7 +431,7 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
       size_t maxseg = 0;
       for (size_t q = 0; q < out_ids.size(); ++q) {
         const OutBlk &ob = outs[out_ids[q]];
-        tiles += (ob.m >= 48 && ob.n >= 48) ? int64_t((ob.m + 63) / 64) * ((ob.n + 63) / 64)
+        tiles += gemm_big_tile(ob.m, ob.n) ? int64_t((ob.m + 63) / 64) * ((ob.n + 63) / 64)
                                             : int64_t((ob.m + 31) / 32) * ((ob.n + 31) / 32) / 4 + 1;
         maxseg = std::max(maxseg, per_out[q].size());
       }

@@ -109,6 +109,17 @@ struct TwoPhasePlan {
   double bytes = 0.0;  // algorithmic HBM bytes: operands once, outputs once, intermediates twice
   int64_t n_gemm = 0;
   int n_split = 1;
+  // algorithmic FLOP by the smaller output side min(m, n) of each GEMM,
+  // bins [1,16) [16,32) [32,48) [48,64) [64,128) [128,256) [256,512) [512,inf)
+  static constexpr int kHistBins = 8;
+  double hist_flop[kHistBins] = {};
+  void hist_add(int m, int n, double f) {
+    static const int edges[kHistBins - 1] = {16, 32, 48, 64, 128, 256, 512};
+    const int s = m < n ? m : n;
+    int b = 0;
+    while (b < kHistBins - 1 && s >= edges[b]) ++b;
+    hist_flop[b] += f;
+  }
   void release(Device *d) {
     for (auto &c : chunks) {
       dev_plan_free(d, c.p1);
@@ -121,6 +132,7 @@ struct TwoPhasePlan {
     bytes = 0.0;
     n_gemm = 0;
     n_split = 1;
+    for (double &h : hist_flop) h = 0.0;
   }
 };
 

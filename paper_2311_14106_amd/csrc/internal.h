@@ -81,6 +81,9 @@ struct GTile {
   int16_t ti, tj;
 };
 constexpr int kSlots = 8;
+// Tile class of a grouped-GEMM output: 64x64 workgroup tiles (LDS-staged)
+// or 32x32 wave tiles (four independent tiles per workgroup).
+inline bool gemm_big_tile(int, int) { return true; }
 struct Bases {
   double *p[kSlots];
 };
@@ -141,6 +144,9 @@ void dev_f2d(Device *, const float *x, double *y, int64_t n);
 constexpr int kTags = 8;
 void dev_timing_enable(Device *, bool on);
 void dev_timing_collect(Device *, double ms[][2], double launches[][2], double flop[][2]);
+// Process-wide totals per kernel, [prec][variant] (prec 0 FP64, 1 FP32),
+// over every context of the process since load (destroyed ones included).
+void dev_timing_process(Device *, double ms[2][2], double launches[2][2], double flop[2][2]);
 
 // Deterministic split-K reduction: y[off+i] += sum_{s<S} P[s*stride + off+i]
 // over a list of blocks (off, len), s ascending.

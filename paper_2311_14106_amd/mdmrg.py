@@ -46,6 +46,7 @@ EXPORTS = {
     'mdmrg_heff_apply': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     'mdmrg_heff_diag': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     'mdmrg_heff_cost': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_i64_p, _c_i64_p]),
+    'mdmrg_heff_histogram': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p]),
     'mdmrg_davidson': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
                                       ctypes.c_int, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_int)]),
     'mdmrg_davidson_mixed': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
@@ -226,6 +227,14 @@ class Context:
                                            ctypes.byref(g)))
         return {'flop': f.value, 'bytes': b.value, 'n_terms': t.value, 'n_gemm': g.value}
 
+    HIST_EDGES = (1, 16, 32, 48, 64, 128, 256, 512)
+
+    def heff_histogram(self):
+        """{bin lower edge: FLOP} of one H_eff x by min(m, n) of each GEMM."""
+        out = np.zeros(8)
+        self._chk(self.lib.mdmrg_heff_histogram(self.h, _dp(out)))
+        return dict(zip(self.HIST_EDGES, out.tolist()))
+
     def davidson(self, x, tol=1e-8, max_iter=200, m_max=24):
         e, r, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
         st = self._chk(self.lib.mdmrg_davidson(self.h, _ptr(x), tol, max_iter, m_max, ctypes.byref(e),
@@ -272,7 +281,7 @@ class Context:
                                               sd.ctypes.data_as(_c_i64_p), _dp(al)))
 
     def stats(self):
-        out = np.zeros(35)
+        out = np.zeros(47)
         self._chk(self.lib.mdmrg_get_stats(self.h, _dp(out)))
         keys = ['diag_h_s', 'ren_s', 'tables_s', 'diag_d_s', 'stvec_s', 'other_s', 'heff_flop', 'n_matvec',
                 'heff_gemm_ms', 'heff_gemm_launches', 'heff_gemm_flop',
@@ -283,4 +292,7 @@ class Context:
                 'heff_t64_ms', 'heff_t64_launches', 'heff_t64_flop',
                 'heff_t32_ms', 'heff_t32_launches', 'heff_t32_flop',
                 'all_t64_ms', 'all_t64_launches', 'all_t32_ms', 'all_t32_launches']
+        for prec in ('f64', 'f32'):
+            for var in ('t64', 't32'):
+                keys += [f'proc_{prec}_{var}_ms', f'proc_{prec}_{var}_launches', f'proc_{prec}_{var}_flop']
         return dict(zip(keys, out.tolist()))

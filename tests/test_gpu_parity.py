@@ -111,6 +111,9 @@ def test_heff_and_diag_match_oracle(name):
         ctx.heff_apply(to_dev(z), hz)
         hz = hz.cpu().numpy()
         assert abs(x @ hz - z @ y) <= 1e-12 * np.linalg.norm(y) * np.linalg.norm(z)
+        # the shape histogram partitions the algorithmic FLOP of the product
+        cost, hist = ctx.heff_cost(), ctx.heff_histogram()
+        assert abs(sum(hist.values()) - cost['flop']) <= 1e-9 * cost['flop']
 
 
 @pytest.mark.parametrize('name,l', [('hubbard_3x3_momentum_D64', 3), ('spinless_4x4_real_D64', 7)])
