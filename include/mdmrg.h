@@ -240,8 +240,8 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
 
 /* Wall seconds per step category (Diag_H, Ren, Tables, Diag_D, StVec,
  * Other) accumulated since creation, the algorithmic FLOP of all H_eff
- * products, and HIP-event timings of the grouped-GEMM launches on the
- * context stream; out must hold 47 doubles:
+ * products, and HIP-event timings of the grouped-GEMM kernel launches on the
+ * context stream; out must hold 36 doubles:
  * [diag_h, ren, tables, diag_d, stvec, other, heff_flop, n_matvec,
  *  heff_gemm_ms, heff_gemm_launches, heff_gemm_flop,
  *  ren_gemm_ms, ren_gemm_launches, ren_gemm_flop,
@@ -249,17 +249,15 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
  *  split_gemm_ms, split_gemm_launches, split_gemm_flop,
  *  heff_phase1_ms, heff_phase1_launches, heff_phase1_flop,
  *  grouped_ms, grouped_launches, grouped_flop (mdmrg_gemm_grouped calls),
- *  heff_tile64_ms, heff_tile64_launches, heff_tile64_flop,
- *  heff_tile32_ms, heff_tile32_launches, heff_tile32_flop,
- *  all_tile64_ms, all_tile64_launches, all_tile32_ms, all_tile32_launches,
- *  proc_f64_tile64_{ms, launches, flop}, proc_f64_tile32_{ms, launches, flop},
- *  proc_f32_tile64_{ms, launches, flop}, proc_f32_tile32_{ms, launches, flop}].
- * tile64 = k_gemm (64x64 workgroup tiles), tile32 = k_gemm_wave (32x32 wave
- * tiles); heff_* = FP64 H_eff products, all_* = every launch of the context
- * (FP64 and FP32), proc_* = every launch of one kernel (element type x tile
- * variant) in the whole process, over all contexts including destroyed ones.
+ *  heff_kernel_ms, heff_kernel_launches, heff_kernel_flop,
+ *  all_kernel_ms, all_kernel_launches,
+ *  proc_f64_ms, proc_f64_launches, proc_f64_flop,
+ *  proc_f32_ms, proc_f32_launches, proc_f32_flop].
  * heff_gemm_* covers the accumulation (second) phase of the FP64 H_eff
- * products and heff_phase1_* their intermediate (first) phase. */
+ * products, heff_phase1_* their intermediate (first) phase and heff_kernel_*
+ * both; all_kernel_* every launch of the context (FP64 and FP32);
+ * proc_f64_* / proc_f32_* every FP64 / FP32 launch of the kernel in the
+ * whole process, over all contexts including destroyed ones. */
 int mdmrg_get_stats(mdmrg_ctx ctx, double *out);
 
 #ifdef __cplusplus

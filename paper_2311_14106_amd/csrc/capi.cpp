@@ -400,14 +400,8 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
   out[6] = s.heff_flop;
   out[7] = s.n_matvec;
   return guarded(ctx, [&] {
-    double ms2[kTags][2], ln2[kTags][2], fl2[kTags][2];
-    dev_timing_collect(ctx->c.dev, ms2, ln2, fl2);
     double ms[kTags], ln[kTags], fl[kTags];
-    for (int i = 0; i < kTags; ++i) {
-      ms[i] = ms2[i][0] + ms2[i][1];
-      ln[i] = ln2[i][0] + ln2[i][1];
-      fl[i] = fl2[i][0] + fl2[i][1];
-    }
+    dev_timing_collect(ctx->c.dev, ms, ln, fl);
     out[8] = ms[1];
     out[9] = ln[1];
     out[10] = fl[1];
@@ -425,28 +419,22 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
     out[22] = ms[3];
     out[23] = ln[3];
     out[24] = fl[3];
-    // per kernel variant: FP64 H_eff products (both phases), then every
-    // FP64-or-FP32 launch of the context
-    for (int k = 0; k < 2; ++k) {
-      out[25 + 3 * k] = ms2[1][k] + ms2[5][k];
-      out[26 + 3 * k] = ln2[1][k] + ln2[5][k];
-      out[27 + 3 * k] = fl2[1][k] + fl2[5][k];
-      double am = 0, al = 0;
-      for (int i = 1; i < kTags; ++i) {
-        am += ms2[i][k];
-        al += ln2[i][k];
-      }
-      out[31 + 2 * k] = am;
-      out[32 + 2 * k] = al;
+    // FP64 H_eff products (both phases), then every launch of the context
+    out[25] = ms[1] + ms[5];
+    out[26] = ln[1] + ln[5];
+    out[27] = fl[1] + fl[5];
+    out[28] = out[29] = 0.0;
+    for (int i = 1; i < kTags; ++i) {
+      out[28] += ms[i];
+      out[29] += ln[i];
     }
-    double pm[2][2], pl[2][2], pf[2][2];
+    double pm[2], pl[2], pf[2];
     dev_timing_process(ctx->c.dev, pm, pl, pf);
-    for (int p = 0; p < 2; ++p)
-      for (int k = 0; k < 2; ++k) {
-        out[35 + 3 * (2 * p + k)] = pm[p][k];
-        out[36 + 3 * (2 * p + k)] = pl[p][k];
-        out[37 + 3 * (2 * p + k)] = pf[p][k];
-      }
+    for (int p = 0; p < 2; ++p) {
+      out[30 + 3 * p] = pm[p];
+      out[31 + 3 * p] = pl[p];
+      out[32 + 3 * p] = pf[p];
+    }
     return MDMRG_OK;
   });
 }

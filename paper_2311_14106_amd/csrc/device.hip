@@ -38,12 +38,12 @@ struct Device {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   struct Pending {
-    int tag, kind, prec;
+    int tag, prec;
     hipEvent_t a, b;
     double flop;
   };
   std::vector<Pending> pending;
-  double ms[kTags][2] = {}, launches[kTags][2] = {}, flop[kTags][2] = {};
+  double ms[kTags] = {}, launches[kTags] = {}, flop[kTags] = {};
 };
 
 static hipEvent_t ev_get(Device *d) {
@@ -57,10 +57,11 @@ static hipEvent_t ev_get(Device *d) {
   return e;
 }
 
-// Process-wide totals per kernel (precision x tile variant), summed over
-// every device context of the process, including destroyed ones.
+// Process-wide totals of the grouped kernel per element type (0 FP64,
+// 1 FP32), summed over every device context of the process, including
+// destroyed ones.
 static std::mutex g_timing_mu;
-static double g_ms[2][2], g_launches[2][2], g_flop[2][2];
+static double g_ms[2], g_launches[2], g_flop[2];
 
 static void timing_drain(Device *d) {
   if (d->pending.empty()) return;
@@ -69,38 +70,36 @@ static void timing_drain(Device *d) {
   for (auto &p : d->pending) {
     float t = 0.f;
     HIP_CHECK(hipEventElapsedTime(&t, p.a, p.b));
-    d->ms[p.tag][p.kind] += t;
-    d->launches[p.tag][p.kind] += 1;
-    d->flop[p.tag][p.kind] += p.flop;
-    g_ms[p.prec][p.kind] += t;
-    g_launches[p.prec][p.kind] += 1;
-    g_flop[p.prec][p.kind] += p.flop;
+    d->ms[p.tag] += t;
+    d->launches[p.tag] += 1;
+    d->flop[p.tag] += p.flop;
+    g_ms[p.prec] += t;
+    g_launches[p.prec] += 1;
+    g_flop[p.prec] += p.flop;
     d->ev_pool.push_back(p.a);
     d->ev_pool.push_back(p.b);
   }
   d->pending.clear();
 }
 
-void dev_timing_process(Device *d, double ms[2][2], double launches[2][2], double flop[2][2]) {
+void dev_timing_process(Device *d, double ms[2], double launches[2], double flop[2]) {
   timing_drain(d);
   std::lock_guard<std::mutex> lk(g_timing_mu);
-  for (int p = 0; p < 2; ++p)
-    for (int k = 0; k < 2; ++k) {
-      ms[p][k] = g_ms[p][k];
-      launches[p][k] = g_launches[p][k];
-      flop[p][k] = g_flop[p][k];
-    }
+  for (int p = 0; p < 2; ++p) {
+    ms[p] = g_ms[p];
+    launches[p] = g_launches[p];
+    flop[p] = g_flop[p];
+  }
 }
 
 void dev_timing_enable(Device *d, bool on) { d->timing = on; }
-void dev_timing_collect(Device *d, double ms[][2], double launches[][2], double flop[][2]) {
+void dev_timing_collect(Device *d, double ms[kTags], double launches[kTags], double flop[kTags]) {
   timing_drain(d);
-  for (int i = 0; i < kTags; ++i)
-    for (int k = 0; k < 2; ++k) {
-      ms[i][k] = d->ms[i][k];
-      launches[i][k] = d->launches[i][k];
-      flop[i][k] = d->flop[i][k];
-    }
+  for (int i = 0; i < kTags; ++i) {
+    ms[i] = d->ms[i];
+    launches[i] = d->launches[i];
+    flop[i] = d->flop[i];
+  }
 }
 
 double wall_seconds() {
@@ -196,10 +195,10 @@ void dev_zero(Device *d, void *dst, size_t bytes) {
   if (bytes % 8) HIP_CHECK(hipMemsetAsync((char *)dst + n * 8, 0, bytes % 8, d->stream));
 }
 
-// ----------------------------------------------------- grouped GEMM (FP64)
-// Workgroup = 4 waves = 64x64 output tile; wave (wm, wn) owns a 32x32
-// quadrant as 2x2 MFMA 16x16x4 accumulators.  K is staged through LDS in
-// steps of 16.  Operand layout of v_mfma_f64_16x16x4f64: lane l supplies
+// ------------------------------------------- grouped GEMM (FP64 and FP32)
+// Workgroup = 8 waves (2 x 4) = 64x64 output tile; each wave owns a 32x16
+// block as 2x1 MFMA 16x16x4 accumulators.  K is staged through LDS in steps
+// of 16.  Operand layout of v_mfma_f64_16x16x4f64: lane l supplies
 // A[l%16][l/16] and B[l/16][l%16]; accumulator element r of lane l is
 // C[l/16 + 4r][l%16] for FP64 and C[4(l/16) + r][l%16] for FP32.
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -233,20 +232,24 @@ struct Mfma<float> {
 
 // Workgroup tile of the grouped kernel: BM x BN outputs per workgroup of
 // WY x WX waves, each wave a (BM/WY) x (BN/WX) block of 16x16 MFMA tiles;
-// K staged through LDS in steps of TK with one step of register prefetch;
-// kXSEG: the prefetch runs across segment boundaries.
-constexpr int kBM = 64, kBN = 64, kWY = 2, kWX = 4;
-constexpr bool kXSEG = false;
+// K staged through LDS in steps of TK with one step of register prefetch.
+template <int BM_, int BN_, int WY_, int WX_>
+struct TileCfg {
+  static constexpr int BM = BM_, BN = BN_, WY = WY_, WX = WX_;
+  static constexpr int NT = 64 * WY * WX;                      // threads per workgroup
+  static constexpr int MI = BM / WY / 16, NI = BN / WX / 16;  // MFMA tiles per wave
+};
+typedef TileCfg<64, 64, 2, 4> Cfg64;
 constexpr int kPad = 2;  // LDS row padding (doubles) of the staged A / B tiles
-constexpr int kNT = 64 * kWY * kWX;  // threads per workgroup
 
 // Per-thread load state of one segment: each thread stages EA elements of
 // op(A) and EB of op(B) per K step.  Element `it` of a thread sits at row
 // i0 + di*it and K offset k0 + dk*it of the staged tile ((di, dk) follow
 // from the operand's transposition), so its memory offset is affine in
 // `it` too: o0 + it*dO.  Base pointers are uniform over the workgroup.
-template <class T, int BM, int BN, int NT = kNT>
+template <class T, class C>
 struct SegLoad {
+  static constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
   static constexpr int EA = BM * TK / NT, EB = BN * TK / NT;
   static_assert(EA >= 1 && EB >= 1 && NT % BM == 0 && NT % BN == 0 && NT % TK == 0, "tile / thread mismatch");
   const T *A, *B;
@@ -260,9 +263,10 @@ struct SegLoad {
   bool idA, tA, tB;
 };
 
-template <class T, int BM, int BN>
-__device__ inline void seg_setup(SegLoad<T, BM, BN> &L, const GSeg &sg, const Bases &bases, const GOut &o,
-                                 int row0, int col0, int tid) {
+template <class T, class C>
+__device__ inline void seg_setup(SegLoad<T, C> &L, const GSeg &sg, const Bases &bases, const GOut &o, int row0,
+                                 int col0, int tid) {
+  constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
   L.A = reinterpret_cast<const T *>(bases.p[sg.a_slot]) + sg.a_off;
   L.B = reinterpret_cast<const T *>(bases.p[sg.b_slot]) + sg.b_off;
   const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB;
@@ -275,7 +279,6 @@ __device__ inline void seg_setup(SegLoad<T, BM, BN> &L, const GSeg &sg, const Ba
   L.db = tB ? TK : TK * sg.ldb;
   // A tile BM x TK: row-major source -> (i, kk) = (e / TK, e % TK);
   // transposed source -> (e % BM, e / BM); e = tid + NT it
-  constexpr int NT = kNT;
   const int i0 = tA ? tid % BM : tid / TK, di = tA ? 0 : NT / TK;
   L.ka0 = tA ? tid / BM : tid % TK;
   L.dka = tA ? NT / BM : 0;
@@ -304,9 +307,9 @@ __device__ inline void seg_setup(SegLoad<T, BM, BN> &L, const GSeg &sg, const Ba
     if (col0 + j0 + dj * it < o.n) L.vb |= 1u << it;
 }
 
-template <class T, int BM, int BN>
-__device__ inline void seg_fetch(const SegLoad<T, BM, BN> &L, int step, T (&ra)[SegLoad<T, BM, BN>::EA],
-                                 T (&rb)[SegLoad<T, BM, BN>::EB]) {
+template <class T, class C>
+__device__ inline void seg_fetch(const SegLoad<T, C> &L, int step, T (&ra)[SegLoad<T, C>::EA],
+                                 T (&rb)[SegLoad<T, C>::EB]) {
   const int k0 = step * TK;
   const int64_t sa = int64_t(step) * L.da, sb = int64_t(step) * L.db;
   const T *Ap = L.A + sa, *Bp = L.B + sb;
@@ -325,12 +328,12 @@ __device__ inline void seg_fetch(const SegLoad<T, BM, BN> &L, int step, T (&ra)[
   }
 }
 
-// LDS position of element `it`: A stage [kk][BM + 2], B stage [kb][BN + 2];
+// LDS position of element `it`: A stage [kk][BM + kPad], B stage [kb][BN + kPad];
 // the row / column of an element is recovered from its thread and `it`
-template <class T, int BM, int BN>
-__device__ inline void seg_store(const SegLoad<T, BM, BN> &L, int tid, const T (&ra)[SegLoad<T, BM, BN>::EA],
-                                 const T (&rb)[SegLoad<T, BM, BN>::EB], T *As, T *Bs) {
-  constexpr int NT = kNT;
+template <class T, class C>
+__device__ inline void seg_store(const SegLoad<T, C> &L, int tid, const T (&ra)[SegLoad<T, C>::EA],
+                                 const T (&rb)[SegLoad<T, C>::EB], T *As, T *Bs) {
+  constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
   const int i0 = L.tA ? tid % BM : tid / TK, di = L.tA ? 0 : NT / TK;
   const int j0 = L.tB ? tid / TK : tid % BN, dj = L.tB ? NT / TK : 0;
 #pragma unroll
@@ -341,11 +344,10 @@ __device__ inline void seg_store(const SegLoad<T, BM, BN> &L, int tid, const T (
 
 // MFMAs of one K step on the LDS stage (Ab, Bb) for this wave's quadrant;
 // 16x16 blocks wholly outside the output are skipped (wave-uniform masks).
-constexpr int kMI = kBM / kWY / 16, kNI = kBN / kWX / 16;  // MFMA tiles per wave
-template <class T, int BM, int BN>
+template <class T, class C>
 __device__ inline void tile_mfma(const T *Ab, const T *Bb, int wm, int wn, int lr, int lk, bool full, int qm,
-                                 int qn, typename Mfma<T>::acc_t (&acc)[kMI][kNI]) {
-  constexpr int MI = kMI, NI = kNI;
+                                 int qn, typename Mfma<T>::acc_t (&acc)[C::MI][C::NI]) {
+  constexpr int BM = C::BM, BN = C::BN, MI = C::MI, NI = C::NI;
 #pragma unroll
   for (int kk = 0; kk < TK; kk += 4) {
     T a[MI], b[NI];
@@ -361,12 +363,12 @@ __device__ inline void tile_mfma(const T *Ab, const T *Bb, int wm, int wn, int l
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(kNT) void k_gemm(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
-                                              const GSeg *__restrict__ segs, Bases bases) {
-  constexpr int BM = kBM, BN = kBN, MI = kMI, NI = kNI;
+template <class T, class C>
+__device__ inline void gemm_tile(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
+                                 const GSeg *__restrict__ segs, const Bases &bases) {
+  constexpr int BM = C::BM, BN = C::BN, MI = C::MI, NI = C::NI;
   typedef typename Mfma<T>::acc_t acc_t;
-  typedef SegLoad<T, BM, BN> SL;
+  typedef SegLoad<T, C> SL;
   __shared__ T As[2][TK * (BM + kPad)];
   __shared__ T Bs[2][TK * (BN + kPad)];
   const GTile tl = tiles[blockIdx.x];
@@ -374,11 +376,11 @@ __global__ __launch_bounds__(kNT) void k_gemm(const GTile *__restrict__ tiles, c
   const GOut o = outs[tl.out];
   const int row0 = int(tl.ti) * BM, col0 = int(tl.tj) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave / kWX) * (BM / kWY), wn = (wave % kWX) * (BN / kWX);
+  const int wm = (wave / C::WX) * (BM / C::WY), wn = (wave % C::WX) * (BN / C::WX);
   const int lr = lane & 15, lk = lane >> 4;
   // rows / columns of this wave's quadrant inside the output (wave-uniform)
   const int qm = o.m - (row0 + wm), qn = o.n - (col0 + wn);
-  const bool full = qm >= BM / kWY && qn >= BN / kWX;
+  const bool full = qm >= BM / C::WY && qn >= BN / C::WX;
   acc_t acc[MI][NI];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
@@ -387,65 +389,26 @@ __global__ __launch_bounds__(kNT) void k_gemm(const GTile *__restrict__ tiles, c
 
   SL L;
   T ra[SL::EA], rb[SL::EB];
-  if (kXSEG) {
-    // one pipeline over all (segment, K step) pairs: the step after the last
-    // one of a segment is the first step of the next non-empty segment, whose
-    // load state replaces the current one (whose data already sits in LDS)
-    int si = 0;
-    while (si < o.seg_count && segs[o.seg_begin + si].k <= 0) ++si;
-    if (si < o.seg_count) {
-      seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
-      int nsteps = (L.k + TK - 1) / TK, step = 0, buf = 0;
-      seg_fetch(L, 0, ra, rb);
-      seg_store(L, tid, ra, rb, As[0], Bs[0]);
+  for (int si = 0; si < o.seg_count; ++si) {
+    seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
+    const int nsteps = (L.k + TK - 1) / TK;
+    if (nsteps == 0) continue;
+    // double-buffered LDS: while the MFMAs consume stage `buf`, the next K
+    // step is fetched into registers and then written to the other stage
+    int buf = 0;
+    seg_fetch(L, 0, ra, rb);
+    seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
+    __syncthreads();
+    for (int step = 0; step < nsteps; ++step) {
+      const bool more = step + 1 < nsteps;
+      if (more) seg_fetch(L, step + 1, ra, rb);
+      tile_mfma<T, C>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
+      buf ^= 1;
+      if (more) seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
       __syncthreads();
-      for (;;) {
-        bool more = true;
-        if (step + 1 < nsteps) {
-          ++step;
-          seg_fetch(L, step, ra, rb);
-        } else {
-          int sn = si + 1;
-          while (sn < o.seg_count && segs[o.seg_begin + sn].k <= 0) ++sn;
-          if (sn < o.seg_count) {
-            si = sn;
-            seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
-            nsteps = (L.k + TK - 1) / TK;
-            step = 0;
-            seg_fetch(L, 0, ra, rb);
-          } else {
-            more = false;
-          }
-        }
-        tile_mfma<T, BM, BN>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
-        if (!more) break;
-        buf ^= 1;
-        seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
-        __syncthreads();
-      }
-    }
-  } else {
-    for (int si = 0; si < o.seg_count; ++si) {
-      seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
-      const int nsteps = (L.k + TK - 1) / TK;
-      if (nsteps == 0) continue;
-      // double-buffered LDS: while the MFMAs consume stage `buf`, the next
-      // K step is fetched into registers and then written to the other stage
-      int buf = 0;
-      seg_fetch(L, 0, ra, rb);
-      seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
-      __syncthreads();
-      for (int step = 0; step < nsteps; ++step) {
-        const bool more = step + 1 < nsteps;
-        if (more) seg_fetch(L, step + 1, ra, rb);
-        tile_mfma<T, BM, BN>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
-        buf ^= 1;
-        if (more) seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
-        __syncthreads();
-      }
     }
   }
-  T *C = reinterpret_cast<T *>(bases.p[o.c_slot]) + o.c_off;
+  T *Cp = reinterpret_cast<T *>(bases.p[o.c_slot]) + o.c_off;
 #pragma unroll
   for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
@@ -455,102 +418,17 @@ __global__ __launch_bounds__(kNT) void k_gemm(const GTile *__restrict__ tiles, c
         const int gi = row0 + wm + mi * 16 + Mfma<T>::row(lk, r);
         const int gj = col0 + wn + ni * 16 + lr;
         if (gi < o.m && gj < o.n) {
-          T *p = C + (int64_t)gi * o.ldc + gj;
+          T *p = Cp + (int64_t)gi * o.ldc + gj;
           const T v = acc[mi][ni][r];
           *p = o.accumulate ? (*p + v) : v;
         }
       }
 }
 
-// Wave-tile variant for small sector blocks: each wave owns an independent
-// 32x32 output tile (2x2 MFMA 16x16x4; the second row / column of MFMA
-// blocks is skipped when the tile has <= 16 rows / columns).  Fragments are
-// loaded straight from global memory (K unrolled by 16), no LDS, no
-// workgroup barrier, so four unrelated small tiles share one workgroup.
-constexpr int WT = 32;
 template <class T>
-__global__ __launch_bounds__(256) void k_gemm_wave(const GTile *__restrict__ tiles, int64_t n_tiles,
-                                                   const GOut *__restrict__ outs,
-                                                   const GSeg *__restrict__ segs, Bases bases) {
-  typedef typename Mfma<T>::acc_t acc_t;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t t = int64_t(blockIdx.x) * 4 + wave;
-  if (t >= n_tiles) return;  // wave-uniform exit; the kernel has no barrier
-  const GTile tl = tiles[t];
-  if (tl.out < 0) return;  // queue padding; wave-uniform
-  const GOut o = outs[tl.out];
-  const int row0 = int(tl.ti) * WT, col0 = int(tl.tj) * WT;
-  const int lr = lane & 15, lk = lane >> 4;
-  const bool m2 = (o.m - row0) > 16, n2 = (o.n - col0) > 16;  // wave-uniform
-  const int gi0 = row0 + lr, gi1 = row0 + 16 + lr, gj0 = col0 + lr, gj1 = col0 + 16 + lr;
-  const bool vi0 = gi0 < o.m, vi1 = m2 && gi1 < o.m, vj0 = gj0 < o.n, vj1 = n2 && gj1 < o.n;
-  acc_t acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
-  for (int si = 0; si < o.seg_count; ++si) {
-    const GSeg sg = segs[o.seg_begin + si];
-    const T *A = reinterpret_cast<const T *>(bases.p[sg.a_slot]) + sg.a_off;
-    const T *B = reinterpret_cast<const T *>(bases.p[sg.b_slot]) + sg.b_off;
-    const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB, idA = sg.flags & SEG_AID;
-    const T alpha = T(sg.alpha);
-    const int64_t lda = sg.lda, ldb = sg.ldb;
-    for (int k0 = 0; k0 < sg.k; k0 += 16) {
-      T a0[4], a1[4], b0[4], b1[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gk = k0 + 4 * u + lk;
-        const bool vk = gk < sg.k;
-        T x0 = T(0), x1 = T(0), y0 = T(0), y1 = T(0);
-        if (vk) {
-          if (idA) {
-            x0 = (vi0 && gi0 == gk) ? T(1) : T(0);
-            x1 = (vi1 && gi1 == gk) ? T(1) : T(0);
-          } else if (tA) {
-            if (vi0) x0 = A[gk * lda + gi0];
-            if (vi1) x1 = A[gk * lda + gi1];
-          } else {
-            if (vi0) x0 = A[gi0 * lda + gk];
-            if (vi1) x1 = A[gi1 * lda + gk];
-          }
-          if (tB) {
-            if (vj0) y0 = B[gj0 * ldb + gk];
-            if (vj1) y1 = B[gj1 * ldb + gk];
-          } else {
-            if (vj0) y0 = B[gk * ldb + gj0];
-            if (vj1) y1 = B[gk * ldb + gj1];
-          }
-        }
-        a0[u] = alpha * x0;
-        a1[u] = alpha * x1;
-        b0[u] = y0;
-        b1[u] = y1;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        acc00 = Mfma<T>::step(a0[u], b0[u], acc00);
-        if (n2) acc01 = Mfma<T>::step(a0[u], b1[u], acc01);
-        if (m2) {
-          acc10 = Mfma<T>::step(a1[u], b0[u], acc10);
-          if (n2) acc11 = Mfma<T>::step(a1[u], b1[u], acc11);
-        }
-      }
-    }
-  }
-  T *C = reinterpret_cast<T *>(bases.p[o.c_slot]) + o.c_off;
-  const acc_t *accs[4] = {&acc00, &acc01, &acc10, &acc11};
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int mi = q >> 1, ni = q & 1;
-    if ((mi && !m2) || (ni && !n2)) continue;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int gi = row0 + mi * 16 + Mfma<T>::row(lk, r);
-      const int gj = col0 + ni * 16 + lr;
-      if (gi < o.m && gj < o.n) {
-        T *pc = C + (int64_t)gi * o.ldc + gj;
-        const T v = (*accs[q])[r];
-        *pc = o.accumulate ? (*pc + v) : v;
-      }
-    }
-  }
+__global__ __launch_bounds__(Cfg64::NT) void k_gemm(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
+                                                    const GSeg *__restrict__ segs, Bases bases) {
+  gemm_tile<T, Cfg64>(tiles, outs, segs, bases);
 }
 
 DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
@@ -567,7 +445,12 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
   auto *dp = new DevPlan();
   dp->n_outs = int64_t(plan.outs.size());
   dp->n_segs = int64_t(plan.segs.size());
-  dp->flop = plan.flop;
+  // algorithmic FLOP of the launch (identity segments excluded)
+  for (const GOut &o : plan.outs)
+    for (int q = 0; q < o.seg_count; ++q) {
+      const GSeg &g = plan.segs[o.seg_begin + q];
+      if (!(g.flags & SEG_AID)) dp->flop += 2.0 * o.m * o.n * g.k;
+    }
   // tiles, largest outputs first (longest-processing-time order)
   std::vector<std::pair<double, int32_t>> work(plan.outs.size());
   for (size_t i = 0; i < plan.outs.size(); ++i) {
@@ -577,64 +460,35 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
     work[i] = {-(kk + 16.0) * o.m * o.n, int32_t(i)};
   }
   std::stable_sort(work.begin(), work.end());
-  // outputs of the big class (gemm_big_tile) use kBM x kBN workgroup tiles, the rest
-  // 32x32 wave tiles (four to a workgroup).  Workgroups of one launch go to
-  // the 8 XCDs round-robin (workgroup b to XCD b mod 8) and every XCD has
-  // its own L2, so outputs are cut into chunks of whole tile rows (at most
-  // 64 tiles: a few A panels against all B panels of the output), chunks are
-  // dealt to per-XCD queues (largest first, to the queue with the least
-  // work) and the queues interleaved: the tiles of a chunk run on one XCD and
-  // share its L2.  Queues are padded with empty tiles (out = -1).
+  // One launch covers every output (small outputs fill the tail of the
+  // largest-first order).  Workgroups of a launch go to the 8 XCDs
+  // round-robin (workgroup b to XCD b mod 8) and every XCD has its own L2,
+  // so outputs are cut into chunks of whole tile rows (at most 64 tiles: a
+  // few A panels against all B panels of the output), chunks are dealt to
+  // per-XCD queues (largest first, to the queue with the least work) and the
+  // queues interleaved: the tiles of a chunk run on one XCD and share its L2.
+  // Queues are padded with empty tiles (out = -1).
   constexpr int kChunkTiles = 64;
-  std::vector<std::vector<GTile>> qb(kXcds), qs(kXcds);
-  double load_b[kXcds] = {}, load_s[kXcds] = {};
+  std::vector<std::vector<GTile>> q(kXcds);
+  double load[kXcds] = {};
   for (auto &w : work) {
     const GOut &o = plan.outs[w.second];
-    double of = 0.0;
-    for (int q = 0; q < o.seg_count; ++q) {
-      const GSeg &g = plan.segs[o.seg_begin + q];
-      if (!(g.flags & SEG_AID)) of += 2.0 * o.m * o.n * g.k;
-    }
-    const bool big = gemm_big_tile(o.m, o.n);
-    (big ? dp->flop_big : dp->flop_small) += of;
-    const int tm = big ? kBM : WT, tn = big ? kBN : WT;
-    double *load = big ? load_b : load_s;
-    const int nti = (o.m + tm - 1) / tm, ntj = (o.n + tn - 1) / tn;
+    const int nti = (o.m + Cfg64::BM - 1) / Cfg64::BM, ntj = (o.n + Cfg64::BN - 1) / Cfg64::BN;
     const int rows = std::max(1, kChunkTiles / ntj);
     for (int i0 = 0; i0 < nti; i0 += rows) {
       const int i1 = std::min(nti, i0 + rows);
       const int x = int(std::min_element(load, load + kXcds) - load);
       load[x] += -w.first * double(i1 - i0) / nti;
-      auto &q = big ? qb[x] : qs[x];
       for (int i = i0; i < i1; ++i)
-        for (int j = 0; j < ntj; ++j) q.push_back(GTile{w.second, int16_t(i), int16_t(j)});
+        for (int j = 0; j < ntj; ++j) q[x].push_back(GTile{w.second, int16_t(i), int16_t(j)});
     }
   }
-  // unit = tiles per workgroup: 1 for the workgroup-tile kernel, 4 for the
-  // wave-tile kernel; position b*unit .. b*unit+unit-1 belongs to workgroup b
-  auto interleave = [](std::vector<std::vector<GTile>> &qs_, int unit) {
-    size_t maxu = 0;
-    for (auto &q : qs_) {
-      while (q.size() % unit) q.push_back(GTile{-1, 0, 0});
-      maxu = std::max(maxu, q.size() / unit);
-    }
-    std::vector<GTile> out;
-    for (size_t u = 0; u < maxu; ++u)
-      for (auto &q : qs_)
-        for (int t = 0; t < unit; ++t) out.push_back(u * unit < q.size() ? q[u * unit + t] : GTile{-1, 0, 0});
-    // trailing empty workgroups are not launched
-    while (out.size() >= size_t(unit)) {
-      bool empty = true;
-      for (int t = 0; t < unit; ++t) empty = empty && out[out.size() - 1 - t].out < 0;
-      if (!empty) break;
-      out.resize(out.size() - unit);
-    }
-    return out;
-  };
-  std::vector<GTile> tiles = interleave(qb, 1), small = interleave(qs, 4);
-  dp->n_big = int64_t(tiles.size());
-  dp->n_small = int64_t(small.size());
-  tiles.insert(tiles.end(), small.begin(), small.end());
+  size_t maxq = 0;
+  for (auto &qq : q) maxq = std::max(maxq, qq.size());
+  std::vector<GTile> tiles;
+  for (size_t u = 0; u < maxq; ++u)
+    for (auto &qq : q) tiles.push_back(u < qq.size() ? qq[u] : GTile{-1, 0, 0});
+  while (!tiles.empty() && tiles.back().out < 0) tiles.pop_back();  // trailing empty workgroups are not launched
   MDMRG_REQUIRE(tiles.size() < (size_t(1) << 31), -6, "grouped GEMM plan has too many tiles");
   dp->n_tiles = int64_t(tiles.size());
   if (dp->n_tiles) {
@@ -660,36 +514,23 @@ void dev_gemm_run(Device *d, const DevPlan *p, const Bases &b, int tag, int prec
   if (!p || p->n_tiles == 0) return;
   if (tag <= 0 || tag >= kTags) tag = 6;  // untagged launches are timed as "other"
   const bool timed = d->timing;
-  for (int kind = 0; kind < 2; ++kind) {
-    const int64_t nt = kind == 0 ? p->n_big : p->n_small;
-    if (!nt) continue;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timed) {
-      if (d->pending.size() > 512) timing_drain(d);
-      e0 = ev_get(d);
-      e1 = ev_get(d);
-      HIP_CHECK(hipEventRecord(e0, d->stream));
-    }
-    if (kind == 0) {
-      if (prec == 0)
-        hipLaunchKernelGGL(k_gemm<double>, dim3(unsigned(nt)), dim3(kNT), 0, d->stream, p->tiles, p->outs, p->segs,
-                           b);
-      else
-        hipLaunchKernelGGL(k_gemm<float>, dim3(unsigned(nt)), dim3(kNT), 0, d->stream, p->tiles, p->outs, p->segs,
-                           b);
-    } else {
-      if (prec == 0)
-        hipLaunchKernelGGL(k_gemm_wave<double>, dim3(unsigned((nt + 3) / 4)), dim3(256), 0, d->stream,
-                           p->tiles + p->n_big, nt, p->outs, p->segs, b);
-      else
-        hipLaunchKernelGGL(k_gemm_wave<float>, dim3(unsigned((nt + 3) / 4)), dim3(256), 0, d->stream,
-                           p->tiles + p->n_big, nt, p->outs, p->segs, b);
-    }
-    HIP_CHECK(hipGetLastError());
-    if (timed) {
-      HIP_CHECK(hipEventRecord(e1, d->stream));
-      d->pending.push_back(Device::Pending{tag, kind, prec ? 1 : 0, e0, e1, kind == 0 ? p->flop_big : p->flop_small});
-    }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    if (d->pending.size() > 512) timing_drain(d);
+    e0 = ev_get(d);
+    e1 = ev_get(d);
+    HIP_CHECK(hipEventRecord(e0, d->stream));
+  }
+  if (prec == 0)
+    hipLaunchKernelGGL(k_gemm<double>, dim3(unsigned(p->n_tiles)), dim3(Cfg64::NT), 0, d->stream, p->tiles, p->outs,
+                       p->segs, b);
+  else
+    hipLaunchKernelGGL(k_gemm<float>, dim3(unsigned(p->n_tiles)), dim3(Cfg64::NT), 0, d->stream, p->tiles, p->outs,
+                       p->segs, b);
+  HIP_CHECK(hipGetLastError());
+  if (timed) {
+    HIP_CHECK(hipEventRecord(e1, d->stream));
+    d->pending.push_back(Device::Pending{tag, prec ? 1 : 0, e0, e1, p->flop});
   }
 }
 

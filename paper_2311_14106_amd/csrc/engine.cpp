@@ -431,8 +431,7 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
       size_t maxseg = 0;
       for (size_t q = 0; q < out_ids.size(); ++q) {
         const OutBlk &ob = outs[out_ids[q]];
-        tiles += gemm_big_tile(ob.m, ob.n) ? int64_t((ob.m + 63) / 64) * ((ob.n + 63) / 64)
-                                            : int64_t((ob.m + 31) / 32) * ((ob.n + 31) / 32) / 4 + 1;
+        tiles += int64_t((ob.m + 63) / 64) * ((ob.n + 63) / 64);
         maxseg = std::max(maxseg, per_out[q].size());
       }
       S = int(std::min<int64_t>(std::max<int64_t>(1, 4096 / std::max<int64_t>(tiles, 1)), 32));
@@ -1044,6 +1043,8 @@ void Context::build_heff(int l) {
     add_set(OpRef{stored ? 1 : 2, make_key(stored ? K_C : K_X, K, kk)}, ident, p.e[1], p.k[1], p.e[2], p.k[2]);
     (void)kS;
   }
+  const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
+  double tv[5] = {wall_seconds(), 0, 0, 0, 0};  // verbose sub-timing: products, combos, tasks, plan
   // on-the-fly complementary operators
   if (!wantL.empty()) {
     Lx = std::make_unique<OpSet>();
@@ -1062,6 +1063,10 @@ void Context::build_heff(int l) {
     Content c;
     combo_content(H, false, l + 2, wantR, c);
     materialize(dev, *Rx, R, c);
+  }
+  if (verbose) {
+    dev_sync(dev);
+    tv[1] = wall_seconds();
   }
   // GEMM tasks
   const Bond &ba = bonds[l], &bb = bonds[l + 2];
@@ -1159,20 +1164,19 @@ void Context::build_heff(int l) {
     for (int i = 0; i < 8; ++i) fprintf(stderr, " <=%d:%.2f", edges[i], tot > 0 ? hist[i] / tot : 0.0);
     fprintf(stderr, "\n");
   }
+  if (verbose) tv[2] = wall_seconds();
   build_two_phase(tasks, outs, scratch_limit, heff, dev, psi.n_elem);
+  if (verbose) tv[3] = wall_seconds();
   if (heff.n_split > 1 && P_scratch_n < heff.n_split * psi.n_elem) {
     if (P_scratch) dev_free(dev, P_scratch);
     P_scratch_n = heff.n_split * psi.n_elem;
     P_scratch = (double *)dev_alloc(dev, sizeof(double) * P_scratch_n);
   }
   if (std::getenv("MDMRG_VERBOSE")) {
-    int64_t big = 0, small = 0, s1 = 0, s2 = 0, o2 = 0;
+    int64_t tiles = 0, s1 = 0, s2 = 0, o2 = 0;
     for (auto &c : heff.chunks) {
       for (DevPlan *p : {c.p1, c.p2})
-        if (p) {
-          big += p->n_big;
-          small += p->n_small;
-        }
+        if (p) tiles += p->n_tiles;
       if (c.p1) s1 += c.p1->n_segs;
       if (c.p2) {
         s2 += c.p2->n_segs;
@@ -1181,9 +1185,9 @@ void Context::build_heff(int l) {
     }
     fprintf(stderr,
             "[mdmrg] bond %d: %zu chunks, scratch %.2f GB, flop %.3e, bytes %.3e, phase-1 outputs %lld, phase-2 "
-            "outputs %lld with %lld segments (split-K %d), tiles big %lld small %lld\n",
+            "outputs %lld with %lld segments (split-K %d), tiles %lld\n",
             l, heff.chunks.size(), heff.scratch * 8e-9, heff.flop, heff.bytes, (long long)s1, (long long)o2,
-            (long long)s2, heff.n_split, (long long)big, (long long)small);
+            (long long)s2, heff.n_split, (long long)tiles);
   }
   ensure_scratch(heff.scratch);
   std::vector<int64_t> boff;
@@ -1196,6 +1200,9 @@ void Context::build_heff(int l) {
   diag = dev_diag_upload(dev, dtasks, boff, bm, bn);
   cur = l;
   dev_sync(dev);
+  if (verbose)
+    fprintf(stderr, "[mdmrg] bond %d tables: products %.3fs, combos %.3fs, tasks %.3fs, plan %.3fs, rest %.3fs\n", l,
+            tv[0] - t0, tv[1] - tv[0], tv[2] - tv[1], tv[3] - tv[2], wall_seconds() - tv[3]);
   stats.t_tables += wall_seconds() - t0;
 }
 

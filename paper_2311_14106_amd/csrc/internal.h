@@ -81,9 +81,6 @@ struct GTile {
   int16_t ti, tj;
 };
 constexpr int kSlots = 8;
-// Tile class of a grouped-GEMM output: 64x64 workgroup tiles (LDS-staged)
-// or 32x32 wave tiles (four independent tiles per workgroup).
-inline bool gemm_big_tile(int, int) { return true; }
 struct Bases {
   double *p[kSlots];
 };
@@ -120,15 +117,14 @@ void dev_zero(Device *, void *dst, size_t bytes);
 void dev_sync(Device *);
 size_t dev_free_bytes(Device *);
 
-// Uploaded grouped-GEMM plan (tiles sorted largest output first).
+// Uploaded grouped-GEMM plan: 64x64 output tiles in launch order (outputs
+// largest first, dealt to per-XCD queues; empty tiles pad the queues).
 struct DevPlan {
   GSeg *segs = nullptr;
   GOut *outs = nullptr;
   GTile *tiles = nullptr;
   int64_t n_tiles = 0, n_outs = 0, n_segs = 0;
-  int64_t n_big = 0, n_small = 0;  // 64x64 workgroup tiles first, then 32x32 wave tiles
-  double flop = 0.0;
-  double flop_big = 0.0, flop_small = 0.0;  // algorithmic FLOP of the outputs of each tile class
+  double flop = 0.0;  // algorithmic FLOP of one launch
 };
 DevPlan *dev_plan_upload(Device *, const GemmPlan &);
 void dev_plan_free(Device *, DevPlan *);
@@ -138,15 +134,16 @@ void dev_plan_free(Device *, DevPlan *);
 void dev_gemm_run(Device *, const DevPlan *, const Bases &, int tag = 0, int prec = 0);
 void dev_d2f(Device *, const double *x, float *y, int64_t n);
 void dev_f2d(Device *, const float *x, double *y, int64_t n);
-// HIP-event timing of tagged grouped-GEMM launches (tag 1..7), kept per
-// kernel variant (0: 64x64 workgroup tiles, 1: 32x32 wave tiles): elapsed
-// milliseconds, launch count and algorithmic FLOP since creation.
+// HIP-event timing of tagged grouped-GEMM launches (tag 1..7; untagged
+// launches count as 6): elapsed milliseconds, launch count and algorithmic
+// FLOP since creation.
 constexpr int kTags = 8;
 void dev_timing_enable(Device *, bool on);
-void dev_timing_collect(Device *, double ms[][2], double launches[][2], double flop[][2]);
-// Process-wide totals per kernel, [prec][variant] (prec 0 FP64, 1 FP32),
-// over every context of the process since load (destroyed ones included).
-void dev_timing_process(Device *, double ms[2][2], double launches[2][2], double flop[2][2]);
+void dev_timing_collect(Device *, double ms[kTags], double launches[kTags], double flop[kTags]);
+// Process-wide totals of the grouped kernel per element type (0 FP64,
+// 1 FP32) over every context of the process since load (destroyed ones
+// included).
+void dev_timing_process(Device *, double ms[2], double launches[2], double flop[2]);
 
 // Deterministic split-K reduction: y[off+i] += sum_{s<S} P[s*stride + off+i]
 // over a list of blocks (off, len), s ascending.

@@ -281,7 +281,7 @@ class Context:
                                               sd.ctypes.data_as(_c_i64_p), _dp(al)))
 
     def stats(self):
-        out = np.zeros(47)
+        out = np.zeros(36)
         self._chk(self.lib.mdmrg_get_stats(self.h, _dp(out)))
         keys = ['diag_h_s', 'ren_s', 'tables_s', 'diag_d_s', 'stvec_s', 'other_s', 'heff_flop', 'n_matvec',
                 'heff_gemm_ms', 'heff_gemm_launches', 'heff_gemm_flop',
@@ -289,10 +289,8 @@ class Context:
                 'heff_flop_split', 'n_matvec_split', 'split_gemm_ms', 'split_gemm_launches',
                 'split_gemm_flop', 'heff_p1_ms', 'heff_p1_launches', 'heff_p1_flop',
                 'grouped_ms', 'grouped_launches', 'grouped_flop',
-                'heff_t64_ms', 'heff_t64_launches', 'heff_t64_flop',
-                'heff_t32_ms', 'heff_t32_launches', 'heff_t32_flop',
-                'all_t64_ms', 'all_t64_launches', 'all_t32_ms', 'all_t32_launches']
-        for prec in ('f64', 'f32'):
-            for var in ('t64', 't32'):
-                keys += [f'proc_{prec}_{var}_ms', f'proc_{prec}_{var}_launches', f'proc_{prec}_{var}_flop']
+                'heff_kernel_ms', 'heff_kernel_launches', 'heff_kernel_flop',
+                'all_kernel_ms', 'all_kernel_launches',
+                'proc_f64_ms', 'proc_f64_launches', 'proc_f64_flop',
+                'proc_f32_ms', 'proc_f32_launches', 'proc_f32_flop']
         return dict(zip(keys, out.tolist()))

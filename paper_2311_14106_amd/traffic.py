@@ -122,7 +122,7 @@ def main():
     r = sub.add_parser('record')
     for a in ('fetch_copy', 'write_copy', 'fetch_bench', 'write_bench', 'out'):
         r.add_argument('--' + a.replace('_', '-'), dest=a, required=True)
-    r.add_argument('--kernel-key', default='t64')
+    r.add_argument('--kernel-key', default='k_gemm<double>')
     r.add_argument('--kernel-name', default='k_gemm<double>')
     r.add_argument('--D', type=int, default=1024)
     r.add_argument('--header', default='')
