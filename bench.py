@@ -123,8 +123,9 @@ def cpu_baseline(mdmrg, budget_s):
 
 def split_compare(ctx, x0, torch, args):
     """Davidson s/step at fixed dE: FP64 form vs mixed precision (FP32
-    products, then FP64 refinement), both from the same start vector at the
-    current bond; E_ref = FP64 solve to |r| <= 1e-10; dE = 1e-9 |E_ref|."""
+    products, then FP64 refinement), eagerly launched and replayed from
+    captured graphs, all from the same start vector at the current bond;
+    E_ref = FP64 solve to |r| <= 1e-10; dE = 1e-9 |E_ref|."""
     from paper_2311_14106_amd import mdmrg
 
     def solve(fn):
@@ -138,21 +139,37 @@ def split_compare(ctx, x0, torch, args):
     s0 = ctx.stats()
     (e_ref, r_ref, n_ref, _), _ = solve(lambda x: ctx.davidson(x, tol=1e-10, max_iter=600))
     (e64, r64, n64, _), t64 = solve(lambda x: ctx.davidson(x, tol=args.split_tol, max_iter=600))
-    (em, rm, nm64, nm32, _), tm = solve(lambda x: ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol,
-                                                                     prec_split=mdmrg.FP32, max_iter=600))
-    de = 1e-9 * abs(e_ref)
+    mixed = lambda x: ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol, prec_split=mdmrg.FP32,
+                                         max_iter=600)
+    (em, rm, nm64, nm32, _), tm = solve(mixed)
     s1 = ctx.stats()
+    # precision + batched form: the same solves with every product replayed
+    # from a captured graph (captured once the kernel variants are tuned)
+    ctx.set_option(mdmrg.OPT_GRAPH, 1)
+    (eg, rg, ng64, ng32, _), tg = solve(mixed)
+    (e64g, _, n64g, _), t64g = solve(lambda x: ctx.davidson(x, tol=args.split_tol, max_iter=600))
+    s2 = ctx.stats()
+    ctx.set_option(mdmrg.OPT_GRAPH, 0)
+    de = 1e-9 * abs(e_ref)
     ms64 = (s1['heff_gemm_ms'] + s1['heff_p1_ms'] - s0['heff_gemm_ms'] - s0['heff_p1_ms']) / max(
         1.0, s1['n_matvec'] - s0['n_matvec'])
     ms32 = (s1['split_gemm_ms'] - s0['split_gemm_ms']) / max(1.0, s1['n_matvec_split'] - s0['n_matvec_split'])
+    g32 = (s2['graph32_ms'] - s1['graph32_ms']) / max(1.0, s2['graph32_launches'] - s1['graph32_launches'])
+    g64 = (s2['graph64_ms'] - s1['graph64_ms']) / max(1.0, s2['graph64_launches'] - s1['graph64_launches'])
     log(f'[bench] fixed-dE: ref E={e_ref:.12f} ({n_ref} products); FP64 {t64:.2f}s {n64} products '
-        f'dE={abs(e64 - e_ref):.1e}; mixed {tm:.2f}s {nm32} FP32 + {nm64} FP64 products dE={abs(em - e_ref):.1e}')
+        f'dE={abs(e64 - e_ref):.1e}; mixed {tm:.2f}s {nm32} FP32 + {nm64} FP64 products dE={abs(em - e_ref):.1e}; '
+        f'mixed+graph {tg:.2f}s dE={abs(eg - e_ref):.1e}; FP64+graph {t64g:.2f}s')
     return {'dE_target': de, 'E_ref': e_ref, 'residual_tol': args.split_tol,
             'fp64': {'davidson_s': t64, 'products': n64, 'dE': abs(e64 - e_ref), 'ok': abs(e64 - e_ref) <= de},
             'mixed_fp32': {'davidson_s': tm, 'products_fp32': nm32, 'products_fp64': nm64,
                            'dE': abs(em - e_ref), 'ok': abs(em - e_ref) <= de},
+            'mixed_fp32_graph': {'davidson_s': tg, 'products_fp32': ng32, 'products_fp64': ng64,
+                                 'dE': abs(eg - e_ref), 'ok': abs(eg - e_ref) <= de},
+            'fp64_graph': {'davidson_s': t64g, 'products': n64g, 'dE': abs(e64g - e_ref),
+                           'ok': abs(e64g - e_ref) <= de},
             'speedup': t64 / tm if tm > 0 else None,
-            'gemm_ms_per_product': {'fp64': ms64, 'fp32': ms32}}
+            'speedup_precision_batched': t64 / tg if tg > 0 else None,
+            'gemm_ms_per_product': {'fp64': ms64, 'fp32': ms32, 'fp64_graph': g64, 'fp32_graph': g32}}
 
 
 def main():
@@ -236,7 +253,8 @@ def main():
     ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
     # the grouped GEMM kernel in the timed FP64 H_eff products (HIP events on
     # the library stream around every launch)
-    name = 'k_gemm<double> (64x64 workgroup tiles)'
+    name = 'k_gemm<double> family (64x64 tiles; autotuned wave split: k_gemm, k_gemm_w16, k_gemm_w4)'
+    kernels = mdmrg.Context.KERNELS
     k_ms, k_launch, k_flop = d['heff_kernel_ms'], max(1.0, d['heff_kernel_launches']), d['heff_kernel_flop']
     achieved_tf = k_flop / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0
     if intensity >= ridge:
@@ -248,11 +266,16 @@ def main():
                 'frac': gbs / PEAK_HBM_GBS, 'traffic': None}
     roof.update({'kernel': name, 'launches': int(k_launch), 'avg_launch_ms': k_ms / k_launch,
                  'flop_per_launch': k_flop / k_launch,
-                 # dispatch indices of this kernel (FP64) in the whole process
-                 'launch_window_whole_process': [int(s0['proc_f64_launches']), int(s1['proc_f64_launches'])],
+                 # per kernel name: FP64 launches in the timed steps and their
+                 # dispatch indices among that kernel's launches in the process
+                 'variant_launches': {k: int(s1[f'proc_f64_{k}_launches'] - s0[f'proc_f64_{k}_launches'])
+                                      for k in kernels},
+                 'launch_windows_whole_process': {f'{k}<double>': [int(s0[f'proc_f64_{k}_launches']),
+                                                                   int(s1[f'proc_f64_{k}_launches'])]
+                                                  for k in kernels},
                  'heff_intensity_flop_per_byte': intensity,
                  'phase1_ms': d['heff_p1_ms'], 'phase2_ms': d['heff_gemm_ms']})
-    roof['traffic'] = measured_traffic('k_gemm<double>', args.D) if args.workload == 'hubbard6x6' else None
+    roof['traffic'] = measured_traffic('k_gemm<double> family', args.D) if args.workload == 'hubbard6x6' else None
     out = {
         'metric': 'H_eff·ψ TFLOP/s and Davidson s/step, FP64 vs split-precision at fixed ΔE',
         'value': heff_flop / wall / 1e12,
@@ -277,6 +300,9 @@ def main():
         'heff_flop_share_by_min_mn': {str(b): v / max(sum(hist.values()), 1.0) for b, v in hist.items()},
         'step_breakdown_s': {k: d[k] / args.steps for k in
                              ('diag_h_s', 'ren_s', 'tables_s', 'diag_d_s', 'stvec_s')},
+        # GPU time and algorithmic FLOP of the renormalisation GEMMs per step
+        'ren_gemm_s_per_step': d['ren_gemm_ms'] * 1e-3 / args.steps,
+        'ren_gemm_tflop_per_step': d['ren_gemm_flop'] / 1e12 / args.steps,
         'energies': energies,
         'hbm_in_use_gb': (total_b - free_b) / 1e9,
         'roofline': roof,
@@ -288,8 +314,9 @@ def main():
     # every launch of the kernel in this process (all contexts), for
     # comparison with a kernel-trace profile of the same command
     sp = ctx.stats()
-    roof['avg_launch_ms_whole_process'] = sp['proc_f64_ms'] / max(1.0, sp['proc_f64_launches'])
-    roof['launches_whole_process'] = int(sp['proc_f64_launches'])
+    roof['avg_launch_ms_whole_process'] = {f'{k}<double>': sp[f'proc_f64_{k}_ms'] / max(1.0, sp[f'proc_f64_{k}_launches'])
+                                           for k in kernels}
+    roof['launches_whole_process'] = {f'{k}<double>': int(sp[f'proc_f64_{k}_launches']) for k in kernels}
     print(json.dumps(out), flush=True)
 
 

@@ -132,9 +132,18 @@ int mdmrg_get_bond(mdmrg_ctx ctx, int bond, int32_t *n_sect, int32_t *qn, int32_
 enum {
   MDMRG_OPT_KEEP_ENVS = 1,     /* 1 (default): keep the operators of every block built;
                                   0: mdmrg_prepare_bond keeps only the blocks of the
-                                  requested bond (memory for one-bond workloads) */
-  MDMRG_OPT_SCRATCH_LIMIT = 2  /* doubles of intermediate storage per product pass
+                                  requested bond and of one step either way (left blocks
+                                  at bonds l-1 and l, right blocks at l+2 and l+3), for
+                                  large-D workloads; a farther move rebuilds from the
+                                  chain end */
+  MDMRG_OPT_SCRATCH_LIMIT = 2, /* doubles of intermediate storage per product pass
                                   (default 2^30); larger values mean fewer passes */
+  MDMRG_OPT_GRAPH = 3          /* 1: after the first products of a bond (which also
+                                  tune the kernel's tile variant per launch), capture
+                                  the bond's H_eff x launch sequence per precision in a
+                                  HIP graph and replay it for every later product
+                                  (x and y staged through context buffers for FP64);
+                                  0 (default): launch eagerly */
 };
 /* Set a context option (EINVAL for unknown options or bad values). */
 int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value);
@@ -241,7 +250,7 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
 /* Wall seconds per step category (Diag_H, Ren, Tables, Diag_D, StVec,
  * Other) accumulated since creation, the algorithmic FLOP of all H_eff
  * products, and HIP-event timings of the grouped-GEMM kernel launches on the
- * context stream; out must hold 36 doubles:
+ * context stream; out must hold 52 doubles:
  * [diag_h, ren, tables, diag_d, stvec, other, heff_flop, n_matvec,
  *  heff_gemm_ms, heff_gemm_launches, heff_gemm_flop,
  *  ren_gemm_ms, ren_gemm_launches, ren_gemm_flop,
@@ -251,13 +260,15 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
  *  grouped_ms, grouped_launches, grouped_flop (mdmrg_gemm_grouped calls),
  *  heff_kernel_ms, heff_kernel_launches, heff_kernel_flop,
  *  all_kernel_ms, all_kernel_launches,
- *  proc_f64_ms, proc_f64_launches, proc_f64_flop,
- *  proc_f32_ms, proc_f32_launches, proc_f32_flop].
- * heff_gemm_* covers the accumulation (second) phase of the FP64 H_eff
- * products, heff_phase1_* their intermediate (first) phase and heff_kernel_*
- * both; all_kernel_* every launch of the context (FP64 and FP32);
- * proc_f64_* / proc_f32_* every FP64 / FP32 launch of the kernel in the
- * whole process, over all contexts including destroyed ones. */
+ *  proc[prec][variant][ms, launches, flop] for prec FP64, FP32 and the
+ *  tile variants k_gemm, k_gemm_w16, k_gemm_w4 (18 values),
+ *  graph64_ms, graph64_launches, graph32_ms, graph32_launches].
+ * heff_gemm_* covers the accumulation (second) phase of the eager FP64
+ * H_eff products, heff_phase1_* their intermediate (first) phase and
+ * heff_kernel_* both; all_kernel_* every kernel launch of the context (FP64
+ * and FP32); proc[..] every launch of one kernel in the whole process, over
+ * all contexts including destroyed ones; graph*_ are whole H_eff products
+ * replayed from a captured graph (MDMRG_OPT_GRAPH). */
 int mdmrg_get_stats(mdmrg_ctx ctx, double *out);
 
 #ifdef __cplusplus

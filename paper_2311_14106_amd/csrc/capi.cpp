@@ -191,6 +191,9 @@ int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value) {
         MDMRG_REQUIRE(value >= (int64_t(1) << 20), MDMRG_EINVAL, "set_option: scratch limit below 2^20 doubles");
         c.scratch_limit = value;
         break;
+      case MDMRG_OPT_GRAPH:
+        c.set_graph(value != 0);
+        break;
       default:
         throw Error(MDMRG_EINVAL, "set_option: unknown option");
     }
@@ -428,13 +431,18 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
       out[28] += ms[i];
       out[29] += ln[i];
     }
-    double pm[2], pl[2], pf[2];
+    double pm[2][kGemmVariants], pl[2][kGemmVariants], pf[2][kGemmVariants];
     dev_timing_process(ctx->c.dev, pm, pl, pf);
-    for (int p = 0; p < 2; ++p) {
-      out[30 + 3 * p] = pm[p];
-      out[31 + 3 * p] = pl[p];
-      out[32 + 3 * p] = pf[p];
-    }
+    for (int p = 0; p < 2; ++p)
+      for (int v = 0; v < kGemmVariants; ++v) {
+        out[30 + 3 * (kGemmVariants * p + v)] = pm[p][v];
+        out[31 + 3 * (kGemmVariants * p + v)] = pl[p][v];
+        out[32 + 3 * (kGemmVariants * p + v)] = pf[p][v];
+      }
+    out[48] = ms[7];
+    out[49] = ln[7];
+    out[50] = ms[8];
+    out[51] = ln[8];
     return MDMRG_OK;
   });
 }

@@ -36,9 +36,10 @@ struct Device {
   size_t syevd_work_n = 0;
   // launch timing
   bool timing = false;
+  bool capturing = false;  // stream capture in progress: no events, no host syncs
   std::vector<hipEvent_t> ev_pool;
   struct Pending {
-    int tag, prec;
+    int tag, prec, variant;  // variant < 0: a graph replay (whole product), not one kernel
     hipEvent_t a, b;
     double flop;
   };
@@ -58,10 +59,10 @@ static hipEvent_t ev_get(Device *d) {
 }
 
 // Process-wide totals of the grouped kernel per element type (0 FP64,
-// 1 FP32), summed over every device context of the process, including
-// destroyed ones.
+// 1 FP32) and tile variant, summed over every device context of the
+// process, including destroyed ones.
 static std::mutex g_timing_mu;
-static double g_ms[2], g_launches[2], g_flop[2];
+static double g_ms[2][kGemmVariants], g_launches[2][kGemmVariants], g_flop[2][kGemmVariants];
 
 static void timing_drain(Device *d) {
   if (d->pending.empty()) return;
@@ -73,23 +74,27 @@ static void timing_drain(Device *d) {
     d->ms[p.tag] += t;
     d->launches[p.tag] += 1;
     d->flop[p.tag] += p.flop;
-    g_ms[p.prec] += t;
-    g_launches[p.prec] += 1;
-    g_flop[p.prec] += p.flop;
+    if (p.variant >= 0) {
+      g_ms[p.prec][p.variant] += t;
+      g_launches[p.prec][p.variant] += 1;
+      g_flop[p.prec][p.variant] += p.flop;
+    }
     d->ev_pool.push_back(p.a);
     d->ev_pool.push_back(p.b);
   }
   d->pending.clear();
 }
 
-void dev_timing_process(Device *d, double ms[2], double launches[2], double flop[2]) {
+void dev_timing_process(Device *d, double ms[2][kGemmVariants], double launches[2][kGemmVariants],
+                        double flop[2][kGemmVariants]) {
   timing_drain(d);
   std::lock_guard<std::mutex> lk(g_timing_mu);
-  for (int p = 0; p < 2; ++p) {
-    ms[p] = g_ms[p];
-    launches[p] = g_launches[p];
-    flop[p] = g_flop[p];
-  }
+  for (int p = 0; p < 2; ++p)
+    for (int v = 0; v < kGemmVariants; ++v) {
+      ms[p][v] = g_ms[p][v];
+      launches[p][v] = g_launches[p][v];
+      flop[p][v] = g_flop[p][v];
+    }
 }
 
 void dev_timing_enable(Device *d, bool on) { d->timing = on; }
@@ -203,7 +208,7 @@ void dev_zero(Device *d, void *dst, size_t bytes) {
 // C[l/16 + 4r][l%16] for FP64 and C[4(l/16) + r][l%16] for FP32.
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int TK = 16;  // K step of the workgroup-tile kernel
+constexpr int kTKmax = 16;  // largest K step of the grouped kernel
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 
 // one MFMA 16x16x4 step in the element type of the kernel: FP64
@@ -233,13 +238,29 @@ struct Mfma<float> {
 // Workgroup tile of the grouped kernel: BM x BN outputs per workgroup of
 // WY x WX waves, each wave a (BM/WY) x (BN/WX) block of 16x16 MFMA tiles;
 // K staged through LDS in steps of TK with one step of register prefetch.
-template <int BM_, int BN_, int WY_, int WX_>
+template <int BM_, int BN_, int WY_, int WX_, int TK_>
 struct TileCfg {
-  static constexpr int BM = BM_, BN = BN_, WY = WY_, WX = WX_;
+  static constexpr int BM = BM_, BN = BN_, WY = WY_, WX = WX_, TK = TK_;
   static constexpr int NT = 64 * WY * WX;                      // threads per workgroup
   static constexpr int MI = BM / WY / 16, NI = BN / WX / 16;  // MFMA tiles per wave
 };
-typedef TileCfg<64, 64, 2, 4> Cfg64;
+// Tile variants (all 64x64 outputs per workgroup, so one tile list serves
+// them all; they differ in how the tile is split over waves).  Every output
+// element is accumulated over K in the same order in all of them, so their
+// results are bitwise identical; the autotuner picks one per plan.
+// The K step is 16 for both element types (a step of 32 for FP32, with the
+// same LDS bytes per stage as FP64, measured slower).
+template <class T>
+constexpr int tk_of() {
+  return 16;
+}
+template <class T>
+using Cfg64 = TileCfg<64, 64, 2, 4, tk_of<T>()>;  // variant 0, k_gemm: 8 waves of 32x16
+template <class T>
+using Cfg64w = TileCfg<64, 64, 4, 4, tk_of<T>()>;  // variant 1, k_gemm_w16: 16 waves of 16x16
+template <class T>
+using Cfg64q = TileCfg<64, 64, 2, 2, tk_of<T>()>;  // variant 2, k_gemm_w4: 4 waves of 32x32
+constexpr int kTileM = 64, kTileN = 64;  // output tile of every variant
 constexpr int kPad = 2;  // LDS row padding (doubles) of the staged A / B tiles
 
 // Per-thread load state of one segment: each thread stages EA elements of
@@ -249,7 +270,7 @@ constexpr int kPad = 2;  // LDS row padding (doubles) of the staged A / B tiles
 // `it` too: o0 + it*dO.  Base pointers are uniform over the workgroup.
 template <class T, class C>
 struct SegLoad {
-  static constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
+  static constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK;
   static constexpr int EA = BM * TK / NT, EB = BN * TK / NT;
   static_assert(EA >= 1 && EB >= 1 && NT % BM == 0 && NT % BN == 0 && NT % TK == 0, "tile / thread mismatch");
   const T *A, *B;
@@ -266,7 +287,7 @@ struct SegLoad {
 template <class T, class C>
 __device__ inline void seg_setup(SegLoad<T, C> &L, const GSeg &sg, const Bases &bases, const GOut &o, int row0,
                                  int col0, int tid) {
-  constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
+  constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK;
   L.A = reinterpret_cast<const T *>(bases.p[sg.a_slot]) + sg.a_off;
   L.B = reinterpret_cast<const T *>(bases.p[sg.b_slot]) + sg.b_off;
   const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB;
@@ -307,66 +328,100 @@ __device__ inline void seg_setup(SegLoad<T, C> &L, const GSeg &sg, const Bases &
     if (col0 + j0 + dj * it < o.n) L.vb |= 1u << it;
 }
 
+// Loads of one K step into registers.  The loads are unconditional (an
+// element outside the operand reads the in-bounds first element of the
+// step instead) and nothing is computed from the loaded values here, so no
+// wait on them is needed before the MFMAs of the current step; masking,
+// alpha and identity factors are applied when the step is written to LDS.
+// ok*: bit it = element it lies inside the operand for this step.
 template <class T, class C>
 __device__ inline void seg_fetch(const SegLoad<T, C> &L, int step, T (&ra)[SegLoad<T, C>::EA],
-                                 T (&rb)[SegLoad<T, C>::EB]) {
-  const int k0 = step * TK;
-  const int64_t sa = int64_t(step) * L.da, sb = int64_t(step) * L.db;
-  const T *Ap = L.A + sa, *Bp = L.B + sb;
+                                 T (&rb)[SegLoad<T, C>::EB], uint32_t &oka, uint32_t &okb) {
+  const int k0 = step * C::TK;
+  const T *Ap = L.A + int64_t(step) * L.da, *Bp = L.B + int64_t(step) * L.db;
+  oka = 0;
+  okb = 0;
 #pragma unroll
   for (int it = 0; it < L.EA; ++it) {
-    const int gk = k0 + L.ka0 + L.dka * it;
-    T v = T(0);
-    if (((L.va >> it) & 1) && gk < L.k)
-      v = L.idA ? ((L.ia0 + L.dia * it == gk) ? L.alpha : T(0)) : L.alpha * Ap[L.oa0 + L.doa * it];
-    ra[it] = v;
+    const bool ok = ((L.va >> it) & 1) && k0 + L.ka0 + L.dka * it < L.k;
+    oka |= uint32_t(ok) << it;
+    if (!L.idA) ra[it] = Ap[ok ? L.oa0 + L.doa * it : 0];
   }
 #pragma unroll
   for (int it = 0; it < L.EB; ++it) {
-    const int gkb = k0 + L.kb0 + L.dkb * it;
-    rb[it] = (((L.vb >> it) & 1) && gkb < L.k) ? Bp[L.ob0 + L.dob * it] : T(0);
+    const bool ok = ((L.vb >> it) & 1) && k0 + L.kb0 + L.dkb * it < L.k;
+    okb |= uint32_t(ok) << it;
+    rb[it] = Bp[ok ? L.ob0 + L.dob * it : 0];
   }
 }
 
-// LDS position of element `it`: A stage [kk][BM + kPad], B stage [kb][BN + kPad];
-// the row / column of an element is recovered from its thread and `it`
+// Write one fetched K step to an LDS stage: A stage [kk][BM + kPad], B stage
+// [kb][BN + kPad]; the row / column of an element is recovered from its
+// thread and `it`.  alpha is folded into A; identity factors are generated.
 template <class T, class C>
-__device__ inline void seg_store(const SegLoad<T, C> &L, int tid, const T (&ra)[SegLoad<T, C>::EA],
-                                 const T (&rb)[SegLoad<T, C>::EB], T *As, T *Bs) {
-  constexpr int BM = C::BM, BN = C::BN, NT = C::NT;
+__device__ inline void seg_store(const SegLoad<T, C> &L, int tid, int step, const T (&ra)[SegLoad<T, C>::EA],
+                                 const T (&rb)[SegLoad<T, C>::EB], uint32_t oka, uint32_t okb, T *As, T *Bs) {
+  constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK;
   const int i0 = L.tA ? tid % BM : tid / TK, di = L.tA ? 0 : NT / TK;
   const int j0 = L.tB ? tid / TK : tid % BN, dj = L.tB ? NT / TK : 0;
+  const int k0 = step * TK;
 #pragma unroll
-  for (int it = 0; it < L.EA; ++it) As[(L.ka0 + L.dka * it) * (BM + kPad) + i0 + di * it] = ra[it];
+  for (int it = 0; it < L.EA; ++it) {
+    const int kk = L.ka0 + L.dka * it;
+    const bool ok = (oka >> it) & 1;
+    T v;
+    if (L.idA)
+      v = (ok && L.ia0 + L.dia * it == k0 + kk) ? L.alpha : T(0);
+    else
+      v = ok ? L.alpha * ra[it] : T(0);
+    As[kk * (BM + kPad) + i0 + di * it] = v;
+  }
 #pragma unroll
-  for (int it = 0; it < L.EB; ++it) Bs[(L.kb0 + L.dkb * it) * (BN + kPad) + j0 + dj * it] = rb[it];
+  for (int it = 0; it < L.EB; ++it)
+    Bs[(L.kb0 + L.dkb * it) * (BN + kPad) + j0 + dj * it] = ((okb >> it) & 1) ? rb[it] : T(0);
 }
 
-// MFMAs of one K step on the LDS stage (Ab, Bb) for this wave's quadrant;
-// 16x16 blocks wholly outside the output are skipped (wave-uniform masks).
+// MFMAs of one K step on the LDS stage (Ab, Bb) for this wave's block;
+// on edge tiles the 16x16 blocks wholly outside the output are skipped
+// (wave-uniform masks, tested once per step, outside the K loop).
 template <class T, class C>
 __device__ inline void tile_mfma(const T *Ab, const T *Bb, int wm, int wn, int lr, int lk, bool full, int qm,
                                  int qn, typename Mfma<T>::acc_t (&acc)[C::MI][C::NI]) {
-  constexpr int BM = C::BM, BN = C::BN, MI = C::MI, NI = C::NI;
+  constexpr int BM = C::BM, BN = C::BN, MI = C::MI, NI = C::NI, TK = C::TK;
+  if (full) {
 #pragma unroll
-  for (int kk = 0; kk < TK; kk += 4) {
-    T a[MI], b[NI];
+    for (int kk = 0; kk < TK; kk += 4) {
+      T a[MI], b[NI];
 #pragma unroll
-    for (int mi = 0; mi < MI; ++mi) a[mi] = Ab[(kk + lk) * (BM + kPad) + wm + 16 * mi + lr];
+      for (int mi = 0; mi < MI; ++mi) a[mi] = Ab[(kk + lk) * (BM + kPad) + wm + 16 * mi + lr];
 #pragma unroll
-    for (int ni = 0; ni < NI; ++ni) b[ni] = Bb[(kk + lk) * (BN + kPad) + wn + 16 * ni + lr];
+      for (int ni = 0; ni < NI; ++ni) b[ni] = Bb[(kk + lk) * (BN + kPad) + wn + 16 * ni + lr];
 #pragma unroll
-    for (int mi = 0; mi < MI; ++mi)
+      for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-      for (int ni = 0; ni < NI; ++ni)
-        if (full || (qm > 16 * mi && qn > 16 * ni)) acc[mi][ni] = Mfma<T>::step(a[mi], b[ni], acc[mi][ni]);
+        for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = Mfma<T>::step(a[mi], b[ni], acc[mi][ni]);
+    }
+  } else if (qm > 0 && qn > 0) {
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      T a[MI], b[NI];
+#pragma unroll
+      for (int mi = 0; mi < MI; ++mi) a[mi] = Ab[(kk + lk) * (BM + kPad) + wm + 16 * mi + lr];
+#pragma unroll
+      for (int ni = 0; ni < NI; ++ni) b[ni] = Bb[(kk + lk) * (BN + kPad) + wn + 16 * ni + lr];
+#pragma unroll
+      for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < NI; ++ni)
+          if (qm > 16 * mi && qn > 16 * ni) acc[mi][ni] = Mfma<T>::step(a[mi], b[ni], acc[mi][ni]);
+    }
   }
 }
 
 template <class T, class C>
 __device__ inline void gemm_tile(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
                                  const GSeg *__restrict__ segs, const Bases &bases) {
-  constexpr int BM = C::BM, BN = C::BN, MI = C::MI, NI = C::NI;
+  constexpr int BM = C::BM, BN = C::BN, MI = C::MI, NI = C::NI, TK = C::TK;
   typedef typename Mfma<T>::acc_t acc_t;
   typedef SegLoad<T, C> SL;
   __shared__ T As[2][TK * (BM + kPad)];
@@ -389,24 +444,27 @@ __device__ inline void gemm_tile(const GTile *__restrict__ tiles, const GOut *__
 
   SL L;
   T ra[SL::EA], rb[SL::EB];
+  uint32_t oka, okb;
   for (int si = 0; si < o.seg_count; ++si) {
     seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
     const int nsteps = (L.k + TK - 1) / TK;
     if (nsteps == 0) continue;
     // double-buffered LDS: while the MFMAs consume stage `buf`, the next K
     // step is fetched into registers and then written to the other stage
+    // (last step peeled so that the loop body has no conditional load or store)
     int buf = 0;
-    seg_fetch(L, 0, ra, rb);
-    seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
+    seg_fetch(L, 0, ra, rb, oka, okb);
+    seg_store(L, tid, 0, ra, rb, oka, okb, As[buf], Bs[buf]);
     __syncthreads();
-    for (int step = 0; step < nsteps; ++step) {
-      const bool more = step + 1 < nsteps;
-      if (more) seg_fetch(L, step + 1, ra, rb);
+    for (int step = 0; step + 1 < nsteps; ++step) {
+      seg_fetch(L, step + 1, ra, rb, oka, okb);
       tile_mfma<T, C>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
       buf ^= 1;
-      if (more) seg_store(L, tid, ra, rb, As[buf], Bs[buf]);
+      seg_store(L, tid, step + 1, ra, rb, oka, okb, As[buf], Bs[buf]);
       __syncthreads();
     }
+    tile_mfma<T, C>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
+    __syncthreads();  // the next segment's first store reuses the stages
   }
   T *Cp = reinterpret_cast<T *>(bases.p[o.c_slot]) + o.c_off;
 #pragma unroll
@@ -426,9 +484,31 @@ __device__ inline void gemm_tile(const GTile *__restrict__ tiles, const GOut *__
 }
 
 template <class T>
-__global__ __launch_bounds__(Cfg64::NT) void k_gemm(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
+__global__ __launch_bounds__(Cfg64<T>::NT) void k_gemm(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
                                                     const GSeg *__restrict__ segs, Bases bases) {
-  gemm_tile<T, Cfg64>(tiles, outs, segs, bases);
+  gemm_tile<T, Cfg64<T>>(tiles, outs, segs, bases);
+}
+template <class T>
+__global__ __launch_bounds__(Cfg64w<T>::NT) void k_gemm_w16(const GTile *__restrict__ tiles,
+                                                         const GOut *__restrict__ outs,
+                                                         const GSeg *__restrict__ segs, Bases bases) {
+  gemm_tile<T, Cfg64w<T>>(tiles, outs, segs, bases);
+}
+template <class T>
+__global__ __launch_bounds__(Cfg64q<T>::NT) void k_gemm_w4(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
+                                                        const GSeg *__restrict__ segs, Bases bases) {
+  gemm_tile<T, Cfg64q<T>>(tiles, outs, segs, bases);
+}
+
+template <class T>
+static void launch_variant(int v, hipStream_t st, const DevPlan *p, const Bases &b) {
+  const dim3 g(unsigned(p->n_tiles));
+  if (v == 1)
+    hipLaunchKernelGGL(k_gemm_w16<T>, g, dim3(Cfg64w<T>::NT), 0, st, p->tiles, p->outs, p->segs, b);
+  else if (v == 2)
+    hipLaunchKernelGGL(k_gemm_w4<T>, g, dim3(Cfg64q<T>::NT), 0, st, p->tiles, p->outs, p->segs, b);
+  else
+    hipLaunchKernelGGL(k_gemm<T>, g, dim3(Cfg64<T>::NT), 0, st, p->tiles, p->outs, p->segs, b);
 }
 
 DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
@@ -437,8 +517,8 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
   for (const GOut &o : plan.outs)
     for (int q = 0; q < o.seg_count; ++q) {
       const GSeg &g = plan.segs[o.seg_begin + q];
-      const int64_t ext_a = (g.flags & SEG_TA) ? int64_t(TK) * g.lda + o.m : int64_t(o.m) * g.lda + TK;
-      const int64_t ext_b = (g.flags & SEG_TB) ? int64_t(o.n) * g.ldb + TK : int64_t(TK) * g.ldb + o.n;
+      const int64_t ext_a = (g.flags & SEG_TA) ? int64_t(kTKmax) * g.lda + o.m : int64_t(o.m) * g.lda + kTKmax;
+      const int64_t ext_b = (g.flags & SEG_TB) ? int64_t(o.n) * g.ldb + kTKmax : int64_t(kTKmax) * g.ldb + o.n;
       MDMRG_REQUIRE(ext_a < (int64_t(1) << 31) && ext_b < (int64_t(1) << 31), -6,
                     "grouped GEMM: operand block too large for 32-bit element offsets");
     }
@@ -473,7 +553,7 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
   double load[kXcds] = {};
   for (auto &w : work) {
     const GOut &o = plan.outs[w.second];
-    const int nti = (o.m + Cfg64::BM - 1) / Cfg64::BM, ntj = (o.n + Cfg64::BN - 1) / Cfg64::BN;
+    const int nti = (o.m + kTileM - 1) / kTileM, ntj = (o.n + kTileN - 1) / kTileN;
     const int rows = std::max(1, kChunkTiles / ntj);
     for (int i0 = 0; i0 < nti; i0 += rows) {
       const int i1 = std::min(nti, i0 + rows);
@@ -504,15 +584,104 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
 
 void dev_plan_free(Device *d, DevPlan *p) {
   if (!p) return;
+  for (auto &evs : p->trial_ev)
+    for (void *e : evs)
+      if (e) d->ev_pool.push_back(static_cast<hipEvent_t>(e));
   dev_free(d, p->segs);
   dev_free(d, p->outs);
   dev_free(d, p->tiles);
   delete p;
 }
 
-void dev_gemm_run(Device *d, const DevPlan *p, const Bases &b, int tag, int prec) {
+void dev_gemm_run(Device *d, DevPlan *p, const Bases &b, int tag, int prec) {
   if (!p || p->n_tiles == 0) return;
   if (tag <= 0 || tag >= kTags) tag = 6;  // untagged launches are timed as "other"
+  // autotuner: the first kGemmVariants launches of a plan (per element type)
+  // run one variant each (they are the plan's real work) and are timed with
+  // their own events; the next launch reads the times and keeps the fastest
+  const int pr = prec ? 1 : 0;
+  int v = p->variant[pr];
+  if (!d->capturing && v < 0) {
+    if (p->trials[pr] < kGemmVariants) {
+      v = p->trials[pr];
+    } else {
+      void **ev = p->trial_ev[pr];
+      HIP_CHECK(hipEventSynchronize(static_cast<hipEvent_t>(ev[2 * kGemmVariants - 1])));
+      float best = 0.f;
+      for (int q = 0; q < kGemmVariants; ++q) {
+        float t = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&t, static_cast<hipEvent_t>(ev[2 * q]), static_cast<hipEvent_t>(ev[2 * q + 1])));
+        p->trial_ms[pr][q] = t;
+        if (q == 0 || t < best) {
+          best = t;
+          v = q;
+        }
+      }
+      for (int q = 0; q < 2 * kGemmVariants; ++q) {
+        d->ev_pool.push_back(static_cast<hipEvent_t>(ev[q]));
+        ev[q] = nullptr;
+      }
+      p->variant[pr] = v;
+    }
+  }
+  if (v < 0) v = 0;  // captured before the plan was tuned
+  const bool trial = !d->capturing && p->variant[pr] < 0;
+  const bool timed = d->timing && !d->capturing;
+  hipEvent_t e0 = nullptr, e1 = nullptr, t0 = nullptr, t1 = nullptr;
+  if (timed) {
+    if (d->pending.size() > 512) timing_drain(d);
+    e0 = ev_get(d);
+    e1 = ev_get(d);
+    HIP_CHECK(hipEventRecord(e0, d->stream));
+  }
+  if (trial) {
+    t0 = ev_get(d);
+    t1 = ev_get(d);
+    HIP_CHECK(hipEventRecord(t0, d->stream));
+  }
+  if (prec == 0)
+    launch_variant<double>(v, d->stream, p, b);
+  else
+    launch_variant<float>(v, d->stream, p, b);
+  HIP_CHECK(hipGetLastError());
+  if (trial) {
+    HIP_CHECK(hipEventRecord(t1, d->stream));
+    p->trial_ev[pr][2 * p->trials[pr]] = t0;
+    p->trial_ev[pr][2 * p->trials[pr] + 1] = t1;
+    p->trials[pr] += 1;
+  }
+  if (timed) {
+    HIP_CHECK(hipEventRecord(e1, d->stream));
+    d->pending.push_back(Device::Pending{tag, prec ? 1 : 0, v, e0, e1, p->flop});
+  }
+}
+
+// ------------------------------------------------------------ graph capture
+struct DevGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+void dev_capture_begin(Device *d) {
+  MDMRG_REQUIRE(!d->capturing, -4, "stream capture already in progress");
+  HIP_CHECK(hipStreamBeginCapture(d->stream, hipStreamCaptureModeThreadLocal));
+  d->capturing = true;
+}
+DevGraph *dev_capture_end(Device *d) {
+  MDMRG_REQUIRE(d->capturing, -4, "no stream capture in progress");
+  auto *g = new DevGraph();
+  d->capturing = false;
+  HIP_CHECK(hipStreamEndCapture(d->stream, &g->graph));
+  HIP_CHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  return g;
+}
+void dev_capture_abort(Device *d) {
+  if (!d->capturing) return;
+  d->capturing = false;
+  hipGraph_t g = nullptr;
+  (void)hipStreamEndCapture(d->stream, &g);
+  if (g) (void)hipGraphDestroy(g);
+}
+void dev_graph_launch(Device *d, DevGraph *g, int tag, double flop) {
   const bool timed = d->timing;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
@@ -521,17 +690,18 @@ void dev_gemm_run(Device *d, const DevPlan *p, const Bases &b, int tag, int prec
     e1 = ev_get(d);
     HIP_CHECK(hipEventRecord(e0, d->stream));
   }
-  if (prec == 0)
-    hipLaunchKernelGGL(k_gemm<double>, dim3(unsigned(p->n_tiles)), dim3(Cfg64::NT), 0, d->stream, p->tiles, p->outs,
-                       p->segs, b);
-  else
-    hipLaunchKernelGGL(k_gemm<float>, dim3(unsigned(p->n_tiles)), dim3(Cfg64::NT), 0, d->stream, p->tiles, p->outs,
-                       p->segs, b);
-  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipGraphLaunch(g->exec, d->stream));
   if (timed) {
     HIP_CHECK(hipEventRecord(e1, d->stream));
-    d->pending.push_back(Device::Pending{tag, prec ? 1 : 0, e0, e1, p->flop});
+    d->pending.push_back(Device::Pending{tag, 0, -1, e0, e1, flop});
   }
+}
+void dev_graph_free(Device *d, DevGraph *g) {
+  if (!g) return;
+  (void)d;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 // ------------------------------------------------------ split-K reduction

@@ -15,6 +15,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <numeric>
+#include <unordered_map>
+#include <unordered_set>
 
 #include "engine.h"
 
@@ -267,16 +269,22 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
   {
     // algorithmic bytes: every distinct operand block read once, every
     // output block written once
-    std::set<std::pair<int, int64_t>> seen;
+    // (slot, element offset) of a block, packed: offsets stay below 2^56
+    auto bkey = [](const Ref &r) { return (uint64_t(r.slot) << 56) ^ uint64_t(r.off); };
+    std::unordered_set<uint64_t> seen;
+    seen.reserve(tasks.size() * 2);
     double elems = 0.0;
     for (const PairTask &t : tasks) {
-      if (!t.idA && seen.insert({t.A.slot, t.A.off}).second) elems += double(t.m) * t.k1;
-      if (seen.insert({t.X.slot, t.X.off}).second) elems += double(t.k1) * t.k2;
-      if (!t.idB && seen.insert({t.B.slot, t.B.off}).second) elems += double(t.k2) * t.n;
+      if (!t.idA && seen.insert(bkey(t.A)).second) elems += double(t.m) * t.k1;
+      if (seen.insert(bkey(t.X)).second) elems += double(t.k1) * t.k2;
+      if (!t.idB && seen.insert(bkey(t.B)).second) elems += double(t.k2) * t.n;
     }
-    std::set<int32_t> so;
+    std::vector<char> so(outs.size(), 0);
     for (const PairTask &t : tasks)
-      if (so.insert(t.out).second) elems += double(outs[t.out].m) * outs[t.out].n;
+      if (!so[t.out]) {
+        so[t.out] = 1;
+        elems += double(outs[t.out].m) * outs[t.out].n;
+      }
     plan.bytes += 8.0 * elems;
   }
   struct TKey {
@@ -286,14 +294,22 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
     int os;
     int64_t oo;
     int tr;
-    bool operator<(const TKey &o) const {
-      return std::tie(order, xs, xo, os, oo, tr) < std::tie(o.order, o.xs, o.xo, o.os, o.oo, o.tr);
+    bool operator==(const TKey &o) const {
+      return order == o.order && xs == o.xs && xo == o.xo && os == o.os && oo == o.oo && tr == o.tr;
+    }
+  };
+  struct TKeyHash {
+    size_t operator()(const TKey &k) const {
+      uint64_t h = uint64_t(k.xo) * 0x9E3779B97F4A7C15ull;
+      h ^= (uint64_t(k.oo) + 0x632BE59BD9B4E019ull + (h << 6) + (h >> 2));
+      h ^= uint64_t(k.order | (k.xs << 2) | (k.os << 6) | (k.tr << 10)) * 0xBF58476D1CE4E5B9ull;
+      return size_t(h ^ (h >> 31));
     }
   };
   size_t i = 0;
   while (i < tasks.size()) {
     GemmPlan p1, p2;
-    std::map<TKey, int64_t> tmap;
+    std::unordered_map<TKey, int64_t, TKeyHash> tmap;
     int64_t used = 0;
     std::vector<std::vector<GSeg>> per_out;
     std::vector<int32_t> out_ids;
@@ -500,6 +516,7 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
 
 void Context::ensure_scratch(int64_t n) {
   if (n <= T_scratch_n) return;
+  release_graphs();  // captured graphs hold the old address
   if (T_scratch) dev_free(dev, T_scratch);
   T_scratch = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(n, 1));
   T_scratch_n = n;
@@ -874,7 +891,27 @@ PsiLayout Context::make_layout(int l) const {
 }
 
 // ------------------------------------------------------------- prepare
+void Context::release_graphs() {
+  dev_graph_free(dev, graph64);
+  dev_graph_free(dev, graph32);
+  graph64 = graph32 = nullptr;
+  eager64 = eager32 = 0;
+}
+
+void Context::set_graph(bool on) {
+  use_graph = on;
+  if (!on) {
+    release_graphs();
+    for (double **p : {&xg, &yg}) {
+      if (*p) dev_free(dev, *p);
+      *p = nullptr;
+    }
+    xg_n = 0;
+  }
+}
+
 void Context::release_bond() {
+  release_graphs();
   for (float **p : {&L32, &R32, &Lx32, &Rx32, &x32, &y32}) {
     if (*p) dev_free(dev, *p);
     *p = nullptr;
@@ -907,6 +944,7 @@ Context::~Context() {
       if (t.data) dev_free(dev, t.data);
     if (T_scratch) dev_free(dev, T_scratch);
     if (P_scratch) dev_free(dev, P_scratch);
+    set_graph(false);
     dev_sync(dev);
   } catch (...) {
   }
@@ -932,7 +970,7 @@ void Context::prepare(int l) {
     if (!Lenv[i0]) Lenv[i0] = env_boundary(true, i0);
     for (int i = i0; i < l; ++i) {
       Lenv[i + 1] = renorm_left(*Lenv[i], i);
-      if (!keep_envs) drop(Lenv[i]);
+      if (!keep_envs && i + 1 < l) drop(Lenv[i]);
     }
   }
   if (!Renv[l + 2]) {
@@ -941,7 +979,16 @@ void Context::prepare(int l) {
     if (!Renv[i0]) Renv[i0] = env_boundary(false, i0);
     for (int i = i0 - 1; i >= l + 2; --i) {
       Renv[i] = renorm_right(*Renv[i + 1], i);
-      if (!keep_envs) drop(Renv[i + 1]);
+      if (!keep_envs && i + 1 > l + 3) drop(Renv[i + 1]);
+    }
+  }
+  if (!keep_envs) {
+    // keep the blocks of this bond and of one step in either direction
+    // (L at bonds l-1, l; R at bonds l+2, l+3), so that the next step of a
+    // sweep needs no rebuild from the chain end
+    for (int j = 0; j <= n; ++j) {
+      if (j != l - 1 && j != l) drop(Lenv[j]);
+      if (j != l + 2 && j != l + 3) drop(Renv[j]);
     }
   }
   dev_sync(dev);
@@ -1168,6 +1215,7 @@ void Context::build_heff(int l) {
   build_two_phase(tasks, outs, scratch_limit, heff, dev, psi.n_elem);
   if (verbose) tv[3] = wall_seconds();
   if (heff.n_split > 1 && P_scratch_n < heff.n_split * psi.n_elem) {
+    release_graphs();
     if (P_scratch) dev_free(dev, P_scratch);
     P_scratch_n = heff.n_split * psi.n_elem;
     P_scratch = (double *)dev_alloc(dev, sizeof(double) * P_scratch_n);
@@ -1225,10 +1273,12 @@ void Context::ensure_fp32() {
 void Context::heff_apply(const double *x, double *y, int prec) {
   MDMRG_REQUIRE(cur >= 0, -4, "heff_apply: no current bond");
   MDMRG_REQUIRE(prec == 0 || prec == 1, -6, "heff_apply: precision form not built");
+  // a graph is captured once every plan of the product has finished its
+  // variant trials (kGemmVariants timed launches, decided at the next one)
+  const int warm = kGemmVariants + 1;
   if (prec == 1) {
     ensure_fp32();
     dev_d2f(dev, x, x32, psi.n_elem);
-    dev_zero(dev, y32, sizeof(float) * psi.n_elem);
     Bases b{};
     b.p[0] = reinterpret_cast<double *>(x32);
     b.p[1] = reinterpret_cast<double *>(y32);
@@ -1237,22 +1287,69 @@ void Context::heff_apply(const double *x, double *y, int prec) {
     b.p[5] = Lx32 ? reinterpret_cast<double *>(Lx32) : b.p[3];
     b.p[6] = Rx32 ? reinterpret_cast<double *>(Rx32) : b.p[4];
     b.p[7] = b.p[1];
-    run_plan(heff, b, 4, 1);
+    auto body = [&] {
+      dev_zero(dev, y32, sizeof(float) * psi.n_elem);
+      run_plan(heff, b, 4, 1);
+    };
+    if (use_graph && !graph32 && eager32 >= warm) {
+      dev_capture_begin(dev);
+      try {
+        body();
+      } catch (...) {
+        dev_capture_abort(dev);
+        throw;
+      }
+      graph32 = dev_capture_end(dev);
+    }
+    if (graph32) {
+      dev_graph_launch(dev, graph32, 8, heff.flop);
+    } else {
+      body();
+      ++eager32;
+    }
     dev_f2d(dev, y32, y, psi.n_elem);
     stats.heff_flop_split += heff.flop;
     stats.n_matvec_split += 1;
     return;
   }
-  dev_zero(dev, y, sizeof(double) * psi.n_elem);
   Bases b{};
-  b.p[0] = const_cast<double *>(x);
-  b.p[1] = y;
   b.p[3] = Lenv[cur]->arena;
   b.p[4] = Renv[cur + 2]->arena;
   b.p[5] = Lx ? Lx->arena : b.p[3];
   b.p[6] = Rx ? Rx->arena : b.p[4];
-  b.p[7] = y;
-  run_plan(heff, b, 1);
+  if (use_graph && eager64 >= warm) {
+    if (!graph64) {
+      if (xg_n < psi.n_elem) {
+        for (double **p : {&xg, &yg}) {
+          if (*p) dev_free(dev, *p);
+          *p = (double *)dev_alloc(dev, sizeof(double) * psi.n_elem);
+        }
+        xg_n = psi.n_elem;
+      }
+      b.p[0] = xg;
+      b.p[1] = yg;
+      b.p[7] = yg;
+      dev_capture_begin(dev);
+      try {
+        dev_zero(dev, yg, sizeof(double) * psi.n_elem);
+        run_plan(heff, b, 1);
+      } catch (...) {
+        dev_capture_abort(dev);
+        throw;
+      }
+      graph64 = dev_capture_end(dev);
+    }
+    dev_d2d(dev, xg, x, sizeof(double) * psi.n_elem);
+    dev_graph_launch(dev, graph64, 7, heff.flop);
+    dev_d2d(dev, y, yg, sizeof(double) * psi.n_elem);
+  } else {
+    b.p[0] = const_cast<double *>(x);
+    b.p[1] = y;
+    b.p[7] = y;
+    dev_zero(dev, y, sizeof(double) * psi.n_elem);
+    run_plan(heff, b, 1);
+    ++eager64;
+  }
   stats.heff_flop += heff.flop;
   stats.n_matvec += 1;
 }

@@ -184,6 +184,15 @@ struct Context {
   Stats stats;
   int64_t scratch_limit = int64_t(1) << 30;  // doubles of phase-1 scratch (8 GB)
   bool keep_envs = true;  // keep every block environment built (needed by sweeps)
+  // graph replay of the H_eff product (MDMRG_OPT_GRAPH): captured per bond and
+  // precision once the first products have tuned the kernel variants
+  bool use_graph = false;
+  DevGraph *graph64 = nullptr, *graph32 = nullptr;
+  double *xg = nullptr, *yg = nullptr;  // FP64 staging of x and y for the graph
+  int64_t xg_n = 0;
+  int eager64 = 0, eager32 = 0;  // eager products at the current bond
+  void set_graph(bool on);
+  void release_graphs();
 
   ~Context();
   void reset_envs();

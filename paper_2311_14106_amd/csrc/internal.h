@@ -117,6 +117,11 @@ void dev_zero(Device *, void *dst, size_t bytes);
 void dev_sync(Device *);
 size_t dev_free_bytes(Device *);
 
+// Tile variants of the grouped kernel (same 64x64 tile list, different
+// split over waves): 0 k_gemm (2x4 waves), 1 k_gemm_w16 (4x4), 2 k_gemm_w4
+// (2x2).
+constexpr int kGemmVariants = 3;
+
 // Uploaded grouped-GEMM plan: 64x64 output tiles in launch order (outputs
 // largest first, dealt to per-XCD queues; empty tiles pad the queues).
 struct DevPlan {
@@ -125,25 +130,40 @@ struct DevPlan {
   GTile *tiles = nullptr;
   int64_t n_tiles = 0, n_outs = 0, n_segs = 0;
   double flop = 0.0;  // algorithmic FLOP of one launch
+  // autotuner state per element type (0 FP64, 1 FP32): the first launches
+  // time one variant each, then the fastest is kept (variant >= 0)
+  int variant[2] = {-1, -1}, trials[2] = {0, 0};
+  void *trial_ev[2][2 * kGemmVariants] = {};
+  float trial_ms[2][kGemmVariants] = {};
 };
 DevPlan *dev_plan_upload(Device *, const GemmPlan &);
 void dev_plan_free(Device *, DevPlan *);
 // prec 0: FP64 operands and results; prec 1: FP32 operands, FP32 MFMA
 // accumulation and FP32 results (base pointers then address float arrays
 // with the same element offsets)
-void dev_gemm_run(Device *, const DevPlan *, const Bases &, int tag = 0, int prec = 0);
+void dev_gemm_run(Device *, DevPlan *, const Bases &, int tag = 0, int prec = 0);
 void dev_d2f(Device *, const double *x, float *y, int64_t n);
 void dev_f2d(Device *, const float *x, double *y, int64_t n);
-// HIP-event timing of tagged grouped-GEMM launches (tag 1..7; untagged
-// launches count as 6): elapsed milliseconds, launch count and algorithmic
-// FLOP since creation.
-constexpr int kTags = 8;
+// HIP-event timing of tagged grouped-GEMM launches (tag 1..6; untagged
+// launches count as 6) and of graph replays (tags 7, 8): elapsed
+// milliseconds, launch count and algorithmic FLOP since creation.
+constexpr int kTags = 9;
 void dev_timing_enable(Device *, bool on);
 void dev_timing_collect(Device *, double ms[kTags], double launches[kTags], double flop[kTags]);
 // Process-wide totals of the grouped kernel per element type (0 FP64,
-// 1 FP32) over every context of the process since load (destroyed ones
-// included).
-void dev_timing_process(Device *, double ms[2], double launches[2], double flop[2]);
+// 1 FP32) and tile variant over every context of the process since load
+// (destroyed ones included).
+void dev_timing_process(Device *, double ms[2][kGemmVariants], double launches[2][kGemmVariants],
+                        double flop[2][kGemmVariants]);
+// Stream capture of the context stream into a graph (no timing events and
+// no host synchronisation inside), replay, and release.  A replay is timed
+// as a whole under `tag` when timing is on.
+struct DevGraph;
+void dev_capture_begin(Device *);
+DevGraph *dev_capture_end(Device *);
+void dev_capture_abort(Device *);
+void dev_graph_launch(Device *, DevGraph *, int tag, double flop);
+void dev_graph_free(Device *, DevGraph *);
 
 // Deterministic split-K reduction: y[off+i] += sum_{s<S} P[s*stride + off+i]
 // over a list of blocks (off, len), s ascending.

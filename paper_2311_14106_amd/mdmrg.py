@@ -18,7 +18,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOCONV, EUNSUP = 0, -1, -2, -3, -4, -5, -6
 SPINLESS, HUBBARD = 0, 1
 REAL, MOMENTUM = 0, 1
 FP64, FP32, BF16X3 = 0, 1, 2
-OPT_KEEP_ENVS, OPT_SCRATCH_LIMIT = 1, 2
+OPT_KEEP_ENVS, OPT_SCRATCH_LIMIT, OPT_GRAPH = 1, 2, 3
 
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)
 _c_i32_p = ctypes.POINTER(ctypes.c_int32)
@@ -228,6 +228,8 @@ class Context:
         return {'flop': f.value, 'bytes': b.value, 'n_terms': t.value, 'n_gemm': g.value}
 
     HIST_EDGES = (1, 16, 32, 48, 64, 128, 256, 512)
+    # tile variants of the grouped kernel (kernel names), in library order
+    KERNELS = ('k_gemm', 'k_gemm_w16', 'k_gemm_w4')
 
     def heff_histogram(self):
         """{bin lower edge: FLOP} of one H_eff x by min(m, n) of each GEMM."""
@@ -281,7 +283,7 @@ class Context:
                                               sd.ctypes.data_as(_c_i64_p), _dp(al)))
 
     def stats(self):
-        out = np.zeros(36)
+        out = np.zeros(52)
         self._chk(self.lib.mdmrg_get_stats(self.h, _dp(out)))
         keys = ['diag_h_s', 'ren_s', 'tables_s', 'diag_d_s', 'stvec_s', 'other_s', 'heff_flop', 'n_matvec',
                 'heff_gemm_ms', 'heff_gemm_launches', 'heff_gemm_flop',
@@ -290,7 +292,9 @@ class Context:
                 'split_gemm_flop', 'heff_p1_ms', 'heff_p1_launches', 'heff_p1_flop',
                 'grouped_ms', 'grouped_launches', 'grouped_flop',
                 'heff_kernel_ms', 'heff_kernel_launches', 'heff_kernel_flop',
-                'all_kernel_ms', 'all_kernel_launches',
-                'proc_f64_ms', 'proc_f64_launches', 'proc_f64_flop',
-                'proc_f32_ms', 'proc_f32_launches', 'proc_f32_flop']
+                'all_kernel_ms', 'all_kernel_launches']
+        for prec in ('f64', 'f32'):
+            for var in self.KERNELS:
+                keys += [f'proc_{prec}_{var}_ms', f'proc_{prec}_{var}_launches', f'proc_{prec}_{var}_flop']
+        keys += ['graph64_ms', 'graph64_launches', 'graph32_ms', 'graph32_launches']
         return dict(zip(keys, out.tolist()))

@@ -7,10 +7,11 @@ separate run, ``--pmc WRITE_SIZE`` (one counter pass per run):
   elementwise copy of 1 GiB three times.  What the counters read for it,
   against the 1 GiB actually read and written, is the scale factor of each
   counter on this GPU.
-* ``python3 -m paper_2311_14106_amd.traffic summarize CSV OUT [--kernel RE]
-  [--window LO HI]`` reduces a counter_collection.csv to per-kernel sums, and
-  for the kernel matching RE to the sum over its dispatches LO..HI-1 (in
-  dispatch order; bench.py prints that window for its timed steps).
+* ``python3 -m paper_2311_14106_amd.traffic summarize CSV OUT [--windows
+  JSON]`` reduces a counter_collection.csv to per-kernel sums and, for each
+  entry {kernel: [LO, HI]} of JSON, to the sum over that kernel's dispatches
+  LO..HI-1 in dispatch order (bench.py prints these windows for its timed
+  steps, one per kernel name).
 * ``python3 -m paper_2311_14106_amd.traffic record ...`` combines the four
   summaries into the text record that bench.py reads back: HBM bytes per
   launch of the kernel, tied to a digest of the kernel and planner sources so
@@ -50,10 +51,8 @@ def copy_kernel():
     print(f'copy: 3 launches of {COPY_BYTES} B read + {COPY_BYTES} B written', flush=True)
 
 
-def summarize(path, kernel=None, window=None):
+def summarize(path, windows=None):
     per = collections.defaultdict(lambda: [set(), 0.0])
-    disp = collections.OrderedDict()
-    by_counter = collections.defaultdict(float)
     rows = []
     with open(path) as f:
         for r in csv.DictReader(f):
@@ -63,22 +62,27 @@ def summarize(path, kernel=None, window=None):
         e = per[(k, c)]
         e[0].add(d)
         e[1] += v
-        if kernel and re.search(kernel, k):
-            disp[d] = disp.get(d, 0.0) + v
-            by_counter[c] += v
     res = {'file': os.path.basename(path),
            'kernels': sorted(({'kernel': k[:120], 'counter': c, 'dispatches': len(ds), 'sum_kib': s}
                               for (k, c), (ds, s) in per.items()), key=lambda x: -x['sum_kib'])[:12]}
-    if kernel:
-        ids = list(disp)
-        res['kernel_re'] = kernel
-        res['kernel_dispatches'] = len(ids)
-        res['kernel_counters'] = dict(by_counter)
-        lo, hi = window if window else (0, len(ids))
-        sel = ids[lo:hi]
-        res['window'] = [lo, hi]
-        res['window_dispatches'] = len(sel)
-        res['window_sum_kib'] = sum(disp[i] for i in sel)
+    if windows:
+        res['windows'] = {}
+        tot_n, tot_s = 0, 0.0
+        for name, (lo, hi) in windows.items():
+            # kernel names print as 'void mdmrg::<name>(...)'
+            pat = re.compile(r'mdmrg::' + re.escape(name) + r'\(')
+            disp = collections.OrderedDict()
+            for d, k, c, v in rows:
+                if pat.search(k):
+                    disp[d] = disp.get(d, 0.0) + v
+            sel = list(disp)[lo:hi]
+            s = sum(disp[i] for i in sel)
+            res['windows'][name] = {'window': [lo, hi], 'dispatches': len(sel), 'sum_kib': s,
+                                    'kernel_dispatches': len(disp)}
+            tot_n += len(sel)
+            tot_s += s
+        res['window_dispatches'] = tot_n
+        res['window_sum_kib'] = tot_s
     return res
 
 
@@ -117,20 +121,19 @@ def main():
     s = sub.add_parser('summarize')
     s.add_argument('csv')
     s.add_argument('out')
-    s.add_argument('--kernel')
-    s.add_argument('--window', type=int, nargs=2)
+    s.add_argument('--windows', type=json.loads, default=None)
     r = sub.add_parser('record')
     for a in ('fetch_copy', 'write_copy', 'fetch_bench', 'write_bench', 'out'):
         r.add_argument('--' + a.replace('_', '-'), dest=a, required=True)
-    r.add_argument('--kernel-key', default='k_gemm<double>')
-    r.add_argument('--kernel-name', default='k_gemm<double>')
+    r.add_argument('--kernel-key', default='k_gemm<double> family')
+    r.add_argument('--kernel-name', default='k_gemm<double>, k_gemm_w16<double>, k_gemm_w4<double>')
     r.add_argument('--D', type=int, default=1024)
     r.add_argument('--header', default='')
     a = ap.parse_args()
     if a.cmd == 'copy':
         copy_kernel()
     elif a.cmd == 'summarize':
-        res = summarize(a.csv, a.kernel, a.window)
+        res = summarize(a.csv, a.windows)
         with open(a.out, 'w') as f:
             json.dump(res, f, indent=1)
         print(json.dumps({k: v for k, v in res.items() if k != 'kernels'}))
