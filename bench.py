@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 MFMA
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 MFMA
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # HBM traffic per launch of the dominant kernel, from FETCH_SIZE / WRITE_SIZE
 # counter passes over this same command (paper_2311_14106_amd/traffic.py)
@@ -143,33 +144,44 @@ def split_compare(ctx, x0, torch, args):
                                          max_iter=600)
     (em, rm, nm64, nm32, _), tm = solve(mixed)
     s1 = ctx.stats()
-    # precision + batched form: the same solves with every product replayed
-    # from a captured graph (captured once the kernel variants are tuned)
-    ctx.set_option(mdmrg.OPT_GRAPH, 1)
-    (eg, rg, ng64, ng32, _), tg = solve(mixed)
-    (e64g, _, n64g, _), t64g = solve(lambda x: ctx.davidson(x, tol=args.split_tol, max_iter=600))
-    s2 = ctx.stats()
-    ctx.set_option(mdmrg.OPT_GRAPH, 0)
     de = 1e-9 * abs(e_ref)
+    out = {}
+    if args.batched:
+        # precision + batched form: the same solves with every product
+        # replayed from a captured graph (captured once the kernel variants
+        # are tuned)
+        ctx.set_option(mdmrg.OPT_GRAPH, 1)
+        (eg, rg, ng64, ng32, _), tg = solve(mixed)
+        (e64g, _, n64g, _), t64g = solve(lambda x: ctx.davidson(x, tol=args.split_tol, max_iter=600))
+        s2 = ctx.stats()
+        ctx.set_option(mdmrg.OPT_GRAPH, 0)
+        g32 = (s2['graph32_ms'] - s1['graph32_ms']) / max(1.0, s2['graph32_launches'] - s1['graph32_launches'])
+        g64 = (s2['graph64_ms'] - s1['graph64_ms']) / max(1.0, s2['graph64_launches'] - s1['graph64_launches'])
+        out = {'mixed_fp32_graph': {'davidson_s': tg, 'products_fp32': ng32, 'products_fp64': ng64,
+                                    'dE': abs(eg - e_ref), 'ok': abs(eg - e_ref) <= de},
+               'fp64_graph': {'davidson_s': t64g, 'products': n64g, 'dE': abs(e64g - e_ref),
+                              'ok': abs(e64g - e_ref) <= de},
+               'speedup_precision_batched': t64 / tg if tg > 0 else None,
+               'graph_ms_per_product': {'fp64': g64, 'fp32': g32}}
     ms64 = (s1['heff_gemm_ms'] + s1['heff_p1_ms'] - s0['heff_gemm_ms'] - s0['heff_p1_ms']) / max(
         1.0, s1['n_matvec'] - s0['n_matvec'])
     ms32 = (s1['split_gemm_ms'] - s0['split_gemm_ms']) / max(1.0, s1['n_matvec_split'] - s0['n_matvec_split'])
-    g32 = (s2['graph32_ms'] - s1['graph32_ms']) / max(1.0, s2['graph32_launches'] - s1['graph32_launches'])
-    g64 = (s2['graph64_ms'] - s1['graph64_ms']) / max(1.0, s2['graph64_launches'] - s1['graph64_launches'])
     log(f'[bench] fixed-dE: ref E={e_ref:.12f} ({n_ref} products); FP64 {t64:.2f}s {n64} products '
-        f'dE={abs(e64 - e_ref):.1e}; mixed {tm:.2f}s {nm32} FP32 + {nm64} FP64 products dE={abs(em - e_ref):.1e}; '
-        f'mixed+graph {tg:.2f}s dE={abs(eg - e_ref):.1e}; FP64+graph {t64g:.2f}s')
-    return {'dE_target': de, 'E_ref': e_ref, 'residual_tol': args.split_tol,
-            'fp64': {'davidson_s': t64, 'products': n64, 'dE': abs(e64 - e_ref), 'ok': abs(e64 - e_ref) <= de},
-            'mixed_fp32': {'davidson_s': tm, 'products_fp32': nm32, 'products_fp64': nm64,
-                           'dE': abs(em - e_ref), 'ok': abs(em - e_ref) <= de},
-            'mixed_fp32_graph': {'davidson_s': tg, 'products_fp32': ng32, 'products_fp64': ng64,
-                                 'dE': abs(eg - e_ref), 'ok': abs(eg - e_ref) <= de},
-            'fp64_graph': {'davidson_s': t64g, 'products': n64g, 'dE': abs(e64g - e_ref),
-                           'ok': abs(e64g - e_ref) <= de},
-            'speedup': t64 / tm if tm > 0 else None,
-            'speedup_precision_batched': t64 / tg if tg > 0 else None,
-            'gemm_ms_per_product': {'fp64': ms64, 'fp32': ms32, 'fp64_graph': g64, 'fp32_graph': g32}}
+        f'dE={abs(e64 - e_ref):.1e}; mixed {tm:.2f}s {nm32} FP32 + {nm64} FP64 products dE={abs(em - e_ref):.1e}')
+    fl = ctx.heff_cost()['flop']
+    res = {'dE_target': de, 'E_ref': e_ref, 'residual_tol': args.split_tol,
+           # GEMM throughput of one product against the MFMA peak of its element type
+           'gemm_tflops': {'fp64': fl / (ms64 * 1e9) if ms64 > 0 else None,
+                           'fp32': fl / (ms32 * 1e9) if ms32 > 0 else None},
+           'gemm_frac_of_peak': {'fp64': fl / (ms64 * 1e9) / PEAK_FP64_TFLOPS if ms64 > 0 else None,
+                                 'fp32': fl / (ms32 * 1e9) / PEAK_FP32_TFLOPS if ms32 > 0 else None},
+           'fp64': {'davidson_s': t64, 'products': n64, 'dE': abs(e64 - e_ref), 'ok': abs(e64 - e_ref) <= de},
+           'mixed_fp32': {'davidson_s': tm, 'products_fp32': nm32, 'products_fp64': nm64,
+                          'dE': abs(em - e_ref), 'ok': abs(em - e_ref) <= de},
+           'speedup': t64 / tm if tm > 0 else None,
+           'gemm_ms_per_product': {'fp64': ms64, 'fp32': ms32}}
+    res.update(out)
+    return res
 
 
 def main():
@@ -187,6 +199,8 @@ def main():
     ap.add_argument('--cpu-budget', type=float, default=15.0)
     ap.add_argument('--no-cpu', action='store_true')
     ap.add_argument('--no-split', action='store_true')
+    ap.add_argument('--batched', action='store_true',
+                    help='also time the fixed-dE solves with every product replayed from a captured graph')
     ap.add_argument('--split-tol', type=float, default=1e-5,
                     help='FP64 residual tolerance of the fixed-dE Davidson comparison')
     args = ap.parse_args()
@@ -314,9 +328,15 @@ def main():
     # every launch of the kernel in this process (all contexts), for
     # comparison with a kernel-trace profile of the same command
     sp = ctx.stats()
-    roof['avg_launch_ms_whole_process'] = {f'{k}<double>': sp[f'proc_f64_{k}_ms'] / max(1.0, sp[f'proc_f64_{k}_launches'])
-                                           for k in kernels}
-    roof['launches_whole_process'] = {f'{k}<double>': int(sp[f'proc_f64_{k}_launches']) for k in kernels}
+    # whole process, every eager FP64 launch: the kernel family and each variant
+    fam_ms = sum(sp[f'proc_f64_{k}_ms'] for k in kernels)
+    fam_n = sum(sp[f'proc_f64_{k}_launches'] for k in kernels)
+    roof['avg_launch_ms_whole_process'] = fam_ms / max(1.0, fam_n)
+    roof['launches_whole_process'] = int(fam_n)
+    roof['variants_whole_process'] = {f'{k}<double>': {'launches': int(sp[f'proc_f64_{k}_launches']),
+                                                       'avg_ms': sp[f'proc_f64_{k}_ms'] /
+                                                       max(1.0, sp[f'proc_f64_{k}_launches'])}
+                                      for k in kernels}
     print(json.dumps(out), flush=True)
 
 
