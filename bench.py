@@ -193,6 +193,9 @@ def main():
     ap.add_argument('--D', type=int, default=1024)
     ap.add_argument('--profile-D', type=int, default=None,
                     help='bond dimension of the profile run (default 128 Hubbard, 64 spinless 8x8)')
+    ap.add_argument('--compress', type=int, default=1,
+                    help='interpolative compression of the cut coupling in the timed steps (the profile run '
+                         'always uses it, so both settings see the same workload)')
     ap.add_argument('--keep-envs', type=int, default=1,
                     help='0: keep only the block environments in use (large D)')
     ap.add_argument('--tol', type=float, default=1e-7)
@@ -220,6 +223,7 @@ def main():
     ctx = mdmrg.Context(0)
     n, spin, target, bonds = make_workload(mdmrg, ctx, args)
     ctx.set_option(mdmrg.OPT_KEEP_ENVS, args.keep_envs)
+    ctx.set_option(mdmrg.OPT_COMPRESS, args.compress)
     l0 = n // 2 - 1 - args.warmup - args.steps // 2
     t0 = time.time()
     ctx.set_mps(*si.flatten_mps(bonds, si.random_mps(bonds, spin, 1, l0), spin))
@@ -306,10 +310,12 @@ def main():
         'config': {'workload': f'{WORKLOADS[args.workload]}, D={args.D}, two-site DMRG steps from bond '
                                f'{l0 + args.warmup}',
                    'D': args.D, 'n_sites': n, 'precision_form': 'plain FP64',
+                   'compressed_cut_coupling': bool(args.compress),
                    'davidson_tol': args.tol},
         'davidson_s_per_step': d['diag_h_s'] / args.steps,
         'matvecs_per_step': nmv_total / args.steps,
         'heff_flop_per_matvec': flop_per_mv,
+        'heff_products_per_matvec': float(np.mean([c['n_terms'] for c in costs])),
         # share of H_eff FLOP by the smaller output side of each GEMM (bin lower edges)
         'heff_flop_share_by_min_mn': {str(b): v / max(sum(hist.values()), 1.0) for b, v in hist.items()},
         'step_breakdown_s': {k: d[k] / args.steps for k in

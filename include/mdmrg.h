@@ -138,12 +138,19 @@ enum {
                                   chain end */
   MDMRG_OPT_SCRATCH_LIMIT = 2, /* doubles of intermediate storage per product pass
                                   (default 2^30); larger values mean fewer passes */
-  MDMRG_OPT_GRAPH = 3          /* 1: after the first products of a bond (which also
+  MDMRG_OPT_GRAPH = 3,         /* 1: after the first products of a bond (which also
                                   tune the kernel's tile variant per launch), capture
                                   the bond's H_eff x launch sequence per precision in a
                                   HIP graph and replay it for every later product
                                   (x and y staged through context buffers for FP64);
                                   0 (default): launch eagerly */
+  MDMRG_OPT_COMPRESS = 4       /* 1 (default): the N^L x O_s x C^R products of a bond are
+                                  grouped by site operator s and quantum-number shift, and
+                                  each group is reduced by an interpolative decomposition
+                                  of its coefficient matrix (relative rank cut 1e-14,
+                                  reconstruction checked to 1e-12) to skeleton products
+                                  with on-the-fly left combinations; 0: one product per
+                                  left operator (takes effect at the next bond prepared) */
 };
 /* Set a context option (EINVAL for unknown options or bad values). */
 int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value);

@@ -194,6 +194,9 @@ int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value) {
       case MDMRG_OPT_GRAPH:
         c.set_graph(value != 0);
         break;
+      case MDMRG_OPT_COMPRESS:
+        c.compress = value != 0;
+        break;
       default:
         throw Error(MDMRG_EINVAL, "set_option: unknown option");
     }

@@ -996,6 +996,99 @@ void Context::prepare(int l) {
   build_heff(l);
 }
 
+// ------------------------------------------------- interpolative decomposition
+// Rows A (m x c, row-major) are approximated as A = T A[skel] with skel a set
+// of r rows picked by Gram-Schmidt with pivoting on the largest residual norm
+// (a rank-revealing QR of A^T); a row is dropped from the basis once its
+// residual is below tol * (largest row norm).  Returns false (no compression)
+// when r is not below m or the explicit reconstruction error exceeds
+// check * (largest row norm).
+static bool interp_decomp(const std::vector<double> &A, int m, int c, double tol, double check,
+                          std::vector<int> &skel, std::vector<double> &T) {
+  std::vector<double> Rr(A);
+  std::vector<double> nrm(m, 0.0);
+  double amax = 0.0;
+  for (int i = 0; i < m; ++i) {
+    double s2 = 0.0;
+    for (int j = 0; j < c; ++j) s2 += A[size_t(i) * c + j] * A[size_t(i) * c + j];
+    nrm[i] = s2;
+    amax = std::max(amax, std::sqrt(s2));
+  }
+  skel.clear();
+  if (amax == 0.0) return false;
+  std::vector<std::vector<double>> Q;
+  std::vector<char> used(m, 0);
+  for (;;) {
+    int best = -1;
+    double bn = 0.0;
+    for (int i = 0; i < m; ++i)
+      if (!used[i] && nrm[i] > bn) {
+        bn = nrm[i];
+        best = i;
+      }
+    if (best < 0 || std::sqrt(bn) <= tol * amax) break;
+    std::vector<double> q(Rr.begin() + size_t(best) * c, Rr.begin() + size_t(best + 1) * c);
+    for (int pass = 0; pass < 2; ++pass)  // reorthogonalise against the basis
+      for (auto &qk : Q) {
+        double d = 0.0;
+        for (int j = 0; j < c; ++j) d += qk[j] * q[j];
+        for (int j = 0; j < c; ++j) q[j] -= d * qk[j];
+      }
+    double qn = 0.0;
+    for (double v : q) qn += v * v;
+    qn = std::sqrt(qn);
+    if (qn <= tol * amax) break;
+    for (double &v : q) v /= qn;
+    used[best] = 1;
+    skel.push_back(best);
+    for (int i = 0; i < m; ++i) {
+      if (used[i]) continue;
+      double *ri = &Rr[size_t(i) * c];
+      double d = 0.0;
+      for (int j = 0; j < c; ++j) d += ri[j] * q[j];
+      double s2 = 0.0;
+      for (int j = 0; j < c; ++j) {
+        ri[j] -= d * q[j];
+        s2 += ri[j] * ri[j];
+      }
+      nrm[i] = s2;
+    }
+    Q.push_back(std::move(q));
+    if (int(skel.size()) >= m) break;
+  }
+  const int r = int(skel.size());
+  if (r == 0 || r >= m) return false;
+  // coefficients of every row in the orthonormal basis, C (m x r); the
+  // skeleton block C[skel] is lower triangular in pick order
+  std::vector<double> C(size_t(m) * r, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int k = 0; k < r; ++k) {
+      double d = 0.0;
+      for (int j = 0; j < c; ++j) d += A[size_t(i) * c + j] * Q[k][j];
+      C[size_t(i) * r + k] = d;
+    }
+  // T C[skel] = C  (row-wise back substitution on the lower-triangular block)
+  T.assign(size_t(m) * r, 0.0);
+  for (int i = 0; i < m; ++i) {
+    for (int k = r - 1; k >= 0; --k) {
+      double v = C[size_t(i) * r + k];
+      for (int k2 = k + 1; k2 < r; ++k2) v -= T[size_t(i) * r + k2] * C[size_t(skel[k2]) * r + k];
+      T[size_t(i) * r + k] = v / C[size_t(skel[k]) * r + k];
+    }
+  }
+  // explicit check of A = T A[skel]
+  for (int i = 0; i < m; ++i) {
+    double e2 = 0.0;
+    for (int j = 0; j < c; ++j) {
+      double v = A[size_t(i) * c + j];
+      for (int k = 0; k < r; ++k) v -= T[size_t(i) * r + k] * A[size_t(skel[k]) * c + j];
+      e2 += v * v;
+    }
+    if (std::sqrt(e2) > check * amax) return false;
+  }
+  return true;
+}
+
 // ------------------------------------------------------------- H_eff
 void Context::build_heff(int l) {
   double t0 = wall_seconds();
@@ -1047,6 +1140,19 @@ void Context::build_heff(int l) {
     add_item2(OpRef{1, kH}, ident, Id, 0, 1.0);
     add_item2(ident, OpRef{1, kH}, Id, 0, 1.0);
   }
+  struct CGroup {
+    int e1[4] = {}, e2[4] = {}, k1 = 0, k2 = 0, nL = 0;
+    QN qL;
+    std::vector<uint64_t> rows, rkey, cols;  // left normal key, right complementary key, right string
+    std::unordered_map<uint64_t, int> row_of, col_of;
+    struct E {
+      int r, c;
+      double v;
+    };
+    std::vector<E> entries;
+  };
+  std::map<std::tuple<uint64_t, int, int64_t>, CGroup> cgroups;  // (site string, ops on site 1, shift of K_L)
+  std::map<uint64_t, std::pair<QN, std::map<uint64_t, double>>> zcombos;  // K_Z combos of L
   for (const Term &t : H.terms) {
     Parts p;
     split(H, t, l, p);
@@ -1060,6 +1166,47 @@ void Context::build_heff(int l) {
       int K[4], kk = 0;
       for (int q = 0; q < 3; ++q)
         for (int i = 0; i < p.k[q]; ++i) K[kk++] = p.e[q][i];
+      if (compress && kL >= 1) {
+        // N^L_{K_L} x O_s x C^R_{K_L s}: collected per (site string s, shift
+        // of K_L); the row of K_L holds the coefficients of C^R_{K_L s} over
+        // the strings of R, i.e. the coefficients of these terms
+        int S[4], ks = 0;
+        for (int q = 1; q < 3; ++q)
+          for (int i = 0; i < p.k[q]; ++i) S[ks++] = p.e[q][i];
+        const QN qL = q_sum(H, p.e[0], kL);
+        auto &g = cgroups[std::make_tuple(make_key(K_N, S, ks), p.k[1], qL.key())];
+        if (g.rows.empty() && g.cols.empty()) {
+          g.k1 = p.k[1];
+          g.k2 = p.k[2];
+          for (int i = 0; i < p.k[1]; ++i) g.e1[i] = p.e[1][i];
+          for (int i = 0; i < p.k[2]; ++i) g.e2[i] = p.e[2][i];
+          g.qL = qL;
+          g.nL = kL;
+        }
+        const uint64_t rk = make_key(K_N, p.e[0], kL);
+        auto ri = g.row_of.find(rk);
+        int row;
+        if (ri == g.row_of.end()) {
+          row = int(g.rows.size());
+          g.row_of[rk] = row;
+          g.rows.push_back(rk);
+          g.rkey.push_back(make_key(K_C, K, kk));
+        } else {
+          row = ri->second;
+        }
+        const uint64_t ck = make_key(K_N, p.e[3], kR);
+        auto ci = g.col_of.find(ck);
+        int col;
+        if (ci == g.col_of.end()) {
+          col = int(g.cols.size());
+          g.col_of[ck] = col;
+          g.cols.push_back(ck);
+        } else {
+          col = ci->second;
+        }
+        g.entries.push_back({row, col, t.c});
+        continue;
+      }
       OpRef lr = kL == 0 ? ident : OpRef{1, make_key(K_N, p.e[0], kL)};
       add_set(lr, OpRef{1, make_key(K_C, K, kk)}, p.e[1], p.k[1], p.e[2], p.k[2]);
       continue;
@@ -1090,16 +1237,53 @@ void Context::build_heff(int l) {
     add_set(OpRef{stored ? 1 : 2, make_key(stored ? K_C : K_X, K, kk)}, ident, p.e[1], p.k[1], p.e[2], p.k[2]);
     (void)kS;
   }
+  // interpolative compression of each group: sum_K N^L_K x O_s x C^R_{K s}
+  // = sum_{j in skel} (sum_K T_Kj N^L_K) x O_s x C^R_{K_j s}, exact because the
+  // stored C^R are linear in their coefficients
+  int64_t n_before = 0, n_after = 0;
+  for (auto &gk : cgroups) {
+    CGroup &g = gk.second;
+    const int m = int(g.rows.size()), c = int(g.cols.size());
+    std::vector<double> A(size_t(m) * c, 0.0);
+    for (auto &e : g.entries) A[size_t(e.r) * c + e.c] += e.v;
+    std::vector<int> skel;
+    std::vector<double> T;
+    const bool ok = m > 1 && interp_decomp(A, m, c, 1e-14, 1e-12, skel, T);
+    n_before += m;
+    if (!ok) {
+      for (int i = 0; i < m; ++i) add_set(OpRef{1, g.rows[i]}, OpRef{1, g.rkey[i]}, g.e1, g.k1, g.e2, g.k2);
+      n_after += m;
+      continue;
+    }
+    const int r = int(skel.size());
+    n_after += r;
+    const std::vector<double> O = two_site(g.e1, g.k1, g.e2, g.k2);
+    for (int k = 0; k < r; ++k) {
+      const uint64_t zk = uint64_t(K_Z) | (uint64_t(g.nL) << 4) | (uint64_t(zcombos.size()) << 8);
+      auto &zc = zcombos[zk];
+      zc.first = g.qL;
+      for (int i = 0; i < m; ++i) {
+        const double v = T[size_t(i) * r + k];
+        if (v != 0.0) zc.second[g.rows[i]] += v;
+      }
+      add_item2(OpRef{2, zk}, OpRef{1, g.rkey[skel[k]]}, O, (g.k1 + g.k2) & 1, 1.0);
+    }
+  }
   const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
+  if (verbose && n_before)
+    fprintf(stderr, "[mdmrg] bond %d: N^L x C^R products %lld -> %lld after interpolative compression\n", l,
+            (long long)n_before, (long long)n_after);
   double tv[5] = {wall_seconds(), 0, 0, 0, 0};  // verbose sub-timing: products, combos, tasks, plan
   // on-the-fly complementary operators
-  if (!wantL.empty()) {
+  if (!wantL.empty() || !zcombos.empty()) {
     Lx = std::make_unique<OpSet>();
     Lx->bond = L.bond;
     for (uint64_t k : wantL) Lx->add(k, combo_delta(H, true, k));
+    for (auto &z : zcombos) Lx->add(z.first, z.second.first);
     Lx->layout(dev);
     Content c;
     combo_content(H, true, l, wantL, c);
+    for (auto &z : zcombos) c[z.first] = z.second.second;
     materialize(dev, *Lx, L, c);
   }
   if (!wantR.empty()) {

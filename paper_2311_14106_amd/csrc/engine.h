@@ -14,7 +14,10 @@ namespace mdmrg {
 // the listed operators (all inside the block); K_C: stored complementary
 // operator whose listed operators lie outside the block; K_X: complementary
 // operator formed on the fly from normal operators at one step.
-enum Kind : int { K_H = 0, K_N = 1, K_C = 2, K_X = 3, K_I = 15 };
+// K_Z: a linear combination of normal operators of the left block that
+// replaces a set of N^L x C^R products by a smaller set (key = K_Z | n << 4 |
+// id << 8, n = length of the combined normal operators)
+enum Kind : int { K_H = 0, K_N = 1, K_C = 2, K_X = 3, K_Z = 4, K_I = 15 };
 uint64_t make_key(int kind, const int *e, int n);
 inline uint64_t ident_key() { return uint64_t(K_I); }
 
@@ -184,6 +187,7 @@ struct Context {
   Stats stats;
   int64_t scratch_limit = int64_t(1) << 30;  // doubles of phase-1 scratch (8 GB)
   bool keep_envs = true;  // keep every block environment built (needed by sweeps)
+  bool compress = true;    // interpolative compression of the N^L x C^R products
   // graph replay of the H_eff product (MDMRG_OPT_GRAPH): captured per bond and
   // precision once the first products have tuned the kernel variants
   bool use_graph = false;
