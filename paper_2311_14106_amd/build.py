@@ -13,7 +13,7 @@ HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 CXX = os.environ.get('CXX', 'g++')
 
 SOURCES = ['device.hip', 'model.cpp', 'engine.cpp', 'capi.cpp']
-COMMON = ['-O3', '-fPIC', '-std=c++17', '-Wall', '-Wno-unused-result']
+COMMON = ['-O3', '-fPIC', '-std=c++17', '-Wall', '-Wno-unused-result', '-pthread']
 HIP_FLAGS = ['-x', 'hip', '--offload-arch=gfx950',
              '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops']
 
@@ -36,7 +36,7 @@ def build(verbose=False):
         objs.append(obj)
     tmp = OUT + '.tmp'
     cmd = [HIPCC, '-shared', '-fPIC', '--offload-arch=gfx950', '-o', tmp] + objs + \
-          ['-L/opt/rocm/lib', '-lrocsolver', '-lrocblas', '-Wl,-rpath,/opt/rocm/lib']
+          ['-L/opt/rocm/lib', '-lrocsolver', '-lrocblas', '-pthread', '-Wl,-rpath,/opt/rocm/lib']
     if verbose:
         print(' '.join(cmd), flush=True)
     subprocess.check_call(cmd)

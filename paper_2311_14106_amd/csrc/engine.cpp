@@ -11,6 +11,8 @@
 // few complementary operators of L that the sums need), so that the number
 // of products is O(n^2) and every product is a pair of dense sector GEMMs.
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -999,10 +1001,13 @@ void Context::prepare(int l) {
 // ------------------------------------------------- interpolative decomposition
 // Rows A (m x c, row-major) are approximated as A = T A[skel] with skel a set
 // of r rows picked by Gram-Schmidt with pivoting on the largest residual norm
-// (a rank-revealing QR of A^T); a row is dropped from the basis once its
-// residual is below tol * (largest row norm).  Returns false (no compression)
-// when r is not below m or the explicit reconstruction error exceeds
-// check * (largest row norm).
+// (a rank-revealing QR of A^T); picking stops once every residual is below
+// tol * (largest row norm).  One pass: the projection of each row on each
+// new basis vector is recorded as it is removed, which gives the
+// coefficients C (m x r) of every row in the orthonormal basis (lower
+// triangular on the skeleton rows), and the final residuals are the
+// reconstruction errors.  Returns false (no compression) when r is not below m
+// or a residual exceeds check * (largest row norm).
 static bool interp_decomp(const std::vector<double> &A, int m, int c, double tol, double check,
                           std::vector<int> &skel, std::vector<double> &T) {
   std::vector<double> Rr(A);
@@ -1015,8 +1020,9 @@ static bool interp_decomp(const std::vector<double> &A, int m, int c, double tol
     amax = std::max(amax, std::sqrt(s2));
   }
   skel.clear();
-  if (amax == 0.0) return false;
+  if (amax == 0.0 || m < 2) return false;
   std::vector<std::vector<double>> Q;
+  std::vector<std::vector<double>> coef(m);  // coef[i][k] = A_i . q_k
   std::vector<char> used(m, 0);
   for (;;) {
     int best = -1;
@@ -1027,19 +1033,23 @@ static bool interp_decomp(const std::vector<double> &A, int m, int c, double tol
         best = i;
       }
     if (best < 0 || std::sqrt(bn) <= tol * amax) break;
+    if (int(skel.size()) + 1 >= m) return false;  // no reduction
     std::vector<double> q(Rr.begin() + size_t(best) * c, Rr.begin() + size_t(best + 1) * c);
-    for (int pass = 0; pass < 2; ++pass)  // reorthogonalise against the basis
-      for (auto &qk : Q) {
-        double d = 0.0;
-        for (int j = 0; j < c; ++j) d += qk[j] * q[j];
-        for (int j = 0; j < c; ++j) q[j] -= d * qk[j];
-      }
+    // reorthogonalise the picked residual against the basis (its earlier
+    // projections are already in coef[best]; the corrections are added)
+    for (size_t k = 0; k < Q.size(); ++k) {
+      double d = 0.0;
+      for (int j = 0; j < c; ++j) d += Q[k][j] * q[j];
+      for (int j = 0; j < c; ++j) q[j] -= d * Q[k][j];
+      coef[best][k] += d;
+    }
     double qn = 0.0;
     for (double v : q) qn += v * v;
     qn = std::sqrt(qn);
     if (qn <= tol * amax) break;
     for (double &v : q) v /= qn;
     used[best] = 1;
+    coef[best].push_back(qn);
     skel.push_back(best);
     for (int i = 0; i < m; ++i) {
       if (used[i]) continue;
@@ -1052,40 +1062,24 @@ static bool interp_decomp(const std::vector<double> &A, int m, int c, double tol
         s2 += ri[j] * ri[j];
       }
       nrm[i] = s2;
+      coef[i].resize(skel.size() - 1, 0.0);
+      coef[i].push_back(d);
     }
     Q.push_back(std::move(q));
-    if (int(skel.size()) >= m) break;
   }
   const int r = int(skel.size());
   if (r == 0 || r >= m) return false;
-  // coefficients of every row in the orthonormal basis, C (m x r); the
-  // skeleton block C[skel] is lower triangular in pick order
-  std::vector<double> C(size_t(m) * r, 0.0);
   for (int i = 0; i < m; ++i)
-    for (int k = 0; k < r; ++k) {
-      double d = 0.0;
-      for (int j = 0; j < c; ++j) d += A[size_t(i) * c + j] * Q[k][j];
-      C[size_t(i) * r + k] = d;
-    }
-  // T C[skel] = C  (row-wise back substitution on the lower-triangular block)
+    if (!used[i] && std::sqrt(nrm[i]) > check * amax) return false;
+  // T C[skel] = C, with C[skel] lower triangular in pick order
+  auto C = [&](int i, int k) { return k < int(coef[i].size()) ? coef[i][k] : 0.0; };
   T.assign(size_t(m) * r, 0.0);
-  for (int i = 0; i < m; ++i) {
+  for (int i = 0; i < m; ++i)
     for (int k = r - 1; k >= 0; --k) {
-      double v = C[size_t(i) * r + k];
-      for (int k2 = k + 1; k2 < r; ++k2) v -= T[size_t(i) * r + k2] * C[size_t(skel[k2]) * r + k];
-      T[size_t(i) * r + k] = v / C[size_t(skel[k]) * r + k];
+      double v = C(i, k);
+      for (int k2 = k + 1; k2 < r; ++k2) v -= T[size_t(i) * r + k2] * C(skel[k2], k);
+      T[size_t(i) * r + k] = v / C(skel[k], k);
     }
-  }
-  // explicit check of A = T A[skel]
-  for (int i = 0; i < m; ++i) {
-    double e2 = 0.0;
-    for (int j = 0; j < c; ++j) {
-      double v = A[size_t(i) * c + j];
-      for (int k = 0; k < r; ++k) v -= T[size_t(i) * r + k] * A[size_t(skel[k]) * c + j];
-      e2 += v * v;
-    }
-    if (std::sqrt(e2) > check * amax) return false;
-  }
   return true;
 }
 
@@ -1241,32 +1235,56 @@ void Context::build_heff(int l) {
   // = sum_{j in skel} (sum_K T_Kj N^L_K) x O_s x C^R_{K_j s}, exact because the
   // stored C^R are linear in their coefficients
   int64_t n_before = 0, n_after = 0;
-  for (auto &gk : cgroups) {
-    CGroup &g = gk.second;
-    const int m = int(g.rows.size()), c = int(g.cols.size());
-    std::vector<double> A(size_t(m) * c, 0.0);
-    for (auto &e : g.entries) A[size_t(e.r) * c + e.c] += e.v;
-    std::vector<int> skel;
-    std::vector<double> T;
-    const bool ok = m > 1 && interp_decomp(A, m, c, 1e-14, 1e-12, skel, T);
-    n_before += m;
-    if (!ok) {
-      for (int i = 0; i < m; ++i) add_set(OpRef{1, g.rows[i]}, OpRef{1, g.rkey[i]}, g.e1, g.k1, g.e2, g.k2);
-      n_after += m;
-      continue;
-    }
-    const int r = int(skel.size());
-    n_after += r;
-    const std::vector<double> O = two_site(g.e1, g.k1, g.e2, g.k2);
-    for (int k = 0; k < r; ++k) {
-      const uint64_t zk = uint64_t(K_Z) | (uint64_t(g.nL) << 4) | (uint64_t(zcombos.size()) << 8);
-      auto &zc = zcombos[zk];
-      zc.first = g.qL;
-      for (int i = 0; i < m; ++i) {
-        const double v = T[size_t(i) * r + k];
-        if (v != 0.0) zc.second[g.rows[i]] += v;
+  {
+    // decompositions of the groups are independent: host threads take them
+    // in turn; the products are then emitted in group order
+    std::vector<CGroup *> gl;
+    for (auto &gk : cgroups) gl.push_back(&gk.second);
+    struct IdOut {
+      bool ok = false;
+      std::vector<int> skel;
+      std::vector<double> T;
+    };
+    std::vector<IdOut> res(gl.size());
+    std::atomic<size_t> next{0};
+    auto work = [&] {
+      for (size_t gi; (gi = next.fetch_add(1)) < gl.size();) {
+        const CGroup &g = *gl[gi];
+        const int m = int(g.rows.size()), c = int(g.cols.size());
+        std::vector<double> A(size_t(m) * c, 0.0);
+        for (auto &e : g.entries) A[size_t(e.r) * c + e.c] += e.v;
+        res[gi].ok = m > 1 && interp_decomp(A, m, c, 1e-14, 1e-12, res[gi].skel, res[gi].T);
       }
-      add_item2(OpRef{2, zk}, OpRef{1, g.rkey[skel[k]]}, O, (g.k1 + g.k2) & 1, 1.0);
+    };
+    const int nth = int(std::min<size_t>(gl.size(), std::max(1u, std::min(16u, std::thread::hardware_concurrency()))));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nth; ++t) pool.emplace_back(work);
+    work();
+    for (auto &th : pool) th.join();
+    for (size_t gi = 0; gi < gl.size(); ++gi) {
+      CGroup &g = *gl[gi];
+      const int m = int(g.rows.size());
+      n_before += m;
+      if (!res[gi].ok) {
+        for (int i = 0; i < m; ++i) add_set(OpRef{1, g.rows[i]}, OpRef{1, g.rkey[i]}, g.e1, g.k1, g.e2, g.k2);
+        n_after += m;
+        continue;
+      }
+      const std::vector<int> &skel = res[gi].skel;
+      const std::vector<double> &T = res[gi].T;
+      const int r = int(skel.size());
+      n_after += r;
+      const std::vector<double> O = two_site(g.e1, g.k1, g.e2, g.k2);
+      for (int k = 0; k < r; ++k) {
+        const uint64_t zk = uint64_t(K_Z) | (uint64_t(g.nL) << 4) | (uint64_t(zcombos.size()) << 8);
+        auto &zc = zcombos[zk];
+        zc.first = g.qL;
+        for (int i = 0; i < m; ++i) {
+          const double v = T[size_t(i) * r + k];
+          if (v != 0.0) zc.second[g.rows[i]] += v;
+        }
+        add_item2(OpRef{2, zk}, OpRef{1, g.rkey[skel[k]]}, O, (g.k1 + g.k2) & 1, 1.0);
+      }
     }
   }
   const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
