@@ -65,9 +65,18 @@ WORKLOADS = {
 }
 
 
+def profile_file(args):
+    return os.path.join(ROOT, 'paper_2311_14106_amd', 'data',
+                        f'sector_profile_{args.workload}_D{args.profile_D}.json')
+
+
 def make_workload(mdmrg, ctx, args):
-    """Hamiltonian of the workload and the sector profile of every bond: a
-    short real two-site run at low bond dimension, scaled to D."""
+    """Hamiltonian of the workload and the sector profile of every bond: the
+    kept sector dimensions of a short real two-site run at low bond
+    dimension (seeded random start, one sweep), scaled to D.  The recorded
+    profile in paper_2311_14106_amd/data is used when present, so that the
+    workload does not follow rounding-level changes of the code through the
+    degenerate low-D run; --write-profile records it."""
     import seeded_inputs as si
     if args.workload == 'hubbard6x6':
         n, spin, target = 36, True, (18, 18)
@@ -77,12 +86,29 @@ def make_workload(mdmrg, ctx, args):
         T, V = mdmrg.build_lattice(mdmrg.SPINLESS, mdmrg.MOMENTUM, 8, 8, 1.0, 2.0)
         T, V = mdmrg.rotate_modes(si.shell_rotation(np.diag(T), 0), T, V, False)
     ctx.set_hamiltonian(n, spin, T, V, target)
-    b0 = si.bond_profile(n, spin, target, 16)
-    ctx.set_mps(*si.flatten_mps(b0, si.random_mps(b0, spin, 1, 0), spin))
-    t0 = time.time()
-    ctx.sweep(1, [args.profile_D], 1e-6)
-    small = [ctx.get_bond(i) for i in range(n + 1)]
-    log(f'[bench] profile run D={args.profile_D}: {time.time() - t0:.1f}s')
+    pf = profile_file(args)
+    if os.path.exists(pf) and not args.write_profile:
+        with open(pf) as f:
+            small = [[(tuple(q), m) for q, m in b] for b in json.load(f)['bonds']]
+        log(f'[bench] sector profile from {os.path.relpath(pf, ROOT)}')
+    else:
+        b0 = si.bond_profile(n, spin, target, 16)
+        ctx.set_mps(*si.flatten_mps(b0, si.random_mps(b0, spin, 1, 0), spin))
+        t0 = time.time()
+        ctx.sweep(1, [args.profile_D], 1e-6)
+        small = [ctx.get_bond(i) for i in range(n + 1)]
+        log(f'[bench] profile run D={args.profile_D}: {time.time() - t0:.1f}s')
+        if args.write_profile:
+            os.makedirs(os.path.dirname(pf), exist_ok=True)
+            with open(pf, 'w') as f:
+                json.dump({'workload': WORKLOADS[args.workload], 'profile_D': args.profile_D,
+                           'recipe': 'one two-site sweep at bond dimension profile_D from a random MPS '
+                                     '(seeded_inputs.bond_profile(n, spin, target, 16), random_mps seed 1, '
+                                     'centre 0), Davidson tolerance 1e-6; kept sector dimensions per bond',
+                           'command': f'python bench.py --workload {args.workload} --profile-D {args.profile_D} '
+                                      f'--write-profile',
+                           'bonds': [[[list(q), int(m)] for q, m in b] for b in small]}, f)
+            log(f'[bench] recorded {os.path.relpath(pf, ROOT)}')
     bonds = si.scale_profile(small, n, spin, target, args.D)
     return n, spin, target, bonds
 
@@ -193,6 +219,9 @@ def main():
     ap.add_argument('--D', type=int, default=1024)
     ap.add_argument('--profile-D', type=int, default=None,
                     help='bond dimension of the profile run (default 128 Hubbard, 64 spinless 8x8)')
+    ap.add_argument('--write-profile', action='store_true',
+                    help='only run the low-D profile sweep and record its sector profile in '
+                         'paper_2311_14106_amd/data')
     ap.add_argument('--compress', type=int, default=1,
                     help='interpolative compression of the cut coupling in the timed steps (the profile run '
                          'always uses it, so both settings see the same workload)')
@@ -222,6 +251,8 @@ def main():
 
     ctx = mdmrg.Context(0)
     n, spin, target, bonds = make_workload(mdmrg, ctx, args)
+    if args.write_profile:
+        return
     ctx.set_option(mdmrg.OPT_KEEP_ENVS, args.keep_envs)
     ctx.set_option(mdmrg.OPT_COMPRESS, args.compress)
     l0 = n // 2 - 1 - args.warmup - args.steps // 2
