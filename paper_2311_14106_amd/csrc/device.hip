@@ -203,7 +203,7 @@ void dev_zero(Device *d, void *dst, size_t bytes) {
 // ------------------------------------------- grouped GEMM (FP64 and FP32)
 // Workgroup = 8 waves (2 x 4) = 64x64 output tile; each wave owns a 32x16
 // block as 2x1 MFMA 16x16x4 accumulators.  K is staged through LDS in steps
-// of 16.  Operand layout of v_mfma_f64_16x16x4f64: lane l supplies
+// of 8 or 16.  Operand layout of v_mfma_f64_16x16x4f64: lane l supplies
 // A[l%16][l/16] and B[l/16][l%16]; accumulator element r of lane l is
 // C[l/16 + 4r][l%16] for FP64 and C[4(l/16) + r][l%16] for FP32.
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -248,18 +248,21 @@ struct TileCfg {
 // them all; they differ in how the tile is split over waves).  Every output
 // element is accumulated over K in the same order in all of them, so their
 // results are bitwise identical; the autotuner picks one per plan.
-// The K step is 16 for both element types (a step of 32 for FP32, with the
-// same LDS bytes per stage as FP64, measured slower).
+// K step: FP64 stages 8 columns per step in the 8- and 4-wave splits (half
+// the LDS of a 16-column step, so twice the workgroups per CU; measured
+// faster on split-K H_eff products) and 16 in the 16-wave split, which keeps
+// the unsplit long-K case; FP32 stages 16 everywhere (32, the same LDS bytes
+// per stage as FP64 at 16, measured slower).
 template <class T>
-constexpr int tk_of() {
-  return 16;
+constexpr int tk_small() {
+  return sizeof(T) == 8 ? 8 : 16;
 }
 template <class T>
-using Cfg64 = TileCfg<64, 64, 2, 4, tk_of<T>()>;  // variant 0, k_gemm: 8 waves of 32x16
+using Cfg64 = TileCfg<64, 64, 2, 4, tk_small<T>()>;  // variant 0, k_gemm: 8 waves of 32x16
 template <class T>
-using Cfg64w = TileCfg<64, 64, 4, 4, tk_of<T>()>;  // variant 1, k_gemm_w16: 16 waves of 16x16
+using Cfg64w = TileCfg<64, 64, 4, 4, 16>;  // variant 1, k_gemm_w16: 16 waves of 16x16
 template <class T>
-using Cfg64q = TileCfg<64, 64, 2, 2, tk_of<T>()>;  // variant 2, k_gemm_w4: 4 waves of 32x32
+using Cfg64q = TileCfg<64, 64, 2, 2, tk_small<T>()>;  // variant 2, k_gemm_w4: 4 waves of 32x32
 constexpr int kTileM = 64, kTileN = 64;  // output tile of every variant
 constexpr int kPad = 2;  // LDS row padding (doubles) of the staged A / B tiles
 
