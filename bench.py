@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 MFMA
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 MFMA
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # HBM traffic per launch of the dominant kernel, from FETCH_SIZE / WRITE_SIZE
 # counter passes over this same command (paper_2311_14106_amd/traffic.py)
@@ -149,8 +150,8 @@ def cpu_baseline(mdmrg, budget_s):
 
 
 def split_compare(ctx, x0, torch, args):
-    """Davidson s/step at fixed dE: FP64 form vs mixed precision (FP32
-    products, then FP64 refinement), eagerly launched and replayed from
+    """Davidson s/step at fixed dE: FP64 form vs mixed precision (FP32 or
+    3xBF16 products, then FP64 refinement), eagerly launched and replayed from
     captured graphs, all from the same start vector at the current bond;
     E_ref = FP64 solve to |r| <= 1e-10; dE = 1e-9 |E_ref|."""
     from paper_2311_14106_amd import mdmrg
@@ -170,6 +171,10 @@ def split_compare(ctx, x0, torch, args):
                                          max_iter=600)
     (em, rm, nm64, nm32, _), tm = solve(mixed)
     s1 = ctx.stats()
+    mixed3 = lambda x: ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol,
+                                          prec_split=mdmrg.BF16X3, max_iter=600)
+    (eb, rb, nb64, nb3, _), tb = solve(mixed3)
+    s1b = ctx.stats()
     de = 1e-9 * abs(e_ref)
     out = {}
     if args.batched:
@@ -192,20 +197,29 @@ def split_compare(ctx, x0, torch, args):
     ms64 = (s1['heff_gemm_ms'] + s1['heff_p1_ms'] - s0['heff_gemm_ms'] - s0['heff_p1_ms']) / max(
         1.0, s1['n_matvec'] - s0['n_matvec'])
     ms32 = (s1['split_gemm_ms'] - s0['split_gemm_ms']) / max(1.0, s1['n_matvec_split'] - s0['n_matvec_split'])
+    msb = (s1b['split_gemm_ms'] - s1['split_gemm_ms']) / max(1.0, s1b['n_matvec_split'] - s1['n_matvec_split'])
     log(f'[bench] fixed-dE: ref E={e_ref:.12f} ({n_ref} products); FP64 {t64:.2f}s {n64} products '
-        f'dE={abs(e64 - e_ref):.1e}; mixed {tm:.2f}s {nm32} FP32 + {nm64} FP64 products dE={abs(em - e_ref):.1e}')
+        f'dE={abs(e64 - e_ref):.1e}; mixed {tm:.2f}s {nm32} FP32 + {nm64} FP64 products dE={abs(em - e_ref):.1e}; '
+        f'mixed 3xBF16 {tb:.2f}s {nb3} 3xBF16 + {nb64} FP64 products dE={abs(eb - e_ref):.1e}')
     fl = ctx.heff_cost()['flop']
     res = {'dE_target': de, 'E_ref': e_ref, 'residual_tol': args.split_tol,
-           # GEMM throughput of one product against the MFMA peak of its element type
+           # GEMM throughput of one product (algorithmic FLOP, 2mnk) against the
+           # MFMA peak of its element type; the 3xBF16 form issues three BF16
+           # MFMA products per algorithmic one
            'gemm_tflops': {'fp64': fl / (ms64 * 1e9) if ms64 > 0 else None,
-                           'fp32': fl / (ms32 * 1e9) if ms32 > 0 else None},
+                           'fp32': fl / (ms32 * 1e9) if ms32 > 0 else None,
+                           'bf16x3': fl / (msb * 1e9) if msb > 0 else None},
            'gemm_frac_of_peak': {'fp64': fl / (ms64 * 1e9) / PEAK_FP64_TFLOPS if ms64 > 0 else None,
-                                 'fp32': fl / (ms32 * 1e9) / PEAK_FP32_TFLOPS if ms32 > 0 else None},
+                                 'fp32': fl / (ms32 * 1e9) / PEAK_FP32_TFLOPS if ms32 > 0 else None,
+                                 'bf16x3_issued': 3 * fl / (msb * 1e9) / PEAK_BF16_TFLOPS if msb > 0 else None},
            'fp64': {'davidson_s': t64, 'products': n64, 'dE': abs(e64 - e_ref), 'ok': abs(e64 - e_ref) <= de},
            'mixed_fp32': {'davidson_s': tm, 'products_fp32': nm32, 'products_fp64': nm64,
                           'dE': abs(em - e_ref), 'ok': abs(em - e_ref) <= de},
+           'mixed_bf16x3': {'davidson_s': tb, 'products_bf16x3': nb3, 'products_fp64': nb64,
+                            'dE': abs(eb - e_ref), 'ok': abs(eb - e_ref) <= de},
            'speedup': t64 / tm if tm > 0 else None,
-           'gemm_ms_per_product': {'fp64': ms64, 'fp32': ms32}}
+           'speedup_bf16x3': t64 / tb if tb > 0 else None,
+           'gemm_ms_per_product': {'fp64': ms64, 'fp32': ms32, 'bf16x3': msb}}
     res.update(out)
     return res
 
@@ -302,7 +316,8 @@ def main():
     ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
     # the grouped GEMM kernel in the timed FP64 H_eff products (HIP events on
     # the library stream around every launch)
-    name = 'k_gemm<double> family (64x64 tiles; autotuned wave split: k_gemm, k_gemm_w16, k_gemm_w4)'
+    name = ('k_gemm<double> family (autotuned per plan: 64x64 tiles over 2x4, 4x4 or 2x2 waves -- k_gemm, '
+            'k_gemm_w16, k_gemm_w4 -- or 128x128 tiles over 2x2 waves, k_gemm_t128)')
     kernels = mdmrg.Context.KERNELS
     k_ms, k_launch, k_flop = d['heff_kernel_ms'], max(1.0, d['heff_kernel_launches']), d['heff_kernel_flop']
     achieved_tf = k_flop / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0

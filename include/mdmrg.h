@@ -144,13 +144,18 @@ enum {
                                   HIP graph and replay it for every later product
                                   (x and y staged through context buffers for FP64);
                                   0 (default): launch eagerly */
-  MDMRG_OPT_COMPRESS = 4       /* 1 (default): the N^L x O_s x C^R products of a bond are
+  MDMRG_OPT_COMPRESS = 4,      /* 1 (default): the N^L x O_s x C^R products of a bond are
                                   grouped by site operator s and quantum-number shift, and
                                   each group is reduced by an interpolative decomposition
                                   of its coefficient matrix (relative rank cut 1e-14,
                                   reconstruction checked to 1e-12) to skeleton products
                                   with on-the-fly left combinations; 0: one product per
                                   left operator (takes effect at the next bond prepared) */
+  MDMRG_OPT_GEMM_VARIANT = 5   /* -1 (default): every grouped-GEMM plan times its first
+                                  launches on the tile variants in turn and keeps the
+                                  fastest; 0..3: every launch of the context uses that
+                                  variant (k_gemm, k_gemm_w16, k_gemm_w4, k_gemm_t128;
+                                  all give bitwise identical results) */
 };
 /* Set a context option (EINVAL for unknown options or bad values). */
 int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value);
@@ -171,7 +176,10 @@ int mdmrg_psi_layout(mdmrg_ctx ctx, int64_t *n_elem, int32_t *n_blk, int32_t *de
  * n_elem doubles, must not alias).  prec MDMRG_FP64 is the plain form;
  * MDMRG_FP32 (split form) runs every GEMM on FP32 shadows of the operators
  * and of x with FP32 MFMA accumulation, y returned in FP64; MDMRG_BF16X3
- * returns EUNSUP in this build. */
+ * (split form) reads the same FP32 shadows and forms every product from
+ * BF16 parts, hi = RNE(v), lo = RNE(v - hi) of each operand element v, as
+ * hi*lo + lo*hi + hi*hi with FP32 accumulation (about 16 significant bits
+ * per operand, BF16 MFMA rate), y returned in FP64.  Other values: EUNSUP. */
 int mdmrg_heff_apply(mdmrg_ctx ctx, int prec, const double *x, double *y);
 
 /* Diagonal of H_eff at the current bond into device buffer d. */
@@ -202,7 +210,7 @@ int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max
                    double *energy, double *resid, int *n_matvec);
 
 /* Mixed-precision Davidson: a Davidson solve whose products use the split
- * form prec_split (MDMRG_FP32) until its residual reaches tol_split or
+ * form prec_split (MDMRG_FP32 or MDMRG_BF16X3) until its residual reaches tol_split or
  * stops decreasing (noise floor of the split operator), then an FP64
  * Davidson from that vector until the FP64 residual <= tol.  *n_mv64 and
  * *n_mv_split count the products of each kind. */
@@ -254,10 +262,23 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
                        int64_t n_out, const int64_t *out_desc, int64_t n_seg, const int64_t *seg_desc,
                        const double *alpha);
 
+/* The same grouped GEMM in a split-precision form (the arithmetic of the
+ * split H_eff products, the FP32 / 3xBF16 forms of the a4 step): every
+ * buffer holds FP32 elements (base_len[i] floats, offsets in floats), alpha
+ * is rounded to FP32 and folded into op(A) before the product, results are
+ * FP32.  prec MDMRG_FP32: FP32 MFMA products and accumulation.  prec
+ * MDMRG_BF16X3: each element v of alpha op(A) and of op(B) is split into
+ * hi = RNE_bf16(v), lo = RNE_bf16(v - hi) and the product is accumulated
+ * in FP32 as hi*lo + lo*hi + hi*hi.  Other prec: EUNSUP; descriptors and
+ * range checks as for mdmrg_gemm_grouped (EINVAL). */
+int mdmrg_gemm_grouped_split(mdmrg_ctx ctx, int prec, int n_bases, const float *const *bases,
+                             const int64_t *base_len, int64_t n_out, const int64_t *out_desc, int64_t n_seg,
+                             const int64_t *seg_desc, const double *alpha);
+
 /* Wall seconds per step category (Diag_H, Ren, Tables, Diag_D, StVec,
  * Other) accumulated since creation, the algorithmic FLOP of all H_eff
  * products, and HIP-event timings of the grouped-GEMM kernel launches on the
- * context stream; out must hold 52 doubles:
+ * context stream; out must hold MDMRG_N_STATS (72) doubles:
  * [diag_h, ren, tables, diag_d, stvec, other, heff_flop, n_matvec,
  *  heff_gemm_ms, heff_gemm_launches, heff_gemm_flop,
  *  ren_gemm_ms, ren_gemm_launches, ren_gemm_flop,
@@ -267,13 +288,17 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
  *  grouped_ms, grouped_launches, grouped_flop (mdmrg_gemm_grouped calls),
  *  heff_kernel_ms, heff_kernel_launches, heff_kernel_flop,
  *  all_kernel_ms, all_kernel_launches,
- *  proc[prec][variant][ms, launches, flop] for prec FP64, FP32 and the
- *  tile variants k_gemm, k_gemm_w16, k_gemm_w4 (18 values),
- *  graph64_ms, graph64_launches, graph32_ms, graph32_launches].
+ *  proc[prec][variant][ms, launches, flop] for prec FP64, FP32, BF16X3 and
+ *  the tile variants k_gemm, k_gemm_w16, k_gemm_w4, k_gemm_t128 (36 values),
+ *  graph64_ms, graph64_launches, graph32_ms, graph32_launches,
+ *  graphbf3_ms, graphbf3_launches]. */
+#define MDMRG_N_STATS 72
+/*
  * heff_gemm_* covers the accumulation (second) phase of the eager FP64
  * H_eff products, heff_phase1_* their intermediate (first) phase and
- * heff_kernel_* both; all_kernel_* every kernel launch of the context (FP64
- * and FP32); proc[..] every launch of one kernel in the whole process, over
+ * heff_kernel_* both; split_gemm_* the eager split-form products (FP32 and
+ * 3xBF16 together); all_kernel_* every kernel launch of the context (all
+ * forms); proc[..] every launch of one kernel in the whole process, over
  * all contexts including destroyed ones; graph*_ are whole H_eff products
  * replayed from a captured graph (MDMRG_OPT_GRAPH). */
 int mdmrg_get_stats(mdmrg_ctx ctx, double *out);

@@ -197,6 +197,10 @@ int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value) {
       case MDMRG_OPT_COMPRESS:
         c.compress = value != 0;
         break;
+      case MDMRG_OPT_GEMM_VARIANT:
+        MDMRG_REQUIRE(value >= -1 && value < kGemmVariants, MDMRG_EINVAL, "set_option: no such tile variant");
+        dev_force_variant(c.dev, int(value));
+        break;
       default:
         throw Error(MDMRG_EINVAL, "set_option: unknown option");
     }
@@ -239,8 +243,8 @@ int mdmrg_psi_layout(mdmrg_ctx ctx, int64_t *n_elem, int32_t *n_blk, int32_t *de
 int mdmrg_heff_apply(mdmrg_ctx ctx, int prec, const double *x, double *y) {
   if (!ctx || !x || !y || x == y) return MDMRG_EINVAL;
   return guarded(ctx, [&] {
-    MDMRG_REQUIRE(prec == MDMRG_FP64 || prec == MDMRG_FP32, MDMRG_EUNSUP,
-                  "heff_apply: precision form not built (FP64 and FP32 are)");
+    MDMRG_REQUIRE(prec == MDMRG_FP64 || prec == MDMRG_FP32 || prec == MDMRG_BF16X3, MDMRG_EUNSUP,
+                  "heff_apply: unknown precision form");
     ctx->c.heff_apply(x, y, prec);
     dev_sync(ctx->c.dev);
     return MDMRG_OK;
@@ -324,9 +328,11 @@ int mdmrg_sweep(mdmrg_ctx ctx, int n_sweeps, const int *D_schedule, int n_sched,
   });
 }
 
-int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, const int64_t *base_len,
-                       int64_t n_out, const int64_t *out_desc, int64_t n_seg, const int64_t *seg_desc,
-                       const double *alpha) {
+// Descriptor check and launch shared by the FP64 and FP32-buffer forms of
+// the grouped GEMM: offsets and lengths are in elements of the buffers.
+static int gemm_grouped_any(mdmrg_ctx ctx, int prec, int n_bases, void *const *bases, const int64_t *base_len,
+                            int64_t n_out, const int64_t *out_desc, int64_t n_seg, const int64_t *seg_desc,
+                            const double *alpha) {
   if (!ctx || n_bases < 1 || n_bases > kSlots || !bases || !base_len || n_out < 0 || n_seg < 0 ||
       (n_out && !out_desc) || (n_seg && (!seg_desc || !alpha)))
     return MDMRG_EINVAL;
@@ -385,13 +391,35 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
       plan.outs.push_back(g);
     }
     Bases b{};
-    for (int i = 0; i < kSlots; ++i) b.p[i] = const_cast<double *>(bases[i < n_bases ? i : 0]);
+    for (int i = 0; i < kSlots; ++i) b.p[i] = static_cast<double *>(bases[i < n_bases ? i : 0]);
     DevPlan *dp = dev_plan_upload(ctx->c.dev, plan);
-    dev_gemm_run(ctx->c.dev, dp, b, 3);
+    dev_gemm_run(ctx->c.dev, dp, b, 3, prec);
     dev_plan_free(ctx->c.dev, dp);
     dev_sync(ctx->c.dev);
     return MDMRG_OK;
   });
+}
+
+int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, const int64_t *base_len,
+                       int64_t n_out, const int64_t *out_desc, int64_t n_seg, const int64_t *seg_desc,
+                       const double *alpha) {
+  if (!bases) return MDMRG_EINVAL;
+  void *p[kSlots] = {};
+  for (int i = 0; i < n_bases && i < kSlots; ++i) p[i] = const_cast<double *>(bases[i]);
+  return gemm_grouped_any(ctx, MDMRG_FP64, n_bases, p, base_len, n_out, out_desc, n_seg, seg_desc, alpha);
+}
+
+int mdmrg_gemm_grouped_split(mdmrg_ctx ctx, int prec, int n_bases, const float *const *bases,
+                             const int64_t *base_len, int64_t n_out, const int64_t *out_desc, int64_t n_seg,
+                             const int64_t *seg_desc, const double *alpha) {
+  if (!ctx || !bases) return MDMRG_EINVAL;
+  if (prec != MDMRG_FP32 && prec != MDMRG_BF16X3) {
+    ctx->c.err = "gemm_grouped_split: prec must be MDMRG_FP32 or MDMRG_BF16X3";
+    return MDMRG_EUNSUP;
+  }
+  void *p[kSlots] = {};
+  for (int i = 0; i < n_bases && i < kSlots; ++i) p[i] = const_cast<float *>(bases[i]);
+  return gemm_grouped_any(ctx, prec, n_bases, p, base_len, n_out, out_desc, n_seg, seg_desc, alpha);
 }
 
 int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
@@ -434,18 +462,21 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
       out[28] += ms[i];
       out[29] += ln[i];
     }
-    double pm[2][kGemmVariants], pl[2][kGemmVariants], pf[2][kGemmVariants];
+    double pm[kPrecs][kGemmVariants], pl[kPrecs][kGemmVariants], pf[kPrecs][kGemmVariants];
     dev_timing_process(ctx->c.dev, pm, pl, pf);
-    for (int p = 0; p < 2; ++p)
+    for (int p = 0; p < kPrecs; ++p)
       for (int v = 0; v < kGemmVariants; ++v) {
-        out[30 + 3 * (kGemmVariants * p + v)] = pm[p][v];
-        out[31 + 3 * (kGemmVariants * p + v)] = pl[p][v];
-        out[32 + 3 * (kGemmVariants * p + v)] = pf[p][v];
+        const int at = 30 + 3 * (kGemmVariants * p + v);
+        out[at] = pm[p][v];
+        out[at + 1] = pl[p][v];
+        out[at + 2] = pf[p][v];
       }
-    out[48] = ms[7];
-    out[49] = ln[7];
-    out[50] = ms[8];
-    out[51] = ln[8];
+    constexpr int g = 30 + 3 * kGemmVariants * kPrecs;
+    static_assert(g + 6 == MDMRG_N_STATS, "stats layout");
+    for (int p = 0; p < kPrecs; ++p) {
+      out[g + 2 * p] = ms[7 + p];
+      out[g + 2 * p + 1] = ln[7 + p];
+    }
     return MDMRG_OK;
   });
 }

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <mutex>
 #include <numeric>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -37,6 +38,7 @@ struct Device {
   // launch timing
   bool timing = false;
   bool capturing = false;  // stream capture in progress: no events, no host syncs
+  int force_variant = -1;  // >= 0: tile variant of every grouped launch
   std::vector<hipEvent_t> ev_pool;
   struct Pending {
     int tag, prec, variant;  // variant < 0: a graph replay (whole product), not one kernel
@@ -58,11 +60,11 @@ static hipEvent_t ev_get(Device *d) {
   return e;
 }
 
-// Process-wide totals of the grouped kernel per element type (0 FP64,
-// 1 FP32) and tile variant, summed over every device context of the
+// Process-wide totals of the grouped kernel per precision form (0 FP64,
+// 1 FP32, 2 3xBF16) and tile variant, summed over every device context of the
 // process, including destroyed ones.
 static std::mutex g_timing_mu;
-static double g_ms[2][kGemmVariants], g_launches[2][kGemmVariants], g_flop[2][kGemmVariants];
+static double g_ms[kPrecs][kGemmVariants], g_launches[kPrecs][kGemmVariants], g_flop[kPrecs][kGemmVariants];
 
 static void timing_drain(Device *d) {
   if (d->pending.empty()) return;
@@ -85,11 +87,11 @@ static void timing_drain(Device *d) {
   d->pending.clear();
 }
 
-void dev_timing_process(Device *d, double ms[2][kGemmVariants], double launches[2][kGemmVariants],
-                        double flop[2][kGemmVariants]) {
+void dev_timing_process(Device *d, double ms[kPrecs][kGemmVariants], double launches[kPrecs][kGemmVariants],
+                        double flop[kPrecs][kGemmVariants]) {
   timing_drain(d);
   std::lock_guard<std::mutex> lk(g_timing_mu);
-  for (int p = 0; p < 2; ++p)
+  for (int p = 0; p < kPrecs; ++p)
     for (int v = 0; v < kGemmVariants; ++v) {
       ms[p][v] = g_ms[p][v];
       launches[p][v] = g_launches[p][v];
@@ -208,7 +210,7 @@ void dev_zero(Device *d, void *dst, size_t bytes) {
 // C[l/16 + 4r][l%16] for FP64 and C[4(l/16) + r][l%16] for FP32.
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int kTKmax = 16;  // largest K step of the grouped kernel
+constexpr int kTKmax = 32;  // largest K step of the grouped kernel
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 
 // one MFMA 16x16x4 step in the element type of the kernel: FP64
@@ -253,17 +255,33 @@ struct TileCfg {
 // faster on split-K H_eff products) and 16 in the 16-wave split, which keeps
 // the unsplit long-K case; FP32 stages 16 everywhere (32, the same LDS bytes
 // per stage as FP64 at 16, measured slower).
+// The 3xBF16 form stages 32 columns per step: one v_mfma_f32_16x16x32_bf16
+// step.
+struct Bf16x3 {};  // element-type tag: FP32 data, products as 3 BF16 MFMAs
 template <class T>
-constexpr int tk_small() {
-  return sizeof(T) == 8 ? 8 : 16;
-}
+struct KStep {  // FP32
+  static constexpr int small = 16, wide = 16;
+};
+template <>
+struct KStep<double> {
+  static constexpr int small = 8, wide = 16;
+};
+template <>
+struct KStep<Bf16x3> {
+  static constexpr int small = 32, wide = 32;
+};
 template <class T>
-using Cfg64 = TileCfg<64, 64, 2, 4, tk_small<T>()>;  // variant 0, k_gemm: 8 waves of 32x16
+using Cfg64 = TileCfg<64, 64, 2, 4, KStep<T>::small>;  // variant 0, k_gemm: 8 waves of 32x16
 template <class T>
-using Cfg64w = TileCfg<64, 64, 4, 4, 16>;  // variant 1, k_gemm_w16: 16 waves of 16x16
+using Cfg64w = TileCfg<64, 64, 4, 4, KStep<T>::wide>;  // variant 1, k_gemm_w16: 16 waves of 16x16
 template <class T>
-using Cfg64q = TileCfg<64, 64, 2, 2, tk_small<T>()>;  // variant 2, k_gemm_w4: 4 waves of 32x32
-constexpr int kTileM = 64, kTileN = 64;  // output tile of every variant
+using Cfg64q = TileCfg<64, 64, 2, 2, KStep<T>::small>;  // variant 2, k_gemm_w4: 4 waves of 32x32
+// variant 3, k_gemm_t128: 128x128 outputs per workgroup, 4 waves of 64x64
+// (twice the operand reuse per fetched byte of the 64x64 tiles; its own
+// tile list)
+template <class T>
+using Cfg128 = TileCfg<128, 128, 2, 2, KStep<T>::small>;
+constexpr int kTileM = 64, kTileN = 64;  // output tile of variants 0-2 (variant 3: 128 x 128)
 constexpr int kPad = 2;  // LDS row padding (doubles) of the staged A / B tiles
 
 // Per-thread load state of one segment: each thread stages EA elements of
@@ -486,27 +504,198 @@ __device__ inline void gemm_tile(const GTile *__restrict__ tiles, const GOut *__
       }
 }
 
+// ---------------------------------------------- 3xBF16 split products
+// Every FP32 operand element x is split when it is staged to LDS into
+// hi = RNE_bf16(x) and lo = RNE_bf16(x - hi) (x - hi is exact in FP32), and
+// a product is formed as hi*lo + lo*hi + hi*hi with FP32 accumulation on
+// v_mfma_f32_16x16x32_bf16 (lo*lo is dropped): about 16 significant bits
+// per operand instead of FP32's 24, at BF16 MFMA rate.  The staged tiles are
+// K-contiguous ([row][k] for A, [column][k] for B), so a lane's 8 operand
+// values of one MFMA are one 16-byte LDS read; the instruction takes from
+// lane l the values of row / column l % 16 at K positions fixed by l / 16,
+// the same for both operands, so the staged K order is the product's K order.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+constexpr int kLdkH = 32 + 8;  // staged row length (BF16 elements; 80 bytes, 16-byte aligned rows)
+
+__device__ inline void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
+  hi = __bf16(v);
+  lo = __bf16(v - float(hi));
+}
+
+template <class C>
+__device__ inline void seg_store_bf3(const SegLoad<float, C> &L, int tid, int step,
+                                     const float (&ra)[SegLoad<float, C>::EA],
+                                     const float (&rb)[SegLoad<float, C>::EB], uint32_t oka, uint32_t okb,
+                                     __bf16 *Ah, __bf16 *Al, __bf16 *Bh, __bf16 *Bl) {
+  constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK;
+  const int i0 = L.tA ? tid % BM : tid / TK, di = L.tA ? 0 : NT / TK;
+  const int j0 = L.tB ? tid / TK : tid % BN, dj = L.tB ? NT / TK : 0;
+  const int k0 = step * TK;
+#pragma unroll
+  for (int it = 0; it < L.EA; ++it) {
+    const int kk = L.ka0 + L.dka * it;
+    const bool ok = (oka >> it) & 1;
+    float v;
+    if (L.idA)
+      v = (ok && L.ia0 + L.dia * it == k0 + kk) ? L.alpha : 0.f;
+    else
+      v = ok ? L.alpha * ra[it] : 0.f;
+    const int e = (i0 + di * it) * kLdkH + kk;
+    split_bf16(v, Ah[e], Al[e]);
+  }
+#pragma unroll
+  for (int it = 0; it < L.EB; ++it) {
+    const int e = (j0 + dj * it) * kLdkH + L.kb0 + L.dkb * it;
+    split_bf16(((okb >> it) & 1) ? rb[it] : 0.f, Bh[e], Bl[e]);
+  }
+}
+
+template <class C>
+__device__ inline void tile_mfma_bf3(const __bf16 *Ah, const __bf16 *Al, const __bf16 *Bh, const __bf16 *Bl, int wm,
+                                     int wn, int lr, int lk, bool full, int qm, int qn,
+                                     v4f (&acc)[C::MI][C::NI]) {
+  constexpr int MI = C::MI, NI = C::NI;
+  static_assert(C::TK == 32, "one MFMA K step per staged step");
+  if (!full && !(qm > 0 && qn > 0)) return;
+  v8bf ah[MI], al[MI], bh[NI], bl[NI];
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi) {
+    const int e = (wm + 16 * mi + lr) * kLdkH + 8 * lk;
+    ah[mi] = *reinterpret_cast<const v8bf *>(Ah + e);
+    al[mi] = *reinterpret_cast<const v8bf *>(Al + e);
+  }
+#pragma unroll
+  for (int ni = 0; ni < NI; ++ni) {
+    const int e = (wn + 16 * ni + lr) * kLdkH + 8 * lk;
+    bh[ni] = *reinterpret_cast<const v8bf *>(Bh + e);
+    bl[ni] = *reinterpret_cast<const v8bf *>(Bl + e);
+  }
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni)
+      if (full || (qm > 16 * mi && qn > 16 * ni)) {
+        v4f c = acc[mi][ni];
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], c, 0, 0, 0);
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], c, 0, 0, 0);
+      }
+}
+
+// Same tile walk as gemm_tile (FP32 data in HBM, FP32 accumulators and
+// results); only the staging and the MFMA step differ.
+template <class C>
+__device__ inline void gemm_tile_bf3(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
+                                     const GSeg *__restrict__ segs, const Bases &bases) {
+  constexpr int BM = C::BM, BN = C::BN, MI = C::MI, NI = C::NI, TK = C::TK;
+  typedef SegLoad<float, C> SL;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * kLdkH], Al[2][BM * kLdkH];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN * kLdkH], Bl[2][BN * kLdkH];
+  const GTile tl = tiles[blockIdx.x];
+  if (tl.out < 0) return;
+  const GOut o = outs[tl.out];
+  const int row0 = int(tl.ti) * BM, col0 = int(tl.tj) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / C::WX) * (BM / C::WY), wn = (wave % C::WX) * (BN / C::WX);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int qm = o.m - (row0 + wm), qn = o.n - (col0 + wn);
+  const bool full = qm >= BM / C::WY && qn >= BN / C::WX;
+  v4f acc[MI][NI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+  SL L;
+  float ra[SL::EA], rb[SL::EB];
+  uint32_t oka, okb;
+  for (int si = 0; si < o.seg_count; ++si) {
+    seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
+    const int nsteps = (L.k + TK - 1) / TK;
+    if (nsteps == 0) continue;
+    int buf = 0;
+    seg_fetch(L, 0, ra, rb, oka, okb);
+    seg_store_bf3(L, tid, 0, ra, rb, oka, okb, Ah[buf], Al[buf], Bh[buf], Bl[buf]);
+    __syncthreads();
+    for (int step = 0; step + 1 < nsteps; ++step) {
+      seg_fetch(L, step + 1, ra, rb, oka, okb);
+      tile_mfma_bf3<C>(Ah[buf], Al[buf], Bh[buf], Bl[buf], wm, wn, lr, lk, full, qm, qn, acc);
+      buf ^= 1;
+      seg_store_bf3(L, tid, step + 1, ra, rb, oka, okb, Ah[buf], Al[buf], Bh[buf], Bl[buf]);
+      __syncthreads();
+    }
+    tile_mfma_bf3<C>(Ah[buf], Al[buf], Bh[buf], Bl[buf], wm, wn, lr, lk, full, qm, qn, acc);
+    __syncthreads();
+  }
+  float *Cp = reinterpret_cast<float *>(bases.p[o.c_slot]) + o.c_off;
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = row0 + wm + mi * 16 + Mfma<float>::row(lk, r);
+        const int gj = col0 + wn + ni * 16 + lr;
+        if (gi < o.m && gj < o.n) {
+          float *p = Cp + (int64_t)gi * o.ldc + gj;
+          const float v = acc[mi][ni][r];
+          *p = o.accumulate ? (*p + v) : v;
+        }
+      }
+}
+
+template <class T, class C>
+__device__ inline void gemm_any(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
+                                const GSeg *__restrict__ segs, const Bases &bases) {
+  if constexpr (std::is_same<T, Bf16x3>::value)
+    gemm_tile_bf3<C>(tiles, outs, segs, bases);
+  else
+    gemm_tile<T, C>(tiles, outs, segs, bases);
+}
+
 template <class T>
 __global__ __launch_bounds__(Cfg64<T>::NT) void k_gemm(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
                                                     const GSeg *__restrict__ segs, Bases bases) {
-  gemm_tile<T, Cfg64<T>>(tiles, outs, segs, bases);
+  gemm_any<T, Cfg64<T>>(tiles, outs, segs, bases);
 }
 template <class T>
 __global__ __launch_bounds__(Cfg64w<T>::NT) void k_gemm_w16(const GTile *__restrict__ tiles,
                                                          const GOut *__restrict__ outs,
                                                          const GSeg *__restrict__ segs, Bases bases) {
-  gemm_tile<T, Cfg64w<T>>(tiles, outs, segs, bases);
+  gemm_any<T, Cfg64w<T>>(tiles, outs, segs, bases);
 }
 template <class T>
 __global__ __launch_bounds__(Cfg64q<T>::NT) void k_gemm_w4(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
                                                         const GSeg *__restrict__ segs, Bases bases) {
-  gemm_tile<T, Cfg64q<T>>(tiles, outs, segs, bases);
+  gemm_any<T, Cfg64q<T>>(tiles, outs, segs, bases);
+}
+
+// 128x128 tiles: FP64 and FP32 are held to 256 registers per lane (2 waves
+// per SIMD, accumulators in VGPRs, no spills); the 3xBF16 form keeps its
+// 80 KB of LDS stages and one wave per SIMD.
+template <class T>
+__global__ __launch_bounds__(Cfg128<T>::NT) void k_gemm_t128(const GTile *__restrict__ tiles,
+                                                          const GOut *__restrict__ outs,
+                                                          const GSeg *__restrict__ segs, Bases bases) {
+  gemm_any<T, Cfg128<T>>(tiles, outs, segs, bases);
+}
+template <>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_t128<double>(
+    const GTile *__restrict__ tiles, const GOut *__restrict__ outs, const GSeg *__restrict__ segs, Bases bases) {
+  gemm_any<double, Cfg128<double>>(tiles, outs, segs, bases);
+}
+template <>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_t128<float>(
+    const GTile *__restrict__ tiles, const GOut *__restrict__ outs, const GSeg *__restrict__ segs, Bases bases) {
+  gemm_any<float, Cfg128<float>>(tiles, outs, segs, bases);
 }
 
 template <class T>
 static void launch_variant(int v, hipStream_t st, const DevPlan *p, const Bases &b) {
   const dim3 g(unsigned(p->n_tiles));
-  if (v == 1)
+  if (v == 3)
+    hipLaunchKernelGGL(k_gemm_t128<T>, dim3(unsigned(p->n_tiles128)), dim3(Cfg128<T>::NT), 0, st, p->tiles128,
+                       p->outs, p->segs, b);
+  else if (v == 1)
     hipLaunchKernelGGL(k_gemm_w16<T>, g, dim3(Cfg64w<T>::NT), 0, st, p->tiles, p->outs, p->segs, b);
   else if (v == 2)
     hipLaunchKernelGGL(k_gemm_w4<T>, g, dim3(Cfg64q<T>::NT), 0, st, p->tiles, p->outs, p->segs, b);
@@ -546,41 +735,48 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
   // One launch covers every output (small outputs fill the tail of the
   // largest-first order).  Workgroups of a launch go to the 8 XCDs
   // round-robin (workgroup b to XCD b mod 8) and every XCD has its own L2,
-  // so outputs are cut into chunks of whole tile rows (at most 64 tiles: a
-  // few A panels against all B panels of the output), chunks are dealt to
-  // per-XCD queues (largest first, to the queue with the least work) and the
-  // queues interleaved: the tiles of a chunk run on one XCD and share its L2.
-  // Queues are padded with empty tiles (out = -1).
-  constexpr int kChunkTiles = 64;
-  std::vector<std::vector<GTile>> q(kXcds);
-  double load[kXcds] = {};
-  for (auto &w : work) {
-    const GOut &o = plan.outs[w.second];
-    const int nti = (o.m + kTileM - 1) / kTileM, ntj = (o.n + kTileN - 1) / kTileN;
-    const int rows = std::max(1, kChunkTiles / ntj);
-    for (int i0 = 0; i0 < nti; i0 += rows) {
-      const int i1 = std::min(nti, i0 + rows);
-      const int x = int(std::min_element(load, load + kXcds) - load);
-      load[x] += -w.first * double(i1 - i0) / nti;
-      for (int i = i0; i < i1; ++i)
-        for (int j = 0; j < ntj; ++j) q[x].push_back(GTile{w.second, int16_t(i), int16_t(j)});
+  // so outputs are cut into chunks of whole tile rows (at most 64 tiles of
+  // 64x64, the same area in 128x128 tiles: a few A panels against all B
+  // panels of the output), chunks are dealt to per-XCD queues (largest
+  // first, to the queue with the least work) and the queues interleaved: the
+  // tiles of a chunk run on one XCD and share its L2.  Queues are padded
+  // with empty tiles (out = -1).
+  auto tile_list = [&](int tm, int tn, int chunk_tiles) {
+    std::vector<std::vector<GTile>> q(kXcds);
+    double load[kXcds] = {};
+    for (auto &w : work) {
+      const GOut &o = plan.outs[w.second];
+      const int nti = (o.m + tm - 1) / tm, ntj = (o.n + tn - 1) / tn;
+      const int rows = std::max(1, chunk_tiles / ntj);
+      for (int i0 = 0; i0 < nti; i0 += rows) {
+        const int i1 = std::min(nti, i0 + rows);
+        const int x = int(std::min_element(load, load + kXcds) - load);
+        load[x] += -w.first * double(i1 - i0) / nti;
+        for (int i = i0; i < i1; ++i)
+          for (int j = 0; j < ntj; ++j) q[x].push_back(GTile{w.second, int16_t(i), int16_t(j)});
+      }
     }
-  }
-  size_t maxq = 0;
-  for (auto &qq : q) maxq = std::max(maxq, qq.size());
-  std::vector<GTile> tiles;
-  for (size_t u = 0; u < maxq; ++u)
-    for (auto &qq : q) tiles.push_back(u < qq.size() ? qq[u] : GTile{-1, 0, 0});
-  while (!tiles.empty() && tiles.back().out < 0) tiles.pop_back();  // trailing empty workgroups are not launched
-  MDMRG_REQUIRE(tiles.size() < (size_t(1) << 31), -6, "grouped GEMM plan has too many tiles");
+    size_t maxq = 0;
+    for (auto &qq : q) maxq = std::max(maxq, qq.size());
+    std::vector<GTile> tiles;
+    for (size_t u = 0; u < maxq; ++u)
+      for (auto &qq : q) tiles.push_back(u < qq.size() ? qq[u] : GTile{-1, 0, 0});
+    while (!tiles.empty() && tiles.back().out < 0) tiles.pop_back();  // trailing empty workgroups are not launched
+    MDMRG_REQUIRE(tiles.size() < (size_t(1) << 31), -6, "grouped GEMM plan has too many tiles");
+    return tiles;
+  };
+  const std::vector<GTile> tiles = tile_list(kTileM, kTileN, 64), tiles128 = tile_list(128, 128, 16);
   dp->n_tiles = int64_t(tiles.size());
+  dp->n_tiles128 = int64_t(tiles128.size());
   if (dp->n_tiles) {
     dp->segs = (GSeg *)dev_alloc(d, sizeof(GSeg) * std::max<size_t>(1, plan.segs.size()));
     dp->outs = (GOut *)dev_alloc(d, sizeof(GOut) * plan.outs.size());
     dp->tiles = (GTile *)dev_alloc(d, sizeof(GTile) * tiles.size());
+    dp->tiles128 = (GTile *)dev_alloc(d, sizeof(GTile) * tiles128.size());
     if (!plan.segs.empty()) dev_h2d(d, dp->segs, plan.segs.data(), sizeof(GSeg) * plan.segs.size());
     dev_h2d(d, dp->outs, plan.outs.data(), sizeof(GOut) * plan.outs.size());
     dev_h2d(d, dp->tiles, tiles.data(), sizeof(GTile) * tiles.size());
+    dev_h2d(d, dp->tiles128, tiles128.data(), sizeof(GTile) * tiles128.size());
   }
   return dp;
 }
@@ -593,8 +789,11 @@ void dev_plan_free(Device *d, DevPlan *p) {
   dev_free(d, p->segs);
   dev_free(d, p->outs);
   dev_free(d, p->tiles);
+  dev_free(d, p->tiles128);
   delete p;
 }
+
+void dev_force_variant(Device *d, int v) { d->force_variant = v; }
 
 void dev_gemm_run(Device *d, DevPlan *p, const Bases &b, int tag, int prec) {
   if (!p || p->n_tiles == 0) return;
@@ -602,8 +801,9 @@ void dev_gemm_run(Device *d, DevPlan *p, const Bases &b, int tag, int prec) {
   // autotuner: the first kGemmVariants launches of a plan (per element type)
   // run one variant each (they are the plan's real work) and are timed with
   // their own events; the next launch reads the times and keeps the fastest
-  const int pr = prec ? 1 : 0;
-  int v = p->variant[pr];
+  MDMRG_REQUIRE(prec >= 0 && prec < kPrecs, -6, "grouped GEMM: unknown precision form");
+  const int pr = prec;
+  int v = d->force_variant >= 0 ? d->force_variant : p->variant[pr];
   if (!d->capturing && v < 0) {
     if (p->trials[pr] < kGemmVariants) {
       v = p->trials[pr];
@@ -628,7 +828,7 @@ void dev_gemm_run(Device *d, DevPlan *p, const Bases &b, int tag, int prec) {
     }
   }
   if (v < 0) v = 0;  // captured before the plan was tuned
-  const bool trial = !d->capturing && p->variant[pr] < 0;
+  const bool trial = !d->capturing && d->force_variant < 0 && p->variant[pr] < 0;
   const bool timed = d->timing && !d->capturing;
   hipEvent_t e0 = nullptr, e1 = nullptr, t0 = nullptr, t1 = nullptr;
   if (timed) {
@@ -644,8 +844,10 @@ void dev_gemm_run(Device *d, DevPlan *p, const Bases &b, int tag, int prec) {
   }
   if (prec == 0)
     launch_variant<double>(v, d->stream, p, b);
-  else
+  else if (prec == 1)
     launch_variant<float>(v, d->stream, p, b);
+  else
+    launch_variant<Bf16x3>(v, d->stream, p, b);
   HIP_CHECK(hipGetLastError());
   if (trial) {
     HIP_CHECK(hipEventRecord(t1, d->stream));
@@ -655,7 +857,7 @@ void dev_gemm_run(Device *d, DevPlan *p, const Bases &b, int tag, int prec) {
   }
   if (timed) {
     HIP_CHECK(hipEventRecord(e1, d->stream));
-    d->pending.push_back(Device::Pending{tag, prec ? 1 : 0, v, e0, e1, p->flop});
+    d->pending.push_back(Device::Pending{tag, prec, v, e0, e1, p->flop});
   }
 }
 

@@ -896,8 +896,9 @@ PsiLayout Context::make_layout(int l) const {
 void Context::release_graphs() {
   dev_graph_free(dev, graph64);
   dev_graph_free(dev, graph32);
-  graph64 = graph32 = nullptr;
-  eager64 = eager32 = 0;
+  dev_graph_free(dev, graphbf3);
+  graph64 = graph32 = graphbf3 = nullptr;
+  eager64 = eager32 = eagerbf3 = 0;
 }
 
 void Context::set_graph(bool on) {
@@ -1474,11 +1475,15 @@ void Context::ensure_fp32() {
 
 void Context::heff_apply(const double *x, double *y, int prec) {
   MDMRG_REQUIRE(cur >= 0, -4, "heff_apply: no current bond");
-  MDMRG_REQUIRE(prec == 0 || prec == 1, -6, "heff_apply: precision form not built");
+  MDMRG_REQUIRE(prec >= 0 && prec <= 2, -6, "heff_apply: unknown precision form");
   // a graph is captured once every plan of the product has finished its
   // variant trials (kGemmVariants timed launches, decided at the next one)
   const int warm = kGemmVariants + 1;
-  if (prec == 1) {
+  if (prec != 0) {
+    // split forms: FP32 shadows of x, y and the operators; prec 1 runs FP32
+    // MFMA products, prec 2 the 3xBF16 products on the same data
+    DevGraph *&graph = prec == 1 ? graph32 : graphbf3;
+    int &eager = prec == 1 ? eager32 : eagerbf3;
     ensure_fp32();
     dev_d2f(dev, x, x32, psi.n_elem);
     Bases b{};
@@ -1491,9 +1496,9 @@ void Context::heff_apply(const double *x, double *y, int prec) {
     b.p[7] = b.p[1];
     auto body = [&] {
       dev_zero(dev, y32, sizeof(float) * psi.n_elem);
-      run_plan(heff, b, 4, 1);
+      run_plan(heff, b, 4, prec);
     };
-    if (use_graph && !graph32 && eager32 >= warm) {
+    if (use_graph && !graph && eager >= warm) {
       dev_capture_begin(dev);
       try {
         body();
@@ -1501,13 +1506,13 @@ void Context::heff_apply(const double *x, double *y, int prec) {
         dev_capture_abort(dev);
         throw;
       }
-      graph32 = dev_capture_end(dev);
+      graph = dev_capture_end(dev);
     }
-    if (graph32) {
-      dev_graph_launch(dev, graph32, 8, heff.flop);
+    if (graph) {
+      dev_graph_launch(dev, graph, prec == 1 ? 8 : 9, heff.flop);
     } else {
       body();
-      ++eager32;
+      ++eager;
     }
     dev_f2d(dev, y32, y, psi.n_elem);
     stats.heff_flop_split += heff.flop;
@@ -1762,7 +1767,7 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
 
 int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_split, int max_iter, int m_max,
                             double *energy, double *resid, int *n_mv64, int *n_mv_split) {
-  MDMRG_REQUIRE(prec_split == 1, -6, "davidson_mixed: only the FP32 split form is built");
+  MDMRG_REQUIRE(prec_split == 1 || prec_split == 2, -6, "davidson_mixed: prec_split must be a split form");
   double e = 0.0, r = 0.0;
   int ns = 0, n64 = 0;
   davidson(x, std::max(tol, tol_split), max_iter, m_max, &e, &r, &ns, prec_split, true);

@@ -191,10 +191,10 @@ struct Context {
   // graph replay of the H_eff product (MDMRG_OPT_GRAPH): captured per bond and
   // precision once the first products have tuned the kernel variants
   bool use_graph = false;
-  DevGraph *graph64 = nullptr, *graph32 = nullptr;
+  DevGraph *graph64 = nullptr, *graph32 = nullptr, *graphbf3 = nullptr;
   double *xg = nullptr, *yg = nullptr;  // FP64 staging of x and y for the graph
   int64_t xg_n = 0;
-  int eager64 = 0, eager32 = 0;  // eager products at the current bond
+  int eager64 = 0, eager32 = 0, eagerbf3 = 0;  // eager products at the current bond
   void set_graph(bool on);
   void release_graphs();
 

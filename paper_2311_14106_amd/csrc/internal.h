@@ -117,44 +117,52 @@ void dev_zero(Device *, void *dst, size_t bytes);
 void dev_sync(Device *);
 size_t dev_free_bytes(Device *);
 
-// Tile variants of the grouped kernel (same 64x64 tile list, different
-// split over waves): 0 k_gemm (2x4 waves), 1 k_gemm_w16 (4x4), 2 k_gemm_w4
-// (2x2).
-constexpr int kGemmVariants = 3;
+// Tile variants of the grouped kernel: 64x64 output tiles (one tile list)
+// split over waves as 0 k_gemm (2x4 waves), 1 k_gemm_w16 (4x4), 2 k_gemm_w4
+// (2x2); 3 k_gemm_t128, 128x128 tiles (their own tile list) over 2x2 waves.
+constexpr int kGemmVariants = 4;
+// Precision forms of the grouped kernel: 0 FP64; 1 FP32 (FP32 operands,
+// MFMA accumulation and results); 2 3xBF16 (FP32 operands and results, each
+// product formed from BF16 hi / lo parts with FP32 accumulation).
+constexpr int kPrecs = 3;
 
 // Uploaded grouped-GEMM plan: 64x64 output tiles in launch order (outputs
 // largest first, dealt to per-XCD queues; empty tiles pad the queues).
 struct DevPlan {
   GSeg *segs = nullptr;
   GOut *outs = nullptr;
-  GTile *tiles = nullptr;
-  int64_t n_tiles = 0, n_outs = 0, n_segs = 0;
+  GTile *tiles = nullptr, *tiles128 = nullptr;  // 64x64 and 128x128 tile lists
+  int64_t n_tiles = 0, n_tiles128 = 0, n_outs = 0, n_segs = 0;
   double flop = 0.0;  // algorithmic FLOP of one launch
-  // autotuner state per element type (0 FP64, 1 FP32): the first launches
-  // time one variant each, then the fastest is kept (variant >= 0)
-  int variant[2] = {-1, -1}, trials[2] = {0, 0};
-  void *trial_ev[2][2 * kGemmVariants] = {};
-  float trial_ms[2][kGemmVariants] = {};
+  // autotuner state per precision form: the first launches time one
+  // variant each, then the fastest is kept (variant >= 0)
+  int variant[kPrecs] = {-1, -1, -1}, trials[kPrecs] = {0, 0, 0};
+  void *trial_ev[kPrecs][2 * kGemmVariants] = {};
+  float trial_ms[kPrecs][kGemmVariants] = {};
 };
 DevPlan *dev_plan_upload(Device *, const GemmPlan &);
+// v in 0..kGemmVariants-1: every later grouped launch of the device uses tile
+// variant v (no autotuning); -1: autotune per plan (default)
+void dev_force_variant(Device *, int v);
 void dev_plan_free(Device *, DevPlan *);
-// prec 0: FP64 operands and results; prec 1: FP32 operands, FP32 MFMA
-// accumulation and FP32 results (base pointers then address float arrays
-// with the same element offsets)
+// prec 0: FP64 operands and results; prec 1 (FP32) and 2 (3xBF16): FP32
+// operands and results (base pointers then address float arrays with the
+// same element offsets)
 void dev_gemm_run(Device *, DevPlan *, const Bases &, int tag = 0, int prec = 0);
 void dev_d2f(Device *, const double *x, float *y, int64_t n);
 void dev_f2d(Device *, const float *x, double *y, int64_t n);
 // HIP-event timing of tagged grouped-GEMM launches (tag 1..6; untagged
-// launches count as 6) and of graph replays (tags 7, 8): elapsed
-// milliseconds, launch count and algorithmic FLOP since creation.
-constexpr int kTags = 9;
+// launches count as 6) and of graph replays (tags 7 FP64, 8 FP32, 9
+// 3xBF16): elapsed milliseconds, launch count and algorithmic FLOP since
+// creation.
+constexpr int kTags = 10;
 void dev_timing_enable(Device *, bool on);
 void dev_timing_collect(Device *, double ms[kTags], double launches[kTags], double flop[kTags]);
-// Process-wide totals of the grouped kernel per element type (0 FP64,
-// 1 FP32) and tile variant over every context of the process since load
-// (destroyed ones included).
-void dev_timing_process(Device *, double ms[2][kGemmVariants], double launches[2][kGemmVariants],
-                        double flop[2][kGemmVariants]);
+// Process-wide totals of the grouped kernel per precision form and tile
+// variant over every context of the process since load (destroyed ones
+// included).
+void dev_timing_process(Device *, double ms[kPrecs][kGemmVariants], double launches[kPrecs][kGemmVariants],
+                        double flop[kPrecs][kGemmVariants]);
 // Stream capture of the context stream into a graph (no timing events and
 // no host synchronisation inside), replay, and release.  A replay is timed
 // as a whole under `tag` when timing is on.

@@ -18,7 +18,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOCONV, EUNSUP = 0, -1, -2, -3, -4, -5, -6
 SPINLESS, HUBBARD = 0, 1
 REAL, MOMENTUM = 0, 1
 FP64, FP32, BF16X3 = 0, 1, 2
-OPT_KEEP_ENVS, OPT_SCRATCH_LIMIT, OPT_GRAPH, OPT_COMPRESS = 1, 2, 3, 4
+OPT_KEEP_ENVS, OPT_SCRATCH_LIMIT, OPT_GRAPH, OPT_COMPRESS, OPT_GEMM_VARIANT = 1, 2, 3, 4, 5
 
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)
 _c_i32_p = ctypes.POINTER(ctypes.c_int32)
@@ -61,6 +61,9 @@ EXPORTS = {
     'mdmrg_gemm_grouped': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
                                           _c_i64_p, ctypes.c_int64, _c_i64_p, ctypes.c_int64, _c_i64_p,
                                           _c_dbl_p]),
+    'mdmrg_gemm_grouped_split': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_void_p), _c_i64_p, ctypes.c_int64,
+                                                _c_i64_p, ctypes.c_int64, _c_i64_p, _c_dbl_p]),
     'mdmrg_get_stats': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p]),
 }
 
@@ -229,7 +232,8 @@ class Context:
 
     HIST_EDGES = (1, 16, 32, 48, 64, 128, 256, 512)
     # tile variants of the grouped kernel (kernel names), in library order
-    KERNELS = ('k_gemm', 'k_gemm_w16', 'k_gemm_w4')
+    KERNELS = ('k_gemm', 'k_gemm_w16', 'k_gemm_w4', 'k_gemm_t128')
+    N_STATS = 72  # MDMRG_N_STATS
 
     def heff_histogram(self):
         """{bin lower edge: FLOP} of one H_eff x by min(m, n) of each GEMM."""
@@ -269,21 +273,27 @@ class Context:
         self._chk(self.lib.mdmrg_sweep(self.h, n_sweeps, _ip(Ds), len(Ds), tol, _dp(E)))
         return E
 
-    def gemm_grouped(self, buffers, out_desc, seg_desc, alpha):
-        """buffers: list of device tensors (float64); descriptors: int64 arrays
-        of shape (n_out, 8) and (n_seg, 8); alpha: float64 (n_seg,)."""
+    def gemm_grouped(self, buffers, out_desc, seg_desc, alpha, prec=FP64):
+        """buffers: list of device tensors (float64 for prec FP64, float32 for
+        the split forms FP32 and BF16X3); descriptors: int64 arrays of shape
+        (n_out, 8) and (n_seg, 8); alpha: float64 (n_seg,)."""
         nb = len(buffers)
         ptrs = (ctypes.c_void_p * nb)(*[_ptr(b).value for b in buffers])
         lens = np.array([b.numel() if hasattr(b, 'numel') else b.size for b in buffers], dtype=np.int64)
         od = np.ascontiguousarray(out_desc, dtype=np.int64).reshape(-1, 8)
         sd = np.ascontiguousarray(seg_desc, dtype=np.int64).reshape(-1, 8)
         al = np.ascontiguousarray(alpha, dtype=np.float64)
-        self._chk(self.lib.mdmrg_gemm_grouped(self.h, nb, ptrs, lens.ctypes.data_as(_c_i64_p), len(od),
-                                              od.ctypes.data_as(_c_i64_p), len(sd),
-                                              sd.ctypes.data_as(_c_i64_p), _dp(al)))
+        if prec == FP64:
+            self._chk(self.lib.mdmrg_gemm_grouped(self.h, nb, ptrs, lens.ctypes.data_as(_c_i64_p), len(od),
+                                                  od.ctypes.data_as(_c_i64_p), len(sd),
+                                                  sd.ctypes.data_as(_c_i64_p), _dp(al)))
+        else:
+            self._chk(self.lib.mdmrg_gemm_grouped_split(self.h, prec, nb, ptrs, lens.ctypes.data_as(_c_i64_p),
+                                                        len(od), od.ctypes.data_as(_c_i64_p), len(sd),
+                                                        sd.ctypes.data_as(_c_i64_p), _dp(al)))
 
     def stats(self):
-        out = np.zeros(52)
+        out = np.zeros(self.N_STATS)
         self._chk(self.lib.mdmrg_get_stats(self.h, _dp(out)))
         keys = ['diag_h_s', 'ren_s', 'tables_s', 'diag_d_s', 'stvec_s', 'other_s', 'heff_flop', 'n_matvec',
                 'heff_gemm_ms', 'heff_gemm_launches', 'heff_gemm_flop',
@@ -293,8 +303,10 @@ class Context:
                 'grouped_ms', 'grouped_launches', 'grouped_flop',
                 'heff_kernel_ms', 'heff_kernel_launches', 'heff_kernel_flop',
                 'all_kernel_ms', 'all_kernel_launches']
-        for prec in ('f64', 'f32'):
+        for prec in ('f64', 'f32', 'bf3'):
             for var in self.KERNELS:
                 keys += [f'proc_{prec}_{var}_ms', f'proc_{prec}_{var}_launches', f'proc_{prec}_{var}_flop']
-        keys += ['graph64_ms', 'graph64_launches', 'graph32_ms', 'graph32_launches']
+        keys += ['graph64_ms', 'graph64_launches', 'graph32_ms', 'graph32_launches',
+                 'graphbf3_ms', 'graphbf3_launches']
+        assert len(keys) == len(out)
         return dict(zip(keys, out.tolist()))

@@ -126,7 +126,8 @@ def main():
     for a in ('fetch_copy', 'write_copy', 'fetch_bench', 'write_bench', 'out'):
         r.add_argument('--' + a.replace('_', '-'), dest=a, required=True)
     r.add_argument('--kernel-key', default='k_gemm<double> family')
-    r.add_argument('--kernel-name', default='k_gemm<double>, k_gemm_w16<double>, k_gemm_w4<double>')
+    r.add_argument('--kernel-name',
+                   default='k_gemm<double>, k_gemm_w16<double>, k_gemm_w4<double>, k_gemm_t128<double>')
     r.add_argument('--D', type=int, default=1024)
     r.add_argument('--header', default='')
     a = ap.parse_args()

@@ -3,9 +3,17 @@ against plain numpy products on random uneven groups: every combination of
 transposed / identity operands, ragged tails, outputs routed to both the
 64x64 workgroup tiles and the 32x32 wave tiles, K concatenated over many
 segments, accumulate and overwrite.  FP64: |C - C_ref| <= 1e-13 * sum|A||B|.
+
+Split forms (mdmrg_gemm_grouped_split, FP32 buffers) against the oracle's
+product model of the same form, evaluated in FP64: the kernel may differ
+from it only by binary32 accumulation, |C - C_model| <= 2^-24 (4K + 16)
+(|C0| + sum|alpha A||B|) with K the summed depth of the output; the 3xBF16
+form also stays within the model's error bound of the exact product.
 """
 import numpy as np
 import pytest
+
+from oracle import split as S
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip('torch')
@@ -83,15 +91,18 @@ def _case(rng, n_out, big):
     return A, B, C, np.array(outs), np.array(segs), np.array(alphas), refs
 
 
+@pytest.mark.parametrize('variant', [0, 1, 2, 3])
 @pytest.mark.parametrize('big,n_out,seed', [(False, 300, 0), (True, 40, 1), (False, 2000, 2), (True, 7, 3)])
-def test_grouped_gemm_matches_numpy(big, n_out, seed):
+def test_grouped_gemm_matches_numpy(big, n_out, seed, variant):
+    """Every tile variant (forced), FP64."""
     mdmrg, ctx = _ctx()
+    ctx.set_option(mdmrg.OPT_GEMM_VARIANT, variant)
     rng = np.random.default_rng(seed)
     A, B, C, outs, segs, alphas, refs = _case(rng, n_out, big)
     dA = torch.from_numpy(A).to('cuda:0')
     dB = torch.from_numpy(B).to('cuda:0')
     dC = torch.from_numpy(C).to('cuda:0')
-    print(f'[gemm parity] big={big} outputs={n_out} segments={len(segs)}', flush=True)
+    print(f'[gemm parity] variant={variant} big={big} outputs={n_out} segments={len(segs)}', flush=True)
     ctx.gemm_grouped([dA, dB, dC], outs, segs, alphas)
     Cg = dC.cpu().numpy()
     for (off, m, n, ldc, ref, aref) in refs:
@@ -119,3 +130,87 @@ def test_grouped_gemm_rejects_out_of_range():
     outs = np.array([[2, 50, 10, 10, 10, 0, 0, 0]])
     with pytest.raises(mdmrg.MdmrgError):
         ctx.gemm_grouped([dA, dB, dC], outs, np.zeros((0, 8)), np.zeros(0))
+
+
+def _operand_views(A, B, seg, m, n):
+    """op(A) (m x k) and op(B) (k x n) of one segment descriptor, read from
+    the flat host buffers; an identity A is returned as None."""
+    _, a_off, lda, _, b_off, ldb, k, flags = (int(v) for v in seg)
+    if flags & 4:
+        Aop = None
+    elif flags & 1:
+        Aop = A[a_off:a_off + k * lda].reshape(k, lda)[:, :m].T
+    else:
+        Aop = A[a_off:a_off + m * lda].reshape(m, lda)[:, :k]
+    if flags & 2:
+        Bop = B[b_off:b_off + n * ldb].reshape(n, ldb)[:, :k].T
+    else:
+        Bop = B[b_off:b_off + k * ldb].reshape(k, ldb)[:, :n]
+    return Aop, Bop, k
+
+
+@pytest.mark.parametrize('variant', [0, 1, 2, 3])
+@pytest.mark.parametrize('prec_name', ['FP32', 'BF16X3'])
+@pytest.mark.parametrize('big,n_out,seed', [(False, 300, 0), (True, 40, 1), (True, 7, 3)])
+def test_split_grouped_gemm_matches_product_model(prec_name, big, n_out, seed, variant):
+    mdmrg, ctx = _ctx()
+    ctx.set_option(mdmrg.OPT_GEMM_VARIANT, variant)
+    prec = getattr(mdmrg, prec_name)
+    rng = np.random.default_rng(100 + seed)
+    A, B, C, outs, segs, alphas, _ = _case(rng, n_out, big)
+    A32, B32, C32 = (np.ascontiguousarray(v, dtype=np.float32) for v in (A, B, C))
+    dA, dB, dC = (torch.from_numpy(v).to('cuda:0') for v in (A32, B32, C32))
+    print(f'[gemm parity {prec_name}] variant={variant} big={big} outputs={n_out} segments={len(segs)}', flush=True)
+    ctx.gemm_grouped([dA, dB, dC], outs, segs, alphas, prec=prec)
+    Cg = dC.cpu().numpy()
+    model = S.product_bf16x3 if prec_name == 'BF16X3' else S.product_fp32
+    worst = 0.0
+    for (_, off, m, n, ldc, s0, ns, acc) in outs:
+        c0 = C32[off:off + m * ldc].reshape(m, ldc)[:, :n].astype(np.float64)
+        want = c0.copy() if acc else np.zeros((m, n))
+        exact = want.copy()
+        scale = np.abs(want)
+        bound = np.zeros((m, n))
+        ktot = 0
+        for q in range(s0, s0 + ns):
+            Aop, Bop, k = _operand_views(A32, B32, segs[q], m, n)
+            if Aop is None:
+                Aop = np.eye(m, dtype=np.float32)
+            Af = S.fold_alpha(alphas[q], Aop)
+            want += model(Af, Bop)
+            exact += Af.astype(np.float64) @ Bop.astype(np.float64)
+            scale += np.abs(Af.astype(np.float64)) @ np.abs(Bop.astype(np.float64))
+            bound += S.error_bound_bf16x3(Af, Bop)
+            ktot += k
+        got = Cg[off:off + m * ldc].reshape(m, ldc)[:, :n].astype(np.float64)
+        tol = 2.0 ** -24 * (4 * ktot + 16) * (scale + 1e-30)
+        assert np.all(np.abs(got - want) <= tol), (prec_name, off)
+        worst = max(worst, float((np.abs(got - exact) / (scale + 1e-30)).max()))
+        if prec_name == 'BF16X3':
+            assert np.all(np.abs(got - exact) <= bound + tol)
+        if ldc > n:
+            assert np.array_equal(Cg[off:off + m * ldc].reshape(m, ldc)[:, n:],
+                                  C32[off:off + m * ldc].reshape(m, ldc)[:, n:])
+    print(f'[gemm parity {prec_name}] max |C - exact| / sum|A||B| = {worst:.2e}', flush=True)
+    # the two forms are different arithmetic: 3xBF16 is visibly less exact
+    if prec_name == 'BF16X3':
+        assert worst > 2.0 ** -22
+    else:
+        assert worst < 2.0 ** -19
+
+
+def test_split_grouped_gemm_rejects_bad_precision():
+    mdmrg, ctx = _ctx()
+    d = torch.zeros(100, dtype=torch.float32, device='cuda:0')
+    outs = np.array([[2, 0, 5, 5, 5, 0, 1, 0]])
+    segs = np.array([[0, 0, 5, 1, 0, 5, 5, 0]])
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        ctx.gemm_grouped([d, d, d], outs, segs, np.ones(1), prec=mdmrg.FP64 + 7)
+    assert e.value.code == mdmrg.EUNSUP
+
+
+def test_forced_variant_option_rejects_unknown_variant():
+    mdmrg, ctx = _ctx()
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        ctx.set_option(mdmrg.OPT_GEMM_VARIANT, 4)
+    assert e.value.code == mdmrg.EINVAL

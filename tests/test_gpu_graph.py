@@ -6,7 +6,7 @@
 * With MDMRG_OPT_GRAPH the product is captured once and replayed; every
   replay, with eager work and synchronisations of the program in between,
   must agree bit for bit with the eager product of a second context, in FP64
-  and in the FP32 split form.
+  and in both split forms (FP32, 3xBF16).
 * A Davidson solve driven by graph replays reaches the same energy.
 """
 import numpy as np
@@ -45,17 +45,26 @@ def test_variants_and_graph_replays_are_bitwise_identical():
     _, ne = a.psi_layout()
     x0 = torch.from_numpy(si.random_vector(ne, 1)).to(dev)
     ys = []
-    for _ in range(6):   # three variant trials, the decision, then the chosen variant
+    for _ in range(6):   # four variant trials, then the decision, which runs the chosen variant
         y = torch.zeros_like(x0)
         a.heff_apply(x0, y)
         ys.append(y)
     for y in ys[1:]:
         assert torch.equal(y, ys[0])
     print(f'[graph] {len(ys)} eager products agree bitwise, |psi| = {ne}', flush=True)
+    # the split forms' variants agree bit for bit too (same K order per element)
+    for prec in (mdmrg.FP32, mdmrg.BF16X3):
+        ys = []
+        for _ in range(5):
+            y = torch.zeros_like(x0)
+            a.heff_apply(x0, y, prec=prec)
+            ys.append(y)
+        for y in ys[1:]:
+            assert torch.equal(y, ys[0]), prec
     a.set_option(mdmrg.OPT_GRAPH, 1)
-    # FP64 products were already warm; FP32 needs its warm-up products (the
-    # variant trials of its own) before the capture: 8 products cover both
-    for prec in (mdmrg.FP64, mdmrg.FP32):
+    # every form has finished its variant trials above; 8 products each,
+    # with capture at the first of them
+    for prec in (mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3):
         for r in range(8):
             x = torch.from_numpy(si.random_vector(ne, 10 + r)).to(dev)
             yg, ye = torch.zeros_like(x), torch.zeros_like(x)
@@ -65,8 +74,9 @@ def test_variants_and_graph_replays_are_bitwise_identical():
             _ = (x * 2.0).sum().item()          # and some eager torch work
             assert torch.equal(yg, ye), (prec, r)
     st = a.stats()
-    assert st['graph64_launches'] >= 1 and st['graph32_launches'] >= 1
-    print(f"[graph] replays: FP64 {int(st['graph64_launches'])}, FP32 {int(st['graph32_launches'])}", flush=True)
+    assert st['graph64_launches'] >= 1 and st['graph32_launches'] >= 1 and st['graphbf3_launches'] >= 1
+    print(f"[graph] replays: FP64 {int(st['graph64_launches'])}, FP32 {int(st['graph32_launches'])}, "
+          f"3xBF16 {int(st['graphbf3_launches'])}", flush=True)
     a.close()
     b.close()
 
