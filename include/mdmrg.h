@@ -210,10 +210,13 @@ int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max
                    double *energy, double *resid, int *n_matvec);
 
 /* Mixed-precision Davidson: a Davidson solve whose products use the split
- * form prec_split (MDMRG_FP32 or MDMRG_BF16X3) until its residual reaches tol_split or
- * stops decreasing (noise floor of the split operator), then an FP64
- * Davidson from that vector until the FP64 residual <= tol.  *n_mv64 and
- * *n_mv_split count the products of each kind. */
+ * form prec_split (MDMRG_FP32 or MDMRG_BF16X3) until its residual reaches
+ * max(tol_split, f) or stops decreasing (no 10% gain over 24 products, or
+ * over 4 within 2f), then an FP64 Davidson from that vector until the FP64
+ * residual <= tol.  f is the noise floor of the split operator, measured
+ * with one split and one FP64 product of the normalised start vector x0:
+ * f = |(H_split - H) x0| / |H x0| * |x0.H x0|.  *n_mv64 and *n_mv_split
+ * count the products of each kind (the floor probe included). */
 int mdmrg_davidson_mixed(mdmrg_ctx ctx, double *x, double tol, int prec_split, double tol_split,
                          int max_iter, int m_max, double *energy, double *resid, int *n_mv64,
                          int *n_mv_split);

@@ -1623,7 +1623,7 @@ static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w, std
 }
 
 int Context::davidson(double *x, double tol, int max_iter, int m_max, double *energy, double *resid,
-                      int *n_mv, int prec, bool stall) {
+                      int *n_mv, int prec, double stall_floor) {
   MDMRG_REQUIRE(cur >= 0, -4, "davidson: no current bond");
   MDMRG_REQUIRE(m_max >= 3 && m_max <= 60, -1, "davidson: m_max must be in [3, 60]");
   const int64_t N = psi.n_elem;
@@ -1678,13 +1678,14 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
       status = -5;
       break;
     }
-    if (stall) {
+    if (stall_floor >= 0.0) {
       // the split-precision operator has a noise floor: stop once the
-      // residual has not dropped by 10% over the last 24 products
+      // residual has not dropped by 10% over the last 24 products, or over
+      // the last 4 once it is within twice the measured floor
       if (rn < 0.9 * best_r) {
         best_r = rn;
         best_at = nmv;
-      } else if (nmv - best_at >= 24) {
+      } else if (nmv - best_at >= (rn <= 2.0 * stall_floor ? 4 : 24)) {
         break;
       }
     }
@@ -1768,10 +1769,43 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
 int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_split, int max_iter, int m_max,
                             double *energy, double *resid, int *n_mv64, int *n_mv_split) {
   MDMRG_REQUIRE(prec_split == 1 || prec_split == 2, -6, "davidson_mixed: prec_split must be a split form");
+  MDMRG_REQUIRE(cur >= 0, -4, "davidson_mixed: no current bond");
+  // Noise floor of the split operator at this bond, from one split and one
+  // FP64 product of the normalised start vector v: the relative
+  // perturbation |(H_split - H) v| / |H v| times the Rayleigh quotient
+  // |v.Hv| (the scale of |H x| near the eigenvector; |H v| of a random start
+  // is larger).  The split solve stops at that residual: below it, split
+  // iterations do little for the FP64 residual.
+  double floor = 0.0;
+  int probe = 0;
+  {
+    const int64_t N = psi.n_elem;
+    double nrm = 0.0;
+    dev_multidot(dev, x, 0, 1, x, N, &nrm);
+    if (nrm > 1e-300 && std::isfinite(nrm)) {
+      double *v = (double *)dev_alloc(dev, sizeof(double) * N);
+      double *a = (double *)dev_alloc(dev, sizeof(double) * N);
+      double *b = (double *)dev_alloc(dev, sizeof(double) * N);
+      dev_d2d(dev, v, x, sizeof(double) * N);
+      dev_scale(dev, 1.0 / std::sqrt(nrm), v, N);
+      heff_apply(v, a, prec_split);
+      heff_apply(v, b, 0);
+      dev_axpy(dev, -1.0, b, a, N);
+      double d2 = 0.0, h2 = 0.0, th = 0.0;
+      dev_multidot(dev, a, 0, 1, a, N, &d2);
+      dev_multidot(dev, b, 0, 1, b, N, &h2);
+      dev_multidot(dev, v, 0, 1, b, N, &th);
+      if (h2 > 0.0 && std::isfinite(d2)) floor = std::sqrt(d2 / h2) * std::fabs(th);
+      for (double *p : {v, a, b}) dev_free(dev, p);
+      probe = 1;
+    }
+  }
   double e = 0.0, r = 0.0;
   int ns = 0, n64 = 0;
-  davidson(x, std::max(tol, tol_split), max_iter, m_max, &e, &r, &ns, prec_split, true);
-  const int st = davidson(x, tol, max_iter, m_max, &e, &r, &n64, 0, false);
+  davidson(x, std::max({tol, tol_split, floor}), max_iter, m_max, &e, &r, &ns, prec_split, floor);
+  const int st = davidson(x, tol, max_iter, m_max, &e, &r, &n64, 0);
+  ns += probe;
+  n64 += probe;
   if (energy) *energy = e;
   if (resid) *resid = r;
   if (n_mv64) *n_mv64 = n64;

@@ -209,10 +209,12 @@ struct Context {
   void build_heff(int l);
   void heff_apply(const double *x, double *y, int prec = 0);
   void heff_diag(double *d);
-  // prec: matrix-vector precision (0 FP64, 1 FP32 split form); stall: stop
-  // when the residual stops decreasing (used for the split-precision phase)
+  // prec: matrix-vector precision (0 FP64, 1 FP32, 2 3xBF16); stall_floor
+  // >= 0: stop when the residual stops decreasing (split-precision phase):
+  // no 10% gain over 24 products, or over 4 once the residual is within
+  // twice stall_floor (the measured noise floor of the split operator)
   int davidson(double *x, double tol, int max_iter, int m_max, double *energy, double *resid, int *n_mv,
-               int prec = 0, bool stall = false);
+               int prec = 0, double stall_floor = -1.0);
   // split-precision Davidson to tol_split, then FP64 Davidson to tol
   int davidson_mixed(double *x, double tol, int prec_split, double tol_split, int max_iter, int m_max,
                      double *energy, double *resid, int *n_mv64, int *n_mv_split);
