@@ -157,7 +157,10 @@ enum {
                                   variant (k_gemm, k_gemm_w16, k_gemm_w4, k_gemm_t128;
                                   all give bitwise identical results) */
 };
-/* Set a context option (EINVAL for unknown options or bad values). */
+/* Set a context option (EINVAL for unknown options or bad values).
+ * With the environment variable MDMRG_VERBOSE set, the library prints
+ * progress lines on stderr: each block environment built, the timing of the
+ * Tables step, the residual after each Davidson product. */
 int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value);
 
 /* Make bond (l, l+1) current: build (on the device) the renormalised
@@ -259,7 +262,9 @@ int mdmrg_sweep(mdmrg_ctx ctx, int n_sweeps, const int *D_schedule, int n_sched,
  * ldb, k, flags (1 = A transposed, 2 = B transposed, 4 = A is the identity).
  * All matrices are FP64 row-major inside caller-owned device buffers
  * bases[0..n_bases-1] (n_bases <= 8) of base_len[i] doubles; offsets are in
- * elements.  Every access range is checked on the host first (EINVAL).
+ * elements; m, n < 2^30.  Every access range is checked on the host first
+ * (EINVAL); an operand whose rows x leading dimension within one 32-deep K
+ * step reaches 2^31 elements is refused (EUNSUP).
  * Outputs must not overlap each other or any operand of the call. */
 int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, const int64_t *base_len,
                        int64_t n_out, const int64_t *out_desc, int64_t n_seg, const int64_t *seg_desc,

@@ -369,7 +369,8 @@ static int gemm_grouped_any(mdmrg_ctx ctx, int prec, int n_bases, void *const *b
       g.seg_begin = int32_t(d[5]);
       g.seg_count = int32_t(d[6]);
       g.accumulate = uint8_t(d[7] != 0);
-      MDMRG_REQUIRE(d[2] >= 1 && d[3] >= 1 && d[4] >= d[3] && d[2] < (1 << 20) && d[3] < (1 << 20) &&
+      MDMRG_REQUIRE(d[2] >= 1 && d[3] >= 1 && d[4] >= d[3] && d[2] < (1 << 30) && d[3] < (1 << 30) &&
+                        d[4] < (int64_t(1) << 31) &&
                         d[5] >= 0 && d[6] >= 0 && d[5] + d[6] <= n_seg,
                     MDMRG_EINVAL, "gemm_grouped: bad output descriptor");
       MDMRG_REQUIRE(in_range(int(d[0]), d[1], (d[2] - 1) * d[4] + d[3] - 1), MDMRG_EINVAL,

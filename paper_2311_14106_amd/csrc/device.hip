@@ -705,8 +705,11 @@ static void launch_variant(int v, hipStream_t st, const DevPlan *p, const Bases 
 
 DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
   // the 64x64 kernel keeps per-thread 32-bit element offsets inside one K
-  // step of an operand block: rows x ld (+16) must stay below 2^31
-  for (const GOut &o : plan.outs)
+  // step of an operand block: rows x ld (+ the K step) must stay below 2^31
+  for (const GOut &o : plan.outs) {
+    // tile origins and row / column indices inside the kernel are 32-bit
+    MDMRG_REQUIRE(o.m >= 1 && o.n >= 1 && o.m < (1 << 30) && o.n < (1 << 30), -6,
+                  "grouped GEMM: output block dimensions out of range");
     for (int q = 0; q < o.seg_count; ++q) {
       const GSeg &g = plan.segs[o.seg_begin + q];
       const int64_t ext_a = (g.flags & SEG_TA) ? int64_t(kTKmax) * g.lda + o.m : int64_t(o.m) * g.lda + kTKmax;
@@ -714,6 +717,7 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
       MDMRG_REQUIRE(ext_a < (int64_t(1) << 31) && ext_b < (int64_t(1) << 31), -6,
                     "grouped GEMM: operand block too large for 32-bit element offsets");
     }
+  }
   auto *dp = new DevPlan();
   dp->n_outs = int64_t(plan.outs.size());
   dp->n_segs = int64_t(plan.segs.size());
@@ -753,7 +757,7 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
         const int x = int(std::min_element(load, load + kXcds) - load);
         load[x] += -w.first * double(i1 - i0) / nti;
         for (int i = i0; i < i1; ++i)
-          for (int j = 0; j < ntj; ++j) q[x].push_back(GTile{w.second, int16_t(i), int16_t(j)});
+          for (int j = 0; j < ntj; ++j) q[x].push_back(GTile{w.second, int32_t(i), int32_t(j)});
       }
     }
     size_t maxq = 0;

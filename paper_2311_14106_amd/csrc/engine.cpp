@@ -967,21 +967,28 @@ void Context::prepare(int l) {
     if (e) e->release(dev);
     e.reset();
   };
+  bool built = false;
   if (!Lenv[l]) {
+    built = true;
     int i0 = l;
     while (i0 > 0 && !Lenv[i0]) --i0;
     if (!Lenv[i0]) Lenv[i0] = env_boundary(true, i0);
+    const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
     for (int i = i0; i < l; ++i) {
       Lenv[i + 1] = renorm_left(*Lenv[i], i);
+      if (verbose) fprintf(stderr, "[mdmrg] left block at bond %d built\n", i + 1);
       if (!keep_envs && i + 1 < l) drop(Lenv[i]);
     }
   }
   if (!Renv[l + 2]) {
+    built = true;
     int i0 = l + 2;
     while (i0 < n && !Renv[i0]) ++i0;
     if (!Renv[i0]) Renv[i0] = env_boundary(false, i0);
+    const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
     for (int i = i0 - 1; i >= l + 2; --i) {
       Renv[i] = renorm_right(*Renv[i + 1], i);
+      if (verbose) fprintf(stderr, "[mdmrg] right block at bond %d built\n", i);
       if (!keep_envs && i + 1 > l + 3) drop(Renv[i + 1]);
     }
   }
@@ -994,7 +1001,7 @@ void Context::prepare(int l) {
       if (j != l + 2 && j != l + 3) drop(Renv[j]);
     }
   }
-  dev_sync(dev);
+  if (built) dev_sync(dev);  // environment builds are timed as Ren
   stats.t_ren += wall_seconds() - t0;
   build_heff(l);
 }
@@ -1626,6 +1633,7 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
                       int *n_mv, int prec, double stall_floor) {
   MDMRG_REQUIRE(cur >= 0, -4, "davidson: no current bond");
   MDMRG_REQUIRE(m_max >= 3 && m_max <= 60, -1, "davidson: m_max must be in [3, 60]");
+  const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
   const int64_t N = psi.n_elem;
   double t0 = wall_seconds();
   double *V = (double *)dev_alloc(dev, sizeof(double) * N * m_max);
@@ -1673,6 +1681,7 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
     dev_multidot(dev, r, 0, 1, r, N, &r2);
     MDMRG_REQUIRE(std::isfinite(r2) && std::isfinite(theta), -3, "davidson: NaN in residual");
     rn = std::sqrt(r2);
+    if (verbose) fprintf(stderr, "[mdmrg] davidson: %d products, |r| = %.3e\n", nmv, rn);
     if (rn <= tol) break;
     if (nmv >= max_iter) {
       status = -5;
@@ -2236,7 +2245,9 @@ void Context::renormalize(int dir) {
   } else {
     if (!Renv[l + 1]) Renv[l + 1] = renorm_right(*Renv[l + 2], l + 1);
   }
-  dev_sync(dev);
+  // no wait here: the host part of the next bond's Tables step overlaps
+  // these launches (its first plan upload waits for the stream), so Ren
+  // counts the host side of the renormalisation and Tables the rest
   stats.t_ren += wall_seconds() - t0;
   prev_psi = psi;
   prev_l = l;

@@ -78,7 +78,7 @@ struct GOut {
 };
 struct GTile {
   int32_t out;
-  int16_t ti, tj;
+  int32_t ti, tj;  // tile row / column within the output (a tall a3 output has millions of tile rows)
 };
 constexpr int kSlots = 8;
 struct Bases {

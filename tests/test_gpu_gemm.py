@@ -214,3 +214,26 @@ def test_forced_variant_option_rejects_unknown_variant():
     with pytest.raises(mdmrg.MdmrgError) as e:
         ctx.set_option(mdmrg.OPT_GEMM_VARIANT, 4)
     assert e.value.code == mdmrg.EINVAL
+
+
+@pytest.mark.parametrize('variant', [0, 1, 2, 3])
+def test_tall_output_beyond_16bit_tile_rows(variant):
+    """One output with more tile rows than a 16-bit index holds (the a3
+    operator accumulation at D=4096 produces such outputs: one row per
+    operator element).  Regression test for tile indices that wrapped."""
+    mdmrg, ctx = _ctx()
+    ctx.set_option(mdmrg.OPT_GEMM_VARIANT, variant)
+    m, k, n = 64 * 32768 + 1000, 5, 3
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((m, k))
+    B = rng.standard_normal((k, n))
+    dA = torch.from_numpy(A.ravel()).to('cuda:0')
+    dB = torch.from_numpy(B.ravel()).to('cuda:0')
+    dC = torch.zeros(m * n, dtype=torch.float64, device='cuda:0')
+    print(f'[gemm tall] variant={variant} m={m}', flush=True)
+    outs = np.array([[2, 0, m, n, n, 0, 1, 0]])
+    segs = np.array([[0, 0, k, 1, 0, n, k, 0]])
+    ctx.gemm_grouped([dA, dB, dC], outs, segs, np.array([1.5]))
+    got = dC.cpu().numpy().reshape(m, n)
+    ref = 1.5 * (A @ B)
+    assert np.all(np.abs(got - ref) <= 1e-13 * (1.5 * np.abs(A) @ np.abs(B) + 1.0))
