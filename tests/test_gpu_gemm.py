@@ -237,3 +237,40 @@ def test_tall_output_beyond_16bit_tile_rows(variant):
     got = dC.cpu().numpy().reshape(m, n)
     ref = 1.5 * (A @ B)
     assert np.all(np.abs(got - ref) <= 1e-13 * (1.5 * np.abs(A) @ np.abs(B) + 1.0))
+
+
+@pytest.mark.parametrize('variant', [0, 1, 2, 3])
+def test_degenerate_groups(variant):
+    """Degenerate shapes, exact results: a launch with no outputs leaves C
+    alone; an output whose segments all have k = 0 (or that has no
+    segment) is zero when overwritten and unchanged when accumulated; 1x1
+    outputs and 1-deep products."""
+    mdmrg, ctx = _ctx()
+    ctx.set_option(mdmrg.OPT_GEMM_VARIANT, variant)
+    A = torch.arange(1.0, 65.0, dtype=torch.float64, device='cuda:0')
+    B = torch.arange(2.0, 66.0, dtype=torch.float64, device='cuda:0')
+    C = torch.full((64,), 7.0, dtype=torch.float64, device='cuda:0')
+    ctx.gemm_grouped([A, B, C], np.zeros((0, 8)), np.zeros((0, 8)), np.zeros(0))
+    assert torch.all(C == 7.0)
+    outs = np.array([
+        [2, 0, 3, 4, 4, 0, 1, 0],     # k = 0, overwrite -> zeros
+        [2, 12, 3, 4, 4, 1, 1, 1],    # k = 0, accumulate -> unchanged
+        [2, 24, 2, 2, 2, 2, 0, 0],    # no segment, overwrite -> zeros
+        [2, 28, 1, 1, 1, 2, 1, 1],    # 1x1, k = 1, accumulate: 7 + 0.5 * A[5] * B[9]
+        [2, 29, 1, 1, 1, 3, 1, 0],    # 1x1, k = 64 (row of A times column of B)
+    ])
+    segs = np.array([
+        [0, 0, 1, 1, 0, 4, 0, 0],
+        [0, 0, 1, 1, 0, 4, 0, 0],
+        [0, 5, 1, 1, 9, 1, 1, 0],
+        [0, 0, 64, 1, 0, 1, 64, 0],
+    ])
+    ctx.gemm_grouped([A, B, C], outs, segs, np.array([1.0, 1.0, 0.5, 1.0]))
+    c = C.cpu().numpy()
+    a, b = np.arange(1.0, 65.0), np.arange(2.0, 66.0)
+    assert np.all(c[0:12] == 0.0)
+    assert np.all(c[12:24] == 7.0)
+    assert np.all(c[24:28] == 0.0)
+    assert c[28] == 7.0 + 0.5 * a[5] * b[9]
+    assert c[29] == float(a @ b)            # integers: exact in FP64
+    assert np.all(c[30:] == 7.0)

@@ -193,7 +193,7 @@ def test_decimation_matches_oracle():
     x = si.random_vector(ne, 8)
     x /= np.linalg.norm(x)
     for direction in (+1, -1):
-        for D in (5, 17, 40):
+        for D in (1, 5, 17, 40, 4096):   # D=1 keeps one state; 4096 keeps every state (no truncation)
             log(f'[decimate] dir {direction} D {D}')
             nb, _, trunc, svn, shalf, tie = dmrg.decimate(mps, l, x, D, direction)
             ctx.set_mps(*si.flatten_mps(bonds, tens, spin))
@@ -242,3 +242,28 @@ def test_split_precision_heff_and_mixed_davidson(form, bound):
     log(f'[split] mixed Davidson: FP64 products {n64}, {form} products {nsp}, E={e:.14f}')
     assert conv and nsp > 0 and r <= 1e-9
     assert abs(e - e_ref) <= 1e-12 * abs(e_ref)
+
+
+def test_davidson_from_zero_start_vector():
+    """A zero start vector is replaced by the library's seeded Gaussian
+    vector; the solve still reaches the lowest eigenvalue of the oracle's
+    H_eff."""
+    mdmrg = _gpu()
+    build, n, spin, target, D, _ = CASES['hubbard_3x3_momentum_D64']
+    T, W = build()
+    l = 4
+    ch = dmrg.Chain(T, W, n, spin, target)
+    bonds = si.bond_profile(n, spin, target, D)
+    tens = si.random_mps(bonds, spin, 3, l)
+    prob = dmrg.TwoSiteProblem(dmrg.MPS(ch, bonds, tens), l)
+    e_ref, _ = prob.lowest(v0=si.random_vector(prob.dim, 1))
+    ctx = mdmrg.Context(0)
+    ctx.set_hamiltonian(n, spin, T, W, target)
+    ctx.set_mps(*si.flatten_mps(bonds, tens, spin))
+    ctx.prepare_bond(l)
+    _, ne = ctx.psi_layout()
+    x = torch.zeros(ne, dtype=torch.float64, device='cuda:0')
+    e, r, nmv, conv = ctx.davidson(x, tol=1e-9, max_iter=400)
+    assert conv and r <= 1e-9
+    assert abs(e - e_ref) <= 1e-12 * abs(e_ref)
+    assert abs(float(x.norm()) - 1.0) <= 1e-12
