@@ -35,15 +35,6 @@ struct Device {
   int *info = nullptr;
   double *syevd_work = nullptr;
   size_t syevd_work_n = 0;
-  // side streams (default priority) and handles for concurrent eigensolves
-  static constexpr int kEig = 4;
-  hipStream_t eig_stream[kEig] = {};
-  rocblas_handle eig_blas[kEig] = {};
-  hipEvent_t eig_ev[kEig + 1] = {};
-  int *eig_info = nullptr;
-  size_t eig_info_n = 0;
-  double *eig_work = nullptr;
-  size_t eig_work_n = 0;
   // launch timing
   bool timing = false;
   bool capturing = false;  // stream capture in progress: no events, no host syncs
@@ -159,15 +150,6 @@ void dev_destroy(Device *d) {
   (void)hipHostFree(d->host_red);
   (void)hipFree(d->info);
   if (d->syevd_work) (void)hipFree(d->syevd_work);
-  for (int q = 0; q < Device::kEig; ++q) {
-    if (d->eig_stream[q]) (void)hipStreamSynchronize(d->eig_stream[q]);
-    if (d->eig_blas[q]) rocblas_destroy_handle(d->eig_blas[q]);
-    if (d->eig_stream[q]) (void)hipStreamDestroy(d->eig_stream[q]);
-  }
-  for (auto e : d->eig_ev)
-    if (e) (void)hipEventDestroy(e);
-  if (d->eig_info) (void)hipFree(d->eig_info);
-  if (d->eig_work) (void)hipFree(d->eig_work);
   if (d->blas) rocblas_destroy_handle(d->blas);
   (void)hipStreamDestroy(d->stream);
   delete d;
@@ -1209,73 +1191,6 @@ void dev_syevd(Device *d, double *A, int n, double *w) {
   HIP_CHECK(hipMemcpyAsync(&info, d->info, sizeof(int), hipMemcpyDeviceToHost, d->stream));
   HIP_CHECK(hipStreamSynchronize(d->stream));
   MDMRG_REQUIRE(info == 0, -3, "rocsolver_dsyevd did not converge (info " + std::to_string(info) + ")");
-}
-
-// Eigensolves of many independent symmetric blocks (the per-sector density
-// matrices): small eigensolves are bound by kernel latency, so they run
-// concurrently on side streams, each with its own rocBLAS handle, largest
-// first and each to the stream with the least work (n^3); the context stream
-// waits for all of them, and the convergence flags are checked after one
-// synchronisation.
-void dev_syevd_batch(Device *d, const std::vector<double *> &A, const std::vector<int> &n,
-                     const std::vector<double *> &w) {
-  const size_t m = A.size();
-  if (m == 0) return;
-  if (!d->eig_stream[0]) {
-    for (int q = 0; q < Device::kEig; ++q) {
-      HIP_CHECK(hipStreamCreate(&d->eig_stream[q]));
-      if (rocblas_create_handle(&d->eig_blas[q]) != rocblas_status_success)
-        throw Error(-3, "rocblas_create_handle failed");
-      rocblas_set_stream(d->eig_blas[q], d->eig_stream[q]);
-    }
-    for (auto &e : d->eig_ev) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  }
-  size_t work = 0;
-  for (int k : n) work += size_t(std::max(k, 1));
-  if (d->eig_info_n < m || d->eig_work_n < work) {
-    // the side streams may still hold work on the old buffers
-    HIP_CHECK(hipStreamSynchronize(d->stream));
-    if (d->eig_info_n < m) {
-      if (d->eig_info) HIP_CHECK(hipFree(d->eig_info));
-      HIP_CHECK(hipMalloc(&d->eig_info, sizeof(int) * m));
-      d->eig_info_n = m;
-    }
-    if (d->eig_work_n < work) {
-      if (d->eig_work) HIP_CHECK(hipFree(d->eig_work));
-      HIP_CHECK(hipMalloc(&d->eig_work, sizeof(double) * work));
-      d->eig_work_n = work;
-    }
-  }
-  std::vector<size_t> order(m);
-  std::iota(order.begin(), order.end(), size_t(0));
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return n[a] > n[b]; });
-  std::vector<size_t> woff(m);
-  size_t off = 0;
-  for (size_t i = 0; i < m; ++i) {
-    woff[i] = off;
-    off += size_t(std::max(n[i], 1));
-  }
-  HIP_CHECK(hipEventRecord(d->eig_ev[Device::kEig], d->stream));
-  for (int q = 0; q < Device::kEig; ++q) HIP_CHECK(hipStreamWaitEvent(d->eig_stream[q], d->eig_ev[Device::kEig], 0));
-  double load[Device::kEig] = {};
-  for (size_t i : order) {
-    if (n[i] <= 0) continue;
-    const int q = int(std::min_element(load, load + Device::kEig) - load);
-    load[q] += double(n[i]) * n[i] * n[i];
-    rocblas_status st = rocsolver_dsyevd(d->eig_blas[q], rocblas_evect_original, rocblas_fill_upper, n[i], A[i],
-                                         n[i], w[i], d->eig_work + woff[i], d->eig_info + i);
-    MDMRG_REQUIRE(st == rocblas_status_success, -3, "rocsolver_dsyevd failed");
-  }
-  for (int q = 0; q < Device::kEig; ++q) {
-    HIP_CHECK(hipEventRecord(d->eig_ev[q], d->eig_stream[q]));
-    HIP_CHECK(hipStreamWaitEvent(d->stream, d->eig_ev[q], 0));
-  }
-  std::vector<int> info(m, 0);
-  HIP_CHECK(hipMemcpyAsync(info.data(), d->eig_info, sizeof(int) * m, hipMemcpyDeviceToHost, d->stream));
-  HIP_CHECK(hipStreamSynchronize(d->stream));
-  for (size_t i = 0; i < m; ++i)
-    MDMRG_REQUIRE(n[i] <= 0 || info[i] == 0, -3,
-                  "rocsolver_dsyevd did not converge (info " + std::to_string(info[i]) + ")");
 }
 
 // ------------------------------------------------------------------ gather

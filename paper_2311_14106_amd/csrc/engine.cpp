@@ -1967,16 +1967,7 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
     woff += secs[i].M;
   }
   double *wv = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, woff));
-  {
-    std::vector<double *> Ap(secs.size()), wp(secs.size());
-    std::vector<int> np(secs.size());
-    for (size_t i = 0; i < secs.size(); ++i) {
-      Ap[i] = rho + secs[i].base;
-      np[i] = secs[i].M;
-      wp[i] = wv + wbase[i];
-    }
-    dev_syevd_batch(dev, Ap, np, wp);
-  }
+  for (size_t i = 0; i < secs.size(); ++i) dev_syevd(dev, rho + secs[i].base, secs[i].M, wv + wbase[i]);
   std::vector<double> wall(std::max<int64_t>(1, woff));
   dev_d2h(dev, wall.data(), wv, sizeof(double) * woff);
   dev_free(dev, wdev);

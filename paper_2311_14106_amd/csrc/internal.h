@@ -215,11 +215,6 @@ void dev_randn(Device *, double *x, int64_t n, uint64_t seed);
 // Symmetric eigensolver (rocSOLVER dsyevd): A (n x n, overwritten by the
 // eigenvectors, column k = eigenvector k), w ascending.  Device pointers.
 void dev_syevd(Device *, double *A, int n, double *w);
-// The same for many independent blocks (A[i]: n[i] x n[i], eigenvalues to
-// w[i]), solved concurrently; returns once all are done (EDEVICE if any did
-// not converge).
-void dev_syevd_batch(Device *, const std::vector<double *> &A, const std::vector<int> &n,
-                     const std::vector<double *> &w);
 // Gather: out[b][i*ncol + j] = E[col[j]*ldE + row0 + i] for a list of blocks
 struct GatherBlk {
   int64_t out_off, e_off;  // out block, start of eigenvector storage
