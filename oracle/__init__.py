@@ -17,6 +17,8 @@ The oracle is deliberately slow and literal:
   code with, and uses none of the operator bookkeeping of, the GPU path.
 * ``davidson``   -- a textbook Davidson eigensolver (Sec. II.A names Lanczos
   or Davidson; the variant used is the reading recorded in the design notes).
+* ``split``      -- the split-precision product model (FP32 and 3xBF16
+  hi/lo products) evaluated in FP64, for the kernel tests of those forms.
 
 Pins (closed forms, brute force on tiny inputs, basis invariance) live in
 ``tests/test_oracle_*.py``.
