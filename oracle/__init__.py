@@ -15,8 +15,11 @@ The oracle is deliberately slow and literal:
   kept as *explicit* Fock-space basis vectors, so that the effective
   Hamiltonian product is the plain projection  P^T H P psi.  It shares no
   code with, and uses none of the operator bookkeeping of, the GPU path.
-* ``davidson``   -- a textbook Davidson eigensolver (Sec. II.A names Lanczos
-  or Davidson; the variant used is the reading recorded in the design notes).
+* eigenpairs -- ``dmrg.TwoSiteProblem.lowest`` takes the lowest eigenpair of
+  H_eff by its plain definition (dense ``eigh`` for small dimensions, scipy's
+  Lanczos ``eigsh`` otherwise); the library's Davidson (Sec. II.A names
+  Lanczos or Davidson) is compared with that eigenvalue, not with another
+  Davidson.
 * ``split``      -- the split-precision product model (FP32 and 3xBF16
   hi/lo products) evaluated in FP64, for the kernel tests of those forms.
 
