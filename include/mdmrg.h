@@ -62,7 +62,10 @@ enum { MDMRG_FP64 = 0, MDMRG_FP32 = 1, MDMRG_BF16X3 = 2 };
 /* ---------------------------------------------------------------- context */
 
 /* Create a context on HIP device `device` with its own (default-priority)
- * stream.  *out receives the handle; on failure *out is NULL. */
+ * stream.  *out receives the handle; on failure *out is NULL.  The context
+ * may hold up to 95% of the device memory free at this call (see
+ * MDMRG_OPT_MEMORY_BUDGET); a call that would need more fails with
+ * MDMRG_ENOMEM. */
 int mdmrg_create(mdmrg_ctx *out, int device);
 /* Release every device and host resource of the context.  NULL is a no-op. */
 void mdmrg_destroy(mdmrg_ctx ctx);
@@ -151,11 +154,17 @@ enum {
                                   reconstruction checked to 1e-12) to skeleton products
                                   with on-the-fly left combinations; 0: one product per
                                   left operator (takes effect at the next bond prepared) */
-  MDMRG_OPT_GEMM_VARIANT = 5   /* -1 (default): every grouped-GEMM plan times its first
+  MDMRG_OPT_GEMM_VARIANT = 5,  /* -1 (default): every grouped-GEMM plan times its first
                                   launches on the tile variants in turn and keeps the
                                   fastest; 0..3: every launch of the context uses that
                                   variant (k_gemm, k_gemm_w16, k_gemm_w4, k_gemm_t128;
                                   all give bitwise identical results) */
+  MDMRG_OPT_MEMORY_BUDGET = 6  /* bytes of device memory the context may hold (its
+                                  operator arenas, wave-function buffers, scratch and
+                                  plans); an allocation beyond it fails with
+                                  MDMRG_ENOMEM before reaching the allocator.  0 (and
+                                  the upper limit): 95% of the device memory free at
+                                  mdmrg_create */
 };
 /* Set a context option (EINVAL for unknown options or bad values).
  * With the environment variable MDMRG_VERBOSE set, the library prints

@@ -35,6 +35,9 @@ struct Device {
   int *info = nullptr;
   double *syevd_work = nullptr;
   size_t syevd_work_n = 0;
+  // allocation budget of the context (dev_alloc / dev_free)
+  std::unordered_map<void *, size_t> live;
+  size_t live_bytes = 0, budget_bytes = 0, budget_default = 0;
   // launch timing
   bool timing = false;
   bool capturing = false;  // stream capture in progress: no events, no host syncs
@@ -129,6 +132,9 @@ Device *dev_create(int device) {
   HIP_CHECK(hipMalloc(&d->red_out, sizeof(double) * kMaxDot));
   HIP_CHECK(hipHostMalloc(&d->host_red, sizeof(double) * kMaxDot));
   HIP_CHECK(hipMalloc(&d->info, sizeof(int)));
+  size_t free_b = 0, total_b = 0;
+  HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+  d->budget_bytes = d->budget_default = size_t(0.95 * double(free_b));
   return d;
 }
 
@@ -155,18 +161,37 @@ void dev_destroy(Device *d) {
   delete d;
 }
 
+// Every allocation of the context is counted against a budget fixed at
+// creation (95% of the device memory free then), so that a workload larger
+// than the card fails here, with ENOMEM and the sizes, instead of in the
+// stream-ordered allocator.
 void *dev_alloc(Device *d, size_t bytes) {
   if (bytes == 0) bytes = 256;
+  if (d->live_bytes + bytes > d->budget_bytes)
+    throw Error(-2, "device memory budget exceeded: " + std::to_string(bytes) + " bytes requested, " +
+                        std::to_string(d->live_bytes) + " in use of " + std::to_string(d->budget_bytes));
   void *p = nullptr;
   hipError_t e = hipMallocAsync(&p, bytes, d->stream);
   if (e != hipSuccess || !p) {
     (void)hipGetLastError();
     throw Error(-2, "device allocation of " + std::to_string(bytes) + " bytes failed");
   }
+  d->live[p] = bytes;
+  d->live_bytes += bytes;
   return p;
 }
+void dev_set_budget(Device *d, size_t bytes) {
+  d->budget_bytes = bytes ? std::min(bytes, d->budget_default) : d->budget_default;
+}
+size_t dev_live_bytes(Device *d) { return d->live_bytes; }
 void dev_free(Device *d, void *p) {
-  if (p) HIP_CHECK(hipFreeAsync(p, d->stream));
+  if (!p) return;
+  auto it = d->live.find(p);
+  if (it != d->live.end()) {
+    d->live_bytes -= it->second;
+    d->live.erase(it);
+  }
+  HIP_CHECK(hipFreeAsync(p, d->stream));
 }
 void dev_h2d(Device *d, void *dst, const void *src, size_t b) {
   if (b) HIP_CHECK(hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, d->stream));

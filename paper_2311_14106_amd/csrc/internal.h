@@ -116,6 +116,11 @@ void dev_d2d(Device *, void *dst, const void *src, size_t bytes);
 void dev_zero(Device *, void *dst, size_t bytes);
 void dev_sync(Device *);
 size_t dev_free_bytes(Device *);
+// Allocation budget of the device context: dev_alloc throws ENOMEM when the
+// live bytes of the context would exceed it.  Default (and upper limit):
+// 95% of the device memory free at creation; 0 restores the default.
+void dev_set_budget(Device *, size_t bytes);
+size_t dev_live_bytes(Device *);
 
 // Tile variants of the grouped kernel: 64x64 output tiles (one tile list)
 // split over waves as 0 k_gemm (2x4 waves), 1 k_gemm_w16 (4x4), 2 k_gemm_w4

@@ -267,3 +267,34 @@ def test_davidson_from_zero_start_vector():
     assert conv and r <= 1e-9
     assert abs(e - e_ref) <= 1e-12 * abs(e_ref)
     assert abs(float(x.norm()) - 1.0) <= 1e-12
+
+
+def test_memory_budget_fails_cleanly_and_context_recovers():
+    """An allocation beyond the context's device-memory budget fails with
+    ENOMEM (the failure is forced from the host with a small budget); with
+    the default budget restored the same context prepares the bond and its
+    H_eff product matches the oracle."""
+    mdmrg = _gpu()
+    build, n, spin, target, D, ls = CASES['spinless_4x5_real_D300']
+    l = ls[0]
+    T, W = build()
+    ch = dmrg.Chain(T, W, n, spin, target)
+    bonds = si.bond_profile(n, spin, target, D)
+    tens = si.random_mps(bonds, spin, 10 + l, l)
+    prob = dmrg.TwoSiteProblem(dmrg.MPS(ch, bonds, tens), l)
+    ctx = mdmrg.Context(0)
+    ctx.set_hamiltonian(n, spin, T, W, target)
+    ctx.set_mps(*si.flatten_mps(bonds, tens, spin))
+    ctx.set_option(mdmrg.OPT_MEMORY_BUDGET, 1 << 20)
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        ctx.prepare_bond(l)
+    assert e.value.code == mdmrg.ENOMEM and 'budget' in str(e.value)
+    ctx.set_option(mdmrg.OPT_MEMORY_BUDGET, 0)
+    ctx.prepare_bond(l)
+    _, ne = ctx.psi_layout()
+    x = si.random_vector(ne, 100 + l)
+    yd = torch.zeros(ne, dtype=torch.float64, device='cuda:0')
+    ctx.heff_apply(to_dev(x), yd)
+    y_ref = prob.matvec(x)
+    assert np.abs(yd.cpu().numpy() - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
+    ctx.close()
