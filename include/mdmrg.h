@@ -223,8 +223,8 @@ int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max
 
 /* Mixed-precision Davidson: a Davidson solve whose products use the split
  * form prec_split (MDMRG_FP32 or MDMRG_BF16X3) until its residual reaches
- * max(tol_split, f) or stops decreasing (no 10% gain over 24 products, or
- * over 4 within 2f), then an FP64 Davidson from that vector until the FP64
+ * tol_split or stops decreasing (no 10% gain over 24 products, or over 4
+ * once within 2f), then an FP64 Davidson from that vector until the FP64
  * residual <= tol.  f is the noise floor of the split operator, measured
  * with one split and one FP64 product of the normalised start vector x0:
  * f = |(H_split - H) x0| / |H x0| * |x0.H x0|.  *n_mv64 and *n_mv_split
