@@ -127,6 +127,15 @@ int mdmrg_n_terms(mdmrg_ctx ctx, int64_t *n_one_body, int64_t *n_two_body);
 int mdmrg_set_mps(mdmrg_ctx ctx, const int32_t *n_sect, const int32_t *sect_qn,
                   const int32_t *sect_dim, const double *data, int64_t n_data);
 
+/* Export the MPS site tensors in the exchange format of mdmrg_set_mps
+ * (the sector lists of the bonds are those of mdmrg_get_bond): *n_needed
+ * receives the number of doubles; with data != NULL (n_data >= that) the
+ * tensors are copied to the host buffer.  After decimation the exported
+ * sites are the library's current tensors: the isometries left and right
+ * of the current bond; the two-site centre itself lives in the Davidson
+ * vector, not in the tensors. */
+int mdmrg_get_mps(mdmrg_ctx ctx, double *data, int64_t n_data, int64_t *n_needed);
+
 /* Sector list of bond i: query with qn = dim = NULL to get *n_sect. */
 int mdmrg_get_bond(mdmrg_ctx ctx, int bond, int32_t *n_sect, int32_t *qn, int32_t *dim);
 

@@ -1,4 +1,5 @@
 // extern "C" boundary of libmdmrg: argument checks, exception -> status.
+#include <algorithm>
 #include <cmath>
 
 #include "../../include/mdmrg.h"
@@ -156,6 +157,47 @@ int mdmrg_set_mps(mdmrg_ctx ctx, const int32_t *n_sect, const int32_t *sect_qn, 
     }
     MDMRG_REQUIRE(pos == n_data, MDMRG_EINVAL, "set_mps: data longer than the sector layout");
     c.have_mps = true;
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_get_mps(mdmrg_ctx ctx, double *data, int64_t n_data, int64_t *n_needed) {
+  if (!ctx) return MDMRG_EINVAL;
+  return guarded(ctx, [&] {
+    Context &c = ctx->c;
+    MDMRG_REQUIRE(c.have_mps, MDMRG_ESTATE, "get_mps: no MPS");
+    const int n = c.ham.n, d = c.ham.d;
+    // the exchange layout of mdmrg_set_mps: site by site, blocks (l, s, r)
+    // in lexicographic order, each row-major; absent blocks are zero
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+      const Bond &L = c.bonds[i], &R = c.bonds[i + 1];
+      for (size_t l = 0; l < L.qn.size(); ++l)
+        for (int st = 0; st < d; ++st) {
+          const int r = R.find(L.qn[l] + c.ham.q_of_state(st));
+          if (r >= 0) total += int64_t(L.dim[l]) * R.dim[r];
+        }
+    }
+    if (n_needed) *n_needed = total;
+    if (!data) return MDMRG_OK;
+    MDMRG_REQUIRE(n_data >= total, MDMRG_EINVAL, "get_mps: data shorter than the sector layout");
+    int64_t pos = 0;
+    for (int i = 0; i < n; ++i) {
+      const Bond &L = c.bonds[i], &R = c.bonds[i + 1];
+      const SiteTensor &T = c.A[i];
+      for (size_t l = 0; l < L.qn.size(); ++l)
+        for (int st = 0; st < d; ++st) {
+          const int r = R.find(L.qn[l] + c.ham.q_of_state(st));
+          if (r < 0) continue;
+          const int64_t sz = int64_t(L.dim[l]) * R.dim[r];
+          const int b = T.find(int(l), st, r);
+          if (b >= 0 && T.data)
+            dev_d2h(c.dev, data + pos, T.data + T.off[b], sizeof(double) * sz);
+          else
+            std::fill(data + pos, data + pos + sz, 0.0);
+          pos += sz;
+        }
+    }
     return MDMRG_OK;
   });
 }

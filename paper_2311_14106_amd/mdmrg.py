@@ -64,6 +64,7 @@ EXPORTS = {
     'mdmrg_gemm_grouped_split': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                                 ctypes.POINTER(ctypes.c_void_p), _c_i64_p, ctypes.c_int64,
                                                 _c_i64_p, ctypes.c_int64, _c_i64_p, _c_dbl_p]),
+    'mdmrg_get_mps': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     'mdmrg_get_stats': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p]),
 }
 
@@ -191,6 +192,14 @@ class Context:
         data = np.ascontiguousarray(data, dtype=np.float64)
         self._chk(self.lib.mdmrg_set_mps(self.h, _ip(n_sect), _ip(sect_qn), _ip(sect_dim), _dp(data),
                                          len(data)))
+
+    def get_mps(self):
+        """Site tensors in the exchange layout of set_mps (flat float64)."""
+        n = ctypes.c_int64()
+        self._chk(self.lib.mdmrg_get_mps(self.h, None, 0, ctypes.byref(n)))
+        data = np.zeros(n.value)
+        self._chk(self.lib.mdmrg_get_mps(self.h, _dp(data), len(data), ctypes.byref(n)))
+        return data
 
     def get_bond(self, i):
         n = ctypes.c_int32()

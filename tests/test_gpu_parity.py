@@ -298,3 +298,42 @@ def test_memory_budget_fails_cleanly_and_context_recovers():
     y_ref = prob.matvec(x)
     assert np.abs(yd.cpu().numpy() - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
     ctx.close()
+
+
+def test_mps_export_round_trip_and_isometry_after_decimation():
+    """mdmrg_get_mps returns exactly what mdmrg_set_mps loaded; after a
+    decimation towards the right, the exported site l is a left isometry on
+    the new bond (sum over left sector and site state of A^T A = 1 per right
+    sector)."""
+    mdmrg = _gpu()
+    T, W = I.hubbard_momentum(3, 3, 1.0, 4.0)
+    n, spin, target, l = 9, True, (4, 4), 3
+    bonds = si.bond_profile(n, spin, target, 64)
+    tens = si.random_mps(bonds, spin, 5, l)
+    flat = si.flatten_mps(bonds, tens, spin)
+    ctx = mdmrg.Context(0)
+    ctx.set_hamiltonian(n, spin, T, W, target)
+    ctx.set_mps(*flat)
+    assert np.array_equal(ctx.get_mps(), flat[3])
+    ctx.prepare_bond(l)
+    _, ne = ctx.psi_layout()
+    ctx.decimate(to_dev(si.random_vector(ne, 9)), 30, +1)
+    data = ctx.get_mps()
+    nb = [ctx.get_bond(i) for i in range(n + 1)]
+    d = 4 if spin else 2
+    pos, gram = 0, {}
+    for i in range(n):
+        for (Ql, ml) in nb[i]:
+            for s in range(d):
+                q = si.local_qn(s, spin)
+                for r, (Qr, mr) in enumerate(nb[i + 1]):
+                    if (Ql[0] + q[0], Ql[1] + q[1]) == Qr:
+                        blk = data[pos:pos + ml * mr].reshape(ml, mr)
+                        pos += ml * mr
+                        if i == l:
+                            gram[r] = gram.get(r, np.zeros((mr, mr))) + blk.T @ blk
+    assert pos == len(data)
+    assert sum(m for _, m in nb[l + 1]) == 30
+    for r, g in gram.items():
+        assert np.abs(g - np.eye(g.shape[0])).max() <= 1e-12, r
+    ctx.close()
