@@ -452,7 +452,9 @@ static void build_two_phase(std::vector<PairTask> &tasks, const std::vector<OutB
         tiles += int64_t((ob.m + 63) / 64) * ((ob.n + 63) / 64);
         maxseg = std::max(maxseg, per_out[q].size());
       }
-      S = int(std::min<int64_t>(std::max<int64_t>(1, 4096 / std::max<int64_t>(tiles, 1)), 32));
+      // about 16384 workgroup tiles (several waves of workgroups per CU, so
+      // the tail of the launch is short), at most 32 partial copies
+      S = int(std::min<int64_t>(std::max<int64_t>(1, 16384 / std::max<int64_t>(tiles, 1)), 32));
       S = int(std::min<size_t>(size_t(S), std::max<size_t>(maxseg, 1)));
       plan.n_split = std::max(plan.n_split, S);
     }
