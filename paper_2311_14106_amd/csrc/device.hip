@@ -280,8 +280,9 @@ struct TileCfg {
 // faster on split-K H_eff products) and 16 in the 16-wave split, which keeps
 // the unsplit long-K case; FP32 stages 16 everywhere (32, the same LDS bytes
 // per stage as FP64 at 16, measured slower).
-// The 3xBF16 form stages 32 columns per step: one v_mfma_f32_16x16x32_bf16
-// step.
+// The 3xBF16 form stages 16 columns per step: one v_mfma_f32_16x16x16_bf16
+// step (a 32-column step on v_mfma_f32_16x16x32_bf16 holds twice the LDS and
+// measured 25% slower).
 struct Bf16x3 {};  // element-type tag: FP32 data, products as 3 BF16 MFMAs
 template <class T>
 struct KStep {  // FP32
@@ -293,7 +294,7 @@ struct KStep<double> {
 };
 template <>
 struct KStep<Bf16x3> {
-  static constexpr int small = 32, wide = 32;
+  static constexpr int small = 16, wide = 16;
 };
 template <class T>
 using Cfg64 = TileCfg<64, 64, 2, 4, KStep<T>::small>;  // variant 0, k_gemm: 8 waves of 32x16
@@ -533,14 +534,15 @@ __device__ inline void gemm_tile(const GTile *__restrict__ tiles, const GOut *__
 // Every FP32 operand element x is split when it is staged to LDS into
 // hi = RNE_bf16(x) and lo = RNE_bf16(x - hi) (x - hi is exact in FP32), and
 // a product is formed as hi*lo + lo*hi + hi*hi with FP32 accumulation on
-// v_mfma_f32_16x16x32_bf16 (lo*lo is dropped): about 16 significant bits
+// v_mfma_f32_16x16x16_bf16 (lo*lo is dropped): about 16 significant bits
 // per operand instead of FP32's 24, at BF16 MFMA rate.  The staged tiles are
-// K-contiguous ([row][k] for A, [column][k] for B), so a lane's 8 operand
-// values of one MFMA are one 16-byte LDS read; the instruction takes from
-// lane l the values of row / column l % 16 at K positions fixed by l / 16,
-// the same for both operands, so the staged K order is the product's K order.
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-constexpr int kLdkH = 32 + 8;  // staged row length (BF16 elements; 80 bytes, 16-byte aligned rows)
+// K-contiguous ([row][k] for A, [column][k] for B, rows of TK + 8 BF16), so
+// a lane's 4 operand values of one MFMA are one 8-byte LDS read; the
+// instruction takes from lane l the values of row / column l % 16 at K
+// positions fixed by l / 16, the same for both operands, so the staged K
+// order is the product's K order.
+typedef short v4s __attribute__((ext_vector_type(4)));  // 4 BF16 bit patterns
+
 
 __device__ inline void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
   hi = __bf16(v);
@@ -565,12 +567,12 @@ __device__ inline void seg_store_bf3(const SegLoad<float, C> &L, int tid, int st
       v = (ok && L.ia0 + L.dia * it == k0 + kk) ? L.alpha : 0.f;
     else
       v = ok ? L.alpha * ra[it] : 0.f;
-    const int e = (i0 + di * it) * kLdkH + kk;
+    const int e = (i0 + di * it) * (C::TK + 8) + kk;
     split_bf16(v, Ah[e], Al[e]);
   }
 #pragma unroll
   for (int it = 0; it < L.EB; ++it) {
-    const int e = (j0 + dj * it) * kLdkH + L.kb0 + L.dkb * it;
+    const int e = (j0 + dj * it) * (C::TK + 8) + L.kb0 + L.dkb * it;
     split_bf16(((okb >> it) & 1) ? rb[it] : 0.f, Bh[e], Bl[e]);
   }
 }
@@ -580,20 +582,20 @@ __device__ inline void tile_mfma_bf3(const __bf16 *Ah, const __bf16 *Al, const _
                                      int wn, int lr, int lk, bool full, int qm, int qn,
                                      v4f (&acc)[C::MI][C::NI]) {
   constexpr int MI = C::MI, NI = C::NI;
-  static_assert(C::TK == 32, "one MFMA K step per staged step");
+  static_assert(C::TK == 16, "one MFMA K step per staged step");
   if (!full && !(qm > 0 && qn > 0)) return;
-  v8bf ah[MI], al[MI], bh[NI], bl[NI];
+  v4s ah[MI], al[MI], bh[NI], bl[NI];
 #pragma unroll
   for (int mi = 0; mi < MI; ++mi) {
-    const int e = (wm + 16 * mi + lr) * kLdkH + 8 * lk;
-    ah[mi] = *reinterpret_cast<const v8bf *>(Ah + e);
-    al[mi] = *reinterpret_cast<const v8bf *>(Al + e);
+    const int e = (wm + 16 * mi + lr) * (C::TK + 8) + 4 * lk;
+    ah[mi] = *reinterpret_cast<const v4s *>(Ah + e);
+    al[mi] = *reinterpret_cast<const v4s *>(Al + e);
   }
 #pragma unroll
   for (int ni = 0; ni < NI; ++ni) {
-    const int e = (wn + 16 * ni + lr) * kLdkH + 8 * lk;
-    bh[ni] = *reinterpret_cast<const v8bf *>(Bh + e);
-    bl[ni] = *reinterpret_cast<const v8bf *>(Bl + e);
+    const int e = (wn + 16 * ni + lr) * (C::TK + 8) + 4 * lk;
+    bh[ni] = *reinterpret_cast<const v4s *>(Bh + e);
+    bl[ni] = *reinterpret_cast<const v4s *>(Bl + e);
   }
 #pragma unroll
   for (int mi = 0; mi < MI; ++mi)
@@ -601,9 +603,9 @@ __device__ inline void tile_mfma_bf3(const __bf16 *Ah, const __bf16 *Al, const _
     for (int ni = 0; ni < NI; ++ni)
       if (full || (qm > 16 * mi && qn > 16 * ni)) {
         v4f c = acc[mi][ni];
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], c, 0, 0, 0);
-        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[mi], bl[ni], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[mi], bh[ni], c, 0, 0, 0);
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[mi], bh[ni], c, 0, 0, 0);
       }
 }
 
@@ -614,8 +616,8 @@ __device__ inline void gemm_tile_bf3(const GTile *__restrict__ tiles, const GOut
                                      const GSeg *__restrict__ segs, const Bases &bases) {
   constexpr int BM = C::BM, BN = C::BN, MI = C::MI, NI = C::NI, TK = C::TK;
   typedef SegLoad<float, C> SL;
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * kLdkH], Al[2][BM * kLdkH];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN * kLdkH], Bl[2][BN * kLdkH];
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * (C::TK + 8)], Al[2][BM * (C::TK + 8)];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN * (C::TK + 8)], Bl[2][BN * (C::TK + 8)];
   const GTile tl = tiles[blockIdx.x];
   if (tl.out < 0) return;
   const GOut o = outs[tl.out];
