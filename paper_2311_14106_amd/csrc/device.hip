@@ -697,8 +697,8 @@ __global__ __launch_bounds__(Cfg64q<T>::NT) void k_gemm_w4(const GTile *__restri
 }
 
 // 128x128 tiles: FP64 and FP32 are held to 256 registers per lane (2 waves
-// per SIMD, accumulators in VGPRs, no spills); the 3xBF16 form keeps its
-// 80 KB of LDS stages and one wave per SIMD.
+// per SIMD, accumulators in VGPRs, no spills); the 3xBF16 form fits that
+// without the bound (49 KB of LDS stages per workgroup).
 template <class T>
 __global__ __launch_bounds__(Cfg128<T>::NT) void k_gemm_t128(const GTile *__restrict__ tiles,
                                                           const GOut *__restrict__ outs,
