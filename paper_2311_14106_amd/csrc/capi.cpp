@@ -1,6 +1,7 @@
 // extern "C" boundary of libmdmrg: argument checks, exception -> status.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 
 #include "../../include/mdmrg.h"
 #include "engine.h"
@@ -38,15 +39,19 @@ int mdmrg_create(mdmrg_ctx *out, int device) {
   if (!out) return MDMRG_EINVAL;
   *out = nullptr;
   try {
-    auto *c = new mdmrg_ctx_s();
+    std::unique_ptr<mdmrg_ctx_s> c(new mdmrg_ctx_s());
     c->c.dev = dev_create(device);
     dev_timing_enable(c->c.dev, true);
-    *out = c;
+    *out = c.release();
     return MDMRG_OK;
   } catch (const Error &e) {
     g_err = e.what();
     return e.code;
-  } catch (...) {
+  } catch (const std::bad_alloc &) {
+    g_err = "host allocation failed";
+    return MDMRG_ENOMEM;
+  } catch (const std::exception &e) {
+    g_err = e.what();
     return MDMRG_EDEVICE;
   }
 }
