@@ -24,6 +24,31 @@
 
 namespace mdmrg {
 
+// Device work vectors of one call, freed when the call returns or throws.
+namespace {
+struct DevVecs {
+  Device *d;
+  std::vector<void *> held;
+  explicit DevVecs(Device *dev) : d(dev) {}
+  double *get(int64_t n) {
+    held.reserve(held.size() + 1);
+    double *q = static_cast<double *>(dev_alloc(d, sizeof(double) * size_t(n)));
+    held.push_back(q);
+    return q;
+  }
+  DevVecs(const DevVecs &) = delete;
+  DevVecs &operator=(const DevVecs &) = delete;
+  ~DevVecs() {
+    for (void *q : held) {
+      try {
+        dev_free(d, q);
+      } catch (...) {
+      }
+    }
+  }
+};
+}  // namespace
+
 uint64_t make_key(int kind, const int *e, int n) {
   uint64_t k = uint64_t(kind) | (uint64_t(n) << 4);
   for (int i = 0; i < n; ++i) k |= uint64_t(e[i] + 1) << (8 + 13 * i);
@@ -1638,11 +1663,12 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
   const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
   const int64_t N = psi.n_elem;
   double t0 = wall_seconds();
-  double *V = (double *)dev_alloc(dev, sizeof(double) * N * m_max);
-  double *AV = (double *)dev_alloc(dev, sizeof(double) * N * m_max);
-  double *dg = (double *)dev_alloc(dev, sizeof(double) * N);
-  double *r = (double *)dev_alloc(dev, sizeof(double) * N);
-  double *ax = (double *)dev_alloc(dev, sizeof(double) * N);
+  DevVecs work(dev);
+  double *V = work.get(N * m_max);
+  double *AV = work.get(N * m_max);
+  double *dg = work.get(N);
+  double *r = work.get(N);
+  double *ax = work.get(N);
   heff_diag(dg);
   // start vector
   double nrm;
@@ -1705,14 +1731,14 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
       std::vector<double> y1(nv);
       for (int i = 0; i < nv; ++i) y1[i] = Y[i * nv + 1];
       double *tv = r;  // reuse r as temporary after saving
-      double *tav = (double *)dev_alloc(dev, sizeof(double) * N);
+      DevVecs tmp(dev);
+      double *tav = tmp.get(N);
       dev_lincomb(dev, V, N, nv, y1.data(), 0.0, tv, N);
       dev_lincomb(dev, AV, N, nv, y1.data(), 0.0, tav, N);
       dev_d2d(dev, V, x, sizeof(double) * N);
       dev_d2d(dev, AV, ax, sizeof(double) * N);
       dev_d2d(dev, V + N, tv, sizeof(double) * N);
       dev_d2d(dev, AV + N, tav, sizeof(double) * N);
-      dev_free(dev, tav);
       std::fill(Hs.begin(), Hs.end(), 0.0);
       double h[2];
       dev_multidot(dev, V, N, 2, AV, N, h);
@@ -1764,11 +1790,6 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
   double xn;
   dev_multidot(dev, x, 0, 1, x, N, &xn);
   dev_scale(dev, 1.0 / std::sqrt(xn), x, N);
-  dev_free(dev, V);
-  dev_free(dev, AV);
-  dev_free(dev, dg);
-  dev_free(dev, r);
-  dev_free(dev, ax);
   dev_sync(dev);
   if (energy) *energy = theta;
   if (resid) *resid = rn;
@@ -1796,9 +1817,8 @@ int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_sp
     double nrm = 0.0;
     dev_multidot(dev, x, 0, 1, x, N, &nrm);
     if (nrm > 1e-300 && std::isfinite(nrm)) {
-      double *v = (double *)dev_alloc(dev, sizeof(double) * N);
-      double *a = (double *)dev_alloc(dev, sizeof(double) * N);
-      double *b = (double *)dev_alloc(dev, sizeof(double) * N);
+      DevVecs work(dev);
+      double *v = work.get(N), *a = work.get(N), *b = work.get(N);
       dev_d2d(dev, v, x, sizeof(double) * N);
       dev_scale(dev, 1.0 / std::sqrt(nrm), v, N);
       heff_apply(v, a, prec_split);
@@ -1809,7 +1829,6 @@ int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_sp
       dev_multidot(dev, b, 0, 1, b, N, &h2);
       dev_multidot(dev, v, 0, 1, b, N, &th);
       if (h2 > 0.0 && std::isfinite(d2)) floor = std::sqrt(d2 / h2) * std::fabs(th);
-      for (double *p : {v, a, b}) dev_free(dev, p);
       probe = 1;
     }
   }
