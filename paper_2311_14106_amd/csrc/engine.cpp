@@ -36,6 +36,14 @@ struct DevVecs {
     held.push_back(q);
     return q;
   }
+  void release(double *q) {  // free one vector before the scope ends
+    for (size_t i = 0; i < held.size(); ++i)
+      if (held[i] == q) {
+        held.erase(held.begin() + i);
+        dev_free(d, q);
+        return;
+      }
+  }
   DevVecs(const DevVecs &) = delete;
   DevVecs &operator=(const DevVecs &) = delete;
   ~DevVecs() {
@@ -1911,7 +1919,8 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
     s.base = tot;
     tot += int64_t(off) * off;
   }
-  double *rho = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, tot));
+  DevVecs work(dev);
+  double *rho = work.get(std::max<int64_t>(1, tot));
   dev_zero(dev, rho, sizeof(double) * std::max<int64_t>(1, tot));
   // rho blocks as grouped GEMM (psi in slot 0, rho in slot 1)
   GemmPlan gp;
@@ -1981,7 +1990,6 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
     dev_plan_free(dev, dp);
   }
   // eigen-decomposition per sector
-  double *wdev = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, tot > 0 ? tot : 1));
   std::vector<std::vector<double>> evals(secs.size());
   int64_t woff = 0;
   std::vector<int64_t> wbase(secs.size());
@@ -1989,12 +1997,11 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
     wbase[i] = woff;
     woff += secs[i].M;
   }
-  double *wv = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, woff));
+  double *wv = work.get(std::max<int64_t>(1, woff));
   for (size_t i = 0; i < secs.size(); ++i) dev_syevd(dev, rho + secs[i].base, secs[i].M, wv + wbase[i]);
   std::vector<double> wall(std::max<int64_t>(1, woff));
   dev_d2h(dev, wall.data(), wv, sizeof(double) * woff);
-  dev_free(dev, wdev);
-  dev_free(dev, wv);
+  work.release(wv);
   // global selection: (-lambda, sector qn, index)
   struct Cand {
     double lam;
@@ -2067,7 +2074,7 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
   }
   T.data = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, T.size));
   dev_gather(dev, gb, cols, rho, T.data, dir < 0);
-  dev_free(dev, rho);
+  work.release(rho);
   // install
   const int site = dir > 0 ? l : l + 1;
   if (A[site].data) dev_free(dev, A[site].data);
@@ -2287,7 +2294,8 @@ void Context::sweep(int n_sweeps, const int *Ds, int n_sched, double tol, double
   MDMRG_REQUIRE(n >= 3, -1, "sweep: need at least 3 sites");
   // start at bond (0, 1)
   prepare(0);
-  double *x = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, psi.n_elem));
+  DevVecs vecs(dev);
+  double *x = vecs.get(std::max<int64_t>(1, psi.n_elem));
   dev_randn(dev, x, psi.n_elem, 1);
   double e = 0.0;
   for (int sw = 0; sw < n_sweeps; ++sw) {
@@ -2302,9 +2310,9 @@ void Context::sweep(int n_sweeps, const int *Ds, int n_sched, double tol, double
         const bool last = dir > 0 ? (l == hi - 1) : (l == lo + 1);
         decimate(x, D, dir, nullptr, nullptr, nullptr);
         renormalize(dir);
-        double *xn = (double *)dev_alloc(dev, sizeof(double) * std::max<int64_t>(1, psi.n_elem));
+        double *xn = vecs.get(std::max<int64_t>(1, psi.n_elem));
         stvec(x, prev_l, dir, prev_psi, xn, psi);
-        dev_free(dev, x);
+        vecs.release(x);
         x = xn;
         l = cur;
         if (last) {
@@ -2315,7 +2323,7 @@ void Context::sweep(int n_sweeps, const int *Ds, int n_sched, double tol, double
     }
     if (energies) energies[sw] = e;
   }
-  dev_free(dev, x);
+  vecs.release(x);
   dev_sync(dev);
 }
 
