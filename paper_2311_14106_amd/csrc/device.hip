@@ -121,7 +121,8 @@ constexpr int kRedBlocks = 256;
 constexpr int kMaxDot = 64;
 
 Device *dev_create(int device) {
-  auto *d = new Device();
+  std::unique_ptr<Device> owner(new Device());  // deleted if a set-up call below fails
+  Device *d = owner.get();
   d->id = device;
   HIP_CHECK(hipSetDevice(device));
   // blocking stream: ordered with work that callers queue on the legacy default stream
@@ -135,7 +136,7 @@ Device *dev_create(int device) {
   size_t free_b = 0, total_b = 0;
   HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
   d->budget_bytes = d->budget_default = size_t(0.95 * double(free_b));
-  return d;
+  return owner.release();
 }
 
 void dev_destroy(Device *d) {

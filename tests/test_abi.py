@@ -66,3 +66,16 @@ def test_rotation_rejects_non_orthogonal(lib):
     with pytest.raises(mdmrg.MdmrgError) as e:
         mdmrg.rotate_modes(np.eye(4) * 1.1, T, V, False)
     assert e.value.code == mdmrg.EINVAL
+
+
+def test_create_rejects_a_device_that_does_not_exist(lib):
+    # an ordinal past any machine's device count: the call fails cleanly,
+    # leaves no handle and says why
+    import ctypes
+    from paper_2311_14106_amd import mdmrg
+    h = ctypes.c_void_p(1)
+    st = lib.mdmrg_create(ctypes.byref(h), 1 << 20)
+    assert st == mdmrg.EDEVICE
+    assert h.value is None
+    assert lib.mdmrg_last_error(None).decode().startswith('HIP error')
+    assert lib.mdmrg_create(None, 0) == mdmrg.EINVAL
