@@ -79,3 +79,23 @@ def test_create_rejects_a_device_that_does_not_exist(lib):
     assert h.value is None
     assert lib.mdmrg_last_error(None).decode().startswith('HIP error')
     assert lib.mdmrg_create(None, 0) == mdmrg.EINVAL
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    from paper_2311_14106_amd import mdmrg
+    with pytest.raises(RuntimeError, match='not built'):
+        mdmrg.load(str(tmp_path / 'libmdmrg.so'))
+
+
+def test_product_path_does_not_use_the_oracle():
+    # the package (binding, build, traffic tool, C/HIP sources) never reaches
+    # into oracle/: no import, no path, no fallback
+    pkg = os.path.join(ROOT, 'paper_2311_14106_amd')
+    hits = []
+    for d, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(('.py', '.cpp', '.hip', '.h')):
+                src = open(os.path.join(d, f)).read()
+                if re.search(r'\boracle\b', src):
+                    hits.append(os.path.relpath(os.path.join(d, f), ROOT))
+    assert not hits, hits
