@@ -17,7 +17,7 @@ momentum basis rotated inside degenerate shells, dense two-body integrals)
 instead; --keep-envs 0 keeps only the block environments in use (large D).
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
-this build runs on one GPU.
+the benchmark runs on one GPU.
 """
 import argparse
 import json
@@ -253,7 +253,7 @@ def main():
     if args.profile_D is None:
         args.profile_D = 128 if args.workload == 'hubbard6x6' else 64
     if args.gpus != 1:
-        print(f'bench.py: --gpus {args.gpus} is not supported; this build runs on exactly one GPU '
+        print(f'bench.py: --gpus {args.gpus} is not supported; the benchmark runs on exactly one GPU '
               f'(run with --gpus 1)', file=sys.stderr)
         sys.exit(2)
 

@@ -52,7 +52,7 @@ enum {
   MDMRG_EDEVICE = -3,  /* HIP / rocSOLVER error, or NaN detected on device  */
   MDMRG_ESTATE = -4,   /* call out of order (no Hamiltonian, no MPS, ...)   */
   MDMRG_ENOCONV = -5,  /* Davidson reached max_iter; best estimate returned */
-  MDMRG_EUNSUP = -6    /* valid request this build does not implement       */
+  MDMRG_EUNSUP = -6    /* valid request the library does not implement      */
 };
 
 enum { MDMRG_MODEL_SPINLESS = 0, MDMRG_MODEL_HUBBARD = 1 };
