@@ -250,6 +250,11 @@ def decimate(mps, l, x, D, direction, tie_tol=1e-10):
     """
     ch = mps.chain
     layout, _ = psi_layout(mps, l)
+    # rho is the density matrix of the normalised state (trace 1), so that
+    # the weights, the truncation error and the entropies do not depend on
+    # the scale of x
+    norm2 = float(np.dot(x, x))
+    assert norm2 > 0.0, 'decimate: zero vector'
     rows = {}   # sector -> list of row keys
     cols = {}
     blocks = []
@@ -290,7 +295,7 @@ def decimate(mps, l, x, D, direction, tie_tol=1e-10):
             i = rows[Q].index(rk)
             j = cols[Q].index(ck)
             M[ro[i]:ro[i + 1], co[j]:co[j + 1]] = blk
-        rho = M @ M.T
+        rho = M @ M.T / norm2
         w, v = np.linalg.eigh(rho)
         w = w[::-1]
         v = v[:, ::-1]

@@ -189,7 +189,8 @@ def test_decimation_keeps_exact_state_and_reports_truncation():
     prob2 = dmrg.TwoSiteProblem(mps2, l + 1)
     x2 = dmrg.start_vector(prob, x, prob2)
     assert np.abs(prob2.to_full(x2) - full).max() < 1e-12
-    # truncating: error equals the discarded weight and S_1/2 >= S_vN
+    # truncating leaves a positive error below 1 and S_1/2 >= S_vN (the
+    # exact values on known spectra are pinned in test_oracle_decimation.py)
     nb, t, trunc, svn, shalf, tie = dmrg.decimate(mps, l, x, 3, +1)
     assert 0.0 < trunc < 1.0
     assert shalf >= svn - 1e-12
