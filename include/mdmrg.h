@@ -61,12 +61,18 @@ enum { MDMRG_FP64 = 0, MDMRG_FP32 = 1, MDMRG_BF16X3 = 2 };
 
 /* ---------------------------------------------------------------- context */
 
-/* Create a context on HIP device `device` with its own (default-priority)
- * stream.  *out receives the handle; on failure *out is NULL.  The context
- * may hold up to 95% of the device memory free at this call (see
+/* Create a context on HIP device `device` (the device that runs the
+ * effective-Hamiltonian products of the DMRG steps, Sec. II.A and III.B).
+ * hip_stream: the caller's hipStream_t on that device (for instance the
+ * stream of a torch.cuda.Stream), on which every device call of the context
+ * is then queued; the caller keeps ownership and must not destroy it before
+ * mdmrg_destroy.  NULL: the context creates a blocking, default-priority
+ * stream of its own.  *out receives the handle; on failure *out is NULL and
+ * mdmrg_last_error(NULL) says why (EINVAL for a stream of another device).
+ * The context may hold up to 95% of the device memory free at this call (see
  * MDMRG_OPT_MEMORY_BUDGET); a call that would need more fails with
  * MDMRG_ENOMEM. */
-int mdmrg_create(mdmrg_ctx *out, int device);
+int mdmrg_create(mdmrg_ctx *out, int device, void *hip_stream);
 /* Release every device and host resource of the context.  NULL is a no-op. */
 void mdmrg_destroy(mdmrg_ctx ctx);
 /* Context-owned, NUL-terminated text of the last error ("" if none). */
@@ -109,18 +115,21 @@ int mdmrg_set_hamiltonian(mdmrg_ctx ctx, int n_sites, int spin_half, const doubl
                           const double *V, int target_a, int target_b);
 
 /* Same with V in coordinate form: nnz entries (p,q,r,s) = ijkl[4*e..4*e+3],
- * value val[e]; repeated entries add up. */
+ * value val[e]; repeated entries add up (the sparse interaction lists of
+ * the lattice models of Eq. (2)-(3)).  Same validation as the dense form,
+ * plus EINVAL for an index outside [0, nso). */
 int mdmrg_set_hamiltonian_coo(mdmrg_ctx ctx, int n_sites, int spin_half, const double *T,
                               int64_t nnz, const int32_t *ijkl, const double *val,
                               int target_a, int target_b);
 
-/* Number of operator terms of the canonical (antisymmetrised) Hamiltonian. */
+/* Number of operator terms of the canonical (antisymmetrised) form of the
+ * Hamiltonian of Eq. (1) set last: one-body and two-body strings. */
 int mdmrg_n_terms(mdmrg_ctx ctx, int64_t *n_one_body, int64_t *n_two_body);
 
 /* ------------------------------------------------------------------- MPS */
 
-/* Load an MPS in the exchange format above.  n_sect[n+1] sector counts per
- * bond; sect_qn[2*S] and sect_dim[S] for all S sectors of all bonds in bond
+/* Load an MPS (Eq. (4), Sec. II.B) in the exchange format above.
+ * n_sect[n+1] sector counts per bond; sect_qn[2*S] and sect_dim[S] for all S sectors of all bonds in bond
  * order; data = site tensors (n_data doubles).  Sites left of the bond later
  * prepared are used as left isometries, sites right of it as right
  * isometries. */
@@ -136,7 +145,9 @@ int mdmrg_set_mps(mdmrg_ctx ctx, const int32_t *n_sect, const int32_t *sect_qn,
  * vector, not in the tensors. */
 int mdmrg_get_mps(mdmrg_ctx ctx, double *data, int64_t n_data, int64_t *n_needed);
 
-/* Sector list of bond i: query with qn = dim = NULL to get *n_sect. */
+/* Sector list of bond i of the MPS (Eq. (4): the quantum-number blocks of
+ * the bond index, dimensions D_i split by sector): query with
+ * qn = dim = NULL to get *n_sect. */
 int mdmrg_get_bond(mdmrg_ctx ctx, int bond, int32_t *n_sect, int32_t *qn, int32_t *dim);
 
 /* ------------------------------------------------------------------- bond */
@@ -184,17 +195,26 @@ int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value);
 /* Make bond (l, l+1) current: build (on the device) the renormalised
  * operators of the left block (sites < l) and the right block
  * (sites > l+1) from the MPS by repeated renormalisation (Sec. II.A), then
- * the "Tables" of the step: sector lists, the wave-function layout and the
- * task lists of the effective Hamiltonian. */
+ * the "Tables" of the step (Sec. III.B, the overhead category of Fig. 7):
+ * sector lists, the wave-function layout and the task lists of the
+ * effective Hamiltonian.  EINVAL if l + 1 is not a site, ESTATE without a
+ * Hamiltonian and an MPS, ENOMEM if the operators exceed the budget. */
 int mdmrg_prepare_bond(mdmrg_ctx ctx, int l);
 
-/* Layout of the current two-site vector.  *n_elem = total doubles,
+/* Layout of the current two-site vector (the wave function of the local
+ * two-site optimisation step, Sec. II.A).  *n_elem = total doubles,
  * *n_blk = number of blocks; if desc != NULL it receives 8 int32 per block:
  * (a, s1, s2, b, m_a, m_b, offset_lo, offset_hi). */
 int mdmrg_psi_layout(mdmrg_ctx ctx, int64_t *n_elem, int32_t *n_blk, int32_t *desc);
 
-/* y = H_eff x at the current bond (x, y: caller-owned device buffers of
- * n_elem doubles, must not alias).  prec MDMRG_FP64 is the plain form;
+/* y = H_eff x at the current bond: the product of the effective
+ * Hamiltonian, built from the renormalised block operators of the left and
+ * right blocks and the two site operators with the integrals of Eq. (1),
+ * with a two-site vector (Sec. II.A; the Diag_H work of Sec. III.B, Fig. 8).
+ * x, y: caller-owned device buffers of n_elem doubles on the context's
+ * device, layout of mdmrg_psi_layout, must not alias (EINVAL); the library
+ * cannot check their length, so a shorter buffer is read or written past its
+ * end.  ESTATE without a current bond.  prec MDMRG_FP64 is the plain form;
  * MDMRG_FP32 (split form) runs every GEMM on FP32 shadows of the operators
  * and of x with FP32 MFMA accumulation, y returned in FP64; MDMRG_BF16X3
  * (split form) reads the same FP32 shadows and forms every product from
@@ -203,10 +223,13 @@ int mdmrg_psi_layout(mdmrg_ctx ctx, int64_t *n_elem, int32_t *n_blk, int32_t *de
  * per operand, BF16 MFMA rate), y returned in FP64.  Other values: EUNSUP. */
 int mdmrg_heff_apply(mdmrg_ctx ctx, int prec, const double *x, double *y);
 
-/* Diagonal of H_eff at the current bond into device buffer d. */
+/* Diagonal of H_eff at the current bond (Sec. II.A; the preconditioner of
+ * the Davidson iteration) into the caller-owned device buffer d of n_elem
+ * doubles.  ESTATE without a current bond. */
 int mdmrg_heff_diag(mdmrg_ctx ctx, double *d);
 
-/* Cost of one H_eff x at the current bond: algorithmic FLOP (sum over GEMM
+/* Cost of one H_eff x at the current bond (the complexity measure of
+ * Sec. III.A, counted in FLOP): algorithmic FLOP (sum over GEMM
  * tasks of 2mnk in the chosen order, no padding, identity products not
  * counted), algorithmic bytes (each distinct operand block read once, each
  * output block written once, intermediates written and read once), the
@@ -214,23 +237,31 @@ int mdmrg_heff_diag(mdmrg_ctx ctx, double *d);
  * pointer may be NULL. */
 int mdmrg_heff_cost(mdmrg_ctx ctx, double *flop, double *bytes, int64_t *n_terms, int64_t *n_gemm);
 
-/* Shape profile of one H_eff x at the current bond (the workload shape the
+/* Shape profile of one H_eff x at the current bond (Sec. III.B: the block
+ * sizes that decide the GPU efficiency; the workload shape the
  * grouped kernels see): algorithmic FLOP of its GEMMs binned by the smaller
  * output side min(m, n), bins [1,16) [16,32) [32,48) [48,64) [64,128)
  * [128,256) [256,512) [512,inf); flop_by_bin must hold 8 doubles.  Sums to
  * the FLOP of mdmrg_heff_cost.  ESTATE before mdmrg_prepare_bond. */
 int mdmrg_heff_histogram(mdmrg_ctx ctx, double *flop_by_bin);
 
-/* Davidson for the lowest eigenpair of H_eff (Sec. II.A), FP64 on device.
- * x (device, n_elem) holds the start vector on entry (normalised inside; if
- * zero, a seeded random vector is used) and the eigenvector on exit.
- * Stops at ||H x - theta x||_2 <= tol with ||x|| = 1.  Returns ENOCONV
- * after max_iter matrix-vector products with the best estimate in
- * *energy / x.  m_max: subspace size before a thick restart to 2 vectors. */
+/* Davidson for the lowest eigenpair of H_eff (the iterative
+ * diagonalisation of the effective Hamiltonian in each local step,
+ * Sec. II.A; its convergence threshold is the epsilon of Sec. III.A-B),
+ * FP64 on device.  x (device, n_elem) holds the start vector on entry
+ * (normalised inside; if zero, a seeded random vector is used) and the
+ * eigenvector on exit.  Stops at ||H x - theta x||_2 <= tol with
+ * ||x|| = 1.  Returns ENOCONV, with the best estimate in *energy / x, after
+ * max_iter matrix-vector products or when the subspace admits no new
+ * direction before tol is reached.  EDEVICE if the start vector or the
+ * residual is not finite (NaN / Inf in x or in the operators).
+ * m_max in [3, 60]: subspace size before a thick restart to 2 vectors. */
 int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max,
                    double *energy, double *resid, int *n_matvec);
 
-/* Mixed-precision Davidson: a Davidson solve whose products use the split
+/* Mixed-precision Davidson (the products beyond the FP64 ceiling of Sec. IV
+ * and Fig. 2, with the final eigenpair held to FP64 accuracy): a Davidson
+ * solve whose products use the split
  * form prec_split (MDMRG_FP32 or MDMRG_BF16X3) until its residual reaches
  * tol_split or stops decreasing (no 10% gain over 24 products, or over 4
  * once within 2f), then an FP64 Davidson from that vector until the FP64
@@ -242,37 +273,54 @@ int mdmrg_davidson_mixed(mdmrg_ctx ctx, double *x, double tol, int prec_split, d
                          int max_iter, int m_max, double *energy, double *resid, int *n_mv64,
                          int *n_mv_split);
 
-/* Reduced-density-matrix truncation of the two-site vector x (Diag_D):
+/* Reduced-density-matrix truncation of the two-site vector x (the Diag_D
+ * category of Sec. III.B; the bond dimension D of Sec. II.A):
  * direction +1 replaces site l by a left isometry and bond l+1 by the kept
  * states of the left enlarged block; -1 replaces site l+1 by a right
- * isometry.  Keeps min(D, available) states ranked by eigenvalue.  Outputs
- * truncation error, von Neumann and half-Renyi entropies (any may be NULL). */
+ * isometry.  rho is the density matrix of the normalised state
+ * x / |x| (trace 1), so any nonzero scale of x gives the same result; EINVAL
+ * for a zero x, EDEVICE for a non-finite one.  Keeps min(D, available) states
+ * ranked by eigenvalue.  Outputs truncation error (discarded weight), von
+ * Neumann entropy -Tr rho ln rho and half-Renyi entropy 2 ln Tr sqrt(rho)
+ * (Sec. II.B), any may be NULL. */
 int mdmrg_decimate(mdmrg_ctx ctx, const double *x, int D, int direction, double *trunc_err,
                    double *s_vn, double *s_half);
 
-/* Renormalisation (Ren_l / Ren_r): after mdmrg_decimate(direction) at bond
+/* Renormalisation (the renormalised block operators of Sec. II.A; Ren_l /
+ * Ren_r of Sec. III.B): after mdmrg_decimate(direction) at bond
  * (l, l+1), build on the device every operator of the grown block (left
  * block of sites <= l for +1, right block of sites >= l+1 for -1) from the
  * new isometry, then make bond (l+direction, l+direction+1) current
- * (as mdmrg_prepare_bond).  ESTATE if the last call at this bond was not
- * mdmrg_decimate with the same direction. */
-int mdmrg_renormalize(mdmrg_ctx ctx, int direction);
+ * (as mdmrg_prepare_bond).  prec selects the arithmetic of the
+ * renormalisation GEMMs: MDMRG_FP64 (plain); MDMRG_FP32 or MDMRG_BF16X3
+ * (split forms, as in mdmrg_heff_apply, on FP32 copies of the source
+ * operators and the isometry, FP32 accumulation).  The new operators are
+ * stored as FP64 either way; a split form perturbs them at its rounding
+ * level (about 1e-7 relative for FP32, 1e-5 for 3xBF16), a first-order
+ * change of H_eff that later FP64 products do not remove.  Other prec:
+ * EUNSUP.  ESTATE if the last call at this bond was not mdmrg_decimate with
+ * the same direction. */
+int mdmrg_renormalize(mdmrg_ctx ctx, int direction, int prec);
 
-/* Start vector of the new current bond (StVec): x_new (n_elem of the new
+/* Start vector of the new current bond (the StVec category of Sec. III.B):
+ * x_new (n_elem of the new
  * layout) = the two-site vector x_old of the previous bond (its layout)
  * written in the new basis,  psi' = P'^T P psi.  Valid right after
  * mdmrg_renormalize; x_old and x_new are caller-owned device buffers. */
 int mdmrg_stvec(mdmrg_ctx ctx, const double *x_old, double *x_new);
 
-/* Finite two-site sweeps from the current MPS (a right then a left
- * half-sweep per sweep), bond dimension D_schedule[min(k, n_sched-1)] in
- * sweep k, Davidson tolerance tol.  energies receives the final energy of
- * each sweep (n_sweeps doubles, may be NULL). */
+/* Finite two-site DMRG sweeps (Sec. II.A) from the current MPS (a right
+ * then a left half-sweep per sweep), bond dimension
+ * D_schedule[min(k, n_sched-1)] in sweep k, Davidson tolerance tol, FP64
+ * throughout.  energies receives the final energy of each sweep (n_sweeps
+ * doubles, may be NULL).  Returns ENOCONV after completing the sweeps if a
+ * Davidson solve missed tol (mdmrg_last_error gives the count). */
 int mdmrg_sweep(mdmrg_ctx ctx, int n_sweeps, const int *D_schedule, int n_sched, double tol,
                 double *energies);
 
 /* The grouped sector-block GEMM that carries every dense contraction of the
- * path (H_eff products, renormalisation, density matrices), exposed for
+ * path (H_eff products, renormalisation, density matrices: the block
+ * operations distributed over GPUs in Sec. III.B, Fig. 7), exposed for
  * direct use.  For each output o (8 int64 per output:
  * slot, offset, m, n, ldc, seg_begin, seg_count, accumulate):
  *   C_o = (accumulate ? C_o : 0) + sum_{s in segments of o} alpha[s] op(A_s) op(B_s)
@@ -289,7 +337,8 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
                        const double *alpha);
 
 /* The same grouped GEMM in a split-precision form (the arithmetic of the
- * split H_eff products, the FP32 / 3xBF16 forms of the a4 step): every
+ * split H_eff products: the products beyond the FP64 ceiling of Sec. IV and
+ * Fig. 2, in FP32 or 3xBF16): every
  * buffer holds FP32 elements (base_len[i] floats, offsets in floats), alpha
  * is rounded to FP32 and folded into op(A) before the product, results are
  * FP32.  prec MDMRG_FP32: FP32 MFMA products and accumulation.  prec
@@ -302,7 +351,7 @@ int mdmrg_gemm_grouped_split(mdmrg_ctx ctx, int prec, int n_bases, const float *
                              const int64_t *seg_desc, const double *alpha);
 
 /* Wall seconds per step category (Diag_H, Ren, Tables, Diag_D, StVec,
- * Other) accumulated since creation, the algorithmic FLOP of all H_eff
+ * Other: the categories of Sec. III.B, Fig. 7) accumulated since creation, the algorithmic FLOP of all H_eff
  * products, and HIP-event timings of the grouped-GEMM kernel launches on the
  * context stream; out must hold MDMRG_N_STATS (72) doubles:
  * [diag_h, ren, tables, diag_d, stvec, other, heff_flop, n_matvec,

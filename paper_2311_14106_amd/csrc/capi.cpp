@@ -35,12 +35,12 @@ extern "C" {
 
 const char *mdmrg_version(void) { return "mdmrg 0.1 (gfx950)"; }
 
-int mdmrg_create(mdmrg_ctx *out, int device) {
+int mdmrg_create(mdmrg_ctx *out, int device, void *hip_stream) {
   if (!out) return MDMRG_EINVAL;
   *out = nullptr;
   try {
     std::unique_ptr<mdmrg_ctx_s> c(new mdmrg_ctx_s());
-    c->c.dev = dev_create(device);
+    c->c.dev = dev_create(device, hip_stream);
     dev_timing_enable(c->c.dev, true);
     *out = c.release();
     return MDMRG_OK;
@@ -352,10 +352,12 @@ int mdmrg_decimate(mdmrg_ctx ctx, const double *x, int D, int direction, double 
   });
 }
 
-int mdmrg_renormalize(mdmrg_ctx ctx, int direction) {
+int mdmrg_renormalize(mdmrg_ctx ctx, int direction, int prec) {
   if (!ctx) return MDMRG_EINVAL;
   return guarded(ctx, [&] {
-    ctx->c.renormalize(direction);
+    MDMRG_REQUIRE(prec == MDMRG_FP64 || prec == MDMRG_FP32 || prec == MDMRG_BF16X3, MDMRG_EUNSUP,
+                  "renormalize: unknown precision form");
+    ctx->c.renormalize(direction, prec);
     return MDMRG_OK;
   });
 }
@@ -373,10 +375,7 @@ int mdmrg_stvec(mdmrg_ctx ctx, const double *x_old, double *x_new) {
 
 int mdmrg_sweep(mdmrg_ctx ctx, int n_sweeps, const int *D_schedule, int n_sched, double tol, double *energies) {
   if (!ctx || !D_schedule) return MDMRG_EINVAL;
-  return guarded(ctx, [&] {
-    ctx->c.sweep(n_sweeps, D_schedule, n_sched, tol, energies);
-    return MDMRG_OK;
-  });
+  return guarded(ctx, [&] { return ctx->c.sweep(n_sweeps, D_schedule, n_sched, tol, energies); });
 }
 
 // Descriptor check and launch shared by the FP64 and FP32-buffer forms of

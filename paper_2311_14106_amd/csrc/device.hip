@@ -28,6 +28,7 @@ namespace mdmrg {
 struct Device {
   int id = 0;
   hipStream_t stream = nullptr;
+  bool own_stream = true;  // false: the caller's stream, not destroyed here
   rocblas_handle blas = nullptr;
   double *red = nullptr;       // reduction partials
   double *red_out = nullptr;   // reduction results (device)
@@ -120,13 +121,23 @@ double wall_seconds() {
 constexpr int kRedBlocks = 256;
 constexpr int kMaxDot = 64;
 
-Device *dev_create(int device) {
+Device *dev_create(int device, void *stream) {
   std::unique_ptr<Device> owner(new Device());  // deleted if a set-up call below fails
   Device *d = owner.get();
   d->id = device;
   HIP_CHECK(hipSetDevice(device));
-  // blocking stream: ordered with work that callers queue on the legacy default stream
-  HIP_CHECK(hipStreamCreate(&d->stream));
+  if (stream) {
+    // the caller's stream (it keeps ownership); its device must be ours
+    d->stream = static_cast<hipStream_t>(stream);
+    d->own_stream = false;
+    int sdev = -1;
+    HIP_CHECK(hipStreamGetDevice(d->stream, &sdev));
+    MDMRG_REQUIRE(sdev == device, -1, "mdmrg_create: the stream belongs to another device");
+  } else {
+    // blocking stream: ordered with work that callers queue on the legacy default stream
+    HIP_CHECK(hipStreamCreate(&d->stream));
+    d->own_stream = true;
+  }
   if (rocblas_create_handle(&d->blas) != rocblas_status_success) throw Error(-3, "rocblas_create_handle failed");
   rocblas_set_stream(d->blas, d->stream);
   HIP_CHECK(hipMalloc(&d->red, sizeof(double) * kRedBlocks * kMaxDot));
@@ -158,7 +169,7 @@ void dev_destroy(Device *d) {
   (void)hipFree(d->info);
   if (d->syevd_work) (void)hipFree(d->syevd_work);
   if (d->blas) rocblas_destroy_handle(d->blas);
-  (void)hipStreamDestroy(d->stream);
+  if (d->own_stream) (void)hipStreamDestroy(d->stream);
   delete d;
 }
 
@@ -213,19 +224,22 @@ size_t dev_free_bytes(Device *d) {
 }
 
 // ------------------------------------------------------------------ zero
-__global__ void k_zero(double *x, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = 0.0;
+// Zero fill of n8 doubles followed by `tail` (< 8) single bytes.
+__global__ void k_zero(double *x, int64_t n8, int tail) {
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < n8; i += (int64_t)gridDim.x * blockDim.x) x[i] = 0.0;
+  if (i0 < tail) reinterpret_cast<unsigned char *>(x + n8)[i0] = 0;
 }
 void dev_zero(Device *d, void *dst, size_t bytes) {
-  // a fill kernel (not a memset node) so that callers may capture it
-  int64_t n = int64_t(bytes / 8);
-  if (n > 0) {
-    int grid = int(std::min<int64_t>((n + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, d->stream, (double *)dst, n);
-    HIP_CHECK(hipGetLastError());
-  }
-  if (bytes % 8) HIP_CHECK(hipMemsetAsync((char *)dst + n * 8, 0, bytes % 8, d->stream));
+  // every byte by a fill kernel, never a memset node, so that the call may
+  // sit inside a captured graph (an FP32 vector of odd length ends in a
+  // 4-byte tail)
+  const int64_t n = int64_t(bytes / 8);
+  const int tail = int(bytes % 8);
+  if (n == 0 && tail == 0) return;
+  const int grid = int(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)));
+  hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, d->stream, (double *)dst, n, tail);
+  HIP_CHECK(hipGetLastError());
 }
 
 // ------------------------------------------- grouped GEMM (FP64 and FP32)

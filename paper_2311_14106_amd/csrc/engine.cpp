@@ -731,13 +731,40 @@ static void renorm_execute(Context &C, bool left, int site, OpSet &Bp, const OpS
     plan.flop += direct.flop;
   }
   C.ensure_scratch(plan.scratch);
-  Bases b{};
-  for (int i = 0; i < kSlots; ++i) b.p[i] = Bp.arena;
-  b.p[1] = Bp.arena;
-  b.p[3] = env.arena;
-  b.p[5] = combo && combo->arena ? combo->arena : Bp.arena;
-  b.p[6] = T.data;
-  C.run_plan(plan, b, 2);
+  if (C.ren_prec == 0) {
+    Bases b{};
+    for (int i = 0; i < kSlots; ++i) b.p[i] = Bp.arena;
+    b.p[1] = Bp.arena;
+    b.p[3] = env.arena;
+    b.p[5] = combo && combo->arena ? combo->arena : Bp.arena;
+    b.p[6] = T.data;
+    C.run_plan(plan, b, 2);
+  } else {
+    // split-precision renormalisation: the same plan on FP32 copies of the
+    // source operators and of the site tensor (FP32 or 3xBF16 products, FP32
+    // accumulation); the new operators are stored back as FP64 masters, so
+    // every later step reads them as usual.  The new arena is all zero at
+    // this point, so converting the FP32 result overwrites nothing.
+    DevVecs tmp(C.dev);
+    auto f32 = [&](const double *src, int64_t n) -> float * {
+      float *f = reinterpret_cast<float *>(tmp.get((std::max<int64_t>(1, n) + 1) / 2));
+      if (n > 0) dev_d2f(C.dev, src, f, n);
+      return f;
+    };
+    float *env32 = f32(env.arena, env.arena_size);
+    float *T32 = f32(T.data, T.size);
+    float *combo32 = combo && combo->arena ? f32(combo->arena, combo->arena_size) : nullptr;
+    float *out32 = reinterpret_cast<float *>(tmp.get((std::max<int64_t>(1, Bp.arena_size) + 1) / 2));
+    dev_zero(C.dev, out32, sizeof(float) * std::max<int64_t>(1, Bp.arena_size));
+    Bases b{};
+    for (int i = 0; i < kSlots; ++i) b.p[i] = reinterpret_cast<double *>(out32);
+    b.p[3] = reinterpret_cast<double *>(env32);
+    if (combo32) b.p[5] = reinterpret_cast<double *>(combo32);
+    b.p[6] = reinterpret_cast<double *>(T32);
+    C.run_plan(plan, b, 2, C.ren_prec);
+    dev_f2d(C.dev, out32, Bp.arena, Bp.arena_size);
+    dev_sync(C.dev);  // the FP32 copies are freed at scope end
+  }
   plan.release(C.dev);
 }
 
@@ -1781,7 +1808,11 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
         dev_lincomb(dev, V, N, nv, c.data(), 1.0, t, N);
       }
       dev_multidot(dev, t, 0, 1, t, N, &tn);
-      if (!(tn > 1e-28)) break;
+      if (!(tn > 1e-28)) {
+        // no new direction: the subspace is exhausted before tol was reached
+        status = -5;
+        break;
+      }
     }
     dev_scale(dev, 1.0 / std::sqrt(tn), t, N);
     heff_apply(t, AV + int64_t(nv) * N, prec);
@@ -1861,6 +1892,14 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
   double t0 = wall_seconds();
   const int l = cur, d = ham.d;
   const Bond &ba = bonds[l], &bb = bonds[l + 2];
+  {
+    // |x|^2 = tr(rho): refuse a zero or non-finite vector before any
+    // eigensolver sees it
+    double nx = 0.0;
+    dev_multidot(dev, x, 0, 1, x, psi.n_elem, &nx);
+    MDMRG_REQUIRE(std::isfinite(nx), -3, "decimate: x is not finite");
+    MDMRG_REQUIRE(nx > 0.0, -1, "decimate: zero vector");
+  }
   // enlarged-block sectors and their row lists
   struct Sec {
     QN q;
@@ -2017,9 +2056,15 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
     return a.k > b.k;
   });
   const int keep = std::min<int>(D, int(cand.size()));
+  // weights of the normalised state: rho / tr(rho), tr(rho) = |x|^2, so the
+  // truncation error and the entropies do not depend on the scale of x
+  double tr = 0.0;
+  for (const Cand &c : cand) tr += std::max(0.0, c.lam);
+  MDMRG_REQUIRE(std::isfinite(tr), -3, "decimate: non-finite density matrix");
+  MDMRG_REQUIRE(tr > 0.0, -1, "decimate: zero vector");
   double kept = 0.0, sv = 0.0, sh = 0.0;
   for (size_t i = 0; i < cand.size(); ++i) {
-    const double p = std::max(0.0, cand[i].lam);
+    const double p = std::max(0.0, cand[i].lam) / tr;
     if (int(i) < keep) kept += p;
     if (p > 1e-14) {  // numerical rank: rounding-level eigenvalues excluded
       sv -= p * std::log(p);
@@ -2263,18 +2308,26 @@ void Context::stvec(const double *x_old, int l, int dir, const PsiLayout &ol, do
   stats.t_stvec += wall_seconds() - t0;
 }
 
-void Context::renormalize(int dir) {
+void Context::renormalize(int dir, int prec) {
+  MDMRG_REQUIRE(prec >= 0 && prec < kPrecs, -6, "renormalize: unknown precision form");
   MDMRG_REQUIRE(cur >= 0 && last_decimated == dir && (dir == 1 || dir == -1), -4,
                 "renormalize: call decimate at the current bond with the same direction first");
   const int l = cur, n = ham.n;
   const int nl = l + dir;
   MDMRG_REQUIRE(nl >= 0 && nl + 1 < n, -1, "renormalize: no bond beyond the chain end");
   double t0 = wall_seconds();
-  if (dir > 0) {
-    if (!Lenv[l + 1]) Lenv[l + 1] = renorm_left(*Lenv[l], l);
-  } else {
-    if (!Renv[l + 1]) Renv[l + 1] = renorm_right(*Renv[l + 2], l + 1);
+  ren_prec = prec;
+  try {
+    if (dir > 0) {
+      if (!Lenv[l + 1]) Lenv[l + 1] = renorm_left(*Lenv[l], l);
+    } else {
+      if (!Renv[l + 1]) Renv[l + 1] = renorm_right(*Renv[l + 2], l + 1);
+    }
+  } catch (...) {
+    ren_prec = 0;
+    throw;
   }
+  ren_prec = 0;
   // no wait here: the host part of the next bond's Tables step overlaps
   // these launches (its first plan upload waits for the stream), so Ren
   // counts the host side of the renormalisation and Tables the rest
@@ -2287,7 +2340,7 @@ void Context::renormalize(int dir) {
 }
 
 // ------------------------------------------------------------- sweeps
-void Context::sweep(int n_sweeps, const int *Ds, int n_sched, double tol, double *energies) {
+int Context::sweep(int n_sweeps, const int *Ds, int n_sched, double tol, double *energies) {
   MDMRG_REQUIRE(have_ham && have_mps, -4, "sweep: Hamiltonian and MPS required");
   MDMRG_REQUIRE(n_sweeps >= 1 && n_sched >= 1, -1, "sweep: bad schedule");
   const int n = ham.n;
@@ -2298,6 +2351,7 @@ void Context::sweep(int n_sweeps, const int *Ds, int n_sched, double tol, double
   double *x = vecs.get(std::max<int64_t>(1, psi.n_elem));
   dev_randn(dev, x, psi.n_elem, 1);
   double e = 0.0;
+  int not_converged = 0;
   for (int sw = 0; sw < n_sweeps; ++sw) {
     const int D = Ds[std::min(sw, n_sched - 1)];
     for (int dir : {1, -1}) {
@@ -2306,7 +2360,7 @@ void Context::sweep(int n_sweeps, const int *Ds, int n_sched, double tol, double
       while (true) {
         double res;
         int nmv;
-        davidson(x, tol, 200, 24, &e, &res, &nmv);
+        if (davidson(x, tol, 200, 24, &e, &res, &nmv) != 0) ++not_converged;
         const bool last = dir > 0 ? (l == hi - 1) : (l == lo + 1);
         decimate(x, D, dir, nullptr, nullptr, nullptr);
         renormalize(dir);
@@ -2325,6 +2379,10 @@ void Context::sweep(int n_sweeps, const int *Ds, int n_sched, double tol, double
   }
   vecs.release(x);
   dev_sync(dev);
+  // every bond was still decimated and the sweep completed; a Davidson solve
+  // that missed tol makes the sweep report ENOCONV
+  if (not_converged) err = "sweep: " + std::to_string(not_converged) + " Davidson solve(s) did not reach tol";
+  return not_converged ? -5 : 0;
 }
 
 }  // namespace mdmrg

@@ -224,13 +224,17 @@ struct Context {
   void decimate(const double *x, int D, int dir, double *trunc, double *svn, double *shalf);
   void stvec(const double *x_old, int l_old, int dir, const PsiLayout &old_layout, double *x_new,
              const PsiLayout &new_layout);
-  // after decimate(dir): environment of the grown block, then bond l+dir
-  void renormalize(int dir);
+  // after decimate(dir): environment of the grown block, then bond l+dir;
+  // prec 0 FP64, 1 FP32, 2 3xBF16 products for that block's GEMMs (the
+  // operators are stored as FP64 either way)
+  void renormalize(int dir, int prec = 0);
+  int ren_prec = 0;  // precision form of the renormalisation GEMMs in progress
   int last_decimated = 0;  // direction of the last decimation at the current bond (0 = none)
   int prev_l = -1, prev_dir = 0;
   PsiLayout prev_psi;
   PsiLayout make_layout(int l) const;
-  void sweep(int n_sweeps, const int *D, int n_sched, double tol, double *energies);
+  // 0, or -5 (ENOCONV) when a Davidson solve of the sweep missed tol
+  int sweep(int n_sweeps, const int *D, int n_sched, double tol, double *energies);
   void ensure_scratch(int64_t n);
   void run_plan(const TwoPhasePlan &p, Bases &b, int tag = 0, int prec = 0);
 };

@@ -106,7 +106,9 @@ struct DiagTask {
 
 // -------------------------------------------------------------- device layer
 struct Device;
-Device *dev_create(int device);
+// stream: the caller's HIP stream (not owned), or nullptr for a stream of
+// the context's own
+Device *dev_create(int device, void *stream);
 void dev_destroy(Device *);
 void *dev_alloc(Device *, size_t bytes);  // throws Error(ENOMEM)
 void dev_free(Device *, void *);

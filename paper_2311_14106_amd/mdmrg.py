@@ -26,7 +26,7 @@ _c_i64_p = ctypes.POINTER(ctypes.c_int64)
 
 EXPORTS = {
     'mdmrg_version': (ctypes.c_char_p, []),
-    'mdmrg_create': (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
+    'mdmrg_create': (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p]),
     'mdmrg_destroy': (None, [ctypes.c_void_p]),
     'mdmrg_last_error': (ctypes.c_char_p, [ctypes.c_void_p]),
     'mdmrg_lattice_nso': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
@@ -54,7 +54,7 @@ EXPORTS = {
                                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     'mdmrg_decimate': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                       _c_dbl_p, _c_dbl_p, _c_dbl_p]),
-    'mdmrg_renormalize': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    'mdmrg_renormalize': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     'mdmrg_stvec': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     'mdmrg_sweep': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_i32_p, ctypes.c_int, ctypes.c_double,
                                    _c_dbl_p]),
@@ -106,12 +106,22 @@ def _ip(a):
     return a.ctypes.data_as(_c_i32_p)
 
 
-def _ptr(t):
-    """Device pointer of a torch tensor (or a raw integer address)."""
-    if isinstance(t, int):
-        return ctypes.c_void_p(t)
-    if isinstance(t, np.ndarray):
-        return ctypes.c_void_p(t.ctypes.data)
+def device_ptr(t, device, numel, dtype='torch.float64', what='buffer'):
+    """Pointer of a device buffer after the checks the C ABI cannot make: a
+    contiguous torch tensor on HIP device `device`, of element type `dtype`
+    and `numel` elements (None: any length).  Raises ValueError otherwise, so
+    that a host array, a tensor on another device, a strided view, a wrong
+    element type or a short buffer never reaches a kernel."""
+    if isinstance(t, np.ndarray) or not hasattr(t, 'data_ptr'):
+        raise ValueError(f'{what}: expected a torch tensor on cuda:{device}, got {type(t).__name__}')
+    if not getattr(t, 'is_cuda', False) or t.device.index != device:
+        raise ValueError(f'{what}: expected a tensor on cuda:{device}, got one on {t.device}')
+    if str(t.dtype) != dtype:
+        raise ValueError(f'{what}: expected {dtype}, got {t.dtype}')
+    if not t.is_contiguous():
+        raise ValueError(f'{what}: tensor must be contiguous')
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f'{what}: expected {numel} elements, got {t.numel()}')
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -140,14 +150,22 @@ def rotate_modes(R, T, V, spin_half, L=None):
 class Context:
     """One library context on one HIP device."""
 
-    def __init__(self, device=0, path=None):
+    def __init__(self, device=0, path=None, stream=None):
+        """stream: a torch.cuda.Stream (or a raw hipStream_t as int) on
+        `device` for every device call of the context; None: the library
+        creates its own."""
         self.lib = load(path) if path else lib()
         h = ctypes.c_void_p()
-        st = self.lib.mdmrg_create(ctypes.byref(h), device)
+        sp = None
+        if stream is not None:
+            sp = stream if isinstance(stream, int) else stream.cuda_stream
+        st = self.lib.mdmrg_create(ctypes.byref(h), device, ctypes.c_void_p(sp) if sp else None)
         if st:
             raise MdmrgError(st, self.lib.mdmrg_last_error(None).decode())
         self.h = h
         self.device = device
+        self.stream = stream  # kept alive as long as the context
+        self._prev_n_elem = None  # layout length of the bond left by renormalize
 
     def close(self):
         if self.h:
@@ -227,11 +245,21 @@ class Context:
                   for (a, s1, s2, b, m, n), o in zip(d[:, :6], off)]
         return blocks, ne.value
 
+    def n_elem(self):
+        """Length of the current two-site vector (doubles)."""
+        ne = ctypes.c_int64()
+        self._chk(self.lib.mdmrg_psi_layout(self.h, ctypes.byref(ne), None, None))
+        return ne.value
+
+    def _vec(self, t, what, numel=-1):
+        return device_ptr(t, self.device, self.n_elem() if numel == -1 else numel, what=what)
+
     def heff_apply(self, x, y, prec=FP64):
-        self._chk(self.lib.mdmrg_heff_apply(self.h, prec, _ptr(x), _ptr(y)))
+        self._chk(self.lib.mdmrg_heff_apply(self.h, prec, self._vec(x, 'heff_apply x'),
+                                            self._vec(y, 'heff_apply y')))
 
     def heff_diag(self, d):
-        self._chk(self.lib.mdmrg_heff_diag(self.h, _ptr(d)))
+        self._chk(self.lib.mdmrg_heff_diag(self.h, self._vec(d, 'heff_diag d')))
 
     def heff_cost(self):
         f, b, t, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
@@ -252,34 +280,42 @@ class Context:
 
     def davidson(self, x, tol=1e-8, max_iter=200, m_max=24):
         e, r, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
-        st = self._chk(self.lib.mdmrg_davidson(self.h, _ptr(x), tol, max_iter, m_max, ctypes.byref(e),
+        st = self._chk(self.lib.mdmrg_davidson(self.h, self._vec(x, 'davidson x'), tol, max_iter, m_max, ctypes.byref(e),
                                                ctypes.byref(r), ctypes.byref(n)), allow=(ENOCONV,))
         return e.value, r.value, n.value, st == OK
 
     def davidson_mixed(self, x, tol=1e-8, tol_split=1e-5, prec_split=FP32, max_iter=200, m_max=24):
         e, r = ctypes.c_double(), ctypes.c_double()
         n64, ns = ctypes.c_int(), ctypes.c_int()
-        st = self._chk(self.lib.mdmrg_davidson_mixed(self.h, _ptr(x), tol, prec_split, tol_split, max_iter, m_max,
+        st = self._chk(self.lib.mdmrg_davidson_mixed(self.h, self._vec(x, 'davidson_mixed x'), tol, prec_split, tol_split, max_iter, m_max,
                                                      ctypes.byref(e), ctypes.byref(r), ctypes.byref(n64),
                                                      ctypes.byref(ns)), allow=(ENOCONV,))
         return e.value, r.value, n64.value, ns.value, st == OK
 
     def decimate(self, x, D, direction):
         t, s, h = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        self._chk(self.lib.mdmrg_decimate(self.h, _ptr(x), D, direction, ctypes.byref(t), ctypes.byref(s),
+        self._chk(self.lib.mdmrg_decimate(self.h, self._vec(x, 'decimate x'), D, direction, ctypes.byref(t), ctypes.byref(s),
                                           ctypes.byref(h)))
         return t.value, s.value, h.value
 
-    def renormalize(self, direction):
-        self._chk(self.lib.mdmrg_renormalize(self.h, direction))
+    def renormalize(self, direction, prec=FP64):
+        ne = self.n_elem()
+        self._chk(self.lib.mdmrg_renormalize(self.h, direction, prec))
+        self._prev_n_elem = ne
 
     def stvec(self, x_old, x_new):
-        self._chk(self.lib.mdmrg_stvec(self.h, _ptr(x_old), _ptr(x_new)))
+        if self._prev_n_elem is None:
+            raise ValueError('stvec: call renormalize first')
+        self._chk(self.lib.mdmrg_stvec(self.h, self._vec(x_old, 'stvec x_old', self._prev_n_elem),
+                                       self._vec(x_new, 'stvec x_new')))
 
-    def sweep(self, n_sweeps, D_schedule, tol=1e-8):
+    def sweep(self, n_sweeps, D_schedule, tol=1e-8, strict=True):
+        """Energies after each sweep.  strict: raise when a Davidson solve of
+        the sweeps missed tol (ENOCONV); otherwise return them anyway."""
         Ds = np.ascontiguousarray(D_schedule, dtype=np.int32)
         E = np.zeros(n_sweeps)
-        self._chk(self.lib.mdmrg_sweep(self.h, n_sweeps, _ip(Ds), len(Ds), tol, _dp(E)))
+        self._chk(self.lib.mdmrg_sweep(self.h, n_sweeps, _ip(Ds), len(Ds), tol, _dp(E)),
+                  allow=() if strict else (ENOCONV,))
         return E
 
     def gemm_grouped(self, buffers, out_desc, seg_desc, alpha, prec=FP64):
@@ -287,8 +323,10 @@ class Context:
         the split forms FP32 and BF16X3); descriptors: int64 arrays of shape
         (n_out, 8) and (n_seg, 8); alpha: float64 (n_seg,)."""
         nb = len(buffers)
-        ptrs = (ctypes.c_void_p * nb)(*[_ptr(b).value for b in buffers])
-        lens = np.array([b.numel() if hasattr(b, 'numel') else b.size for b in buffers], dtype=np.int64)
+        dt = 'torch.float64' if prec == FP64 else 'torch.float32'
+        ptrs = (ctypes.c_void_p * nb)(*[device_ptr(b, self.device, None, dt, f'gemm_grouped buffer {i}').value
+                                        for i, b in enumerate(buffers)])
+        lens = np.array([b.numel() for b in buffers], dtype=np.int64)
         od = np.ascontiguousarray(out_desc, dtype=np.int64).reshape(-1, 8)
         sd = np.ascontiguousarray(seg_desc, dtype=np.int64).reshape(-1, 8)
         al = np.ascontiguousarray(alpha, dtype=np.float64)

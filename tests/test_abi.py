@@ -74,11 +74,11 @@ def test_create_rejects_a_device_that_does_not_exist(lib):
     import ctypes
     from paper_2311_14106_amd import mdmrg
     h = ctypes.c_void_p(1)
-    st = lib.mdmrg_create(ctypes.byref(h), 1 << 20)
+    st = lib.mdmrg_create(ctypes.byref(h), 1 << 20, None)
     assert st == mdmrg.EDEVICE
     assert h.value is None
     assert lib.mdmrg_last_error(None).decode().startswith('HIP error')
-    assert lib.mdmrg_create(None, 0) == mdmrg.EINVAL
+    assert lib.mdmrg_create(None, 0, None) == mdmrg.EINVAL
 
 
 def test_binding_fails_loudly_without_the_library(tmp_path):

@@ -1,0 +1,291 @@
+"""The boundary of libmdmrg on the GPU: error paths, input forms, streams.
+
+* Invalid input is refused with the documented status and no device work:
+  non-Hermitian T or V and an unreachable target sector (EINVAL), a start
+  vector holding NaN (EDEVICE).
+* Davidson cut off at max_iter returns ENOCONV with its best estimate, a
+  Rayleigh quotient of H_eff, so it lies above the lowest eigenvalue.
+* The coordinate (COO) form of V gives the same H_eff as the dense form and
+  as the oracle.
+* A context created on a caller's torch stream computes the same products
+  as one with its own stream.
+* Decimation reports the quantities of the normalised state for any scale
+  of x, as the oracle does (Sec. II.B).
+* Split-precision renormalisation perturbs the next bond's H_eff by about
+  its rounding level, and not at all in FP64.
+* The split-form product of a vector of odd length (an FP32 buffer ending in
+  a 4-byte tail) replays from a captured graph bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import dmrg
+from oracle import integrals as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip('torch')
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip('no GPU')
+    from paper_2311_14106_amd import mdmrg
+    return mdmrg
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to('cuda:0')
+
+
+def _hubbard33(mdmrg, l=3, D=64, seed=5, stream=None):
+    T, W = I.hubbard_momentum(3, 3, 1.0, 4.0)
+    n, spin, target = 9, True, (4, 4)
+    bonds = si.bond_profile(n, spin, target, D)
+    tens = si.random_mps(bonds, spin, seed, l)
+    ctx = mdmrg.Context(0, stream=stream)
+    ctx.set_hamiltonian(n, spin, T, W, target)
+    ctx.set_mps(*si.flatten_mps(bonds, tens, spin))
+    ctx.prepare_bond(l)
+    return ctx, (T, W, n, spin, target, bonds, tens)
+
+
+def test_invalid_hamiltonians_are_refused():
+    mdmrg = _gpu()
+    ctx = mdmrg.Context(0)
+    T, W = I.spinless_real_space(3, 3, 1.0, 1.0)
+    n = 9
+    log('[boundary] non-Hermitian T')
+    Tb = T.copy()
+    Tb[0, 1] += 1e-6
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        ctx.set_hamiltonian(n, False, Tb, W, (4, 0))
+    assert e.value.code == mdmrg.EINVAL
+    log('[boundary] non-Hermitian V')
+    Wb = W.copy()
+    Wb[0, 1, 1, 2] += 1e-6    # V[p,q,r,s] without its partner V[s,r,q,p]
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        ctx.set_hamiltonian(n, False, T, Wb, (4, 0))
+    assert e.value.code == mdmrg.EINVAL
+    log('[boundary] unreachable target')
+    for tgt in ((10, 0), (-1, 0)):
+        with pytest.raises(mdmrg.MdmrgError) as e:
+            ctx.set_hamiltonian(n, False, T, W, tgt)
+        assert e.value.code == mdmrg.EINVAL
+    Ts, Ws = I.hubbard_momentum(3, 3, 1.0, 4.0)
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        ctx.set_hamiltonian(n, True, Ts, Ws, (4, 10))
+    assert e.value.code == mdmrg.EINVAL
+    log('[boundary] COO index out of range')
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        ctx.set_hamiltonian_coo(n, False, T, np.array([[0, 1, 1, 9]]), np.array([1.0]), (4, 0))
+    assert e.value.code == mdmrg.EINVAL
+    # nothing is left half-set: a valid Hamiltonian is accepted afterwards
+    ctx.set_hamiltonian(n, False, T, W, (4, 0))
+    ctx.close()
+
+
+def test_nan_start_vector_is_a_device_error():
+    mdmrg = _gpu()
+    ctx, _ = _hubbard33(mdmrg)
+    ne = ctx.n_elem()
+    x = to_dev(si.random_vector(ne, 1))
+    x[ne // 2] = float('nan')
+    log('[boundary] NaN in the Davidson start vector')
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        ctx.davidson(x, tol=1e-9, max_iter=50)
+    assert e.value.code == mdmrg.EDEVICE
+    # a NaN vector given to decimation is refused as well
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        ctx.decimate(x, 16, +1)
+    assert e.value.code == mdmrg.EDEVICE
+    # and the context still works
+    x = to_dev(si.random_vector(ne, 1))
+    e_, r, nmv, conv = ctx.davidson(x, tol=1e-8, max_iter=300)
+    assert conv
+    ctx.close()
+
+
+def test_max_iter_returns_enoconv_with_best_estimate():
+    mdmrg = _gpu()
+    ctx, (T, W, n, spin, target, bonds, tens) = _hubbard33(mdmrg)
+    prob = dmrg.TwoSiteProblem(dmrg.MPS(dmrg.Chain(T, W, n, spin, target), bonds, tens), 3)
+    e_ref, _ = prob.lowest(v0=si.random_vector(prob.dim, 1))
+    ne = ctx.n_elem()
+    x = to_dev(si.random_vector(ne, 2))
+    log('[boundary] Davidson with max_iter 3')
+    e3, r3, n3, conv3 = ctx.davidson(x, tol=1e-12, max_iter=3)
+    assert not conv3 and n3 == 3 and r3 > 1e-12
+    # the estimate is the Rayleigh quotient of the returned unit vector
+    xv = x.cpu().numpy()
+    assert abs(np.linalg.norm(xv) - 1.0) < 1e-12
+    assert abs(xv @ prob.matvec(xv) - e3) <= 1e-12 * abs(e3)
+    assert e3 >= e_ref - 1e-12 * abs(e_ref)
+    # continuing from it converges to the lowest eigenvalue
+    e, r, nmv, conv = ctx.davidson(x, tol=1e-9, max_iter=400)
+    assert conv and abs(e - e_ref) <= 1e-12 * abs(e_ref)
+    ctx.close()
+
+
+def test_coo_form_matches_dense_form_and_oracle():
+    mdmrg = _gpu()
+    T, W = I.hubbard_momentum(3, 3, 1.0, 4.0)
+    n, spin, target, l = 9, True, (4, 4), 4
+    bonds = si.bond_profile(n, spin, target, 48)
+    tens = si.random_mps(bonds, spin, 6, l)
+    prob = dmrg.TwoSiteProblem(dmrg.MPS(dmrg.Chain(T, W, n, spin, target), bonds, tens), l)
+    nz = np.argwhere(W != 0.0)
+    # shuffled, with every entry split in two halves (repeated entries add up)
+    rng = np.random.default_rng(0)
+    nz = nz[rng.permutation(len(nz))]
+    vals = W[tuple(nz.T)]
+    ijkl = np.concatenate([nz, nz]).astype(np.int32)
+    val = np.concatenate([0.25 * vals, 0.75 * vals])
+    ys = []
+    for form in ('dense', 'coo'):
+        log(f'[boundary] H_eff from the {form} form of V')
+        ctx = mdmrg.Context(0)
+        if form == 'dense':
+            ctx.set_hamiltonian(n, spin, T, W, target)
+        else:
+            ctx.set_hamiltonian_coo(n, spin, T, ijkl, val, target)
+        ctx.set_mps(*si.flatten_mps(bonds, tens, spin))
+        ctx.prepare_bond(l)
+        ne = ctx.n_elem()
+        assert ne == prob.dim
+        x = to_dev(si.random_vector(ne, 3))
+        y = torch.zeros_like(x)
+        ctx.heff_apply(x, y)
+        ys.append(y.cpu().numpy())
+        ctx.close()
+    y_ref = prob.matvec(si.random_vector(prob.dim, 3))
+    for y in ys:
+        assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
+    assert np.abs(ys[0] - ys[1]).max() <= 1e-13 * np.abs(y_ref).max()
+
+
+def test_context_on_a_caller_stream():
+    mdmrg = _gpu()
+    s = torch.cuda.Stream()
+    a, _ = _hubbard33(mdmrg, stream=s)
+    b, _ = _hubbard33(mdmrg)
+    ne = a.n_elem()
+    x = to_dev(si.random_vector(ne, 4))
+    ya, yb = torch.zeros_like(x), torch.zeros_like(x)
+    log('[boundary] products on a torch side stream')
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        a.heff_apply(x, ya)
+    torch.cuda.current_stream().wait_stream(s)
+    b.heff_apply(x, yb)
+    torch.cuda.synchronize()
+    assert torch.equal(ya, yb)
+    xa, xb = x.clone(), x.clone()
+    torch.cuda.synchronize()   # the copies are queued on torch's stream
+    ea = a.davidson(xa, tol=1e-9, max_iter=300)[0]
+    eb = b.davidson(xb, tol=1e-9, max_iter=300)[0]
+    assert abs(ea - eb) <= 1e-12 * abs(eb)
+    a.close()
+    b.close()
+    # a context destroyed before its caller's stream leaves the stream usable
+    with torch.cuda.stream(s):
+        z = (x * 2.0).sum().item()
+    assert np.isfinite(z)
+
+
+def test_decimation_is_scale_invariant():
+    mdmrg = _gpu()
+    ctx, (T, W, n, spin, target, bonds, tens) = _hubbard33(mdmrg)
+    mps = dmrg.MPS(dmrg.Chain(T, W, n, spin, target), bonds, tens)
+    x = si.random_vector(ctx.n_elem(), 8)
+    ref = dmrg.decimate(mps, 3, x / np.linalg.norm(x), 17, +1)
+    for c in (1.0, 7.5, 1e-3):
+        ctx.set_mps(*si.flatten_mps(bonds, tens, spin))
+        ctx.prepare_bond(3)
+        log(f'[boundary] decimation of {c} * x')
+        trunc, svn, shalf = ctx.decimate(to_dev(c * x), 17, +1)
+        assert abs(trunc - ref[2]) <= 1e-12
+        assert abs(svn - ref[3]) <= 1e-12 * ref[3]
+        assert abs(shalf - ref[4]) <= 1e-12 * ref[4]
+    ctx.close()
+
+
+def test_split_renormalisation_perturbs_at_its_rounding_level():
+    mdmrg = _gpu()
+    ys = {}
+    for prec in (mdmrg.FP64, mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3):
+        ctx, _ = _hubbard33(mdmrg, l=3, D=64)
+        x = to_dev(si.random_vector(ctx.n_elem(), 9))
+        ctx.decimate(x, 48, +1)
+        log(f'[boundary] renormalisation in form {prec}')
+        ctx.renormalize(+1, prec)
+        z = to_dev(si.random_vector(ctx.n_elem(), 10))
+        y = torch.zeros_like(z)
+        ctx.heff_apply(z, y)
+        ys.setdefault(prec, []).append(y.cpu().numpy())
+        ctx.close()
+    y64 = ys[mdmrg.FP64][0]
+    scale = np.abs(y64).max()
+    # FP64 renormalisation is deterministic
+    assert np.array_equal(ys[mdmrg.FP64][0], ys[mdmrg.FP64][1])
+    d32 = np.abs(ys[mdmrg.FP32][0] - y64).max() / scale
+    dbf = np.abs(ys[mdmrg.BF16X3][0] - y64).max() / scale
+    log(f'[boundary] next-bond H_eff change: FP32 {d32:.2e}, 3xBF16 {dbf:.2e}')
+    # binary32 rounding of operands, products and sums over short K
+    assert 0.0 < d32 <= 1e-5
+    # 16 significant bits per operand
+    assert 0.0 < dbf <= 1e-3
+
+
+def test_split_graph_replay_with_odd_vector_length():
+    mdmrg = _gpu()
+    T, W = I.hubbard_momentum(3, 3, 1.0, 4.0)
+    n, spin, target = 9, True, (4, 4)
+    ch = dmrg.Chain(T, W, n, spin, target)
+    found = None
+    for D in (31, 33, 37, 41, 47, 53):
+        bonds = si.bond_profile(n, spin, target, D)
+        for l in range(n - 1):
+            # the layout is integer bookkeeping: its length decides the case
+            if dmrg.psi_layout(dmrg.MPS(ch, bonds, [{}] * n), l)[1] % 2 == 1:
+                found = (D, l)
+                break
+        if found:
+            break
+    assert found, 'no bond with an odd vector length in the sampled profiles'
+    D, l = found
+    bonds = si.bond_profile(n, spin, target, D)
+    tens = si.random_mps(bonds, spin, 2, l)
+    a, b = mdmrg.Context(0), mdmrg.Context(0)
+    for c in (a, b):
+        c.set_hamiltonian(n, spin, T, W, target)
+        c.set_mps(*si.flatten_mps(bonds, tens, spin))
+        c.prepare_bond(l)
+    ne = a.n_elem()
+    assert ne % 2 == 1
+    log(f'[boundary] odd length {ne} (D {D}, bond {l}): graph replay of the split forms')
+    x0 = to_dev(si.random_vector(ne, 1))
+    for prec in (mdmrg.FP32, mdmrg.BF16X3, mdmrg.FP64):
+        for _ in range(5):   # variant trials and decision
+            a.heff_apply(x0, torch.zeros_like(x0), prec=prec)
+    a.set_option(mdmrg.OPT_GRAPH, 1)
+    for prec in (mdmrg.FP32, mdmrg.BF16X3, mdmrg.FP64):
+        for r in range(4):
+            x = to_dev(si.random_vector(ne, 20 + r))
+            yg = torch.full_like(x, 7.0)   # stale content must not survive
+            ye = torch.zeros_like(x)
+            a.heff_apply(x, yg, prec=prec)
+            b.heff_apply(x, ye, prec=prec)
+            torch.cuda.synchronize()
+            assert torch.equal(yg, ye), (prec, r)
+    st = a.stats()
+    assert st['graph32_launches'] >= 1 and st['graphbf3_launches'] >= 1 and st['graph64_launches'] >= 1
+    a.close()
+    b.close()
