@@ -1708,11 +1708,13 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
   // start vector
   double nrm;
   dev_multidot(dev, x, 0, 1, x, N, &nrm);
+  // a non-finite start vector is an error (checked before the zero test,
+  // which a NaN norm would also fail); only an exact zero is replaced
+  MDMRG_REQUIRE(std::isfinite(nrm), -3, "davidson: start vector is not finite");
   if (!(nrm > 1e-300)) {
     dev_randn(dev, x, N, 3);
     dev_multidot(dev, x, 0, 1, x, N, &nrm);
   }
-  MDMRG_REQUIRE(std::isfinite(nrm), -3, "davidson: start vector is not finite");
   dev_d2d(dev, V, x, sizeof(double) * N);
   dev_scale(dev, 1.0 / std::sqrt(nrm), V, N);
   heff_apply(V, AV, prec);
@@ -1892,14 +1894,14 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
   double t0 = wall_seconds();
   const int l = cur, d = ham.d;
   const Bond &ba = bonds[l], &bb = bonds[l + 2];
-  {
-    // |x|^2 = tr(rho): refuse a zero or non-finite vector before any
-    // eigensolver sees it
-    double nx = 0.0;
-    dev_multidot(dev, x, 0, 1, x, psi.n_elem, &nx);
-    MDMRG_REQUIRE(std::isfinite(nx), -3, "decimate: x is not finite");
-    MDMRG_REQUIRE(nx > 0.0, -1, "decimate: zero vector");
-  }
+  // |x|^2 = tr(x x^T): refuse a zero or non-finite vector before any
+  // eigensolver sees it; rho is formed from x / |x| (trace 1), so that the
+  // eigensolver sees the same matrix for any scale of x
+  double nx = 0.0;
+  dev_multidot(dev, x, 0, 1, x, psi.n_elem, &nx);
+  MDMRG_REQUIRE(std::isfinite(nx), -3, "decimate: x is not finite");
+  MDMRG_REQUIRE(nx > 0.0, -1, "decimate: zero vector");
+  const double rho_scale = 1.0 / nx;
   // enlarged-block sectors and their row lists
   struct Sec {
     QN q;
@@ -1981,7 +1983,7 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
               const int p1 = psi.find(a, s1, s2, int(b)), p2 = psi.find(a2, s1b, s2, int(b));
               if (p1 < 0 || p2 < 0) continue;
               GSeg g{};
-              g.alpha = 1.0;
+              g.alpha = rho_scale;
               g.a_slot = 0;
               g.a_off = psi.blk[p1].off;
               g.lda = psi.blk[p1].n;
@@ -2003,7 +2005,7 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
               const int p1 = psi.find(int(a), s1, s2, b), p2 = psi.find(int(a), s1, s2b, b2);
               if (p1 < 0 || p2 < 0) continue;
               GSeg g{};
-              g.alpha = 1.0;
+              g.alpha = rho_scale;
               g.a_slot = 0;
               g.a_off = psi.blk[p1].off;
               g.lda = psi.blk[p1].n;
@@ -2056,8 +2058,8 @@ void Context::decimate(const double *x, int D, int dir, double *trunc, double *s
     return a.k > b.k;
   });
   const int keep = std::min<int>(D, int(cand.size()));
-  // weights of the normalised state: rho / tr(rho), tr(rho) = |x|^2, so the
-  // truncation error and the entropies do not depend on the scale of x
+  // weights of the normalised state: rho was formed from x / |x|; dividing
+  // by the computed trace as well keeps the weights summing to 1 to rounding
   double tr = 0.0;
   for (const Cand &c : cand) tr += std::max(0.0, c.lam);
   MDMRG_REQUIRE(std::isfinite(tr), -3, "decimate: non-finite density matrix");
