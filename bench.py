@@ -1,7 +1,12 @@
 """Benchmark: H_eff psi TFLOP/s and Davidson s/step on one MI355X.
 
 Workload (default): Hubbard model on a 6x6 torus, t=1, U=4, 18 up + 18 down
-electrons, momentum basis, U(1)xU(1), bond dimension D=1024, FP64 plain form.
+electrons, momentum basis, U(1)xU(1), bond dimension D=2048, FP64 plain form
+in the timed steps; the split-precision forms (FP32 and 3xBF16 products,
+eager and replayed from captured graphs) are compared with it at fixed
+energy error after the timed steps, and a short segment of steps is run again
+in each split form (mixed Davidson and split renormalisation) for the
+per-step energy error against the FP64 steps.
 A step is one pass of the hot path at one bond: Davidson diagonalisation of
 H_eff (every product on the GPU), density-matrix decimation, renormalisation
 of the grown block (with the operator tables of the next bond) and the start
@@ -14,7 +19,8 @@ renormalised on the GPU.  Inputs are resident in HBM before timing starts.
 
 --workload spinless8x8 selects the spinless 8x8 torus (t=1, V=2, N=32,
 momentum basis rotated inside degenerate shells, dense two-body integrals)
-instead; --keep-envs 0 keeps only the block environments in use (large D).
+instead; --keep-envs 1 keeps the block environments of every bond visited
+(default 0: only those of the current bond and one step either way).
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
 the benchmark runs on one GPU.
@@ -35,20 +41,22 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 MFMA
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # HBM traffic per launch of the dominant kernel, from FETCH_SIZE / WRITE_SIZE
-# counter passes over this same command (paper_2311_14106_amd/traffic.py)
-TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'k_gemm_traffic_hubbard6x6_D1024.txt')
+# counter passes over this same command (paper_2311_14106_amd/traffic.py),
+# one record per workload and bond dimension
+TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'k_gemm_traffic_{workload}_D{D}.txt')
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel_key, D):
-    """HBM bytes per launch recorded for this kernel and bond dimension, or
-    None when absent or taken on other kernel / planner sources."""
+def measured_traffic(kernel_key, workload, D):
+    """HBM bytes per launch recorded for this kernel, workload and bond
+    dimension, or None when absent or taken on other kernel / planner
+    sources."""
     from paper_2311_14106_amd import traffic
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILE.format(workload=workload, D=D)) as f:
             txt = f.read()
         rec = json.loads(txt[txt.index('{'):txt.rindex('}') + 1])
     except (OSError, ValueError):
@@ -150,10 +158,14 @@ def cpu_baseline(mdmrg, budget_s):
 
 
 def split_compare(ctx, x0, torch, args):
-    """Davidson s/step at fixed dE: FP64 form vs mixed precision (FP32 or
-    3xBF16 products, then FP64 refinement), eagerly launched and replayed from
-    captured graphs, all from the same start vector at the current bond;
-    E_ref = FP64 solve to |r| <= 1e-10; dE = 1e-9 |E_ref|."""
+    """Davidson s/step at fixed dE: the plain FP64 form against the mixed
+    precision forms (FP32 or 3xBF16 products, then FP64 refinement), launched
+    eagerly and replayed from captured graphs (the precision + batched form),
+    all from the same start vector at the current bond.  E_ref = FP64 solve to
+    |r| <= 1e-10; dE = 1e-9 |E_ref|.  Every form is warmed up at the bond
+    before any timed solve (tile-variant trials of each plan, FP32 operator
+    copies, graph capture), so all timed solves start from the same tuned
+    state."""
     from paper_2311_14106_amd import mdmrg
 
     def solve(fn):
@@ -164,40 +176,35 @@ def split_compare(ctx, x0, torch, args):
         torch.cuda.synchronize()
         return res, time.time() - t0
 
-    s0 = ctx.stats()
+    def warm(n=6):
+        y = torch.empty_like(x0)
+        for prec in (mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3):
+            for _ in range(n):
+                ctx.heff_apply(x0, y, prec=prec)
+        torch.cuda.synchronize()
+
+    def plain(x):
+        return ctx.davidson(x, tol=args.split_tol, max_iter=600)
+
+    def mixed(prec):
+        return lambda x: ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol, prec_split=prec,
+                                            max_iter=600)
+
+    ctx.set_option(mdmrg.OPT_GRAPH, 0)
+    warm()
     (e_ref, r_ref, n_ref, _), _ = solve(lambda x: ctx.davidson(x, tol=1e-10, max_iter=600))
-    (e64, r64, n64, _), t64 = solve(lambda x: ctx.davidson(x, tol=args.split_tol, max_iter=600))
-    mixed = lambda x: ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol, prec_split=mdmrg.FP32,
-                                         max_iter=600)
-    (em, rm, nm64, nm32, _), tm = solve(mixed)
-    s1 = ctx.stats()
-    mixed3 = lambda x: ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol,
-                                          prec_split=mdmrg.BF16X3, max_iter=600)
-    (eb, rb, nb64, nb3, _), tb = solve(mixed3)
-    s1b = ctx.stats()
     de = 1e-9 * abs(e_ref)
-    out = {}
-    if args.batched:
-        # precision + batched form: the same solves with every product
-        # replayed from a captured graph (captured once the kernel variants
-        # are tuned)
-        ctx.set_option(mdmrg.OPT_GRAPH, 1)
-        (eg, rg, ng64, ng32, _), tg = solve(mixed)
-        (e64g, _, n64g, _), t64g = solve(lambda x: ctx.davidson(x, tol=args.split_tol, max_iter=600))
-        s2 = ctx.stats()
-        ctx.set_option(mdmrg.OPT_GRAPH, 0)
-        g32 = (s2['graph32_ms'] - s1['graph32_ms']) / max(1.0, s2['graph32_launches'] - s1['graph32_launches'])
-        g64 = (s2['graph64_ms'] - s1['graph64_ms']) / max(1.0, s2['graph64_launches'] - s1['graph64_launches'])
-        out = {'mixed_fp32_graph': {'davidson_s': tg, 'products_fp32': ng32, 'products_fp64': ng64,
-                                    'dE': abs(eg - e_ref), 'ok': abs(eg - e_ref) <= de},
-               'fp64_graph': {'davidson_s': t64g, 'products': n64g, 'dE': abs(e64g - e_ref),
-                              'ok': abs(e64g - e_ref) <= de},
-               'speedup_precision_batched': t64 / tg if tg > 0 else None,
-               'graph_ms_per_product': {'fp64': g64, 'fp32': g32}}
+    s0 = ctx.stats()
+    (e64, r64, n64, _), t64 = solve(plain)
+    s1 = ctx.stats()
+    (em, rm, nm64, nm32, _), tm = solve(mixed(mdmrg.FP32))
+    s2 = ctx.stats()
+    (eb, rb, nb64, nb3, _), tb = solve(mixed(mdmrg.BF16X3))
+    s3 = ctx.stats()
     ms64 = (s1['heff_gemm_ms'] + s1['heff_p1_ms'] - s0['heff_gemm_ms'] - s0['heff_p1_ms']) / max(
         1.0, s1['n_matvec'] - s0['n_matvec'])
-    ms32 = (s1['split_gemm_ms'] - s0['split_gemm_ms']) / max(1.0, s1['n_matvec_split'] - s0['n_matvec_split'])
-    msb = (s1b['split_gemm_ms'] - s1['split_gemm_ms']) / max(1.0, s1b['n_matvec_split'] - s1['n_matvec_split'])
+    ms32 = (s2['split_gemm_ms'] - s1['split_gemm_ms']) / max(1.0, s2['n_matvec_split'] - s1['n_matvec_split'])
+    msb = (s3['split_gemm_ms'] - s2['split_gemm_ms']) / max(1.0, s3['n_matvec_split'] - s2['n_matvec_split'])
     log(f'[bench] fixed-dE: ref E={e_ref:.12f} ({n_ref} products); FP64 {t64:.2f}s {n64} products '
         f'dE={abs(e64 - e_ref):.1e}; mixed {tm:.2f}s {nm32} FP32 + {nm64} FP64 products dE={abs(em - e_ref):.1e}; '
         f'mixed 3xBF16 {tb:.2f}s {nb3} 3xBF16 + {nb64} FP64 products dE={abs(eb - e_ref):.1e}')
@@ -220,8 +227,100 @@ def split_compare(ctx, x0, torch, args):
            'speedup': t64 / tm if tm > 0 else None,
            'speedup_bf16x3': t64 / tb if tb > 0 else None,
            'gemm_ms_per_product': {'fp64': ms64, 'fp32': ms32, 'bf16x3': msb}}
-    res.update(out)
+    if args.batched:
+        # precision + batched form: the same solves with every product
+        # replayed from the graph captured at the bond (one product per form
+        # captures it before the timed solves)
+        ctx.set_option(mdmrg.OPT_GRAPH, 1)
+        warm(1)
+        g0 = ctx.stats()
+        (e64g, _, n64g, _), t64g = solve(plain)
+        g1 = ctx.stats()
+        (eg, rg, ng64, ng32, _), tg = solve(mixed(mdmrg.FP32))
+        g2 = ctx.stats()
+        (ebg, rbg, nbg64, nbg3, _), tbg = solve(mixed(mdmrg.BF16X3))
+        g3 = ctx.stats()
+        ctx.set_option(mdmrg.OPT_GRAPH, 0)
+
+        def per(a, b, key):
+            n = b[key + '_launches'] - a[key + '_launches']
+            return (b[key + '_ms'] - a[key + '_ms']) / n if n > 0 else None
+        forms = {'mixed_fp32_graph': tg, 'mixed_bf16x3_graph': tbg}
+        best = min(forms, key=forms.get)
+        res.update({
+            'fp64_graph': {'davidson_s': t64g, 'products': n64g, 'dE': abs(e64g - e_ref),
+                           'ok': abs(e64g - e_ref) <= de},
+            'mixed_fp32_graph': {'davidson_s': tg, 'products_fp32': ng32, 'products_fp64': ng64,
+                                 'dE': abs(eg - e_ref), 'ok': abs(eg - e_ref) <= de},
+            'mixed_bf16x3_graph': {'davidson_s': tbg, 'products_bf16x3': nbg3, 'products_fp64': nbg64,
+                                   'dE': abs(ebg - e_ref), 'ok': abs(ebg - e_ref) <= de},
+            # Davidson s/step of the plain FP64 form (eager) over that of the
+            # faster precision + batched form, both at fixed dE
+            'speedup_precision_batched': t64 / forms[best] if forms[best] > 0 else None,
+            'precision_batched_form': best,
+            'speedup_fp32_graph': t64 / tg if tg > 0 else None,
+            'speedup_bf16x3_graph': t64 / tbg if tbg > 0 else None,
+            'graph_ms_per_product': {'fp64': per(g0, g1, 'graph64'), 'fp32': per(g1, g2, 'graph32'),
+                                     'bf16x3': per(g2, g3, 'graphbf3')}})
+        log(f'[bench] batched: FP64 graph {t64g:.2f}s; mixed FP32 graph {tg:.2f}s ({ng32}+{ng64}); '
+            f'mixed 3xBF16 graph {tbg:.2f}s ({nbg3}+{nbg64}); precision+batched speedup '
+            f'{res["speedup_precision_batched"]:.2f} ({best})')
     return res
+
+
+def exported_mps(ctx, n):
+    """The context's MPS in the exchange arrays of set_mps (sector lists of
+    the bonds as they are now, after the truncations of the steps)."""
+    bonds = [ctx.get_bond(i) for i in range(n + 1)]
+    n_sect = np.array([len(b) for b in bonds], dtype=np.int32)
+    sect_qn = np.array([q for b in bonds for (Q, m) in b for q in Q], dtype=np.int32)
+    sect_dim = np.array([m for b in bonds for (Q, m) in b], dtype=np.int32)
+    return n_sect, sect_qn, sect_dim, ctx.get_mps()
+
+
+def drift_segment(ctx, x0, l, n, torch, args):
+    """Per-step energy error of the split forms against the plain FP64 run:
+    from the same MPS and start vector at bond l, the same args.drift_steps
+    steps are run once per form -- FP64 (Davidson and renormalisation in
+    FP64), FP32 and 3xBF16 (mixed Davidson with that split form, then FP64
+    refinement to the same residual tolerance; renormalisation GEMMs in that
+    split form).  A perturbed renormalised operator is a first-order change of
+    every later H_eff, so the error of step k > 0 includes k split
+    renormalisations."""
+    from paper_2311_14106_amd import mdmrg
+    mps = exported_mps(ctx, n)
+    runs = {}
+    for name, prec in (('fp64', mdmrg.FP64), ('fp32', mdmrg.FP32), ('bf16x3', mdmrg.BF16X3)):
+        ctx.set_mps(*mps)
+        ctx.prepare_bond(l)
+        x = x0.clone()
+        es, ts = [], []
+        for k in range(args.drift_steps):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            if prec == mdmrg.FP64:
+                e, r, nmv, conv = ctx.davidson(x, tol=args.tol, max_iter=400)
+            else:
+                e, r, n64, ns, conv = ctx.davidson_mixed(x, tol=args.tol, tol_split=args.tol, prec_split=prec,
+                                                         max_iter=400)
+            ctx.decimate(x, args.D, +1)
+            ctx.renormalize(+1, prec)
+            x2 = torch.empty(ctx.n_elem(), dtype=torch.float64, device='cuda:0')
+            ctx.stvec(x, x2)
+            x = x2
+            torch.cuda.synchronize()
+            es.append(e)
+            ts.append(time.time() - t0)
+        runs[name] = (es, ts)
+        log(f'[bench] drift segment {name}: E = {", ".join(f"{e:.12f}" for e in es)}')
+    ref = runs['fp64'][0]
+    out = {'bond': l, 'steps': args.drift_steps, 'davidson_tol': args.tol, 'E_fp64': ref,
+           's_per_step': {k: v[1] for k, v in runs.items()}}
+    for name in ('fp32', 'bf16x3'):
+        es = runs[name][0]
+        out[name] = {'E': es, 'dE': [e - r for e, r in zip(es, ref)],
+                     'dE_rel': [abs(e - r) / abs(r) for e, r in zip(es, ref)]}
+    return out
 
 
 def main():
@@ -230,7 +329,7 @@ def main():
     ap.add_argument('--steps', type=int, default=3)
     ap.add_argument('--warmup', type=int, default=1)
     ap.add_argument('--workload', choices=sorted(WORKLOADS), default='hubbard6x6')
-    ap.add_argument('--D', type=int, default=1024)
+    ap.add_argument('--D', type=int, default=2048)
     ap.add_argument('--profile-D', type=int, default=None,
                     help='bond dimension of the profile run (default 128 Hubbard, 64 spinless 8x8)')
     ap.add_argument('--write-profile', action='store_true',
@@ -239,14 +338,17 @@ def main():
     ap.add_argument('--compress', type=int, default=1,
                     help='interpolative compression of the cut coupling in the timed steps (the profile run '
                          'always uses it, so both settings see the same workload)')
-    ap.add_argument('--keep-envs', type=int, default=1,
-                    help='0: keep only the block environments in use (large D)')
+    ap.add_argument('--keep-envs', type=int, default=0,
+                    help='1: keep the block environments of every bond visited')
     ap.add_argument('--tol', type=float, default=1e-7)
     ap.add_argument('--cpu-budget', type=float, default=15.0)
     ap.add_argument('--no-cpu', action='store_true')
-    ap.add_argument('--no-split', action='store_true')
-    ap.add_argument('--batched', action='store_true',
-                    help='also time the fixed-dE solves with every product replayed from a captured graph')
+    ap.add_argument('--no-split', action='store_true',
+                    help='skip everything after the timed steps except the CPU baseline')
+    ap.add_argument('--no-batched', dest='batched', action='store_false',
+                    help='skip the graph-replayed (precision + batched) solves of the fixed-dE comparison')
+    ap.add_argument('--drift-steps', type=int, default=3,
+                    help='steps of the per-step energy-error segment of the split forms (0: skip)')
     ap.add_argument('--split-tol', type=float, default=1e-5,
                     help='FP64 residual tolerance of the fixed-dE Davidson comparison')
     args = ap.parse_args()
@@ -269,7 +371,10 @@ def main():
         return
     ctx.set_option(mdmrg.OPT_KEEP_ENVS, args.keep_envs)
     ctx.set_option(mdmrg.OPT_COMPRESS, args.compress)
-    l0 = n // 2 - 1 - args.warmup - args.steps // 2
+    l0 = max(0, n // 2 - 1 - args.warmup - args.steps // 2)
+    if l0 + args.warmup + args.steps + max(args.drift_steps, 1) + 1 >= n:
+        print(f'bench.py: {args.warmup} + {args.steps} steps from bond {l0} run past the chain end', file=sys.stderr)
+        sys.exit(2)
     t0 = time.time()
     ctx.set_mps(*si.flatten_mps(bonds, si.random_mps(bonds, spin, 1, l0), spin))
     ctx.prepare_bond(l0)
@@ -339,9 +444,16 @@ def main():
                                                   for k in kernels},
                  'heff_intensity_flop_per_byte': intensity,
                  'phase1_ms': d['heff_p1_ms'], 'phase2_ms': d['heff_gemm_ms']})
-    roof['traffic'] = measured_traffic('k_gemm<double> family', args.D) if args.workload == 'hubbard6x6' else None
+    roof['traffic'] = measured_traffic('k_gemm<double> family', args.workload, args.D)
+    # H_eff products of the timed steps: their own GPU time (both phases and
+    # the split-K reductions are inside the events of the two phases' launches
+    # and the reductions are small) and the Davidson wall time around them
+    heff_gpu_s = (d['heff_gemm_ms'] + d['heff_p1_ms']) * 1e-3
     out = {
         'metric': 'H_eff·ψ TFLOP/s and Davidson s/step, FP64 vs split-precision at fixed ΔE',
+        # algorithmic H_eff FLOP of the timed steps over their whole wall time
+        # (Davidson, decimation, renormalisation with the next bond's tables,
+        # start vector)
         'value': heff_flop / wall / 1e12,
         'unit': 'TFLOP/s',
         'n_gpus': 1,
@@ -357,7 +469,10 @@ def main():
                                f'{l0 + args.warmup}',
                    'D': args.D, 'n_sites': n, 'precision_form': 'plain FP64',
                    'compressed_cut_coupling': bool(args.compress),
-                   'davidson_tol': args.tol},
+                   'davidson_tol': args.tol, 'keep_envs': args.keep_envs},
+        'value_definition': 'algorithmic H_eff FLOP of the timed steps / wall time of the whole steps',
+        'heff_tflops_in_davidson': heff_flop / max(d['diag_h_s'], 1e-12) / 1e12,
+        'heff_tflops_products_gpu': heff_flop / max(heff_gpu_s, 1e-12) / 1e12,
         'davidson_s_per_step': d['diag_h_s'] / args.steps,
         'matvecs_per_step': nmv_total / args.steps,
         'heff_flop_per_matvec': flop_per_mv,
@@ -373,8 +488,11 @@ def main():
         'hbm_in_use_gb': (total_b - free_b) / 1e9,
         'roofline': roof,
     }
+    lc = l0 + args.warmup + args.steps
     if not args.no_split:
         out['split_precision'] = split_compare(ctx, x, torch, args)
+        if args.drift_steps > 0:
+            out['split_drift'] = drift_segment(ctx, x, lc, n, torch, args)
     if not args.no_cpu:
         out['cpu_baseline'] = cpu_baseline(mdmrg, args.cpu_budget)
     # every launch of the kernel in this process (all contexts), for

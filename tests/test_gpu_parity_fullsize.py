@@ -1,0 +1,137 @@
+"""H_eff psi against the oracle at a workload shape where the grouped kernel
+runs its full-size paths.
+
+Spinless fermions on a 4x6 torus (t=1, V=1, N=12, real space, Eq. (3) with
+t'=0), bond dimension D=1024 at the middle bond (l=11): sector blocks of
+up to 232 rows, so that nearly all of the product's FLOP sits in GEMMs with
+min(m, n) >= 128 and every output spans several 64x64 tiles with a ragged
+edge.  The oracle holds the N=12 Fock sector explicitly (2.7 M states), and
+its H_eff psi is the literal projection P^T H P psi (Sec. II.A).
+
+* Every tile variant of the grouped kernel, forced for all launches, and the
+  autotuned choice: elementwise |y - y_ref| <= 1e-12 max|y_ref| (FP64 sums of
+  O(10^3) O(1) products), and bitwise equal to each other (every variant
+  accumulates each output element in the same K order).
+* The product cut into several passes by a small intermediate-storage limit
+  (more than one pair of grouped launches per product): same bound.
+* The split forms against the FP64 oracle, normwise, within their rounding
+  model: two chained products (intermediate, then accumulation), each
+  element of each operand carrying a relative error of at most 2^-24 (FP32)
+  or about 2^-16 (3xBF16: hi*lo + lo*hi + hi*hi drops lo*lo and the rounding
+  of lo).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import dmrg
+from oracle import integrals as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip('torch')
+
+N_SITES, SPIN, TARGET, D, BOND = 24, False, (12, 0), 1024, 11
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope='module')
+def case():
+    if not torch.cuda.is_available():
+        pytest.skip('no GPU')
+    from paper_2311_14106_amd import mdmrg
+    T, W = I.spinless_real_space(4, 6, 1.0, 1.0)
+    bonds = si.bond_profile(N_SITES, SPIN, TARGET, D)
+    tens = si.random_mps(bonds, SPIN, 10, BOND)
+    log(f'[fullsize parity] oracle: 4x6 spinless, D={D}, bond {BOND}')
+    prob = dmrg.TwoSiteProblem(dmrg.MPS(dmrg.Chain(T, W, N_SITES, SPIN, TARGET), bonds, tens), BOND)
+    x = si.random_vector(prob.dim, 1)
+    y_ref = prob.matvec(x)
+    ctx = mdmrg.Context(0)
+    ctx.set_hamiltonian(N_SITES, SPIN, T, W, TARGET)
+    ctx.set_mps(*si.flatten_mps(bonds, tens, SPIN))
+    log('[fullsize parity] library: environments and tables')
+    ctx.prepare_bond(BOND)
+    blocks, ne = ctx.psi_layout()
+    assert ne == prob.dim and blocks == list(prob.layout)
+    yield mdmrg, ctx, x, y_ref
+    ctx.close()
+
+
+def _apply(ctx, x, prec=0):
+    xd = torch.from_numpy(x).to('cuda:0')
+    yd = torch.zeros_like(xd)
+    ctx.heff_apply(xd, yd, prec=prec)
+    torch.cuda.synchronize()
+    return yd
+
+
+def test_workload_shape_is_full_size(case):
+    mdmrg, ctx, x, y_ref = case
+    hist = ctx.heff_histogram()
+    tot = sum(hist.values())
+    big = sum(v for b, v in hist.items() if b >= 128)
+    log(f'[fullsize parity] FLOP share with min(m, n) >= 128: {big / tot:.3f}')
+    assert big >= 0.5 * tot
+
+
+def test_every_tile_variant_matches_oracle(case):
+    mdmrg, ctx, x, y_ref = case
+    scale = np.abs(y_ref).max()
+    ys = []
+    for variant in (0, 1, 2, 3):
+        ctx.set_option(mdmrg.OPT_GEMM_VARIANT, variant)
+        log(f'[fullsize parity] variant {variant}')
+        ys.append(_apply(ctx, x))
+    ctx.set_option(mdmrg.OPT_GEMM_VARIANT, -1)
+    log('[fullsize parity] autotuned')
+    ys += [_apply(ctx, x) for _ in range(6)]   # trials of every plan, then its choice
+    for yd in ys:
+        y = yd.cpu().numpy()
+        assert np.abs(y - y_ref).max() <= 1e-12 * scale
+        assert torch.equal(yd, ys[0])
+
+
+def test_several_passes_match_oracle(case):
+    mdmrg, ctx, x, y_ref = case
+    cost = ctx.heff_cost()
+    s0 = ctx.stats()
+    _apply(ctx, x)
+    s1 = ctx.stats()
+    one_pass = s1['heff_kernel_launches'] - s0['heff_kernel_launches']
+    # intermediates of at most 2^20 doubles per pass
+    ctx.set_option(mdmrg.OPT_SCRATCH_LIMIT, 1 << 20)
+    ctx.prepare_bond(BOND)
+    log('[fullsize parity] product in several passes')
+    s0 = ctx.stats()
+    yd = _apply(ctx, x)
+    s1 = ctx.stats()
+    passes = s1['heff_kernel_launches'] - s0['heff_kernel_launches']
+    ctx.set_option(mdmrg.OPT_SCRATCH_LIMIT, 1 << 30)
+    ctx.prepare_bond(BOND)
+    assert passes >= 2 * one_pass and passes >= 4
+    assert abs(ctx.heff_cost()['flop'] - cost['flop']) <= 1e-9 * cost['flop']
+    y = yd.cpu().numpy()
+    assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
+
+
+@pytest.mark.parametrize('prec,u', [(1, 2.0 ** -24), (2, 2.0 ** -16)])
+def test_split_forms_within_rounding_model(case, prec, u):
+    mdmrg, ctx, x, y_ref = case
+    log(f'[fullsize parity] split form {prec}')
+    for _ in range(5):
+        _apply(ctx, x, prec)   # variant trials
+    y = _apply(ctx, x, prec).cpu().numpy()
+    err = np.linalg.norm(y - y_ref) / np.linalg.norm(y_ref)
+    log(f'[fullsize parity] split form {prec}: normwise relative error {err:.2e} (u = {u:.1e})')
+    # operands rounded once (u each), the intermediate rounded once more,
+    # FP32 accumulation over K of a few thousand: random-sign sums grow as
+    # sqrt(K) u; 64 u covers the two chained products with margin, and a
+    # dropped cross term (error ~2^-8) or FP32 shadows of the wrong operator
+    # fail it
+    assert 0.0 < err <= 64 * u
