@@ -336,6 +336,25 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
                        int64_t n_out, const int64_t *out_desc, int64_t n_seg, const int64_t *seg_desc,
                        const double *alpha);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * grouped GEMM of mdmrg_gemm_grouped, same descriptors, range checks and
+ * results, without any device allocation.  The segment, output and tile
+ * descriptors are staged in a static per-GPU array of
+ * MDMRG_NOALLOC_STAGING_BYTES (16 MiB) that the library holds on each GPU it
+ * runs on until the process ends; a call whose descriptors and tile list
+ * need more returns MDMRG_EINVAL ("above the static staging limit").  The
+ * launch uses the tile variant forced by MDMRG_OPT_GEMM_VARIANT, else
+ * k_gemm_w4 (no autotuning; every variant gives the same bits), and the call
+ * returns after the launch has completed on the context stream.  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * host threads, or contexts on other streams) race and must be serialised
+ * by the caller. */
+#define MDMRG_NOALLOC_STAGING_BYTES (16u << 20)
+int mdmrg_gemm_grouped_noalloc(mdmrg_ctx ctx, int n_bases, const double *const *bases, const int64_t *base_len,
+                               int64_t n_out, const int64_t *out_desc, int64_t n_seg, const int64_t *seg_desc,
+                               const double *alpha);
+
 /* The same grouped GEMM in a split-precision form (the arithmetic of the
  * split H_eff products: the products beyond the FP64 ceiling of Sec. IV and
  * Fig. 2, in FP32 or 3xBF16): every

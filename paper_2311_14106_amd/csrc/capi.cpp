@@ -382,7 +382,7 @@ int mdmrg_sweep(mdmrg_ctx ctx, int n_sweeps, const int *D_schedule, int n_sched,
 // the grouped GEMM: offsets and lengths are in elements of the buffers.
 static int gemm_grouped_any(mdmrg_ctx ctx, int prec, int n_bases, void *const *bases, const int64_t *base_len,
                             int64_t n_out, const int64_t *out_desc, int64_t n_seg, const int64_t *seg_desc,
-                            const double *alpha) {
+                            const double *alpha, bool noalloc = false) {
   if (!ctx || n_bases < 1 || n_bases > kSlots || !bases || !base_len || n_out < 0 || n_seg < 0 ||
       (n_out && !out_desc) || (n_seg && (!seg_desc || !alpha)))
     return MDMRG_EINVAL;
@@ -443,6 +443,10 @@ static int gemm_grouped_any(mdmrg_ctx ctx, int prec, int n_bases, void *const *b
     }
     Bases b{};
     for (int i = 0; i < kSlots; ++i) b.p[i] = static_cast<double *>(bases[i < n_bases ? i : 0]);
+    if (noalloc) {
+      dev_gemm_run_noalloc(ctx->c.dev, plan, b);  // waits for the launch
+      return MDMRG_OK;
+    }
     DevPlan *dp = dev_plan_upload(ctx->c.dev, plan);
     dev_gemm_run(ctx->c.dev, dp, b, 3, prec);
     dev_plan_free(ctx->c.dev, dp);
@@ -458,6 +462,17 @@ int mdmrg_gemm_grouped(mdmrg_ctx ctx, int n_bases, const double *const *bases, c
   void *p[kSlots] = {};
   for (int i = 0; i < n_bases && i < kSlots; ++i) p[i] = const_cast<double *>(bases[i]);
   return gemm_grouped_any(ctx, MDMRG_FP64, n_bases, p, base_len, n_out, out_desc, n_seg, seg_desc, alpha);
+}
+
+static_assert(kNoAllocStagingBytes == MDMRG_NOALLOC_STAGING_BYTES, "staging size of the header and the device layer");
+
+int mdmrg_gemm_grouped_noalloc(mdmrg_ctx ctx, int n_bases, const double *const *bases, const int64_t *base_len,
+                               int64_t n_out, const int64_t *out_desc, int64_t n_seg, const int64_t *seg_desc,
+                               const double *alpha) {
+  if (!bases) return MDMRG_EINVAL;
+  void *p[kSlots] = {};
+  for (int i = 0; i < n_bases && i < kSlots; ++i) p[i] = const_cast<double *>(bases[i]);
+  return gemm_grouped_any(ctx, MDMRG_FP64, n_bases, p, base_len, n_out, out_desc, n_seg, seg_desc, alpha, true);
 }
 
 int mdmrg_gemm_grouped_split(mdmrg_ctx ctx, int prec, int n_bases, const float *const *bases,

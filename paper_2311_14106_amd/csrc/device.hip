@@ -43,6 +43,7 @@ struct Device {
   bool timing = false;
   bool capturing = false;  // stream capture in progress: no events, no host syncs
   int force_variant = -1;  // >= 0: tile variant of every grouped launch
+  unsigned char *staging = nullptr;  // device address of this GPU's copy of `scratch` (set at creation)
   std::vector<hipEvent_t> ev_pool;
   struct Pending {
     int tag, prec, variant;  // variant < 0: a graph replay (whole product), not one kernel
@@ -121,6 +122,27 @@ double wall_seconds() {
 constexpr int kRedBlocks = 256;
 constexpr int kMaxDot = 64;
 
+// Staging area of the allocation-free grouped GEMM (dev_gemm_run_noalloc):
+// the plan's segment, output and tile descriptors.  Every GPU the library
+// runs on holds its own copy of the array until the process ends.  In host
+// code `scratch` names a host-side stand-in, not device memory: kernels and
+// copies take the address hipGetSymbolAddress gives for the device, looked
+// up once per device when the first context on it is created.
+static __device__ __align__(256) unsigned char scratch[kNoAllocStagingBytes];
+static std::mutex g_scratch_mu;
+static std::unordered_map<int, unsigned char *> g_scratch_addr;  // device id -> its copy of `scratch`
+
+static unsigned char *scratch_address(int device) {  // the device must be current
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) return it->second;
+  void *ptr = nullptr;
+  HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  MDMRG_REQUIRE(ptr != nullptr, -3, "hipGetSymbolAddress returned no address for the staging array");
+  g_scratch_addr[device] = static_cast<unsigned char *>(ptr);
+  return static_cast<unsigned char *>(ptr);
+}
+
 Device *dev_create(int device, void *stream) {
   std::unique_ptr<Device> owner(new Device());  // deleted if a set-up call below fails
   Device *d = owner.get();
@@ -144,6 +166,7 @@ Device *dev_create(int device, void *stream) {
   HIP_CHECK(hipMalloc(&d->red_out, sizeof(double) * kMaxDot));
   HIP_CHECK(hipHostMalloc(&d->host_red, sizeof(double) * kMaxDot));
   HIP_CHECK(hipMalloc(&d->info, sizeof(int)));
+  d->staging = scratch_address(device);
   size_t free_b = 0, total_b = 0;
   HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
   d->budget_bytes = d->budget_default = size_t(0.95 * double(free_b));
@@ -745,7 +768,9 @@ static void launch_variant(int v, hipStream_t st, const DevPlan *p, const Bases 
     hipLaunchKernelGGL(k_gemm<T>, g, dim3(Cfg64<T>::NT), 0, st, p->tiles, p->outs, p->segs, b);
 }
 
-DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
+// Range limits of the kernels' 32-bit element and tile arithmetic, checked
+// on the host for every output and segment of a plan.
+static void plan_check(const GemmPlan &plan) {
   // the 64x64 kernel keeps per-thread 32-bit element offsets inside one K
   // step of an operand block: rows x ld (+ the K step) must stay below 2^31
   for (const GOut &o : plan.outs) {
@@ -760,16 +785,28 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
                     "grouped GEMM: operand block too large for 32-bit element offsets");
     }
   }
-  auto *dp = new DevPlan();
-  dp->n_outs = int64_t(plan.outs.size());
-  dp->n_segs = int64_t(plan.segs.size());
-  // algorithmic FLOP of the launch (identity segments excluded)
+}
+
+static double plan_flop(const GemmPlan &plan) {
+  double f = 0.0;  // identity segments excluded
   for (const GOut &o : plan.outs)
     for (int q = 0; q < o.seg_count; ++q) {
       const GSeg &g = plan.segs[o.seg_begin + q];
-      if (!(g.flags & SEG_AID)) dp->flop += 2.0 * o.m * o.n * g.k;
+      if (!(g.flags & SEG_AID)) f += 2.0 * o.m * o.n * g.k;
     }
-  // tiles, largest outputs first (longest-processing-time order)
+  return f;
+}
+
+// Launch order of the tm x tn output tiles of a plan.  One launch covers
+// every output, largest first (longest-processing-time order; small outputs
+// fill the tail).  Workgroups of a launch go to the 8 XCDs round-robin
+// (workgroup b to XCD b mod 8) and every XCD has its own L2, so outputs are
+// cut into chunks of whole tile rows (at most chunk_tiles tiles: a few A
+// panels against all B panels of the output), chunks are dealt to per-XCD
+// queues (largest first, to the queue with the least work) and the queues
+// interleaved: the tiles of a chunk run on one XCD and share its L2.  Queues
+// are padded with empty tiles (out = -1).
+static std::vector<GTile> plan_tiles(const GemmPlan &plan, int tm, int tn, int chunk_tiles) {
   std::vector<std::pair<double, int32_t>> work(plan.outs.size());
   for (size_t i = 0; i < plan.outs.size(); ++i) {
     const GOut &o = plan.outs[i];
@@ -778,40 +815,37 @@ DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
     work[i] = {-(kk + 16.0) * o.m * o.n, int32_t(i)};
   }
   std::stable_sort(work.begin(), work.end());
-  // One launch covers every output (small outputs fill the tail of the
-  // largest-first order).  Workgroups of a launch go to the 8 XCDs
-  // round-robin (workgroup b to XCD b mod 8) and every XCD has its own L2,
-  // so outputs are cut into chunks of whole tile rows (at most 64 tiles of
-  // 64x64, the same area in 128x128 tiles: a few A panels against all B
-  // panels of the output), chunks are dealt to per-XCD queues (largest
-  // first, to the queue with the least work) and the queues interleaved: the
-  // tiles of a chunk run on one XCD and share its L2.  Queues are padded
-  // with empty tiles (out = -1).
-  auto tile_list = [&](int tm, int tn, int chunk_tiles) {
-    std::vector<std::vector<GTile>> q(kXcds);
-    double load[kXcds] = {};
-    for (auto &w : work) {
-      const GOut &o = plan.outs[w.second];
-      const int nti = (o.m + tm - 1) / tm, ntj = (o.n + tn - 1) / tn;
-      const int rows = std::max(1, chunk_tiles / ntj);
-      for (int i0 = 0; i0 < nti; i0 += rows) {
-        const int i1 = std::min(nti, i0 + rows);
-        const int x = int(std::min_element(load, load + kXcds) - load);
-        load[x] += -w.first * double(i1 - i0) / nti;
-        for (int i = i0; i < i1; ++i)
-          for (int j = 0; j < ntj; ++j) q[x].push_back(GTile{w.second, int32_t(i), int32_t(j)});
-      }
+  std::vector<std::vector<GTile>> q(kXcds);
+  double load[kXcds] = {};
+  for (auto &w : work) {
+    const GOut &o = plan.outs[w.second];
+    const int nti = (o.m + tm - 1) / tm, ntj = (o.n + tn - 1) / tn;
+    const int rows = std::max(1, chunk_tiles / ntj);
+    for (int i0 = 0; i0 < nti; i0 += rows) {
+      const int i1 = std::min(nti, i0 + rows);
+      const int x = int(std::min_element(load, load + kXcds) - load);
+      load[x] += -w.first * double(i1 - i0) / nti;
+      for (int i = i0; i < i1; ++i)
+        for (int j = 0; j < ntj; ++j) q[x].push_back(GTile{w.second, int32_t(i), int32_t(j)});
     }
-    size_t maxq = 0;
-    for (auto &qq : q) maxq = std::max(maxq, qq.size());
-    std::vector<GTile> tiles;
-    for (size_t u = 0; u < maxq; ++u)
-      for (auto &qq : q) tiles.push_back(u < qq.size() ? qq[u] : GTile{-1, 0, 0});
-    while (!tiles.empty() && tiles.back().out < 0) tiles.pop_back();  // trailing empty workgroups are not launched
-    MDMRG_REQUIRE(tiles.size() < (size_t(1) << 31), -6, "grouped GEMM plan has too many tiles");
-    return tiles;
-  };
-  const std::vector<GTile> tiles = tile_list(kTileM, kTileN, 64), tiles128 = tile_list(128, 128, 16);
+  }
+  size_t maxq = 0;
+  for (auto &qq : q) maxq = std::max(maxq, qq.size());
+  std::vector<GTile> tiles;
+  for (size_t u = 0; u < maxq; ++u)
+    for (auto &qq : q) tiles.push_back(u < qq.size() ? qq[u] : GTile{-1, 0, 0});
+  while (!tiles.empty() && tiles.back().out < 0) tiles.pop_back();  // trailing empty workgroups are not launched
+  MDMRG_REQUIRE(tiles.size() < (size_t(1) << 31), -6, "grouped GEMM plan has too many tiles");
+  return tiles;
+}
+
+DevPlan *dev_plan_upload(Device *d, const GemmPlan &plan) {
+  plan_check(plan);
+  auto *dp = new DevPlan();
+  dp->n_outs = int64_t(plan.outs.size());
+  dp->n_segs = int64_t(plan.segs.size());
+  dp->flop = plan_flop(plan);  // algorithmic FLOP of the launch
+  const std::vector<GTile> tiles = plan_tiles(plan, kTileM, kTileN, 64), tiles128 = plan_tiles(plan, 128, 128, 16);
   dp->n_tiles = int64_t(tiles.size());
   dp->n_tiles128 = int64_t(tiles128.size());
   if (dp->n_tiles) {
@@ -905,6 +939,44 @@ void dev_gemm_run(Device *d, DevPlan *p, const Bases &b, int tag, int prec) {
     HIP_CHECK(hipEventRecord(e1, d->stream));
     d->pending.push_back(Device::Pending{tag, prec, v, e0, e1, p->flop});
   }
+}
+
+// Allocation-free form of dev_plan_upload + dev_gemm_run: the descriptors
+// and the tile list are copied into this device's static staging array
+// (kNoAllocStagingBytes) instead of allocations; the launch uses the forced
+// tile variant, else k_gemm_w4 (no autotuning trials, no timing events).
+// Waits for the launch, so the staging array is free again on return.  Calls
+// that overlap on one device (two host threads, or contexts on different
+// streams) race on the array.
+void dev_gemm_run_noalloc(Device *d, const GemmPlan &plan, const Bases &b) {
+  plan_check(plan);
+  const int v = d->force_variant >= 0 ? d->force_variant : 2;
+  const std::vector<GTile> tiles = plan_tiles(plan, v == 3 ? 128 : kTileM, v == 3 ? 128 : kTileN, v == 3 ? 16 : 64);
+  if (tiles.empty()) return;
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t b_segs = sizeof(GSeg) * std::max<size_t>(1, plan.segs.size());
+  const size_t b_outs = sizeof(GOut) * plan.outs.size(), b_tiles = sizeof(GTile) * tiles.size();
+  const size_t need = up(b_segs) + up(b_outs) + up(b_tiles);
+  if (need > kNoAllocStagingBytes)
+    throw Error(-1, "gemm_grouped_noalloc: the plan needs " + std::to_string(need) +
+                        " bytes of descriptors and tiles, above the static staging limit of " +
+                        std::to_string(kNoAllocStagingBytes) + " bytes");
+  MDMRG_REQUIRE(d->staging != nullptr, -4, "gemm_grouped_noalloc: no staging address for this device");
+  DevPlan p;
+  p.segs = reinterpret_cast<GSeg *>(d->staging);
+  p.outs = reinterpret_cast<GOut *>(d->staging + up(b_segs));
+  GTile *t = reinterpret_cast<GTile *>(d->staging + up(b_segs) + up(b_outs));
+  (v == 3 ? p.tiles128 : p.tiles) = t;
+  p.n_outs = int64_t(plan.outs.size());
+  p.n_segs = int64_t(plan.segs.size());
+  (v == 3 ? p.n_tiles128 : p.n_tiles) = int64_t(tiles.size());
+  if (!plan.segs.empty()) dev_h2d(d, p.segs, plan.segs.data(), sizeof(GSeg) * plan.segs.size());
+  dev_h2d(d, p.outs, plan.outs.data(), b_outs);
+  dev_h2d(d, t, tiles.data(), b_tiles);
+  launch_variant<double>(v, d->stream, &p, b);
+  HIP_CHECK(hipGetLastError());
+  // the host descriptor vectors and the staging array stay in use until here
+  dev_sync(d);
 }
 
 // ------------------------------------------------------------ graph capture

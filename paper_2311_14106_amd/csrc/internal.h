@@ -152,6 +152,12 @@ DevPlan *dev_plan_upload(Device *, const GemmPlan &);
 // variant v (no autotuning); -1: autotune per plan (default)
 void dev_force_variant(Device *, int v);
 void dev_plan_free(Device *, DevPlan *);
+// Bytes of the static per-device staging array of dev_gemm_run_noalloc.
+constexpr size_t kNoAllocStagingBytes = size_t(16) << 20;
+// FP64 grouped GEMM without any allocation: the plan goes into the static
+// staging array of the device, the launch uses the forced variant or
+// k_gemm_w4 and is waited for.  EINVAL (-1) if the plan does not fit.
+void dev_gemm_run_noalloc(Device *, const GemmPlan &, const Bases &);
 // prec 0: FP64 operands and results; prec 1 (FP32) and 2 (3xBF16): FP32
 // operands and results (base pointers then address float arrays with the
 // same element offsets)

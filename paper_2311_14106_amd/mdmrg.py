@@ -61,6 +61,9 @@ EXPORTS = {
     'mdmrg_gemm_grouped': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
                                           _c_i64_p, ctypes.c_int64, _c_i64_p, ctypes.c_int64, _c_i64_p,
                                           _c_dbl_p]),
+    'mdmrg_gemm_grouped_noalloc': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                                  _c_i64_p, ctypes.c_int64, _c_i64_p, ctypes.c_int64, _c_i64_p,
+                                                  _c_dbl_p]),
     'mdmrg_gemm_grouped_split': (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                                 ctypes.POINTER(ctypes.c_void_p), _c_i64_p, ctypes.c_int64,
                                                 _c_i64_p, ctypes.c_int64, _c_i64_p, _c_dbl_p]),
@@ -338,6 +341,22 @@ class Context:
             self._chk(self.lib.mdmrg_gemm_grouped_split(self.h, prec, nb, ptrs, lens.ctypes.data_as(_c_i64_p),
                                                         len(od), od.ctypes.data_as(_c_i64_p), len(sd),
                                                         sd.ctypes.data_as(_c_i64_p), _dp(al)))
+
+    def gemm_grouped_noalloc(self, buffers, out_desc, seg_desc, alpha):
+        """mdmrg_gemm_grouped_noalloc: the FP64 grouped GEMM of gemm_grouped
+        with its descriptors staged in the library's static per-GPU array
+        (no device allocation); same arguments as gemm_grouped in FP64."""
+        nb = len(buffers)
+        ptrs = (ctypes.c_void_p * nb)(*[device_ptr(b, self.device, None, 'torch.float64',
+                                                   f'gemm_grouped_noalloc buffer {i}').value
+                                        for i, b in enumerate(buffers)])
+        lens = np.array([b.numel() for b in buffers], dtype=np.int64)
+        od = np.ascontiguousarray(out_desc, dtype=np.int64).reshape(-1, 8)
+        sd = np.ascontiguousarray(seg_desc, dtype=np.int64).reshape(-1, 8)
+        al = np.ascontiguousarray(alpha, dtype=np.float64)
+        self._chk(self.lib.mdmrg_gemm_grouped_noalloc(self.h, nb, ptrs, lens.ctypes.data_as(_c_i64_p), len(od),
+                                                      od.ctypes.data_as(_c_i64_p), len(sd),
+                                                      sd.ctypes.data_as(_c_i64_p), _dp(al)))
 
     def stats(self):
         out = np.zeros(self.N_STATS)
