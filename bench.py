@@ -19,8 +19,10 @@ renormalised on the GPU.  Inputs are resident in HBM before timing starts.
 
 --workload spinless8x8 selects the spinless 8x8 torus (t=1, V=2, N=32,
 momentum basis rotated inside degenerate shells, dense two-body integrals)
-instead; --keep-envs 1 keeps the block environments of every bond visited
-(default 0: only those of the current bond and one step either way).
+instead; --keep-envs selects the blocks kept per bond (default 2: the left
+block of the current bond and every right block ahead, so the walk to the
+right never rebuilds a block; 3, for the 8x8 workload at D=4096, keeps only
+what one step to the right needs).
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
 the benchmark runs on one GPU.
@@ -338,8 +340,10 @@ def main():
     ap.add_argument('--compress', type=int, default=1,
                     help='interpolative compression of the cut coupling in the timed steps (the profile run '
                          'always uses it, so both settings see the same workload)')
-    ap.add_argument('--keep-envs', type=int, default=0,
-                    help='1: keep the block environments of every bond visited')
+    ap.add_argument('--keep-envs', type=int, default=2, choices=(0, 1, 2, 3),
+                    help='blocks kept per bond (MDMRG_OPT_KEEP_ENVS): 2 (default) a walk to the right (the '
+                         'left block of the bond and every right block ahead, built once from the chain end); '
+                         '3 one step to the right only (the D=4096 workload); 0 one step either way; 1 all')
     ap.add_argument('--tol', type=float, default=1e-7)
     ap.add_argument('--cpu-budget', type=float, default=15.0)
     ap.add_argument('--no-cpu', action='store_true')

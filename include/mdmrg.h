@@ -153,12 +153,19 @@ int mdmrg_get_bond(mdmrg_ctx ctx, int bond, int32_t *n_sect, int32_t *qn, int32_
 /* ------------------------------------------------------------------- bond */
 
 enum {
-  MDMRG_OPT_KEEP_ENVS = 1,     /* 1 (default): keep the operators of every block built;
-                                  0: mdmrg_prepare_bond keeps only the blocks of the
-                                  requested bond and of one step either way (left blocks
-                                  at bonds l-1 and l, right blocks at l+2 and l+3), for
-                                  large-D workloads; a farther move rebuilds from the
-                                  chain end */
+  MDMRG_OPT_KEEP_ENVS = 1,     /* which block operators mdmrg_prepare_bond keeps at bond l
+                                  (large-D workloads; a block that is needed later and
+                                  was dropped is rebuilt from the chain end):
+                                  1 (default): every block built;
+                                  0: this bond's and one step either way (left blocks at
+                                  bonds l-1 and l, right blocks at l+2 and l+3);
+                                  2: a walk to the right (left block at l, every right
+                                  block at bonds >= l+2);
+                                  3: one step to the right (left block at l, right blocks
+                                  at l+2 and l+3).
+                                  Right blocks are built before left ones, and the
+                                  operators a renormalisation forms on the fly are made
+                                  in batches of at most 2^28 doubles */
   MDMRG_OPT_SCRATCH_LIMIT = 2, /* doubles of intermediate storage per product pass
                                   (default 2^30); larger values mean fewer passes */
   MDMRG_OPT_GRAPH = 3,         /* 1: after the first products of a bond (which also

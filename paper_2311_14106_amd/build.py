@@ -1,6 +1,8 @@
-"""Build libmdmrg.so in-tree for gfx950 with hipcc.
+"""Build libmdmrg.so in-tree for gfx950 with hipcc, and the range-checking
+host-only variant libmdmrg_check.so (device layer replaced by
+csrc/device_check.cpp: no GPU, no arithmetic, every device access checked).
 
-Usage: python -m paper_2311_14106_amd.build   (or build() from Python)
+Usage: python -m paper_2311_14106_amd.build [--check]   (or build() / build_check())
 """
 import os
 import subprocess
@@ -44,5 +46,32 @@ def build(verbose=False):
     return OUT
 
 
+CHECK_OUT = os.path.join(HERE, 'libmdmrg_check.so')
+CHECK_SOURCES = ['device_check.cpp', 'model.cpp', 'engine.cpp', 'capi.cpp']
+
+
+def build_check(verbose=False):
+    """Host-only build with the range-checking device layer (g++, -O2)."""
+    objdir = os.path.join(HERE, '_build', 'check')
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    for src in CHECK_SOURCES:
+        obj = os.path.join(objdir, src + '.o')
+        cmd = [CXX, '-O2', '-fPIC', '-std=c++17', '-Wall', '-Wno-unused-result', '-pthread',
+               '-I', os.path.join(HERE, '..', 'include'), '-c', os.path.join(CSRC, src), '-o', obj]
+        if verbose:
+            print(' '.join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(obj)
+    tmp = CHECK_OUT + '.tmp'
+    cmd = [CXX, '-shared', '-fPIC', '-pthread', '-o', tmp] + objs
+    subprocess.check_call(cmd)
+    os.replace(tmp, CHECK_OUT)
+    return CHECK_OUT
+
+
 if __name__ == '__main__':
-    print(build(verbose='-v' in sys.argv))
+    if '--check' in sys.argv:
+        print(build_check(verbose='-v' in sys.argv))
+    else:
+        print(build(verbose='-v' in sys.argv))

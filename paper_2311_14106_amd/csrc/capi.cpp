@@ -232,7 +232,8 @@ int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value) {
     Context &c = ctx->c;
     switch (option) {
       case MDMRG_OPT_KEEP_ENVS:
-        c.keep_envs = value != 0;
+        MDMRG_REQUIRE(value >= 0 && value <= 3, MDMRG_EINVAL, "set_option: keep-envs mode must be 0..3");
+        c.keep_envs = int(value);
         break;
       case MDMRG_OPT_SCRATCH_LIMIT:
         MDMRG_REQUIRE(value >= (int64_t(1) << 20), MDMRG_EINVAL, "set_option: scratch limit below 2^20 doubles");

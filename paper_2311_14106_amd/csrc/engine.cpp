@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <limits>
 #include <numeric>
 #include <unordered_map>
 #include <unordered_set>
@@ -601,7 +602,8 @@ static void add_item(Recipe &r, OpRef ref, const std::vector<double> &M, int par
 }
 
 static void renorm_execute(Context &C, bool left, int site, OpSet &Bp, const OpSet &env, const OpSet *combo,
-                           const std::unordered_map<uint64_t, Recipe> &recipes) {
+                           const std::unordered_map<uint64_t, Recipe> &recipes,
+                           const std::vector<uint64_t> *keys = nullptr) {
   const Hamiltonian &H = C.ham;
   const int d = H.d;
   const Bond &bo = C.bonds[left ? site : site + 1];  // old block bond
@@ -610,7 +612,7 @@ static void renorm_execute(Context &C, bool left, int site, OpSet &Bp, const OpS
   std::vector<PairTask> tasks;
   std::vector<OutBlk> outs;
   GemmPlan direct;  // identity X: Y += alpha op(A) op(B), one GEMM each
-  for (uint64_t key : Bp.order) {
+  for (uint64_t key : keys ? *keys : Bp.order) {
     auto rit = recipes.find(key);
     if (rit == recipes.end()) continue;
     const auto [g, idx] = Bp.ops.at(key);
@@ -723,7 +725,10 @@ static void renorm_execute(Context &C, bool left, int site, OpSet &Bp, const OpS
     }
   }
   TwoPhasePlan plan;
-  build_two_phase(tasks, outs, C.scratch_limit, plan, C.dev);
+  // intermediates of the renormalisation products in passes of at most the
+  // combination limit, so that an environment build holds little besides
+  // the old and the new block
+  build_two_phase(tasks, outs, std::min(C.scratch_limit, C.ren_combo_limit), plan, C.dev);
   if (!direct.outs.empty()) {
     Chunk ch;
     ch.p2 = dev_plan_upload(C.dev, direct);
@@ -768,6 +773,74 @@ static void renorm_execute(Context &C, bool left, int site, OpSet &Bp, const OpS
   plan.release(C.dev);
 }
 
+// Elements of one block operator with quantum-number shift delta on bond b
+// (the group size of OpSet::layout).
+static int64_t op_elems(const Bond &b, QN delta) {
+  int64_t n = 0;
+  for (size_t c = 0; c < b.qn.size(); ++c) {
+    const int r = b.find(b.qn[c] + delta);
+    if (r >= 0) n += int64_t(b.dim[r]) * b.dim[c];
+  }
+  return n;
+}
+
+// Renormalise the recipes of the new block Bp in batches of its operators.
+// The on-the-fly combinations of the old block's operators that a batch
+// reads (a3: one grouped GEMM per shift group) are formed for that batch
+// only and released after its products, so their storage stays below
+// `limit` doubles (or one batch's need) however many operators the block
+// holds: at large D a block carries thousands of operators of tens of MB.
+// The split-precision forms convert the whole new block once, so they run
+// as a single batch.
+static void renorm_batched(Context &C, bool left, int site, OpSet &Bp, const OpSet &env, int content_bond,
+                           const std::unordered_map<uint64_t, Recipe> &rec) {
+  const Hamiltonian &H = C.ham;
+  const int64_t limit = C.ren_prec == 0 ? C.ren_combo_limit : std::numeric_limits<int64_t>::max();
+  std::vector<std::vector<uint64_t>> batches(1);
+  std::vector<std::set<uint64_t>> wanted(1);
+  int64_t acc = 0;
+  for (uint64_t key : Bp.order) {
+    auto it = rec.find(key);
+    if (it == rec.end()) continue;
+    for (int pass = 0; pass < 2; ++pass) {
+      int64_t need = 0;
+      for (auto &item : it->second.items)
+        if (item.first.src == 2 && !wanted.back().count(item.first.key))
+          need += op_elems(*env.bond, combo_delta(H, left, item.first.key));
+      if (pass == 0 && acc + need > limit && !batches.back().empty()) {
+        batches.emplace_back();
+        wanted.emplace_back();
+        acc = 0;
+        continue;
+      }
+      acc += need;
+      for (auto &item : it->second.items)
+        if (item.first.src == 2) wanted.back().insert(item.first.key);
+      batches.back().push_back(key);
+      break;
+    }
+  }
+  // content of every combination read by any batch (host only), in one pass
+  // over the terms; each batch materialises its own keys from it
+  std::set<uint64_t> all;
+  for (auto &w : wanted) all.insert(w.begin(), w.end());
+  Content content;
+  combo_content(H, left, content_bond, all, content);
+  for (size_t b = 0; b < batches.size(); ++b) {
+    if (batches[b].empty()) continue;
+    std::unique_ptr<OpSet> X;
+    if (!wanted[b].empty()) {
+      X = std::make_unique<OpSet>();
+      X->bond = env.bond;
+      for (uint64_t k : wanted[b]) X->add(k, combo_delta(H, left, k));
+      X->layout(C.dev);
+      materialize(C.dev, *X, env, content);
+    }
+    renorm_execute(C, left, site, Bp, env, X.get(), rec, &batches[b]);
+    if (X) X->release(C.dev);
+  }
+}
+
 // L(bond site) + site -> L(bond site+1), with A[site] a left isometry
 std::unique_ptr<OpSet> Context::renorm_left(const OpSet &L, int site) {
   const Hamiltonian &H = ham;
@@ -777,7 +850,6 @@ std::unique_ptr<OpSet> Context::renorm_left(const OpSet &L, int site) {
   need_left(H, site + 1, *Lp);
   Lp->layout(dev);
   std::unordered_map<uint64_t, Recipe> rec;
-  std::set<uint64_t> wanted;
   std::vector<double> I(d * d, 0.0);
   for (int s = 0; s < d; ++s) I[s * d + s] = 1.0;
   const uint64_t kH = make_key(K_H, nullptr, 0);
@@ -789,7 +861,6 @@ std::unique_ptr<OpSet> Context::renorm_left(const OpSet &L, int site) {
     const uint64_t sk = make_key(K_N, es, ks);
     if (!seen.insert({src, sk ^ (newkey * 0x9E3779B97F4A7C15ull)}).second) return;
     add_item(rec[newkey], src, H.site_matrix(site, es, ks), ks & 1, 1.0);
-    if (src.src == 2) wanted.insert(src.key);
   };
   for (const Term &t : H.terms) {
     Parts p;
@@ -838,19 +909,8 @@ std::unique_ptr<OpSet> Context::renorm_left(const OpSet &L, int site) {
       add_item(rec[key], OpRef{1, make_key(K_N, e, kin)}, H.site_matrix(site, e + kin, n - kin), (n - kin) & 1, 1.0);
     }
   }
-  // combos of L needed by the recipes
-  std::unique_ptr<OpSet> X;
-  if (!wanted.empty()) {
-    X = std::make_unique<OpSet>();
-    X->bond = L.bond;
-    for (uint64_t k : wanted) X->add(k, combo_delta(H, true, k));
-    X->layout(dev);
-    Content content;
-    combo_content(H, true, site, wanted, content);
-    materialize(dev, *X, L, content);
-  }
-  renorm_execute(*this, true, site, *Lp, L, X.get(), rec);
-  if (X) X->release(dev);
+  // with the combos of L that the recipes read, formed per batch
+  renorm_batched(*this, true, site, *Lp, L, site, rec);
   return Lp;
 }
 
@@ -863,7 +923,6 @@ std::unique_ptr<OpSet> Context::renorm_right(const OpSet &R, int site) {
   need_right(H, site, *Rp);
   Rp->layout(dev);
   std::unordered_map<uint64_t, Recipe> rec;
-  std::set<uint64_t> wanted;
   std::vector<double> I(d * d, 0.0);
   for (int s = 0; s < d; ++s) I[s * d + s] = 1.0;
   const uint64_t kH = make_key(K_H, nullptr, 0);
@@ -874,7 +933,6 @@ std::unique_ptr<OpSet> Context::renorm_right(const OpSet &R, int site) {
     const uint64_t sk = make_key(K_N, es, ks);
     if (!seen.insert({src, sk ^ (newkey * 0x9E3779B97F4A7C15ull)}).second) return;
     add_item(rec[newkey], src, H.site_matrix(site, es, ks), ks & 1, 1.0);
-    if (src.src == 2) wanted.insert(src.key);
   };
   for (const Term &t : H.terms) {
     // parts relative to the new block: outside (< site), site, R (> site)
@@ -920,18 +978,7 @@ std::unique_ptr<OpSet> Context::renorm_right(const OpSet &R, int site) {
     else
       add_item(rec[key], OpRef{1, key}, I, 0, 1.0);
   }
-  std::unique_ptr<OpSet> X;
-  if (!wanted.empty()) {
-    X = std::make_unique<OpSet>();
-    X->bond = R.bond;
-    for (uint64_t k : wanted) X->add(k, combo_delta(H, false, k));
-    X->layout(dev);
-    Content content;
-    combo_content(H, false, site + 1, wanted, content);
-    materialize(dev, *X, R, content);
-  }
-  renorm_execute(*this, false, site, *Rp, R, X.get(), rec);
-  if (X) X->release(dev);
+  renorm_batched(*this, false, site, *Rp, R, site + 1, rec);
   return Rp;
 }
 
@@ -1030,39 +1077,49 @@ void Context::prepare(int l) {
     e.reset();
   };
   bool built = false;
-  if (!Lenv[l]) {
-    built = true;
-    int i0 = l;
-    while (i0 > 0 && !Lenv[i0]) --i0;
-    if (!Lenv[i0]) Lenv[i0] = env_boundary(true, i0);
-    const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
-    for (int i = i0; i < l; ++i) {
-      Lenv[i + 1] = renorm_left(*Lenv[i], i);
-      if (verbose) fprintf(stderr, "[mdmrg] left block at bond %d built\n", i + 1);
-      if (!keep_envs && i + 1 < l) drop(Lenv[i]);
-    }
+  const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
+  // the builds start from the nearest existing block on each side
+  int li = l, ri = l + 2;
+  while (li > 0 && !Lenv[li]) --li;
+  while (ri < n && !Renv[ri]) ++ri;
+  // blocks kept at this bond (MDMRG_OPT_KEEP_ENVS): 1 every block built;
+  // 0 this bond's and one step either way (L at l-1, l; R at l+2, l+3);
+  // 2 a walk to the right (L at l; every R at bonds >= l+2, so each later
+  // step finds its right block); 3 one step to the right (L at l; R at l+2,
+  // l+3).  Blocks outside the set are dropped before any build, and each
+  // source block once the next one is built.
+  auto keepL = [&](int j) { return keep_envs == 1 || j == l || (keep_envs == 0 && j == l - 1); };
+  auto keepR = [&](int j) {
+    return keep_envs == 1 || j == l + 2 || (keep_envs == 2 && j > l + 2) ||
+           ((keep_envs == 0 || keep_envs == 3) && j == l + 3);
+  };
+  for (int j = 0; j <= n; ++j) {
+    if (!keepL(j) && j != li) drop(Lenv[j]);
+    if (!keepR(j) && j != ri) drop(Renv[j]);
   }
+  // right blocks first: they carry the complementary operators with two
+  // outside indices, the largest blocks of the chain, and are built while no
+  // left block of this bond holds memory yet
   if (!Renv[l + 2]) {
     built = true;
-    int i0 = l + 2;
-    while (i0 < n && !Renv[i0]) ++i0;
-    if (!Renv[i0]) Renv[i0] = env_boundary(false, i0);
-    const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
-    for (int i = i0 - 1; i >= l + 2; --i) {
+    if (!Renv[ri]) Renv[ri] = env_boundary(false, ri);
+    for (int i = ri - 1; i >= l + 2; --i) {
       Renv[i] = renorm_right(*Renv[i + 1], i);
       if (verbose) fprintf(stderr, "[mdmrg] right block at bond %d built\n", i);
-      if (!keep_envs && i + 1 > l + 3) drop(Renv[i + 1]);
+      if (!keepR(i + 1)) drop(Renv[i + 1]);
     }
   }
-  if (!keep_envs) {
-    // keep the blocks of this bond and of one step in either direction
-    // (L at bonds l-1, l; R at bonds l+2, l+3), so that the next step of a
-    // sweep needs no rebuild from the chain end
-    for (int j = 0; j <= n; ++j) {
-      if (j != l - 1 && j != l) drop(Lenv[j]);
-      if (j != l + 2 && j != l + 3) drop(Renv[j]);
+  if (!Lenv[l]) {
+    built = true;
+    if (!Lenv[li]) Lenv[li] = env_boundary(true, li);
+    for (int i = li; i < l; ++i) {
+      Lenv[i + 1] = renorm_left(*Lenv[i], i);
+      if (verbose) fprintf(stderr, "[mdmrg] left block at bond %d built\n", i + 1);
+      if (!keepL(i)) drop(Lenv[i]);
     }
   }
+  if (!keepL(li)) drop(Lenv[li]);
+  if (!keepR(ri)) drop(Renv[ri]);
   if (built) dev_sync(dev);  // environment builds are timed as Ren
   stats.t_ren += wall_seconds() - t0;
   build_heff(l);
@@ -2318,6 +2375,12 @@ void Context::renormalize(int dir, int prec) {
   const int nl = l + dir;
   MDMRG_REQUIRE(nl >= 0 && nl + 1 < n, -1, "renormalize: no bond beyond the chain end");
   double t0 = wall_seconds();
+  // the products of this bond are done: its plans, combinations, FP32
+  // shadows and graphs are released before the new block is allocated
+  // (the wave-function layout is kept for the start vector)
+  const PsiLayout old_psi = psi;
+  release_bond();
+  cur = l;
   ren_prec = prec;
   try {
     if (dir > 0) {
@@ -2334,7 +2397,7 @@ void Context::renormalize(int dir, int prec) {
   // these launches (its first plan upload waits for the stream), so Ren
   // counts the host side of the renormalisation and Tables the rest
   stats.t_ren += wall_seconds() - t0;
-  prev_psi = psi;
+  prev_psi = old_psi;
   prev_l = l;
   prev_dir = dir;
   prepare(nl);

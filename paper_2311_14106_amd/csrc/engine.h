@@ -186,7 +186,10 @@ struct Context {
   int64_t heff_terms = 0;
   Stats stats;
   int64_t scratch_limit = int64_t(1) << 30;  // doubles of phase-1 scratch (8 GB)
-  bool keep_envs = true;  // keep every block environment built (needed by sweeps)
+  // doubles of on-the-fly combinations formed at once by a renormalisation
+  // (the new block's operators are renormalised in batches that fit)
+  int64_t ren_combo_limit = int64_t(1) << 28;
+  int keep_envs = 1;  // blocks kept per bond (MDMRG_OPT_KEEP_ENVS): 1 all, 0/2/3 see prepare()
   bool compress = true;    // interpolative compression of the N^L x C^R products
   // graph replay of the H_eff product (MDMRG_OPT_GRAPH): captured per bond and
   // precision once the first products have tuned the kernel variants
