@@ -22,6 +22,11 @@ The oracle is deliberately slow and literal:
   Davidson.
 * ``split``      -- the split-precision product model (FP32 and 3xBF16
   hi/lo products) evaluated in FP64, for the kernel tests of those forms.
+* ``su2``        -- Clebsch-Gordan coefficients and 6j symbols in exact
+  rational arithmetic (Racah formulas), SU(2) multiplet bases of small
+  spin-1/2 fermion blocks, Wigner-Eckart reduced elements and the 6j
+  product rule of coupled operators (the algebra of the spin-adapted form,
+  Sec. IV).
 
 Pins (closed forms, brute force on tiny inputs, basis invariance) live in
 ``tests/test_oracle_*.py``.
