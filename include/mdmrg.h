@@ -186,12 +186,15 @@ enum {
                                   fastest; 0..3: every launch of the context uses that
                                   variant (k_gemm, k_gemm_w16, k_gemm_w4, k_gemm_t128;
                                   all give bitwise identical results) */
-  MDMRG_OPT_MEMORY_BUDGET = 6  /* bytes of device memory the context may hold (its
+  MDMRG_OPT_MEMORY_BUDGET = 6, /* bytes of device memory the context may hold (its
                                   operator arenas, wave-function buffers, scratch and
                                   plans); an allocation beyond it fails with
                                   MDMRG_ENOMEM before reaching the allocator.  0 (and
                                   the upper limit): 95% of the device memory free at
                                   mdmrg_create */
+  MDMRG_OPT_DAVIDSON_KEEP = 7  /* Ritz vectors (lowest first) kept when the Davidson
+                                  subspace reaches m_max and is restarted, 2..58 (default
+                                  2; at most m_max - 2 are kept) */
 };
 /* Set a context option (EINVAL for unknown options or bad values).
  * With the environment variable MDMRG_VERBOSE set, the library prints

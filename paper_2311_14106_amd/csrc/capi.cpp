@@ -249,6 +249,10 @@ int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value) {
         MDMRG_REQUIRE(value >= 0, MDMRG_EINVAL, "set_option: negative memory budget");
         dev_set_budget(c.dev, size_t(value));
         break;
+      case MDMRG_OPT_DAVIDSON_KEEP:
+        MDMRG_REQUIRE(value >= 2 && value <= 58, MDMRG_EINVAL, "set_option: Davidson restart size must be 2..58");
+        c.davidson_keep = int(value);
+        break;
       case MDMRG_OPT_GEMM_VARIANT:
         MDMRG_REQUIRE(value >= -1 && value < kGemmVariants, MDMRG_EINVAL, "set_option: no such tile variant");
         dev_force_variant(c.dev, int(value));

@@ -208,8 +208,21 @@ void *dev_alloc(Device *d, size_t bytes) {
   void *p = nullptr;
   hipError_t e = hipMallocAsync(&p, bytes, d->stream);
   if (e != hipSuccess || !p) {
+    // the stream-ordered pool keeps freed blocks reserved: once the stream
+    // has drained, return them to the device and try once more (a large
+    // workload frees and allocates blocks of ~100 GB in turn)
     (void)hipGetLastError();
-    throw Error(-2, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    HIP_CHECK(hipStreamSynchronize(d->stream));
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, d->id) == hipSuccess && pool) (void)hipMemPoolTrimTo(pool, 0);
+    (void)hipGetLastError();
+    p = nullptr;
+    e = hipMallocAsync(&p, bytes, d->stream);
+  }
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error(-2, "device allocation of " + std::to_string(bytes) + " bytes failed (" +
+                        std::to_string(d->live_bytes) + " bytes in use by the context)");
   }
   d->live[p] = bytes;
   d->live_bytes += bytes;

@@ -1821,28 +1821,27 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
       }
     }
     if (nv == m_max) {
-      // thick restart to the two lowest Ritz vectors
-      std::vector<double> y1(nv);
-      for (int i = 0; i < nv; ++i) y1[i] = Y[i * nv + 1];
-      double *tv = r;  // reuse r as temporary after saving
+      // thick restart to the lowest Ritz vectors (x first): their products
+      // follow from the stored ones, so the restart costs no product
+      const int keep = std::max(2, std::min(davidson_keep, m_max - 2));
       DevVecs tmp(dev);
-      double *tav = tmp.get(N);
-      dev_lincomb(dev, V, N, nv, y1.data(), 0.0, tv, N);
-      dev_lincomb(dev, AV, N, nv, y1.data(), 0.0, tav, N);
-      dev_d2d(dev, V, x, sizeof(double) * N);
-      dev_d2d(dev, AV, ax, sizeof(double) * N);
-      dev_d2d(dev, V + N, tv, sizeof(double) * N);
-      dev_d2d(dev, AV + N, tav, sizeof(double) * N);
+      double *tv = tmp.get(int64_t(keep) * N), *tav = tmp.get(int64_t(keep) * N);
+      std::vector<double> yk(nv);
+      for (int c = 0; c < keep; ++c) {
+        for (int i = 0; i < nv; ++i) yk[i] = Y[i * nv + c];
+        dev_lincomb(dev, V, N, nv, yk.data(), 0.0, tv + int64_t(c) * N, N);
+        dev_lincomb(dev, AV, N, nv, yk.data(), 0.0, tav + int64_t(c) * N, N);
+      }
+      dev_d2d(dev, V, tv, sizeof(double) * N * keep);
+      dev_d2d(dev, AV, tav, sizeof(double) * N * keep);
       std::fill(Hs.begin(), Hs.end(), 0.0);
-      double h[2];
-      dev_multidot(dev, V, N, 2, AV, N, h);
-      Hs[0] = h[0];
-      dev_multidot(dev, V, N, 2, AV + N, N, h);
-      Hs[1] = h[0];
-      Hs[m_max + 1] = h[1];
-      Hs[m_max] = h[0];
-      nv = 2;
-      // recompute residual of x
+      std::vector<double> h(keep);
+      for (int j = 0; j < keep; ++j) {
+        dev_multidot(dev, V, N, keep, AV + int64_t(j) * N, N, h.data());
+        for (int i = 0; i < keep; ++i) Hs[i * m_max + j] = h[i];
+      }
+      nv = keep;
+      // residual of x (the first kept vector)
       dev_d2d(dev, r, ax, sizeof(double) * N);
       dev_axpy(dev, -theta, x, r, N);
     }

@@ -189,6 +189,9 @@ struct Context {
   // doubles of on-the-fly combinations formed at once by a renormalisation
   // (the new block's operators are renormalised in batches that fit)
   int64_t ren_combo_limit = int64_t(1) << 28;
+  // Ritz vectors kept at a thick restart of the Davidson subspace
+  // (MDMRG_OPT_DAVIDSON_KEEP)
+  int davidson_keep = 2;
   int keep_envs = 1;  // blocks kept per bond (MDMRG_OPT_KEEP_ENVS): 1 all, 0/2/3 see prepare()
   bool compress = true;    // interpolative compression of the N^L x C^R products
   // graph replay of the H_eff product (MDMRG_OPT_GRAPH): captured per bond and
