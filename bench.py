@@ -426,7 +426,7 @@ def main():
     # the grouped GEMM kernel in the timed FP64 H_eff products (HIP events on
     # the library stream around every launch)
     name = ('k_gemm<double> family (autotuned per plan: 64x64 tiles over 2x4, 4x4 or 2x2 waves -- k_gemm, '
-            'k_gemm_w16, k_gemm_w4 -- or 128x128 tiles over 2x2 waves, k_gemm_t128)')
+            'k_gemm_w16, k_gemm_w4 -- or 128x128 tiles over 2x4 waves, k_gemm_t128)')
     kernels = mdmrg.Context.KERNELS
     k_ms, k_launch, k_flop = d['heff_kernel_ms'], max(1.0, d['heff_kernel_launches']), d['heff_kernel_flop']
     achieved_tf = k_flop / (k_ms * 1e-3) / 1e12 if k_ms > 0 else 0.0

@@ -192,9 +192,16 @@ enum {
                                   MDMRG_ENOMEM before reaching the allocator.  0 (and
                                   the upper limit): 95% of the device memory free at
                                   mdmrg_create */
-  MDMRG_OPT_DAVIDSON_KEEP = 7  /* Ritz vectors (lowest first) kept when the Davidson
+  MDMRG_OPT_DAVIDSON_KEEP = 7, /* Ritz vectors (lowest first) kept when the Davidson
                                   subspace reaches m_max and is restarted, 2..58 (default
                                   2; at most m_max - 2 are kept) */
+  MDMRG_OPT_DAVIDSON_OLSEN = 8, /* 1: Olsen's correction vector t = P r - eps P x,
+                                  eps = (x.P r)/(x.P x), P = (theta - diag H_eff)^-1;
+                                  0 (default): t = P r */
+  MDMRG_OPT_MIXED_LADDER = 9   /* 1: a mixed solve with prec_split MDMRG_BF16X3 runs an
+                                  FP32 stage (to tol_split or its own noise floor)
+                                  between the 3xBF16 and the FP64 stages; 0 (default):
+                                  3xBF16 then FP64 */
 };
 /* Set a context option (EINVAL for unknown options or bad values).
  * With the environment variable MDMRG_VERBOSE set, the library prints
@@ -273,9 +280,10 @@ int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max
  * and Fig. 2, with the final eigenpair held to FP64 accuracy): a Davidson
  * solve whose products use the split
  * form prec_split (MDMRG_FP32 or MDMRG_BF16X3) until its residual reaches
- * tol_split or stops decreasing (no 10% gain over 24 products, or over 4
- * once within 2f), then an FP64 Davidson from that vector until the FP64
- * residual <= tol.  f is the noise floor of the split operator, measured
+ * tol_split or stops decreasing (no 10% gain over 4 products once within
+ * 2f, over 24 within 20f, over 64 elsewhere), then (MDMRG_OPT_MIXED_LADDER,
+ * 3xBF16 only) an FP32 stage the same way, then an FP64 Davidson from that
+ * vector until the FP64 residual <= tol.  f is the noise floor of the split operator, measured
  * with one split and one FP64 product of the normalised start vector x0:
  * f = |(H_split - H) x0| / |H x0| * |x0.H x0|.  *n_mv64 and *n_mv_split
  * count the products of each kind (the floor probe included). */

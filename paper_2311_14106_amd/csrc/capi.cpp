@@ -253,6 +253,12 @@ int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value) {
         MDMRG_REQUIRE(value >= 2 && value <= 58, MDMRG_EINVAL, "set_option: Davidson restart size must be 2..58");
         c.davidson_keep = int(value);
         break;
+      case MDMRG_OPT_DAVIDSON_OLSEN:
+        c.davidson_olsen = value != 0;
+        break;
+      case MDMRG_OPT_MIXED_LADDER:
+        c.mixed_ladder = value != 0;
+        break;
       case MDMRG_OPT_GEMM_VARIANT:
         MDMRG_REQUIRE(value >= -1 && value < kGemmVariants, MDMRG_EINVAL, "set_option: no such tile variant");
         dev_force_variant(c.dev, int(value));

@@ -353,11 +353,14 @@ template <class T>
 using Cfg64w = TileCfg<64, 64, 4, 4, KStep<T>::wide>;  // variant 1, k_gemm_w16: 16 waves of 16x16
 template <class T>
 using Cfg64q = TileCfg<64, 64, 2, 2, KStep<T>::small>;  // variant 2, k_gemm_w4: 4 waves of 32x32
-// variant 3, k_gemm_t128: 128x128 outputs per workgroup, 4 waves of 64x64
-// (twice the operand reuse per fetched byte of the 64x64 tiles; its own
-// tile list)
+// variant 3, k_gemm_t128: 128x128 outputs per workgroup, 8 waves (2 x 4) of
+// 64x32 (twice the operand reuse per fetched byte of the 64x64 tiles; its
+// own tile list).  Eight waves keep 4 (FP64, 3xBF16) or 5 (FP32) waves per
+// SIMD; four waves of 64x64 held two and measured 9-55% slower per product
+// (6x6 Hubbard, D=2048: FP64 62.9 -> 57.8 ms, FP32 53.2 -> 34.4 ms, 3xBF16
+// 32.7 -> 23.3 ms).
 template <class T>
-using Cfg128 = TileCfg<128, 128, 2, 2, KStep<T>::small>;
+using Cfg128 = TileCfg<128, 128, 2, 4, KStep<T>::small>;
 constexpr int kTileM = 64, kTileN = 64;  // output tile of variants 0-2 (variant 3: 128 x 128)
 constexpr int kPad = 2;  // LDS row padding (doubles) of the staged A / B tiles
 
@@ -747,24 +750,13 @@ __global__ __launch_bounds__(Cfg64q<T>::NT) void k_gemm_w4(const GTile *__restri
   gemm_any<T, Cfg64q<T>>(tiles, outs, segs, bases);
 }
 
-// 128x128 tiles: FP64 and FP32 are held to 256 registers per lane (2 waves
-// per SIMD, accumulators in VGPRs, no spills); the 3xBF16 form fits that
-// without the bound (49 KB of LDS stages per workgroup).
+// 128x128 tiles: 118 (FP64), 92 (FP32) and 115 (3xBF16) registers per lane,
+// 33 KB (FP64, FP32) and 48 KB (3xBF16) of LDS stages per workgroup.
 template <class T>
 __global__ __launch_bounds__(Cfg128<T>::NT) void k_gemm_t128(const GTile *__restrict__ tiles,
                                                           const GOut *__restrict__ outs,
                                                           const GSeg *__restrict__ segs, Bases bases) {
   gemm_any<T, Cfg128<T>>(tiles, outs, segs, bases);
-}
-template <>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_t128<double>(
-    const GTile *__restrict__ tiles, const GOut *__restrict__ outs, const GSeg *__restrict__ segs, Bases bases) {
-  gemm_any<double, Cfg128<double>>(tiles, outs, segs, bases);
-}
-template <>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_t128<float>(
-    const GTile *__restrict__ tiles, const GOut *__restrict__ outs, const GSeg *__restrict__ segs, Bases bases) {
-  gemm_any<float, Cfg128<float>>(tiles, outs, segs, bases);
 }
 
 template <class T>

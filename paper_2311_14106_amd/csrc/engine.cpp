@@ -1761,6 +1761,7 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
   double *dg = work.get(N);
   double *r = work.get(N);
   double *ax = work.get(N);
+  double *px = davidson_olsen ? work.get(N) : nullptr;
   heff_diag(dg);
   // start vector
   double nrm;
@@ -1811,12 +1812,15 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
     }
     if (stall_floor >= 0.0) {
       // the split-precision operator has a noise floor: stop once the
-      // residual has not dropped by 10% over the last 24 products, or over
-      // the last 4 once it is within twice the measured floor
+      // residual has not dropped by 10% over the last 4 products within
+      // twice the measured floor, over 24 within 20 times it, and over 64
+      // elsewhere (far above the floor a plateau is slow convergence, e.g.
+      // after a restart, not the floor)
+      const int window = rn <= 2.0 * stall_floor ? 4 : rn <= 20.0 * stall_floor ? 24 : 64;
       if (rn < 0.9 * best_r) {
         best_r = rn;
         best_at = nmv;
-      } else if (nmv - best_at >= (rn <= 2.0 * stall_floor ? 4 : 24)) {
+      } else if (nmv - best_at >= window) {
         break;
       }
     }
@@ -1845,9 +1849,18 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
       dev_d2d(dev, r, ax, sizeof(double) * N);
       dev_axpy(dev, -theta, x, r, N);
     }
-    // correction vector
+    // correction vector: t = P r with P = (theta - diag H)^-1 (Davidson);
+    // with the Olsen variant t = P r - eps P x, eps = (x.P r)/(x.P x), which
+    // removes the component of the correction that merely rescales x
     double *t = V + int64_t(nv) * N;
     dev_precond(dev, r, dg, theta, 1e-8, t, N);
+    if (davidson_olsen) {
+      dev_precond(dev, x, dg, theta, 1e-8, px, N);
+      double xt = 0.0, xp = 0.0;
+      dev_multidot(dev, x, 0, 1, t, N, &xt);
+      dev_multidot(dev, x, 0, 1, px, N, &xp);
+      if (std::fabs(xp) > 1e-300) dev_axpy(dev, -xt / xp, px, t, N);
+    }
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<double> c(nv);
       dev_multidot(dev, V, N, nv, t, N, c.data());
@@ -1907,7 +1920,7 @@ int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_sp
   // stagnates; within twice the floor it stops after 4 products without a
   // 10% gain (24 elsewhere), since there split iterations do little for the
   // FP64 residual.
-  double floor = 0.0;
+  double floor = 0.0, floor32 = 0.0;
   int probe = 0;
   {
     const int64_t N = psi.n_elem;
@@ -1926,14 +1939,33 @@ int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_sp
       dev_multidot(dev, b, 0, 1, b, N, &h2);
       dev_multidot(dev, v, 0, 1, b, N, &th);
       if (h2 > 0.0 && std::isfinite(d2)) floor = std::sqrt(d2 / h2) * std::fabs(th);
+      if (prec_split == 2 && mixed_ladder) {
+        // floor of the FP32 stage from one FP32 product of the same vector
+        heff_apply(v, a, 1);
+        dev_axpy(dev, -1.0, b, a, N);
+        dev_multidot(dev, a, 0, 1, a, N, &d2);
+        if (h2 > 0.0 && std::isfinite(d2)) floor32 = std::max(1e-300, std::sqrt(d2 / h2) * std::fabs(th));
+      }
       probe = 1;
     }
   }
   double e = 0.0, r = 0.0;
   int ns = 0, n64 = 0;
+  const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
   davidson(x, std::max(tol, tol_split), max_iter, m_max, &e, &r, &ns, prec_split, floor);
+  if (verbose)
+    fprintf(stderr, "[mdmrg] mixed: split stage %d products, |r| = %.3e (floor %.3e)\n", ns, r, floor);
+  if (prec_split == 2 && mixed_ladder) {
+    // FP32 stage between the 3xBF16 and the FP64 solves: it takes the
+    // residual from the 3xBF16 floor down towards tol_split at FP32 cost
+    int n32 = 0;
+    davidson(x, std::max(tol, tol_split), max_iter, m_max, &e, &r, &n32, 1, floor32);
+    ns += n32;
+    if (verbose)
+      fprintf(stderr, "[mdmrg] mixed: FP32 stage %d products, |r| = %.3e (floor %.3e)\n", n32, r, floor32);
+  }
   const int st = davidson(x, tol, max_iter, m_max, &e, &r, &n64, 0);
-  ns += probe;
+  ns += probe + (floor32 > 0.0 ? 1 : 0);
   n64 += probe;
   if (energy) *energy = e;
   if (resid) *resid = r;

@@ -192,6 +192,9 @@ struct Context {
   // Ritz vectors kept at a thick restart of the Davidson subspace
   // (MDMRG_OPT_DAVIDSON_KEEP)
   int davidson_keep = 2;
+  bool davidson_olsen = false;  // Olsen correction (MDMRG_OPT_DAVIDSON_OLSEN)
+  // 3xBF16 mixed solves pass through an FP32 stage (MDMRG_OPT_MIXED_LADDER)
+  bool mixed_ladder = false;
   int keep_envs = 1;  // blocks kept per bond (MDMRG_OPT_KEEP_ENVS): 1 all, 0/2/3 see prepare()
   bool compress = true;    // interpolative compression of the N^L x C^R products
   // graph replay of the H_eff product (MDMRG_OPT_GRAPH): captured per bond and
@@ -217,8 +220,9 @@ struct Context {
   void heff_diag(double *d);
   // prec: matrix-vector precision (0 FP64, 1 FP32, 2 3xBF16); stall_floor
   // >= 0: stop when the residual stops decreasing (split-precision phase):
-  // no 10% gain over 24 products, or over 4 once the residual is within
-  // twice stall_floor (the measured noise floor of the split operator)
+  // no 10% gain over 4 products within twice stall_floor (the measured
+  // noise floor of the split operator), over 24 within 20 times it, over 64
+  // elsewhere
   int davidson(double *x, double tol, int max_iter, int m_max, double *energy, double *resid, int *n_mv,
                int prec = 0, double stall_floor = -1.0);
   // split-precision Davidson to tol_split, then FP64 Davidson to tol

@@ -126,7 +126,7 @@ size_t dev_live_bytes(Device *);
 
 // Tile variants of the grouped kernel: 64x64 output tiles (one tile list)
 // split over waves as 0 k_gemm (2x4 waves), 1 k_gemm_w16 (4x4), 2 k_gemm_w4
-// (2x2); 3 k_gemm_t128, 128x128 tiles (their own tile list) over 2x2 waves.
+// (2x2); 3 k_gemm_t128, 128x128 tiles (their own tile list) over 2x4 waves.
 constexpr int kGemmVariants = 4;
 // Precision forms of the grouped kernel: 0 FP64; 1 FP32 (FP32 operands,
 // MFMA accumulation and results); 2 3xBF16 (FP32 operands and results, each
