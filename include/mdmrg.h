@@ -198,10 +198,14 @@ enum {
   MDMRG_OPT_DAVIDSON_OLSEN = 8, /* 1: Olsen's correction vector t = P r - eps P x,
                                   eps = (x.P r)/(x.P x), P = (theta - diag H_eff)^-1;
                                   0 (default): t = P r */
-  MDMRG_OPT_MIXED_LADDER = 9   /* 1: a mixed solve with prec_split MDMRG_BF16X3 runs an
+  MDMRG_OPT_MIXED_LADDER = 9,  /* 1: a mixed solve with prec_split MDMRG_BF16X3 runs an
                                   FP32 stage (to tol_split or its own noise floor)
                                   between the 3xBF16 and the FP64 stages; 0 (default):
                                   3xBF16 then FP64 */
+  MDMRG_OPT_MIXED_HANDOVER = 10 /* 1..16: each stage of a mixed solve after the first
+                                  starts from this many lowest Ritz vectors of the
+                                  previous stage (one product each in its own precision);
+                                  1 (default): from the eigenvector estimate alone */
 };
 /* Set a context option (EINVAL for unknown options or bad values).
  * With the environment variable MDMRG_VERBOSE set, the library prints

@@ -1749,7 +1749,8 @@ static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w, std
 }
 
 int Context::davidson(double *x, double tol, int max_iter, int m_max, double *energy, double *resid,
-                      int *n_mv, int prec, double stall_floor) {
+                      int *n_mv, int prec, double stall_floor, const double *V0, int k0, double *Vout, int kout,
+                      int *k_written) {
   MDMRG_REQUIRE(cur >= 0, -4, "davidson: no current bond");
   MDMRG_REQUIRE(m_max >= 3 && m_max <= 60, -1, "davidson: m_max must be in [3, 60]");
   const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
@@ -1779,20 +1780,48 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
   int nmv = 1, nv = 1;
   double best_r = 1e300;
   int best_at = 0;
+  floor_checks = 0;
   std::vector<double> Hs(size_t(m_max) * m_max, 0.0);
   {
     double h;
     dev_multidot(dev, V, 0, 1, AV, N, &h);
     Hs[0] = h;
   }
+  // further start vectors (Ritz vectors of an earlier solve in another
+  // precision): orthonormalised against the subspace, one product each
+  for (int j = 1; j < k0 && nv < m_max - 2; ++j) {
+    double *t = V + int64_t(nv) * N;
+    dev_d2d(dev, t, V0 + int64_t(j) * N, sizeof(double) * N);
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<double> c(nv);
+      dev_multidot(dev, V, N, nv, t, N, c.data());
+      for (auto &v : c) v = -v;
+      dev_lincomb(dev, V, N, nv, c.data(), 1.0, t, N);
+    }
+    double tn;
+    dev_multidot(dev, t, 0, 1, t, N, &tn);
+    if (!(tn > 1e-20)) continue;
+    dev_scale(dev, 1.0 / std::sqrt(tn), t, N);
+    heff_apply(t, AV + int64_t(nv) * N, prec);
+    ++nmv;
+    std::vector<double> col(nv + 1);
+    dev_multidot(dev, V, N, nv + 1, AV + int64_t(nv) * N, N, col.data());
+    for (int i = 0; i <= nv; ++i) {
+      Hs[i * m_max + nv] = col[i];
+      Hs[nv * m_max + i] = col[i];
+    }
+    ++nv;
+  }
   double theta = Hs[0], rn = 1e300;
   int status = 0;
   std::vector<double> w, Y;
+  int nv_y = 0;  // subspace size of the Ritz vectors in Y
   while (true) {
     std::vector<double> S(size_t(nv) * nv);
     for (int i = 0; i < nv; ++i)
       for (int j = 0; j < nv; ++j) S[i * nv + j] = 0.5 * (Hs[i * m_max + j] + Hs[j * m_max + i]);
     jacobi_eig(nv, S, w, Y);
+    nv_y = nv;
     theta = w[0];
     std::vector<double> y(nv);
     for (int i = 0; i < nv; ++i) y[i] = Y[i * nv + 0];
@@ -1821,7 +1850,24 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
         best_r = rn;
         best_at = nmv;
       } else if (nmv - best_at >= window) {
-        break;
+        // the floor, or slow convergence (a plateau after a restart)?  One
+        // FP64 product of the Ritz vector decides: an FP64 residual close to
+        // the split one means the split operator's rounding is not what
+        // stops progress, so the split solve goes on (at most 3 checks)
+        if (prec == 0 || floor_checks >= 3) break;
+        DevVecs tmp(dev);
+        double *hx = tmp.get(N);
+        heff_apply(x, hx, 0);
+        ++floor_checks;
+        double xh = 0.0, r2 = 0.0;
+        dev_multidot(dev, x, 0, 1, hx, N, &xh);
+        dev_axpy(dev, -xh, x, hx, N);  // FP64 residual H x - (x.Hx) x, |x| = 1
+        dev_multidot(dev, hx, 0, 1, hx, N, &r2);
+        const double r64 = std::sqrt(r2);
+        if (verbose) fprintf(stderr, "[mdmrg] davidson: split |r| = %.3e, FP64 |r| = %.3e\n", rn, r64);
+        if (!(r64 <= 2.0 * rn)) break;
+        best_r = rn;
+        best_at = nmv;
       }
     }
     if (nv == m_max) {
@@ -1896,6 +1942,17 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
     }
     ++nv;
   }
+  // the lowest Ritz vectors of the final subspace, for a following solve
+  if (k_written) *k_written = 0;
+  if (Vout && kout > 0 && !Y.empty() && nv_y == nv) {
+    const int kk = std::min(kout, nv);
+    std::vector<double> yk(nv);
+    for (int c = 0; c < kk; ++c) {
+      for (int i = 0; i < nv; ++i) yk[i] = Y[i * nv + c];
+      dev_lincomb(dev, V, N, nv, yk.data(), 0.0, Vout + int64_t(c) * N, N);
+    }
+    if (k_written) *k_written = kk;
+  }
   // normalise the returned vector
   double xn;
   dev_multidot(dev, x, 0, 1, x, N, &xn);
@@ -1952,21 +2009,30 @@ int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_sp
   double e = 0.0, r = 0.0;
   int ns = 0, n64 = 0;
   const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
-  davidson(x, std::max(tol, tol_split), max_iter, m_max, &e, &r, &ns, prec_split, floor);
+  // the next stage starts from the lowest Ritz vectors of the previous one
+  // (MDMRG_OPT_MIXED_HANDOVER; 1 = the eigenvector estimate alone), one
+  // product each in its own precision
+  const int kh = std::max(1, std::min(mixed_handover, m_max - 3));
+  DevVecs hand(dev);
+  double *Vk = kh > 1 ? hand.get(int64_t(kh) * psi.n_elem) : nullptr;
+  int kw = 0;
+  davidson(x, std::max(tol, tol_split), max_iter, m_max, &e, &r, &ns, prec_split, floor, nullptr, 0, Vk, kh, &kw);
+  int checks = floor_checks;  // FP64 products of the split stages' floor checks
   if (verbose)
     fprintf(stderr, "[mdmrg] mixed: split stage %d products, |r| = %.3e (floor %.3e)\n", ns, r, floor);
   if (prec_split == 2 && mixed_ladder) {
     // FP32 stage between the 3xBF16 and the FP64 solves: it takes the
     // residual from the 3xBF16 floor down towards tol_split at FP32 cost
     int n32 = 0;
-    davidson(x, std::max(tol, tol_split), max_iter, m_max, &e, &r, &n32, 1, floor32);
+    davidson(x, std::max(tol, tol_split), max_iter, m_max, &e, &r, &n32, 1, floor32, Vk, kw, Vk, kh, &kw);
     ns += n32;
+    checks += floor_checks;
     if (verbose)
       fprintf(stderr, "[mdmrg] mixed: FP32 stage %d products, |r| = %.3e (floor %.3e)\n", n32, r, floor32);
   }
-  const int st = davidson(x, tol, max_iter, m_max, &e, &r, &n64, 0);
+  const int st = davidson(x, tol, max_iter, m_max, &e, &r, &n64, 0, -1.0, Vk, kw);
   ns += probe + (floor32 > 0.0 ? 1 : 0);
-  n64 += probe;
+  n64 += probe + checks;
   if (energy) *energy = e;
   if (resid) *resid = r;
   if (n_mv64) *n_mv64 = n64;

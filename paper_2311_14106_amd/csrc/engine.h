@@ -192,7 +192,9 @@ struct Context {
   // Ritz vectors kept at a thick restart of the Davidson subspace
   // (MDMRG_OPT_DAVIDSON_KEEP)
   int davidson_keep = 2;
-  bool davidson_olsen = false;  // Olsen correction (MDMRG_OPT_DAVIDSON_OLSEN)
+  bool davidson_olsen = false;
+  int floor_checks = 0;  // FP64 floor-check products of the last split Davidson
+  int mixed_handover = 1;  // Ritz vectors handed from one mixed stage to the next  // Olsen correction (MDMRG_OPT_DAVIDSON_OLSEN)
   // 3xBF16 mixed solves pass through an FP32 stage (MDMRG_OPT_MIXED_LADDER)
   bool mixed_ladder = false;
   int keep_envs = 1;  // blocks kept per bond (MDMRG_OPT_KEEP_ENVS): 1 all, 0/2/3 see prepare()
@@ -223,8 +225,12 @@ struct Context {
   // no 10% gain over 4 products within twice stall_floor (the measured
   // noise floor of the split operator), over 24 within 20 times it, over 64
   // elsewhere
+  // V0 (k0 vectors, the first equal to x): further start vectors; Vout
+  // (kout vectors): receives the lowest Ritz vectors of the final subspace,
+  // their number in *k_written
   int davidson(double *x, double tol, int max_iter, int m_max, double *energy, double *resid, int *n_mv,
-               int prec = 0, double stall_floor = -1.0);
+               int prec = 0, double stall_floor = -1.0, const double *V0 = nullptr, int k0 = 0,
+               double *Vout = nullptr, int kout = 0, int *k_written = nullptr);
   // split-precision Davidson to tol_split, then FP64 Davidson to tol
   int davidson_mixed(double *x, double tol, int prec_split, double tol_split, int max_iter, int m_max,
                      double *energy, double *resid, int *n_mv64, int *n_mv_split);
