@@ -34,13 +34,14 @@ def main():
     ap.add_argument('--reps', type=int, default=4)
     ap.add_argument('--variants', default='-1,0,1,2,3', help='-1: autotuned')
     ap.add_argument('--precs', default='fp64,fp32,bf16x3')
+    ap.add_argument('--lib', default=None, help='path of another build of libmdmrg.so (default: the in-tree one)')
     a = ap.parse_args()
     sys.path.insert(0, ROOT)
     import torch
 
     import seeded_inputs as si
     from paper_2311_14106_amd import mdmrg
-    ctx = mdmrg.Context(0)
+    ctx = mdmrg.Context(0, path=a.lib)
     if a.workload == 'hubbard6x6':
         n, spin, target = 36, True, (18, 18)
         T, V = mdmrg.build_lattice(mdmrg.HUBBARD, mdmrg.MOMENTUM, 6, 6, 1.0, 4.0)
