@@ -2474,10 +2474,11 @@ void Context::renormalize(int dir, int prec) {
   double t0 = wall_seconds();
   // the products of this bond are done: its plans, combinations, FP32
   // shadows and graphs are released before the new block is allocated
-  // (the wave-function layout is kept for the start vector)
+  // (the wave-function layout is kept for the start vector); until the new
+  // bond is prepared there is no current bond, so a failure below leaves a
+  // state in which products are refused (ESTATE) until prepare_bond
   const PsiLayout old_psi = psi;
   release_bond();
-  cur = l;
   ren_prec = prec;
   try {
     if (dir > 0) {

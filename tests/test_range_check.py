@@ -12,7 +12,9 @@ and the allocated bytes are tracked:
   the middle bond, right blocks built first, renormalisation combinations in
   bounded batches, keep-envs 3) peaks below 265 GB of device memory, so it
   fits the 288 GB of one MI355X;
-* a buffer shorter than the layout (a mistake planted on the CPU) is caught.
+* a buffer shorter than the layout (a mistake planted on the CPU) is caught;
+* a renormalisation that runs out of device memory leaves no current bond
+  (products refused with ESTATE) and the context recovers.
 """
 import ctypes
 import json
@@ -135,4 +137,29 @@ def test_short_buffer_is_caught(chk):
     st = ctx.lib.mdmrg_heff_apply(ctx.h, mdmrg.FP64, ctypes.c_void_p(x), ctypes.c_void_p(y))
     assert st == mdmrg.EDEVICE
     assert 'range check' in ctx.lib.mdmrg_last_error(ctx.h).decode()
+    ctx.close()
+
+
+def test_failed_renormalisation_leaves_no_current_bond(chk):
+    """A renormalisation that runs out of device memory (budget set just
+    above what the context holds) reports ENOMEM; products are then refused
+    with ESTATE instead of running on the released plans, and the context
+    recovers with prepare_bond once memory is available."""
+    mdmrg, L = chk
+    ctx, n = _context(mdmrg, L, 'hubbard6x6', 256, 0)
+    l = n // 2 - 1
+    ctx.prepare_bond(l)
+    _, ne = ctx.psi_layout()
+    x = L.mdmrg_check_alloc(8 * ne)
+    y = L.mdmrg_check_alloc(8 * ne)
+    assert ctx.lib.mdmrg_decimate(ctx.h, ctypes.c_void_p(x), 256, 1, None, None, None) == 0
+    ctx.set_option(mdmrg.OPT_MEMORY_BUDGET, L.mdmrg_check_live_bytes() + 4096)
+    st = ctx.lib.mdmrg_renormalize(ctx.h, 1, mdmrg.FP64)
+    assert st == mdmrg.ENOMEM, ctx.lib.mdmrg_last_error(ctx.h)
+    assert ctx.lib.mdmrg_heff_apply(ctx.h, mdmrg.FP64, ctypes.c_void_p(x), ctypes.c_void_p(y)) == mdmrg.ESTATE
+    ctx.set_option(mdmrg.OPT_MEMORY_BUDGET, 0)
+    ctx.prepare_bond(l)
+    _, ne2 = ctx.psi_layout()
+    assert ne2 == ne
+    assert ctx.lib.mdmrg_heff_apply(ctx.h, mdmrg.FP64, ctypes.c_void_p(x), ctypes.c_void_p(y)) == 0
     ctx.close()
