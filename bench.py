@@ -19,10 +19,11 @@ renormalised on the GPU.  Inputs are resident in HBM before timing starts.
 
 --workload spinless8x8 selects the spinless 8x8 torus (t=1, V=2, N=32,
 momentum basis rotated inside degenerate shells, dense two-body integrals)
-instead; --keep-envs selects the blocks kept per bond (default 2: the left
-block of the current bond and every right block ahead, so the walk to the
-right never rebuilds a block; 3, for the 8x8 workload at D=4096, keeps only
-what one step to the right needs).
+instead; --keep-envs selects the blocks kept per bond (default 2 for the
+6x6 workload: the left block of the current bond and every right block
+ahead, so the walk to the right never rebuilds a block; default 3 for the
+8x8 workload, whose right blocks ahead would not fit: only what one step to
+the right needs, the next step rebuilding from the chain end).
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
 the benchmark runs on one GPU.
@@ -340,10 +341,11 @@ def main():
     ap.add_argument('--compress', type=int, default=1,
                     help='interpolative compression of the cut coupling in the timed steps (the profile run '
                          'always uses it, so both settings see the same workload)')
-    ap.add_argument('--keep-envs', type=int, default=2, choices=(0, 1, 2, 3),
-                    help='blocks kept per bond (MDMRG_OPT_KEEP_ENVS): 2 (default) a walk to the right (the '
-                         'left block of the bond and every right block ahead, built once from the chain end); '
-                         '3 one step to the right only (the D=4096 workload); 0 one step either way; 1 all')
+    ap.add_argument('--keep-envs', type=int, default=None, choices=(0, 1, 2, 3),
+                    help='blocks kept per bond (MDMRG_OPT_KEEP_ENVS): 2 a walk to the right (the left block of '
+                         'the bond and every right block ahead, built once from the chain end; default for '
+                         'hubbard6x6); 3 one step to the right only (default for spinless8x8, whose right blocks '
+                         'ahead take 540 GB at D=2048); 0 one step either way; 1 all')
     ap.add_argument('--tol', type=float, default=1e-7)
     ap.add_argument('--cpu-budget', type=float, default=15.0)
     ap.add_argument('--no-cpu', action='store_true')
@@ -358,6 +360,8 @@ def main():
     args = ap.parse_args()
     if args.profile_D is None:
         args.profile_D = 128 if args.workload == 'hubbard6x6' else 64
+    if args.keep_envs is None:
+        args.keep_envs = 2 if args.workload == 'hubbard6x6' else 3
     if args.gpus != 1:
         print(f'bench.py: --gpus {args.gpus} is not supported; the benchmark runs on exactly one GPU '
               f'(run with --gpus 1)', file=sys.stderr)
