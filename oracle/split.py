@@ -11,6 +11,12 @@ the reading recorded in the design notes:
   numbers, hi = RNE(v) and lo = RNE(v - hi), and a product of two elements
   is approximated by  hi_a*lo_b + lo_a*hi_b + hi_a*hi_b  (lo*lo dropped),
   accumulated in binary32.
+* 6xBF16 form: v is split into three bfloat16 numbers, hi = RNE(v),
+  mid = RNE(v - hi), lo = RNE(v - hi - mid) (each difference exact in
+  binary32), and a product is approximated by the six terms down to
+  2^-16 relative: hi*lo + lo*hi + mid*mid + hi*mid + mid*hi + hi*hi
+  (mid*lo, lo*mid and lo*lo dropped), accumulated in binary32 -- about the
+  accuracy of binary32 operands at the bfloat16 product rate.
 
 bfloat16 is the upper half of a binary32 word: sign, the 8 exponent bits and
 the top 7 stored significand bits (8 significant bits).  RNE rounds the
@@ -42,6 +48,17 @@ def split_bf16(x):
     return hi, lo
 
 
+def split3_bf16(x):
+    """(hi, mid, lo): hi = RNE_bf16(x), mid = RNE_bf16(x - hi),
+    lo = RNE_bf16(x - hi - mid); both differences are exact in binary32."""
+    x = np.asarray(x, dtype=np.float32)
+    hi = bf16_rne(x)
+    r1 = (x - hi).astype(np.float32)
+    mid = bf16_rne(r1)
+    lo = bf16_rne((r1 - mid).astype(np.float32))
+    return hi, mid, lo
+
+
 def fold_alpha(alpha, A):
     """alpha op(A) as the split forms stage it: the product rounded to
     binary32 before any split."""
@@ -56,6 +73,15 @@ def product_bf16x3(A, B):
     return ah @ bl + al @ bh + ah @ bh
 
 
+def product_bf16x6(A, B):
+    """The 6xBF16 product of binary32 matrices A and B, in FP64: the terms
+    hi*lo + lo*hi + mid*mid + hi*mid + mid*hi + hi*hi of the three-way
+    splits."""
+    ah, am, al = (v.astype(np.float64) for v in split3_bf16(A))
+    bh, bm, bl = (v.astype(np.float64) for v in split3_bf16(B))
+    return ah @ bl + al @ bh + am @ bm + ah @ bm + am @ bh + ah @ bh
+
+
 def product_fp32(A, B):
     """The FP32 product model: binary32 operands, exact products (in FP64)."""
     return np.asarray(A, dtype=np.float32).astype(np.float64) @ np.asarray(B, dtype=np.float32).astype(np.float64)
@@ -67,3 +93,13 @@ def error_bound_bf16x3(A, B):
     |ab - (hi_a lo_b + lo_a hi_b + hi_a hi_b)| <= (2^-16 + 2^-16 + 2^-16 +
     higher order) |a||b| < 3.1 * 2^-16 |a||b|."""
     return 3.1 * 2.0 ** -16 * (np.abs(np.asarray(A, np.float64)) @ np.abs(np.asarray(B, np.float64)))
+
+
+def error_bound_bf16x6(A, B):
+    """Elementwise bound of |product_bf16x6(A, B) - A B| for binary32 A, B:
+    a = hi + mid + lo + e with |mid| <= 2^-8 |a|, |lo| <= 2^-16 |a| and
+    |e| <= 2^-24 |a| (each RNE_bf16 keeps the relative error of its part to
+    2^-8); the dropped terms mid*lo', lo*mid', lo*lo' and the representation
+    errors e*b, a*e' give at most (4 + higher order) 2^-24 |a||b| < 4.1 *
+    2^-24 |a||b| per term."""
+    return 4.1 * 2.0 ** -24 * (np.abs(np.asarray(A, np.float64)) @ np.abs(np.asarray(B, np.float64)))
