@@ -160,16 +160,20 @@ def cpu_baseline(mdmrg, budget_s):
                       f'{os.environ.get("OMP_NUM_THREADS", "default")}'}
 
 
+SPLIT_FORMS = (('fp32', 'FP32', 'graph32'), ('bf16x3', 'BF16X3', 'graphbf3'), ('bf16x6', 'BF16X6', 'graphbf6'))
+
+
 def split_compare(ctx, x0, torch, args):
     """Davidson s/step at fixed dE: the plain FP64 form against the mixed
-    precision forms (FP32 or 3xBF16 products, then FP64 refinement), launched
-    eagerly and replayed from captured graphs (the precision + batched form),
-    all from the same start vector at the current bond.  E_ref = FP64 solve to
-    |r| <= 1e-10; dE = 1e-9 |E_ref|.  Every form is warmed up at the bond
-    before any timed solve (tile-variant trials of each plan, FP32 operator
-    copies, graph capture), so all timed solves start from the same tuned
-    state."""
+    precision forms (FP32, 3xBF16 or 6xBF16 products, then FP64 refinement),
+    launched eagerly and replayed from captured graphs (the precision +
+    batched form), all from the same start vector at the current bond.
+    E_ref = FP64 solve to |r| <= 1e-10; dE = 1e-9 |E_ref|.  Every form is
+    warmed up at the bond before any timed solve (tile-variant trials of each
+    plan, FP32 operator copies, graph capture), so all timed solves start from
+    the same tuned state."""
     from paper_2311_14106_amd import mdmrg
+    forms = [(name, getattr(mdmrg, const), tag) for name, const, tag in SPLIT_FORMS]
 
     def solve(fn):
         x = x0.clone()
@@ -181,7 +185,7 @@ def split_compare(ctx, x0, torch, args):
 
     def warm(n=6):
         y = torch.empty_like(x0)
-        for prec in (mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3):
+        for prec in [mdmrg.FP64] + [p for _, p, _ in forms]:
             for _ in range(n):
                 ctx.heff_apply(x0, y, prec=prec)
         torch.cuda.synchronize()
@@ -193,6 +197,11 @@ def split_compare(ctx, x0, torch, args):
         return lambda x: ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol, prec_split=prec,
                                             max_iter=600)
 
+    def entry(sol, t, name):
+        e, r, n64, ns, _ = sol
+        return {'davidson_s': t, f'products_{name}': ns, 'products_fp64': n64, 'dE': abs(e - e_ref),
+                'ok': abs(e - e_ref) <= de}
+
     ctx.set_option(mdmrg.OPT_GRAPH, 0)
     warm()
     (e_ref, r_ref, n_ref, _), _ = solve(lambda x: ctx.davidson(x, tol=1e-10, max_iter=600))
@@ -200,36 +209,39 @@ def split_compare(ctx, x0, torch, args):
     s0 = ctx.stats()
     (e64, r64, n64, _), t64 = solve(plain)
     s1 = ctx.stats()
-    (em, rm, nm64, nm32, _), tm = solve(mixed(mdmrg.FP32))
-    s2 = ctx.stats()
-    (eb, rb, nb64, nb3, _), tb = solve(mixed(mdmrg.BF16X3))
-    s3 = ctx.stats()
     ms64 = (s1['heff_gemm_ms'] + s1['heff_p1_ms'] - s0['heff_gemm_ms'] - s0['heff_p1_ms']) / max(
         1.0, s1['n_matvec'] - s0['n_matvec'])
-    ms32 = (s2['split_gemm_ms'] - s1['split_gemm_ms']) / max(1.0, s2['n_matvec_split'] - s1['n_matvec_split'])
-    msb = (s3['split_gemm_ms'] - s2['split_gemm_ms']) / max(1.0, s3['n_matvec_split'] - s2['n_matvec_split'])
-    log(f'[bench] fixed-dE: ref E={e_ref:.12f} ({n_ref} products); FP64 {t64:.2f}s {n64} products '
-        f'dE={abs(e64 - e_ref):.1e}; mixed {tm:.2f}s {nm32} FP32 + {nm64} FP64 products dE={abs(em - e_ref):.1e}; '
-        f'mixed 3xBF16 {tb:.2f}s {nb3} 3xBF16 + {nb64} FP64 products dE={abs(eb - e_ref):.1e}')
     fl = ctx.heff_cost()['flop']
     res = {'dE_target': de, 'E_ref': e_ref, 'residual_tol': args.split_tol,
-           # GEMM throughput of one product (algorithmic FLOP, 2mnk) against the
-           # MFMA peak of its element type; the 3xBF16 form issues three BF16
-           # MFMA products per algorithmic one
-           'gemm_tflops': {'fp64': fl / (ms64 * 1e9) if ms64 > 0 else None,
-                           'fp32': fl / (ms32 * 1e9) if ms32 > 0 else None,
-                           'bf16x3': fl / (msb * 1e9) if msb > 0 else None},
-           'gemm_frac_of_peak': {'fp64': fl / (ms64 * 1e9) / PEAK_FP64_TFLOPS if ms64 > 0 else None,
-                                 'fp32': fl / (ms32 * 1e9) / PEAK_FP32_TFLOPS if ms32 > 0 else None,
-                                 'bf16x3_issued': 3 * fl / (msb * 1e9) / PEAK_BF16_TFLOPS if msb > 0 else None},
            'fp64': {'davidson_s': t64, 'products': n64, 'dE': abs(e64 - e_ref), 'ok': abs(e64 - e_ref) <= de},
-           'mixed_fp32': {'davidson_s': tm, 'products_fp32': nm32, 'products_fp64': nm64,
-                          'dE': abs(em - e_ref), 'ok': abs(em - e_ref) <= de},
-           'mixed_bf16x3': {'davidson_s': tb, 'products_bf16x3': nb3, 'products_fp64': nb64,
-                            'dE': abs(eb - e_ref), 'ok': abs(eb - e_ref) <= de},
-           'speedup': t64 / tm if tm > 0 else None,
-           'speedup_bf16x3': t64 / tb if tb > 0 else None,
-           'gemm_ms_per_product': {'fp64': ms64, 'fp32': ms32, 'bf16x3': msb}}
+           'gemm_ms_per_product': {'fp64': ms64}}
+    # GEMM throughput of one product (algorithmic FLOP, 2mnk) against the
+    # MFMA peak of its element type; the 3xBF16 and 6xBF16 forms issue three
+    # and six BF16 MFMA products per algorithmic one
+    tfl = {'fp64': fl / (ms64 * 1e9) if ms64 > 0 else None}
+    frac = {'fp64': tfl['fp64'] / PEAK_FP64_TFLOPS if ms64 > 0 else None}
+    line = [f'FP64 {t64:.2f}s {n64} products dE={abs(e64 - e_ref):.1e}']
+    times = {}
+    for name, prec, _ in forms:
+        a = ctx.stats()
+        sol, t = solve(mixed(prec))
+        b = ctx.stats()
+        ms = (b['split_gemm_ms'] - a['split_gemm_ms']) / max(1.0, b['n_matvec_split'] - a['n_matvec_split'])
+        res['mixed_' + name] = entry(sol, t, name)
+        res['gemm_ms_per_product'][name] = ms
+        tfl[name] = fl / (ms * 1e9) if ms > 0 else None
+        if name == 'fp32':
+            frac[name] = tfl[name] / PEAK_FP32_TFLOPS if ms > 0 else None
+        else:
+            frac[name + '_issued'] = int(name[-1]) * tfl[name] / PEAK_BF16_TFLOPS if ms > 0 else None
+        times['mixed_' + name] = t
+        line.append(f'mixed {name} {t:.2f}s {sol[3]} + {sol[2]} FP64 products dE={abs(sol[0] - e_ref):.1e}')
+    log(f'[bench] fixed-dE: ref E={e_ref:.12f} ({n_ref} products); ' + '; '.join(line))
+    res['gemm_tflops'] = tfl
+    res['gemm_frac_of_peak'] = frac
+    res['speedup'] = t64 / times['mixed_fp32'] if times['mixed_fp32'] > 0 else None
+    for name, _, _ in forms[1:]:
+        res['speedup_' + name] = t64 / times['mixed_' + name] if times['mixed_' + name] > 0 else None
     if args.batched:
         # precision + batched form: the same solves with every product
         # replayed from the graph captured at the bond (one product per form
@@ -239,35 +251,33 @@ def split_compare(ctx, x0, torch, args):
         g0 = ctx.stats()
         (e64g, _, n64g, _), t64g = solve(plain)
         g1 = ctx.stats()
-        (eg, rg, ng64, ng32, _), tg = solve(mixed(mdmrg.FP32))
-        g2 = ctx.stats()
-        (ebg, rbg, nbg64, nbg3, _), tbg = solve(mixed(mdmrg.BF16X3))
-        g3 = ctx.stats()
-        ctx.set_option(mdmrg.OPT_GRAPH, 0)
 
         def per(a, b, key):
             n = b[key + '_launches'] - a[key + '_launches']
             return (b[key + '_ms'] - a[key + '_ms']) / n if n > 0 else None
-        forms = {'mixed_fp32_graph': tg, 'mixed_bf16x3_graph': tbg}
-        best = min(forms, key=forms.get)
-        res.update({
-            'fp64_graph': {'davidson_s': t64g, 'products': n64g, 'dE': abs(e64g - e_ref),
-                           'ok': abs(e64g - e_ref) <= de},
-            'mixed_fp32_graph': {'davidson_s': tg, 'products_fp32': ng32, 'products_fp64': ng64,
-                                 'dE': abs(eg - e_ref), 'ok': abs(eg - e_ref) <= de},
-            'mixed_bf16x3_graph': {'davidson_s': tbg, 'products_bf16x3': nbg3, 'products_fp64': nbg64,
-                                   'dE': abs(ebg - e_ref), 'ok': abs(ebg - e_ref) <= de},
-            # Davidson s/step of the plain FP64 form (eager) over that of the
-            # faster precision + batched form, both at fixed dE
-            'speedup_precision_batched': t64 / forms[best] if forms[best] > 0 else None,
-            'precision_batched_form': best,
-            'speedup_fp32_graph': t64 / tg if tg > 0 else None,
-            'speedup_bf16x3_graph': t64 / tbg if tbg > 0 else None,
-            'graph_ms_per_product': {'fp64': per(g0, g1, 'graph64'), 'fp32': per(g1, g2, 'graph32'),
-                                     'bf16x3': per(g2, g3, 'graphbf3')}})
-        log(f'[bench] batched: FP64 graph {t64g:.2f}s; mixed FP32 graph {tg:.2f}s ({ng32}+{ng64}); '
-            f'mixed 3xBF16 graph {tbg:.2f}s ({nbg3}+{nbg64}); precision+batched speedup '
-            f'{res["speedup_precision_batched"]:.2f} ({best})')
+        res['fp64_graph'] = {'davidson_s': t64g, 'products': n64g, 'dE': abs(e64g - e_ref),
+                             'ok': abs(e64g - e_ref) <= de}
+        gms = {'fp64': per(g0, g1, 'graph64')}
+        gtimes = {}
+        for name, prec, tag in forms:
+            a = ctx.stats()
+            sol, t = solve(mixed(prec))
+            b = ctx.stats()
+            res[f'mixed_{name}_graph'] = entry(sol, t, name)
+            res[f'speedup_{name}_graph'] = t64 / t if t > 0 else None
+            gms[name] = per(a, b, tag)
+            gtimes[f'mixed_{name}_graph'] = t
+        ctx.set_option(mdmrg.OPT_GRAPH, 0)
+        # the precision + batched form is the fastest graph-replayed mixed
+        # form that reached dE; its Davidson s/step against the plain FP64
+        # form (eager), both at fixed dE
+        ok = {k: v for k, v in gtimes.items() if res[k]['ok']} or gtimes
+        best = min(ok, key=ok.get)
+        res.update({'speedup_precision_batched': t64 / ok[best] if ok[best] > 0 else None,
+                    'precision_batched_form': best, 'graph_ms_per_product': gms})
+        log(f'[bench] batched: FP64 graph {t64g:.2f}s; ' +
+            '; '.join(f'{k} {v:.2f}s' for k, v in gtimes.items()) +
+            f'; precision+batched speedup {res["speedup_precision_batched"]:.2f} ({best})')
     return res
 
 
@@ -285,7 +295,7 @@ def drift_segment(ctx, x0, l, n, torch, args):
     """Per-step energy error of the split forms against the plain FP64 run:
     from the same MPS and start vector at bond l, the same args.drift_steps
     steps are run once per form -- FP64 (Davidson and renormalisation in
-    FP64), FP32 and 3xBF16 (mixed Davidson with that split form, then FP64
+    FP64), FP32, 3xBF16 and 6xBF16 (mixed Davidson with that split form, then FP64
     refinement to the same residual tolerance; renormalisation GEMMs in that
     split form).  A perturbed renormalised operator is a first-order change of
     every later H_eff, so the error of step k > 0 includes k split
@@ -293,7 +303,8 @@ def drift_segment(ctx, x0, l, n, torch, args):
     from paper_2311_14106_amd import mdmrg
     mps = exported_mps(ctx, n)
     runs = {}
-    for name, prec in (('fp64', mdmrg.FP64), ('fp32', mdmrg.FP32), ('bf16x3', mdmrg.BF16X3)):
+    for name, prec in (('fp64', mdmrg.FP64), ('fp32', mdmrg.FP32), ('bf16x3', mdmrg.BF16X3),
+                       ('bf16x6', mdmrg.BF16X6)):
         ctx.set_mps(*mps)
         ctx.prepare_bond(l)
         x = x0.clone()
@@ -319,7 +330,7 @@ def drift_segment(ctx, x0, l, n, torch, args):
     ref = runs['fp64'][0]
     out = {'bond': l, 'steps': args.drift_steps, 'davidson_tol': args.tol, 'E_fp64': ref,
            's_per_step': {k: v[1] for k, v in runs.items()}}
-    for name in ('fp32', 'bf16x3'):
+    for name in ('fp32', 'bf16x3', 'bf16x6'):
         es = runs[name][0]
         out[name] = {'E': es, 'dE': [e - r for e, r in zip(es, ref)],
                      'dE_rel': [abs(e - r) / abs(r) for e, r in zip(es, ref)]}

@@ -57,7 +57,7 @@ enum {
 
 enum { MDMRG_MODEL_SPINLESS = 0, MDMRG_MODEL_HUBBARD = 1 };
 enum { MDMRG_BASIS_REAL = 0, MDMRG_BASIS_MOMENTUM = 1 };
-enum { MDMRG_FP64 = 0, MDMRG_FP32 = 1, MDMRG_BF16X3 = 2 };
+enum { MDMRG_FP64 = 0, MDMRG_FP32 = 1, MDMRG_BF16X3 = 2, MDMRG_BF16X6 = 3 };
 
 /* ---------------------------------------------------------------- context */
 
@@ -241,7 +241,11 @@ int mdmrg_psi_layout(mdmrg_ctx ctx, int64_t *n_elem, int32_t *n_blk, int32_t *de
  * (split form) reads the same FP32 shadows and forms every product from
  * BF16 parts, hi = RNE(v), lo = RNE(v - hi) of each operand element v, as
  * hi*lo + lo*hi + hi*hi with FP32 accumulation (about 16 significant bits
- * per operand, BF16 MFMA rate), y returned in FP64.  Other values: EUNSUP. */
+ * per operand, BF16 MFMA rate), y returned in FP64; MDMRG_BF16X6 (split
+ * form) splits every element into three BF16 parts, hi = RNE(v),
+ * mid = RNE(v - hi), lo = RNE(v - hi - mid), and sums the six products
+ * hi*lo + lo*hi + mid*mid + hi*mid + mid*hi + hi*hi in FP32 (about the
+ * accuracy of FP32 operands at the BF16 MFMA rate).  Other values: EUNSUP. */
 int mdmrg_heff_apply(mdmrg_ctx ctx, int prec, const double *x, double *y);
 
 /* Diagonal of H_eff at the current bond (Sec. II.A; the preconditioner of
@@ -283,7 +287,8 @@ int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max
 /* Mixed-precision Davidson (the products beyond the FP64 ceiling of Sec. IV
  * and Fig. 2, with the final eigenpair held to FP64 accuracy): a Davidson
  * solve whose products use the split
- * form prec_split (MDMRG_FP32 or MDMRG_BF16X3) until its residual reaches
+ * form prec_split (MDMRG_FP32, MDMRG_BF16X3 or MDMRG_BF16X6) until its
+ * residual reaches
  * tol_split or stops decreasing (no 10% gain over 4 products once within
  * 2f, over 24 within 20f, over 64 elsewhere), then (MDMRG_OPT_MIXED_LADDER,
  * 3xBF16 only) an FP32 stage the same way, then an FP64 Davidson from that
@@ -314,9 +319,9 @@ int mdmrg_decimate(mdmrg_ctx ctx, const double *x, int D, int direction, double 
  * block of sites <= l for +1, right block of sites >= l+1 for -1) from the
  * new isometry, then make bond (l+direction, l+direction+1) current
  * (as mdmrg_prepare_bond).  prec selects the arithmetic of the
- * renormalisation GEMMs: MDMRG_FP64 (plain); MDMRG_FP32 or MDMRG_BF16X3
- * (split forms, as in mdmrg_heff_apply, on FP32 copies of the source
- * operators and the isometry, FP32 accumulation).  The new operators are
+ * renormalisation GEMMs: MDMRG_FP64 (plain); MDMRG_FP32, MDMRG_BF16X3 or
+ * MDMRG_BF16X6 (split forms, as in mdmrg_heff_apply, on FP32 copies of the
+ * source operators and the isometry, FP32 accumulation).  The new operators are
  * stored as FP64 either way; a split form perturbs them at its rounding
  * level (about 1e-7 relative for FP32, 1e-5 for 3xBF16), a first-order
  * change of H_eff that later FP64 products do not remove.  Other prec:
@@ -379,13 +384,16 @@ int mdmrg_gemm_grouped_noalloc(mdmrg_ctx ctx, int n_bases, const double *const *
 
 /* The same grouped GEMM in a split-precision form (the arithmetic of the
  * split H_eff products: the products beyond the FP64 ceiling of Sec. IV and
- * Fig. 2, in FP32 or 3xBF16): every
+ * Fig. 2, in FP32, 3xBF16 or 6xBF16): every
  * buffer holds FP32 elements (base_len[i] floats, offsets in floats), alpha
  * is rounded to FP32 and folded into op(A) before the product, results are
  * FP32.  prec MDMRG_FP32: FP32 MFMA products and accumulation.  prec
  * MDMRG_BF16X3: each element v of alpha op(A) and of op(B) is split into
  * hi = RNE_bf16(v), lo = RNE_bf16(v - hi) and the product is accumulated
- * in FP32 as hi*lo + lo*hi + hi*hi.  Other prec: EUNSUP; descriptors and
+ * in FP32 as hi*lo + lo*hi + hi*hi.  prec MDMRG_BF16X6: three parts,
+ * mid = RNE_bf16(v - hi), lo = RNE_bf16(v - hi - mid), and the six products
+ * hi*lo + lo*hi + mid*mid + hi*mid + mid*hi + hi*hi.  Other prec: EUNSUP;
+ * descriptors and
  * range checks as for mdmrg_gemm_grouped (EINVAL). */
 int mdmrg_gemm_grouped_split(mdmrg_ctx ctx, int prec, int n_bases, const float *const *bases,
                              const int64_t *base_len, int64_t n_out, const int64_t *out_desc, int64_t n_seg,
@@ -394,7 +402,7 @@ int mdmrg_gemm_grouped_split(mdmrg_ctx ctx, int prec, int n_bases, const float *
 /* Wall seconds per step category (Diag_H, Ren, Tables, Diag_D, StVec,
  * Other: the categories of Sec. III.B, Fig. 7) accumulated since creation, the algorithmic FLOP of all H_eff
  * products, and HIP-event timings of the grouped-GEMM kernel launches on the
- * context stream; out must hold MDMRG_N_STATS (72) doubles:
+ * context stream; out must hold MDMRG_N_STATS (86) doubles:
  * [diag_h, ren, tables, diag_d, stvec, other, heff_flop, n_matvec,
  *  heff_gemm_ms, heff_gemm_launches, heff_gemm_flop,
  *  ren_gemm_ms, ren_gemm_launches, ren_gemm_flop,
@@ -404,16 +412,16 @@ int mdmrg_gemm_grouped_split(mdmrg_ctx ctx, int prec, int n_bases, const float *
  *  grouped_ms, grouped_launches, grouped_flop (mdmrg_gemm_grouped calls),
  *  heff_kernel_ms, heff_kernel_launches, heff_kernel_flop,
  *  all_kernel_ms, all_kernel_launches,
- *  proc[prec][variant][ms, launches, flop] for prec FP64, FP32, BF16X3 and
- *  the tile variants k_gemm, k_gemm_w16, k_gemm_w4, k_gemm_t128 (36 values),
- *  graph64_ms, graph64_launches, graph32_ms, graph32_launches,
- *  graphbf3_ms, graphbf3_launches]. */
-#define MDMRG_N_STATS 72
+ *  proc[prec][variant][ms, launches, flop] for prec FP64, FP32, BF16X3,
+ *  BF16X6 and the tile variants k_gemm, k_gemm_w16, k_gemm_w4, k_gemm_t128
+ *  (48 values), graph64_ms, graph64_launches, graph32_ms, graph32_launches,
+ *  graphbf3_ms, graphbf3_launches, graphbf6_ms, graphbf6_launches]. */
+#define MDMRG_N_STATS 86
 /*
  * heff_gemm_* covers the accumulation (second) phase of the eager FP64
  * H_eff products, heff_phase1_* their intermediate (first) phase and
- * heff_kernel_* both; split_gemm_* the eager split-form products (FP32 and
- * 3xBF16 together); all_kernel_* every kernel launch of the context (all
+ * heff_kernel_* both; split_gemm_* the eager split-form products (FP32,
+ * 3xBF16 and 6xBF16 together); all_kernel_* every kernel launch of the context (all
  * forms); proc[..] every launch of one kernel in the whole process, over
  * all contexts including destroyed ones; graph*_ are whole H_eff products
  * replayed from a captured graph (MDMRG_OPT_GRAPH). */

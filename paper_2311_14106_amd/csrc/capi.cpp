@@ -309,7 +309,7 @@ int mdmrg_psi_layout(mdmrg_ctx ctx, int64_t *n_elem, int32_t *n_blk, int32_t *de
 int mdmrg_heff_apply(mdmrg_ctx ctx, int prec, const double *x, double *y) {
   if (!ctx || !x || !y || x == y) return MDMRG_EINVAL;
   return guarded(ctx, [&] {
-    MDMRG_REQUIRE(prec == MDMRG_FP64 || prec == MDMRG_FP32 || prec == MDMRG_BF16X3, MDMRG_EUNSUP,
+    MDMRG_REQUIRE(prec == MDMRG_FP64 || prec == MDMRG_FP32 || prec == MDMRG_BF16X3 || prec == MDMRG_BF16X6, MDMRG_EUNSUP,
                   "heff_apply: unknown precision form");
     ctx->c.heff_apply(x, y, prec);
     dev_sync(ctx->c.dev);
@@ -370,7 +370,7 @@ int mdmrg_decimate(mdmrg_ctx ctx, const double *x, int D, int direction, double 
 int mdmrg_renormalize(mdmrg_ctx ctx, int direction, int prec) {
   if (!ctx) return MDMRG_EINVAL;
   return guarded(ctx, [&] {
-    MDMRG_REQUIRE(prec == MDMRG_FP64 || prec == MDMRG_FP32 || prec == MDMRG_BF16X3, MDMRG_EUNSUP,
+    MDMRG_REQUIRE(prec == MDMRG_FP64 || prec == MDMRG_FP32 || prec == MDMRG_BF16X3 || prec == MDMRG_BF16X6, MDMRG_EUNSUP,
                   "renormalize: unknown precision form");
     ctx->c.renormalize(direction, prec);
     return MDMRG_OK;
@@ -494,8 +494,8 @@ int mdmrg_gemm_grouped_split(mdmrg_ctx ctx, int prec, int n_bases, const float *
                              const int64_t *base_len, int64_t n_out, const int64_t *out_desc, int64_t n_seg,
                              const int64_t *seg_desc, const double *alpha) {
   if (!ctx || !bases) return MDMRG_EINVAL;
-  if (prec != MDMRG_FP32 && prec != MDMRG_BF16X3) {
-    ctx->c.err = "gemm_grouped_split: prec must be MDMRG_FP32 or MDMRG_BF16X3";
+  if (prec != MDMRG_FP32 && prec != MDMRG_BF16X3 && prec != MDMRG_BF16X6) {
+    ctx->c.err = "gemm_grouped_split: prec must be MDMRG_FP32, MDMRG_BF16X3 or MDMRG_BF16X6";
     return MDMRG_EUNSUP;
   }
   void *p[kSlots] = {};
@@ -553,7 +553,7 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out) {
         out[at + 2] = pf[p][v];
       }
     constexpr int g = 30 + 3 * kGemmVariants * kPrecs;
-    static_assert(g + 6 == MDMRG_N_STATS, "stats layout");
+    static_assert(g + 2 * kPrecs == MDMRG_N_STATS, "stats layout");
     for (int p = 0; p < kPrecs; ++p) {
       out[g + 2 * p] = ms[7 + p];
       out[g + 2 * p + 1] = ln[7 + p];

@@ -335,6 +335,7 @@ struct TileCfg {
 // step (a 32-column step on v_mfma_f32_16x16x32_bf16 holds twice the LDS and
 // measured 25% slower).
 struct Bf16x3 {};  // element-type tag: FP32 data, products as 3 BF16 MFMAs
+struct Bf16x6 {};  // element-type tag: FP32 data, three BF16 parts, 6 BF16 MFMAs
 template <class T>
 struct KStep {  // FP32
   static constexpr int small = 16, wide = 16;
@@ -345,6 +346,10 @@ struct KStep<double> {
 };
 template <>
 struct KStep<Bf16x3> {
+  static constexpr int small = 16, wide = 16;
+};
+template <>
+struct KStep<Bf16x6> {
   static constexpr int small = 16, wide = 16;
 };
 template <class T>
@@ -598,16 +603,34 @@ __device__ inline void gemm_tile(const GTile *__restrict__ tiles, const GOut *__
 typedef short v4s __attribute__((ext_vector_type(4)));  // 4 BF16 bit patterns
 
 
-__device__ inline void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
-  hi = __bf16(v);
-  lo = __bf16(v - float(hi));
+// Parts of one staged element: NP = 2 gives hi = RNE(v), lo = RNE(v - hi)
+// (3xBF16); NP = 3 adds a middle part, hi = RNE(v), mid = RNE(v - hi),
+// lo = RNE(v - hi - mid) (6xBF16).  Every difference is exact in FP32.
+template <int NP, int LEN>
+__device__ inline void split_parts(float v, __bf16 (&P)[NP][LEN], int e) {
+  const __bf16 hi = __bf16(v);
+  const float r1 = v - float(hi);
+  P[0][e] = hi;
+  if constexpr (NP == 2) {
+    P[1][e] = __bf16(r1);
+  } else {
+    const __bf16 mid = __bf16(r1);
+    P[1][e] = mid;
+    P[2][e] = __bf16(r1 - float(mid));
+  }
 }
 
-template <class C>
-__device__ inline void seg_store_bf3(const SegLoad<float, C> &L, int tid, int step,
+// LDS stage of one operand: NP part arrays, rows of TK + 8 BF16 (K-contiguous)
+template <class C, int NP>
+using StageA = __bf16[NP][C::BM * (C::TK + 8)];
+template <class C, int NP>
+using StageB = __bf16[NP][C::BN * (C::TK + 8)];
+
+template <class C, int NP>
+__device__ inline void seg_store_bfs(const SegLoad<float, C> &L, int tid, int step,
                                      const float (&ra)[SegLoad<float, C>::EA],
                                      const float (&rb)[SegLoad<float, C>::EB], uint32_t oka, uint32_t okb,
-                                     __bf16 *Ah, __bf16 *Al, __bf16 *Bh, __bf16 *Bl) {
+                                     StageA<C, NP> &Ap, StageB<C, NP> &Bp) {
   constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK;
   const int i0 = L.tA ? tid % BM : tid / TK, di = L.tA ? 0 : NT / TK;
   const int j0 = L.tB ? tid / TK : tid % BN, dj = L.tB ? NT / TK : 0;
@@ -621,57 +644,61 @@ __device__ inline void seg_store_bf3(const SegLoad<float, C> &L, int tid, int st
       v = (ok && L.ia0 + L.dia * it == k0 + kk) ? L.alpha : 0.f;
     else
       v = ok ? L.alpha * ra[it] : 0.f;
-    const int e = (i0 + di * it) * (C::TK + 8) + kk;
-    split_bf16(v, Ah[e], Al[e]);
+    split_parts<NP>(v, Ap, (i0 + di * it) * (C::TK + 8) + kk);
   }
 #pragma unroll
-  for (int it = 0; it < L.EB; ++it) {
-    const int e = (j0 + dj * it) * (C::TK + 8) + L.kb0 + L.dkb * it;
-    split_bf16(((okb >> it) & 1) ? rb[it] : 0.f, Bh[e], Bl[e]);
-  }
+  for (int it = 0; it < L.EB; ++it)
+    split_parts<NP>(((okb >> it) & 1) ? rb[it] : 0.f, Bp, (j0 + dj * it) * (C::TK + 8) + L.kb0 + L.dkb * it);
 }
 
-template <class C>
-__device__ inline void tile_mfma_bf3(const __bf16 *Ah, const __bf16 *Al, const __bf16 *Bh, const __bf16 *Bl, int wm,
-                                     int wn, int lr, int lk, bool full, int qm, int qn,
-                                     v4f (&acc)[C::MI][C::NI]) {
+// One 16-deep K step of BF16 products: NP = 2: hi*lo + lo*hi + hi*hi;
+// NP = 3: hi*lo + lo*hi + mid*mid + hi*mid + mid*hi + hi*hi (smallest
+// terms first, so that the FP32 accumulator rounds them before the large
+// ones).
+template <class C, int NP>
+__device__ inline void tile_mfma_bfs(const StageA<C, NP> &Ap, const StageB<C, NP> &Bp, int wm, int wn, int lr,
+                                     int lk, bool full, int qm, int qn, v4f (&acc)[C::MI][C::NI]) {
   constexpr int MI = C::MI, NI = C::NI;
   static_assert(C::TK == 16, "one MFMA K step per staged step");
   if (!full && !(qm > 0 && qn > 0)) return;
-  v4s ah[MI], al[MI], bh[NI], bl[NI];
+  v4s a[NP][MI], b[NP][NI];
 #pragma unroll
-  for (int mi = 0; mi < MI; ++mi) {
-    const int e = (wm + 16 * mi + lr) * (C::TK + 8) + 4 * lk;
-    ah[mi] = *reinterpret_cast<const v4s *>(Ah + e);
-    al[mi] = *reinterpret_cast<const v4s *>(Al + e);
-  }
+  for (int q = 0; q < NP; ++q) {
 #pragma unroll
-  for (int ni = 0; ni < NI; ++ni) {
-    const int e = (wn + 16 * ni + lr) * (C::TK + 8) + 4 * lk;
-    bh[ni] = *reinterpret_cast<const v4s *>(Bh + e);
-    bl[ni] = *reinterpret_cast<const v4s *>(Bl + e);
+    for (int mi = 0; mi < MI; ++mi)
+      a[q][mi] = *reinterpret_cast<const v4s *>(Ap[q] + (wm + 16 * mi + lr) * (C::TK + 8) + 4 * lk);
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni)
+      b[q][ni] = *reinterpret_cast<const v4s *>(Bp[q] + (wn + 16 * ni + lr) * (C::TK + 8) + 4 * lk);
   }
+  constexpr int H = 0, M = 1, Lo = NP - 1;  // part indices (M unused for NP = 2)
 #pragma unroll
   for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
     for (int ni = 0; ni < NI; ++ni)
       if (full || (qm > 16 * mi && qn > 16 * ni)) {
         v4f c = acc[mi][ni];
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[mi], bl[ni], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[mi], bh[ni], c, 0, 0, 0);
-        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[mi], bh[ni], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[Lo][ni], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[Lo][mi], b[H][ni], c, 0, 0, 0);
+        if constexpr (NP == 3) {
+          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[M][mi], b[M][ni], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[M][ni], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[M][mi], b[H][ni], c, 0, 0, 0);
+        }
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[H][ni], c, 0, 0, 0);
       }
 }
 
 // Same tile walk as gemm_tile (FP32 data in HBM, FP32 accumulators and
-// results); only the staging and the MFMA step differ.
-template <class C>
-__device__ inline void gemm_tile_bf3(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
+// results); only the staging and the MFMA step differ.  NP BF16 parts per
+// operand element, each in its own K-contiguous LDS array.
+template <class C, int NP>
+__device__ inline void gemm_tile_bfs(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
                                      const GSeg *__restrict__ segs, const Bases &bases) {
   constexpr int BM = C::BM, BN = C::BN, MI = C::MI, NI = C::NI, TK = C::TK;
   typedef SegLoad<float, C> SL;
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * (C::TK + 8)], Al[2][BM * (C::TK + 8)];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN * (C::TK + 8)], Bl[2][BN * (C::TK + 8)];
+  __shared__ __attribute__((aligned(16))) StageA<C, NP> As[2];
+  __shared__ __attribute__((aligned(16))) StageB<C, NP> Bs[2];
   const GTile tl = tiles[blockIdx.x];
   if (tl.out < 0) return;
   const GOut o = outs[tl.out];
@@ -695,16 +722,16 @@ __device__ inline void gemm_tile_bf3(const GTile *__restrict__ tiles, const GOut
     if (nsteps == 0) continue;
     int buf = 0;
     seg_fetch(L, 0, ra, rb, oka, okb);
-    seg_store_bf3(L, tid, 0, ra, rb, oka, okb, Ah[buf], Al[buf], Bh[buf], Bl[buf]);
+    seg_store_bfs<C, NP>(L, tid, 0, ra, rb, oka, okb, As[buf], Bs[buf]);
     __syncthreads();
     for (int step = 0; step + 1 < nsteps; ++step) {
       seg_fetch(L, step + 1, ra, rb, oka, okb);
-      tile_mfma_bf3<C>(Ah[buf], Al[buf], Bh[buf], Bl[buf], wm, wn, lr, lk, full, qm, qn, acc);
+      tile_mfma_bfs<C, NP>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
       buf ^= 1;
-      seg_store_bf3(L, tid, step + 1, ra, rb, oka, okb, Ah[buf], Al[buf], Bh[buf], Bl[buf]);
+      seg_store_bfs<C, NP>(L, tid, step + 1, ra, rb, oka, okb, As[buf], Bs[buf]);
       __syncthreads();
     }
-    tile_mfma_bf3<C>(Ah[buf], Al[buf], Bh[buf], Bl[buf], wm, wn, lr, lk, full, qm, qn, acc);
+    tile_mfma_bfs<C, NP>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
     __syncthreads();
   }
   float *Cp = reinterpret_cast<float *>(bases.p[o.c_slot]) + o.c_off;
@@ -728,7 +755,9 @@ template <class T, class C>
 __device__ inline void gemm_any(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
                                 const GSeg *__restrict__ segs, const Bases &bases) {
   if constexpr (std::is_same<T, Bf16x3>::value)
-    gemm_tile_bf3<C>(tiles, outs, segs, bases);
+    gemm_tile_bfs<C, 2>(tiles, outs, segs, bases);
+  else if constexpr (std::is_same<T, Bf16x6>::value)
+    gemm_tile_bfs<C, 3>(tiles, outs, segs, bases);
   else
     gemm_tile<T, C>(tiles, outs, segs, bases);
 }
@@ -931,8 +960,10 @@ void dev_gemm_run(Device *d, DevPlan *p, const Bases &b, int tag, int prec) {
     launch_variant<double>(v, d->stream, p, b);
   else if (prec == 1)
     launch_variant<float>(v, d->stream, p, b);
-  else
+  else if (prec == 2)
     launch_variant<Bf16x3>(v, d->stream, p, b);
+  else
+    launch_variant<Bf16x6>(v, d->stream, p, b);
   HIP_CHECK(hipGetLastError());
   if (trial) {
     HIP_CHECK(hipEventRecord(t1, d->stream));

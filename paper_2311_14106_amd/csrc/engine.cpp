@@ -1006,8 +1006,9 @@ void Context::release_graphs() {
   dev_graph_free(dev, graph64);
   dev_graph_free(dev, graph32);
   dev_graph_free(dev, graphbf3);
-  graph64 = graph32 = graphbf3 = nullptr;
-  eager64 = eager32 = eagerbf3 = 0;
+  dev_graph_free(dev, graphbf6);
+  graph64 = graph32 = graphbf3 = graphbf6 = nullptr;
+  eager64 = eager32 = eagerbf3 = eagerbf6 = 0;
 }
 
 void Context::set_graph(bool on) {
@@ -1601,15 +1602,16 @@ void Context::ensure_fp32() {
 
 void Context::heff_apply(const double *x, double *y, int prec) {
   MDMRG_REQUIRE(cur >= 0, -4, "heff_apply: no current bond");
-  MDMRG_REQUIRE(prec >= 0 && prec <= 2, -6, "heff_apply: unknown precision form");
+  MDMRG_REQUIRE(prec >= 0 && prec < kPrecs, -6, "heff_apply: unknown precision form");
   // a graph is captured once every plan of the product has finished its
   // variant trials (kGemmVariants timed launches, decided at the next one)
   const int warm = kGemmVariants + 1;
   if (prec != 0) {
     // split forms: FP32 shadows of x, y and the operators; prec 1 runs FP32
-    // MFMA products, prec 2 the 3xBF16 products on the same data
-    DevGraph *&graph = prec == 1 ? graph32 : graphbf3;
-    int &eager = prec == 1 ? eager32 : eagerbf3;
+    // MFMA products, prec 2 the 3xBF16 and prec 3 the 6xBF16 products on
+    // the same data
+    DevGraph *&graph = prec == 1 ? graph32 : prec == 2 ? graphbf3 : graphbf6;
+    int &eager = prec == 1 ? eager32 : prec == 2 ? eagerbf3 : eagerbf6;
     ensure_fp32();
     dev_d2f(dev, x, x32, psi.n_elem);
     Bases b{};
@@ -1635,7 +1637,7 @@ void Context::heff_apply(const double *x, double *y, int prec) {
       graph = dev_capture_end(dev);
     }
     if (graph) {
-      dev_graph_launch(dev, graph, prec == 1 ? 8 : 9, heff.flop);
+      dev_graph_launch(dev, graph, 7 + prec, heff.flop);
     } else {
       body();
       ++eager;
@@ -1967,7 +1969,7 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
 
 int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_split, int max_iter, int m_max,
                             double *energy, double *resid, int *n_mv64, int *n_mv_split) {
-  MDMRG_REQUIRE(prec_split == 1 || prec_split == 2, -6, "davidson_mixed: prec_split must be a split form");
+  MDMRG_REQUIRE(prec_split >= 1 && prec_split < kPrecs, -6, "davidson_mixed: prec_split must be a split form");
   MDMRG_REQUIRE(cur >= 0, -4, "davidson_mixed: no current bond");
   // Noise floor of the split operator at this bond, from one split and one
   // FP64 product of the normalised start vector v: the relative

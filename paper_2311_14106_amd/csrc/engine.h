@@ -202,10 +202,10 @@ struct Context {
   // graph replay of the H_eff product (MDMRG_OPT_GRAPH): captured per bond and
   // precision once the first products have tuned the kernel variants
   bool use_graph = false;
-  DevGraph *graph64 = nullptr, *graph32 = nullptr, *graphbf3 = nullptr;
+  DevGraph *graph64 = nullptr, *graph32 = nullptr, *graphbf3 = nullptr, *graphbf6 = nullptr;
   double *xg = nullptr, *yg = nullptr;  // FP64 staging of x and y for the graph
   int64_t xg_n = 0;
-  int eager64 = 0, eager32 = 0, eagerbf3 = 0;  // eager products at the current bond
+  int eager64 = 0, eager32 = 0, eagerbf3 = 0, eagerbf6 = 0;  // eager products at the current bond
   void set_graph(bool on);
   void release_graphs();
 
@@ -220,7 +220,7 @@ struct Context {
   void build_heff(int l);
   void heff_apply(const double *x, double *y, int prec = 0);
   void heff_diag(double *d);
-  // prec: matrix-vector precision (0 FP64, 1 FP32, 2 3xBF16); stall_floor
+  // prec: matrix-vector precision (0 FP64, 1 FP32, 2 3xBF16, 3 6xBF16); stall_floor
   // >= 0: stop when the residual stops decreasing (split-precision phase):
   // no 10% gain over 4 products within twice stall_floor (the measured
   // noise floor of the split operator), over 24 within 20 times it, over 64
@@ -241,7 +241,7 @@ struct Context {
   void stvec(const double *x_old, int l_old, int dir, const PsiLayout &old_layout, double *x_new,
              const PsiLayout &new_layout);
   // after decimate(dir): environment of the grown block, then bond l+dir;
-  // prec 0 FP64, 1 FP32, 2 3xBF16 products for that block's GEMMs (the
+  // prec 0 FP64, 1 FP32, 2 3xBF16, 3 6xBF16 products for that block's GEMMs (the
   // operators are stored as FP64 either way)
   void renormalize(int dir, int prec = 0);
   int ren_prec = 0;  // precision form of the renormalisation GEMMs in progress

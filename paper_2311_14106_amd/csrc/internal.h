@@ -130,8 +130,9 @@ size_t dev_live_bytes(Device *);
 constexpr int kGemmVariants = 4;
 // Precision forms of the grouped kernel: 0 FP64; 1 FP32 (FP32 operands,
 // MFMA accumulation and results); 2 3xBF16 (FP32 operands and results, each
-// product formed from BF16 hi / lo parts with FP32 accumulation).
-constexpr int kPrecs = 3;
+// product formed from BF16 hi / lo parts with FP32 accumulation); 3 6xBF16
+// (the same with hi / mid / lo parts and six BF16 products).
+constexpr int kPrecs = 4;
 
 // Uploaded grouped-GEMM plan: 64x64 output tiles in launch order (outputs
 // largest first, dealt to per-XCD queues; empty tiles pad the queues).
@@ -143,7 +144,7 @@ struct DevPlan {
   double flop = 0.0;  // algorithmic FLOP of one launch
   // autotuner state per precision form: the first launches time one
   // variant each, then the fastest is kept (variant >= 0)
-  int variant[kPrecs] = {-1, -1, -1}, trials[kPrecs] = {0, 0, 0};
+  int variant[kPrecs] = {-1, -1, -1, -1}, trials[kPrecs] = {0, 0, 0, 0};
   void *trial_ev[kPrecs][2 * kGemmVariants] = {};
   float trial_ms[kPrecs][kGemmVariants] = {};
 };
@@ -158,17 +159,17 @@ constexpr size_t kNoAllocStagingBytes = size_t(16) << 20;
 // staging array of the device, the launch uses the forced variant or
 // k_gemm_w4 and is waited for.  EINVAL (-1) if the plan does not fit.
 void dev_gemm_run_noalloc(Device *, const GemmPlan &, const Bases &);
-// prec 0: FP64 operands and results; prec 1 (FP32) and 2 (3xBF16): FP32
-// operands and results (base pointers then address float arrays with the
-// same element offsets)
+// prec 0: FP64 operands and results; prec 1 (FP32), 2 (3xBF16) and 3
+// (6xBF16): FP32 operands and results (base pointers then address float
+// arrays with the same element offsets)
 void dev_gemm_run(Device *, DevPlan *, const Bases &, int tag = 0, int prec = 0);
 void dev_d2f(Device *, const double *x, float *y, int64_t n);
 void dev_f2d(Device *, const float *x, double *y, int64_t n);
 // HIP-event timing of tagged grouped-GEMM launches (tag 1..6; untagged
 // launches count as 6) and of graph replays (tags 7 FP64, 8 FP32, 9
-// 3xBF16): elapsed milliseconds, launch count and algorithmic FLOP since
-// creation.
-constexpr int kTags = 10;
+// 3xBF16, 10 6xBF16): elapsed milliseconds, launch count and algorithmic
+// FLOP since creation.
+constexpr int kTags = 11;
 void dev_timing_enable(Device *, bool on);
 void dev_timing_collect(Device *, double ms[kTags], double launches[kTags], double flop[kTags]);
 // Process-wide totals of the grouped kernel per precision form and tile

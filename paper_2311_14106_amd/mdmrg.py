@@ -17,7 +17,7 @@ DEFAULT_LIB = os.path.join(HERE, 'libmdmrg.so')
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOCONV, EUNSUP = 0, -1, -2, -3, -4, -5, -6
 SPINLESS, HUBBARD = 0, 1
 REAL, MOMENTUM = 0, 1
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 OPT_KEEP_ENVS, OPT_SCRATCH_LIMIT, OPT_GRAPH, OPT_COMPRESS, OPT_GEMM_VARIANT, OPT_MEMORY_BUDGET = 1, 2, 3, 4, 5, 6
 OPT_DAVIDSON_KEEP, OPT_DAVIDSON_OLSEN, OPT_MIXED_LADDER, OPT_MIXED_HANDOVER = 7, 8, 9, 10
 
@@ -274,7 +274,7 @@ class Context:
     HIST_EDGES = (1, 16, 32, 48, 64, 128, 256, 512)
     # tile variants of the grouped kernel (kernel names), in library order
     KERNELS = ('k_gemm', 'k_gemm_w16', 'k_gemm_w4', 'k_gemm_t128')
-    N_STATS = 72  # MDMRG_N_STATS
+    N_STATS = 86  # MDMRG_N_STATS
 
     def heff_histogram(self):
         """{bin lower edge: FLOP} of one H_eff x by min(m, n) of each GEMM."""
@@ -324,7 +324,7 @@ class Context:
 
     def gemm_grouped(self, buffers, out_desc, seg_desc, alpha, prec=FP64):
         """buffers: list of device tensors (float64 for prec FP64, float32 for
-        the split forms FP32 and BF16X3); descriptors: int64 arrays of shape
+        the split forms FP32, BF16X3 and BF16X6); descriptors: int64 arrays of shape
         (n_out, 8) and (n_seg, 8); alpha: float64 (n_seg,)."""
         nb = len(buffers)
         dt = 'torch.float64' if prec == FP64 else 'torch.float32'
@@ -370,10 +370,10 @@ class Context:
                 'grouped_ms', 'grouped_launches', 'grouped_flop',
                 'heff_kernel_ms', 'heff_kernel_launches', 'heff_kernel_flop',
                 'all_kernel_ms', 'all_kernel_launches']
-        for prec in ('f64', 'f32', 'bf3'):
+        for prec in ('f64', 'f32', 'bf3', 'bf6'):
             for var in self.KERNELS:
                 keys += [f'proc_{prec}_{var}_ms', f'proc_{prec}_{var}_launches', f'proc_{prec}_{var}_flop']
         keys += ['graph64_ms', 'graph64_launches', 'graph32_ms', 'graph32_launches',
-                 'graphbf3_ms', 'graphbf3_launches']
+                 'graphbf3_ms', 'graphbf3_launches', 'graphbf6_ms', 'graphbf6_launches']
         assert len(keys) == len(out)
         return dict(zip(keys, out.tolist()))

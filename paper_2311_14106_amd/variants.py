@@ -23,7 +23,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-PREC = {'fp64': 0, 'fp32': 1, 'bf16x3': 2}
+PREC = {'fp64': 0, 'fp32': 1, 'bf16x3': 2, 'bf16x6': 3}
 
 
 def main():

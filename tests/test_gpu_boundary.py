@@ -220,7 +220,7 @@ def test_decimation_is_scale_invariant():
 def test_split_renormalisation_perturbs_at_its_rounding_level():
     mdmrg = _gpu()
     ys = {}
-    for prec in (mdmrg.FP64, mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3):
+    for prec in (mdmrg.FP64, mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3, mdmrg.BF16X6):
         ctx, _ = _hubbard33(mdmrg, l=3, D=64)
         x = to_dev(si.random_vector(ctx.n_elem(), 9))
         ctx.decimate(x, 48, +1)
@@ -237,11 +237,14 @@ def test_split_renormalisation_perturbs_at_its_rounding_level():
     assert np.array_equal(ys[mdmrg.FP64][0], ys[mdmrg.FP64][1])
     d32 = np.abs(ys[mdmrg.FP32][0] - y64).max() / scale
     dbf = np.abs(ys[mdmrg.BF16X3][0] - y64).max() / scale
-    log(f'[boundary] next-bond H_eff change: FP32 {d32:.2e}, 3xBF16 {dbf:.2e}')
+    db6 = np.abs(ys[mdmrg.BF16X6][0] - y64).max() / scale
+    log(f'[boundary] next-bond H_eff change: FP32 {d32:.2e}, 3xBF16 {dbf:.2e}, 6xBF16 {db6:.2e}')
     # binary32 rounding of operands, products and sums over short K
     assert 0.0 < d32 <= 1e-5
     # 16 significant bits per operand
     assert 0.0 < dbf <= 1e-3
+    # about 24 bits per operand: as the FP32 form
+    assert 0.0 < db6 <= 2e-5
 
 
 def test_split_graph_replay_with_odd_vector_length():

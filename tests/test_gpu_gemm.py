@@ -150,7 +150,7 @@ def _operand_views(A, B, seg, m, n):
 
 
 @pytest.mark.parametrize('variant', [0, 1, 2, 3])
-@pytest.mark.parametrize('prec_name', ['FP32', 'BF16X3'])
+@pytest.mark.parametrize('prec_name', ['FP32', 'BF16X3', 'BF16X6'])
 @pytest.mark.parametrize('big,n_out,seed', [(False, 300, 0), (True, 40, 1), (True, 7, 3)])
 def test_split_grouped_gemm_matches_product_model(prec_name, big, n_out, seed, variant):
     mdmrg, ctx = _ctx()
@@ -163,7 +163,8 @@ def test_split_grouped_gemm_matches_product_model(prec_name, big, n_out, seed, v
     print(f'[gemm parity {prec_name}] variant={variant} big={big} outputs={n_out} segments={len(segs)}', flush=True)
     ctx.gemm_grouped([dA, dB, dC], outs, segs, alphas, prec=prec)
     Cg = dC.cpu().numpy()
-    model = S.product_bf16x3 if prec_name == 'BF16X3' else S.product_fp32
+    model = {'FP32': S.product_fp32, 'BF16X3': S.product_bf16x3, 'BF16X6': S.product_bf16x6}[prec_name]
+    split_bound = {'BF16X3': S.error_bound_bf16x3, 'BF16X6': S.error_bound_bf16x6}.get(prec_name)
     worst = 0.0
     for (_, off, m, n, ldc, s0, ns, acc) in outs:
         c0 = C32[off:off + m * ldc].reshape(m, ldc)[:, :n].astype(np.float64)
@@ -180,19 +181,21 @@ def test_split_grouped_gemm_matches_product_model(prec_name, big, n_out, seed, v
             want += model(Af, Bop)
             exact += Af.astype(np.float64) @ Bop.astype(np.float64)
             scale += np.abs(Af.astype(np.float64)) @ np.abs(Bop.astype(np.float64))
-            bound += S.error_bound_bf16x3(Af, Bop)
+            if split_bound is not None:
+                bound += split_bound(Af, Bop)
             ktot += k
         got = Cg[off:off + m * ldc].reshape(m, ldc)[:, :n].astype(np.float64)
         tol = 2.0 ** -24 * (4 * ktot + 16) * (scale + 1e-30)
         assert np.all(np.abs(got - want) <= tol), (prec_name, off)
         worst = max(worst, float((np.abs(got - exact) / (scale + 1e-30)).max()))
-        if prec_name == 'BF16X3':
+        if split_bound is not None:
             assert np.all(np.abs(got - exact) <= bound + tol)
         if ldc > n:
             assert np.array_equal(Cg[off:off + m * ldc].reshape(m, ldc)[:, n:],
                                   C32[off:off + m * ldc].reshape(m, ldc)[:, n:])
     print(f'[gemm parity {prec_name}] max |C - exact| / sum|A||B| = {worst:.2e}', flush=True)
-    # the two forms are different arithmetic: 3xBF16 is visibly less exact
+    # different arithmetic: 3xBF16 is visibly less exact; 6xBF16 keeps the
+    # mid*mid and hi*mid terms and is as exact as the FP32 form
     if prec_name == 'BF16X3':
         assert worst > 2.0 ** -22
     else:

@@ -53,7 +53,7 @@ def test_variants_and_graph_replays_are_bitwise_identical():
         assert torch.equal(y, ys[0])
     print(f'[graph] {len(ys)} eager products agree bitwise, |psi| = {ne}', flush=True)
     # the split forms' variants agree bit for bit too (same K order per element)
-    for prec in (mdmrg.FP32, mdmrg.BF16X3):
+    for prec in (mdmrg.FP32, mdmrg.BF16X3, mdmrg.BF16X6):
         ys = []
         for _ in range(5):
             y = torch.zeros_like(x0)
@@ -64,7 +64,7 @@ def test_variants_and_graph_replays_are_bitwise_identical():
     a.set_option(mdmrg.OPT_GRAPH, 1)
     # every form has finished its variant trials above; 8 products each,
     # with capture at the first of them
-    for prec in (mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3):
+    for prec in (mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3, mdmrg.BF16X6):
         for r in range(8):
             x = torch.from_numpy(si.random_vector(ne, 10 + r)).to(dev)
             yg, ye = torch.zeros_like(x), torch.zeros_like(x)
@@ -75,8 +75,9 @@ def test_variants_and_graph_replays_are_bitwise_identical():
             assert torch.equal(yg, ye), (prec, r)
     st = a.stats()
     assert st['graph64_launches'] >= 1 and st['graph32_launches'] >= 1 and st['graphbf3_launches'] >= 1
+    assert st['graphbf6_launches'] >= 1
     print(f"[graph] replays: FP64 {int(st['graph64_launches'])}, FP32 {int(st['graph32_launches'])}, "
-          f"3xBF16 {int(st['graphbf3_launches'])}", flush=True)
+          f"3xBF16 {int(st['graphbf3_launches'])}, 6xBF16 {int(st['graphbf6_launches'])}", flush=True)
     a.close()
     b.close()
 

@@ -204,12 +204,13 @@ def test_decimation_matches_oracle():
                 assert ctx.get_bond(l + 1) == nb      # kept sector dimensions: exact
 
 
-@pytest.mark.parametrize('form,bound', [('FP32', 1e-5), ('BF16X3', 5e-4)])
+@pytest.mark.parametrize('form,bound', [('FP32', 1e-5), ('BF16X3', 5e-4), ('BF16X6', 2e-5)])
 def test_split_precision_heff_and_mixed_davidson(form, bound):
     """Split forms: the product error stays within the rounding of the form
     (FP32: |y32 - y| <= 1e-5 max|y|; 3xBF16, about 16 significant bits per
-    operand and two GEMM phases: <= 5e-4 max|y|), the 3xBF16 product is
-    less exact than the FP32 one (it is a different arithmetic), and the
+    operand and two GEMM phases: <= 5e-4 max|y|; 6xBF16, about 24 bits per
+    operand: <= 2e-5 max|y|), the 3xBF16 product is less exact than the
+    FP32 and 6xBF16 ones (it is a different arithmetic), and the
     mixed-precision Davidson (split products, then FP64 refinement) reaches
     the lowest FP64 eigenvalue of the oracle's H_eff to 1e-12 relative."""
     mdmrg = _gpu()
@@ -237,6 +238,10 @@ def test_split_precision_heff_and_mixed_davidson(form, bound):
         ctx.heff_apply(to_dev(x), yd, prec=mdmrg.FP32)
         err32 = np.abs(yd.cpu().numpy() - y_ref).max() / np.abs(y_ref).max()
         assert err > 4 * err32
+    if form == 'BF16X6':
+        ctx.heff_apply(to_dev(x), yd, prec=mdmrg.BF16X3)
+        err3 = np.abs(yd.cpu().numpy() - y_ref).max() / np.abs(y_ref).max()
+        assert 4 * err < err3
     xd = to_dev(si.random_vector(ne, 2))
     e, r, n64, nsp, conv = ctx.davidson_mixed(xd, tol=1e-9, tol_split=1e-5, prec_split=prec)
     log(f'[split] mixed Davidson: FP64 products {n64}, {form} products {nsp}, E={e:.14f}')

@@ -120,7 +120,7 @@ def test_several_passes_match_oracle(case):
     assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
 
 
-@pytest.mark.parametrize('prec,u', [(1, 2.0 ** -24), (2, 2.0 ** -16)])
+@pytest.mark.parametrize('prec,u', [(1, 2.0 ** -24), (2, 2.0 ** -16), (3, 2.0 ** -24)])
 def test_split_forms_within_rounding_model(case, prec, u):
     mdmrg, ctx, x, y_ref = case
     log(f'[fullsize parity] split form {prec}')

@@ -107,7 +107,7 @@ def test_full_size_step_stays_in_bounds(chk, workload, D, l, keep):
     mdmrg, L = chk
     ctx, n = _context(mdmrg, L, workload, D, keep)
     n0 = L.mdmrg_check_launches()
-    for prec in (mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3):
+    for prec in (mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3, mdmrg.BF16X6):
         _step(mdmrg, L, ctx, l, D, [mdmrg.FP64, prec])
         l += 1
     assert L.mdmrg_check_launches() - n0 > 100
@@ -119,7 +119,7 @@ def test_largest_workload_fits_one_gpu(chk):
     the right): environment build, products in all forms, one step."""
     mdmrg, L = chk
     ctx, n = _context(mdmrg, L, 'spinless8x8', 4096, 3)
-    ne = _step(mdmrg, L, ctx, n // 2 - 1, 4096, [mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3, mdmrg.FP64])
+    ne = _step(mdmrg, L, ctx, n // 2 - 1, 4096, [mdmrg.FP64, mdmrg.FP32, mdmrg.BF16X3, mdmrg.BF16X6, mdmrg.FP64])
     peak = L.mdmrg_check_peak_bytes()
     print(f'|psi| {ne}, peak device memory {peak / 1e9:.1f} GB')
     assert ne > 10_000_000
