@@ -369,158 +369,158 @@ using Cfg128 = TileCfg<128, 128, 2, 4, KStep<T>::small>;
 constexpr int kTileM = 64, kTileN = 64;  // output tile of variants 0-2 (variant 3: 128 x 128)
 constexpr int kPad = 2;  // LDS row padding (doubles) of the staged A / B tiles
 
-// Per-thread load state of one segment: each thread stages EA elements of
-// op(A) and EB of op(B) per K step.  Element `it` of a thread sits at row
-// i0 + di*it and K offset k0 + dk*it of the staged tile ((di, dk) follow
-// from the operand's transposition), so its memory offset is affine in
-// `it` too: o0 + it*dO.  Base pointers are uniform over the workgroup.
+// Operand loads of the grouped kernel are buffer loads: a workgroup-uniform
+// base (the tile's first row / column of the operand at the step's first K
+// position, advanced by scalar arithmetic per K step) and per-thread byte
+// offsets fixed for a whole segment.  An element outside the output, or
+// past K in a segment's last step, gets an offset beyond the buffer's range,
+// for which the hardware returns 0 without a memory access, so a K step
+// needs no address or mask arithmetic.  The host keeps every valid offset
+// below 2^30 (plan_check).
+constexpr int32_t kOffOut = int32_t(0x80000000u);  // beyond the buffer range: the load returns 0
+constexpr int32_t kBufRange = 0x7fffffff;          // buffer size in bytes
+
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const char *base) {
+  // raw buffer (stride 0), range kBufRange bytes; dword 3 as the gfx9 family needs
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(base), short(0), kBufRange, 0x00020000);
+}
+template <class T>
+__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, int32_t off);
+template <>
+__device__ inline float buf_load<float>(__amdgpu_buffer_rsrc_t r, int32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ inline double buf_load<double>(__amdgpu_buffer_rsrc_t r, int32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+// Per-thread load state of one segment (FP64 and FP32 forms): each thread
+// stages EA elements of op(A) and EB of op(B) per K step.  Element `it` of
+// a thread sits at row i0 + di*it and K offset ka0 + dka*it of the staged A
+// tile (K offset kb0 + dkb*it and column j0 + dj*it of the B tile); (di, dka)
+// and (dkb, dj) follow from the operand's transposition, chosen so that
+// consecutive threads read consecutive addresses.
 template <class T, class C>
 struct SegLoad {
   static constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK;
   static constexpr int EA = BM * TK / NT, EB = BN * TK / NT;
   static_assert(EA >= 1 && EB >= 1 && NT % BM == 0 && NT % BN == 0 && NT % TK == 0, "tile / thread mismatch");
-  const T *A, *B;
-  int32_t oa0, doa, ob0, dob;  // element offset of it = 0 and per-it increment
-  int32_t da, db;              // advance per K step (elements)
-  int32_t ka0, dka, kb0, dkb;  // K offset within the step: k0 + dk*it
-  int32_t ia0, dia;            // A: first output row and its increment (identity operands)
-  uint32_t va, vb;             // bit it: element it lies inside the output
+  const char *A, *B;       // step-0 bases of the tile's operand panels (uniform)
+  int64_t da, db;          // bytes per K step (uniform)
+  int32_t oa[EA], ob[EB];  // byte offsets of the thread's elements from the step base, or kOffOut
+  int i0, di, ka0, dka;    // A tile: row and K offset of element 0, increments
+  int j0, dj, kb0, dkb;    // B tile: column and K offset, increments
+  int ga, ma;              // A: output row of element 0, rows of the output (identity operands)
   int k;
   T alpha;
-  bool idA, tA, tB;
+  bool idA;
 };
 
 template <class T, class C>
 __device__ inline void seg_setup(SegLoad<T, C> &L, const GSeg &sg, const Bases &bases, const GOut &o, int row0,
                                  int col0, int tid) {
-  constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK;
-  L.A = reinterpret_cast<const T *>(bases.p[sg.a_slot]) + sg.a_off;
-  L.B = reinterpret_cast<const T *>(bases.p[sg.b_slot]) + sg.b_off;
+  constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK, EA = SegLoad<T, C>::EA, EB = SegLoad<T, C>::EB;
+  constexpr int ES = int(sizeof(T));
+  const T *A = reinterpret_cast<const T *>(bases.p[sg.a_slot]) + sg.a_off;
+  const T *B = reinterpret_cast<const T *>(bases.p[sg.b_slot]) + sg.b_off;
   const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB;
-  L.tA = tA;
-  L.tB = tB;
   L.idA = sg.flags & SEG_AID;
   L.alpha = T(sg.alpha);
   L.k = sg.k;
-  L.da = tA ? TK * sg.lda : TK;
-  L.db = tB ? TK : TK * sg.ldb;
+  L.ma = o.m;
   // A tile BM x TK: row-major source -> (i, kk) = (e / TK, e % TK);
   // transposed source -> (e % BM, e / BM); e = tid + NT it
-  const int i0 = tA ? tid % BM : tid / TK, di = tA ? 0 : NT / TK;
+  L.i0 = tA ? tid % BM : tid / TK;
+  L.di = tA ? 0 : NT / TK;
   L.ka0 = tA ? tid / BM : tid % TK;
   L.dka = tA ? NT / BM : 0;
-  L.ia0 = row0 + i0;
-  L.dia = di;
-  const int j0 = tB ? tid / TK : tid % BN, dj = tB ? NT / TK : 0;
-  // offsets are formed only for rows / columns inside the output (later
-  // elements of a thread never re-enter it), so they stay within the
-  // operand extents the host checked against 32-bit range
-  const bool a_in = row0 + i0 < o.m, b_in = col0 + j0 < o.n;
-  L.oa0 = !a_in ? 0 : (tA ? L.ka0 * sg.lda + i0 + row0 : (i0 + row0) * sg.lda + L.ka0);
-  L.doa = tA ? L.dka * sg.lda : di * sg.lda;
+  L.ga = row0 + L.i0;
+  L.A = reinterpret_cast<const char *>(tA ? A + row0 : A + int64_t(row0) * sg.lda);
+  L.da = ES * (tA ? int64_t(TK) * sg.lda : int64_t(TK));
+#pragma unroll
+  for (int it = 0; it < EA; ++it) {
+    const int i = L.i0 + L.di * it, kk = L.ka0 + L.dka * it;
+    L.oa[it] = row0 + i < o.m ? ES * (tA ? kk * sg.lda + i : i * sg.lda + kk) : kOffOut;
+  }
   // B tile TK x BN: row-major source -> (kb, j) = (e / BN, e % BN);
   // transposed source -> (e % TK, e / TK)
+  L.j0 = tB ? tid / TK : tid % BN;
+  L.dj = tB ? NT / TK : 0;
   L.kb0 = tB ? tid % TK : tid / BN;
   L.dkb = tB ? 0 : NT / BN;
-  L.ob0 = !b_in ? 0 : (tB ? (j0 + col0) * sg.ldb + L.kb0 : L.kb0 * sg.ldb + j0 + col0);
-  L.dob = tB ? dj * sg.ldb : L.dkb * sg.ldb;
-  L.va = 0;
-  L.vb = 0;
+  L.B = reinterpret_cast<const char *>(tB ? B + int64_t(col0) * sg.ldb : B + col0);
+  L.db = ES * (tB ? int64_t(TK) : int64_t(TK) * sg.ldb);
 #pragma unroll
-  for (int it = 0; it < L.EA; ++it)
-    if (L.ia0 + di * it < o.m) L.va |= 1u << it;
-#pragma unroll
-  for (int it = 0; it < L.EB; ++it)
-    if (col0 + j0 + dj * it < o.n) L.vb |= 1u << it;
+  for (int it = 0; it < EB; ++it) {
+    const int j = L.j0 + L.dj * it, kb = L.kb0 + L.dkb * it;
+    L.ob[it] = col0 + j < o.n ? ES * (tB ? j * sg.ldb + kb : kb * sg.ldb + j) : kOffOut;
+  }
 }
 
-// Loads of one K step into registers.  The loads are unconditional (an
-// element outside the operand reads the in-bounds first element of the
-// step instead) and nothing is computed from the loaded values here, so no
-// wait on them is needed before the MFMAs of the current step; masking,
-// alpha and identity factors are applied when the step is written to LDS.
-// ok*: bit it = element it lies inside the operand for this step.
-template <class T, class C>
+// Loads of one K step.  EDGE: the step may reach past K (only a segment's
+// last step can); the offsets of positions past K are replaced by kOffOut.
+// Nothing is computed from the loaded values here, so no wait on them is
+// needed before the MFMAs of the current step.
+template <bool EDGE, class T, class C>
 __device__ inline void seg_fetch(const SegLoad<T, C> &L, int step, T (&ra)[SegLoad<T, C>::EA],
-                                 T (&rb)[SegLoad<T, C>::EB], uint32_t &oka, uint32_t &okb) {
+                                 T (&rb)[SegLoad<T, C>::EB]) {
   const int k0 = step * C::TK;
-  const T *Ap = L.A + int64_t(step) * L.da, *Bp = L.B + int64_t(step) * L.db;
-  oka = 0;
-  okb = 0;
+  const __amdgpu_buffer_rsrc_t rA = buf_rsrc(L.A + step * L.da), rB = buf_rsrc(L.B + step * L.db);
+  if (!L.idA) {
 #pragma unroll
-  for (int it = 0; it < L.EA; ++it) {
-    const bool ok = ((L.va >> it) & 1) && k0 + L.ka0 + L.dka * it < L.k;
-    oka |= uint32_t(ok) << it;
-    if (!L.idA) ra[it] = Ap[ok ? L.oa0 + L.doa * it : 0];
+    for (int it = 0; it < SegLoad<T, C>::EA; ++it)
+      ra[it] = buf_load<T>(rA, !EDGE || k0 + L.ka0 + L.dka * it < L.k ? L.oa[it] : kOffOut);
   }
 #pragma unroll
-  for (int it = 0; it < L.EB; ++it) {
-    const bool ok = ((L.vb >> it) & 1) && k0 + L.kb0 + L.dkb * it < L.k;
-    okb |= uint32_t(ok) << it;
-    rb[it] = Bp[ok ? L.ob0 + L.dob * it : 0];
-  }
+  for (int it = 0; it < SegLoad<T, C>::EB; ++it)
+    rb[it] = buf_load<T>(rB, !EDGE || k0 + L.kb0 + L.dkb * it < L.k ? L.ob[it] : kOffOut);
 }
 
 // Write one fetched K step to an LDS stage: A stage [kk][BM + kPad], B stage
-// [kb][BN + kPad]; the row / column of an element is recovered from its
-// thread and `it`.  alpha is folded into A; identity factors are generated.
+// [kb][BN + kPad].  alpha is folded into A; identity factors are generated.
 template <class T, class C>
-__device__ inline void seg_store(const SegLoad<T, C> &L, int tid, int step, const T (&ra)[SegLoad<T, C>::EA],
-                                 const T (&rb)[SegLoad<T, C>::EB], uint32_t oka, uint32_t okb, T *As, T *Bs) {
-  constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK;
-  const int i0 = L.tA ? tid % BM : tid / TK, di = L.tA ? 0 : NT / TK;
-  const int j0 = L.tB ? tid / TK : tid % BN, dj = L.tB ? NT / TK : 0;
-  const int k0 = step * TK;
+__device__ inline void seg_store(const SegLoad<T, C> &L, int step, const T (&ra)[SegLoad<T, C>::EA],
+                                 const T (&rb)[SegLoad<T, C>::EB], T *As, T *Bs) {
+  constexpr int BM = C::BM, BN = C::BN;
+  const int k0 = step * C::TK;
 #pragma unroll
-  for (int it = 0; it < L.EA; ++it) {
+  for (int it = 0; it < SegLoad<T, C>::EA; ++it) {
     const int kk = L.ka0 + L.dka * it;
-    const bool ok = (oka >> it) & 1;
     T v;
-    if (L.idA)
-      v = (ok && L.ia0 + L.dia * it == k0 + kk) ? L.alpha : T(0);
-    else
-      v = ok ? L.alpha * ra[it] : T(0);
-    As[kk * (BM + kPad) + i0 + di * it] = v;
+    if (L.idA) {
+      const int g = L.ga + L.di * it;
+      v = (g < L.ma && k0 + kk < L.k && g == k0 + kk) ? L.alpha : T(0);
+    } else {
+      v = L.alpha * ra[it];
+    }
+    As[kk * (BM + kPad) + L.i0 + L.di * it] = v;
   }
 #pragma unroll
-  for (int it = 0; it < L.EB; ++it)
-    Bs[(L.kb0 + L.dkb * it) * (BN + kPad) + j0 + dj * it] = ((okb >> it) & 1) ? rb[it] : T(0);
+  for (int it = 0; it < SegLoad<T, C>::EB; ++it) Bs[(L.kb0 + L.dkb * it) * (BN + kPad) + L.j0 + L.dj * it] = rb[it];
 }
 
-// MFMAs of one K step on the LDS stage (Ab, Bb) for this wave's block;
-// on edge tiles the 16x16 blocks wholly outside the output are skipped
-// (wave-uniform masks, tested once per step, outside the K loop).
+// MFMAs of one K step on the LDS stage (Ab, Bb) for this wave's block.  A
+// wave whose block lies wholly outside the output skips the step; a partly
+// covered block runs every MFMA (rows and columns outside the output are
+// staged as zeros and their accumulators are never stored), which keeps the
+// step free of per-tile branches.
 template <class T, class C>
-__device__ inline void tile_mfma(const T *Ab, const T *Bb, int wm, int wn, int lr, int lk, bool full, int qm,
-                                 int qn, typename Mfma<T>::acc_t (&acc)[C::MI][C::NI]) {
+__device__ inline void tile_mfma(const T *Ab, const T *Bb, int wm, int wn, int lr, int lk, int qm, int qn,
+                                 typename Mfma<T>::acc_t (&acc)[C::MI][C::NI]) {
   constexpr int BM = C::BM, BN = C::BN, MI = C::MI, NI = C::NI, TK = C::TK;
-  if (full) {
+  if (qm <= 0 || qn <= 0) return;
 #pragma unroll
-    for (int kk = 0; kk < TK; kk += 4) {
-      T a[MI], b[NI];
+  for (int kk = 0; kk < TK; kk += 4) {
+    T a[MI], b[NI];
 #pragma unroll
-      for (int mi = 0; mi < MI; ++mi) a[mi] = Ab[(kk + lk) * (BM + kPad) + wm + 16 * mi + lr];
+    for (int mi = 0; mi < MI; ++mi) a[mi] = Ab[(kk + lk) * (BM + kPad) + wm + 16 * mi + lr];
 #pragma unroll
-      for (int ni = 0; ni < NI; ++ni) b[ni] = Bb[(kk + lk) * (BN + kPad) + wn + 16 * ni + lr];
+    for (int ni = 0; ni < NI; ++ni) b[ni] = Bb[(kk + lk) * (BN + kPad) + wn + 16 * ni + lr];
 #pragma unroll
-      for (int mi = 0; mi < MI; ++mi)
+    for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = Mfma<T>::step(a[mi], b[ni], acc[mi][ni]);
-    }
-  } else if (qm > 0 && qn > 0) {
-#pragma unroll
-    for (int kk = 0; kk < TK; kk += 4) {
-      T a[MI], b[NI];
-#pragma unroll
-      for (int mi = 0; mi < MI; ++mi) a[mi] = Ab[(kk + lk) * (BM + kPad) + wm + 16 * mi + lr];
-#pragma unroll
-      for (int ni = 0; ni < NI; ++ni) b[ni] = Bb[(kk + lk) * (BN + kPad) + wn + 16 * ni + lr];
-#pragma unroll
-      for (int mi = 0; mi < MI; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < NI; ++ni)
-          if (qm > 16 * mi && qn > 16 * ni) acc[mi][ni] = Mfma<T>::step(a[mi], b[ni], acc[mi][ni]);
-    }
+      for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = Mfma<T>::step(a[mi], b[ni], acc[mi][ni]);
   }
 }
 
@@ -541,7 +541,6 @@ __device__ inline void gemm_tile(const GTile *__restrict__ tiles, const GOut *__
   const int lr = lane & 15, lk = lane >> 4;
   // rows / columns of this wave's quadrant inside the output (wave-uniform)
   const int qm = o.m - (row0 + wm), qn = o.n - (col0 + wn);
-  const bool full = qm >= BM / C::WY && qn >= BN / C::WX;
   acc_t acc[MI][NI];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
@@ -550,26 +549,32 @@ __device__ inline void gemm_tile(const GTile *__restrict__ tiles, const GOut *__
 
   SL L;
   T ra[SL::EA], rb[SL::EB];
-  uint32_t oka, okb;
   for (int si = 0; si < o.seg_count; ++si) {
     seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
     const int nsteps = (L.k + TK - 1) / TK;
     if (nsteps == 0) continue;
     // double-buffered LDS: while the MFMAs consume stage `buf`, the next K
-    // step is fetched into registers and then written to the other stage
-    // (last step peeled so that the loop body has no conditional load or store)
+    // step is fetched into registers and then written to the other stage;
+    // steps 0 .. nsteps-2 are whole, the last one may end past K
     int buf = 0;
-    seg_fetch(L, 0, ra, rb, oka, okb);
-    seg_store(L, tid, 0, ra, rb, oka, okb, As[buf], Bs[buf]);
+    seg_fetch<true>(L, 0, ra, rb);
+    seg_store(L, 0, ra, rb, As[buf], Bs[buf]);
     __syncthreads();
-    for (int step = 0; step + 1 < nsteps; ++step) {
-      seg_fetch(L, step + 1, ra, rb, oka, okb);
-      tile_mfma<T, C>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
+    for (int step = 1; step + 1 < nsteps; ++step) {
+      seg_fetch<false>(L, step, ra, rb);
+      tile_mfma<T, C>(As[buf], Bs[buf], wm, wn, lr, lk, qm, qn, acc);
       buf ^= 1;
-      seg_store(L, tid, step + 1, ra, rb, oka, okb, As[buf], Bs[buf]);
+      seg_store(L, step, ra, rb, As[buf], Bs[buf]);
       __syncthreads();
     }
-    tile_mfma<T, C>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
+    if (nsteps > 1) {
+      seg_fetch<true>(L, nsteps - 1, ra, rb);
+      tile_mfma<T, C>(As[buf], Bs[buf], wm, wn, lr, lk, qm, qn, acc);
+      buf ^= 1;
+      seg_store(L, nsteps - 1, ra, rb, As[buf], Bs[buf]);
+      __syncthreads();
+    }
+    tile_mfma<T, C>(As[buf], Bs[buf], wm, wn, lr, lk, qm, qn, acc);
     __syncthreads();  // the next segment's first store reuses the stages
   }
   T *Cp = reinterpret_cast<T *>(bases.p[o.c_slot]) + o.c_off;
@@ -603,52 +608,194 @@ __device__ inline void gemm_tile(const GTile *__restrict__ tiles, const GOut *__
 typedef short v4s __attribute__((ext_vector_type(4)));  // 4 BF16 bit patterns
 
 
-// Parts of one staged element: NP = 2 gives hi = RNE(v), lo = RNE(v - hi)
-// (3xBF16); NP = 3 adds a middle part, hi = RNE(v), mid = RNE(v - hi),
-// lo = RNE(v - hi - mid) (6xBF16).  Every difference is exact in FP32.
-template <int NP, int LEN>
-__device__ inline void split_parts(float v, __bf16 (&P)[NP][LEN], int e) {
-  const __bf16 hi = __bf16(v);
-  const float r1 = v - float(hi);
-  P[0][e] = hi;
-  if constexpr (NP == 2) {
-    P[1][e] = __bf16(r1);
-  } else {
-    const __bf16 mid = __bf16(r1);
-    P[1][e] = mid;
-    P[2][e] = __bf16(r1 - float(mid));
-  }
-}
-
 // LDS stage of one operand: NP part arrays, rows of TK + 8 BF16 (K-contiguous)
 template <class C, int NP>
 using StageA = __bf16[NP][C::BM * (C::TK + 8)];
 template <class C, int NP>
 using StageB = __bf16[NP][C::BN * (C::TK + 8)];
 
-template <class C, int NP>
-__device__ inline void seg_store_bfs(const SegLoad<float, C> &L, int tid, int step,
-                                     const float (&ra)[SegLoad<float, C>::EA],
-                                     const float (&rb)[SegLoad<float, C>::EB], uint32_t oka, uint32_t okb,
-                                     StageA<C, NP> &Ap, StageB<C, NP> &Bp) {
-  constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK;
-  const int i0 = L.tA ? tid % BM : tid / TK, di = L.tA ? 0 : NT / TK;
-  const int j0 = L.tB ? tid / TK : tid % BN, dj = L.tB ? NT / TK : 0;
-  const int k0 = step * TK;
+// Staging of the split forms.  Each thread stages R = BM*TK/NT (1, 2 or
+// 4) elements of op(A) and as many of op(B) per K step, mapped so that
+// every load instruction is coalesced:
+// * an operand stored M- (N-)contiguous: consecutive threads take
+//   consecutive rows (columns) and a thread holds R consecutive K positions
+//   of its row, so each BF16 part goes to LDS as one packed write of R values;
+// * an operand stored K-contiguous: consecutive threads take consecutive K
+//   positions of a row and a thread's elements lie NT/TK rows apart, each
+//   part written as single values.
+// Element `it` of a thread is at row r0 + dr*it and K position k0 + dk*it of
+// the staged tile.  Loads are buffer loads from a workgroup-uniform base
+// (the tile's first row / column at the step's first K position, advanced
+// by scalar arithmetic per step) at per-thread byte offsets fixed for the
+// whole segment; an element outside the output, or past K in the last
+// step, gets an offset beyond the buffer's range, for which the hardware
+// returns 0 -- so no per-step address or mask arithmetic is needed.
+
+template <class C>
+struct SegLoadK {
+  static constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK;
+  static constexpr int RA = BM * TK / NT, RB = BN * TK / NT;
+  static_assert((RA == 1 || RA == 2 || RA == 4) && (RB == 1 || RB == 2 || RB == 4), "R must be 1, 2 or 4");
+  const char *A, *B;          // step-0 bases of the tile's operand panels (uniform)
+  int64_t da, db;             // bytes per K step (uniform)
+  int32_t oa[RA], ob[RB];     // byte offsets of the thread's elements from the step base, or kOffOut
+  int ia, dia, ka, dka;       // A: row and K position of element 0 and their per-element increments
+  int jb, djb, kb, dkb;       // B: column and K position, the same
+  int k;
+  float alpha;
+  bool idA, pa, pb;  // identity A; packed staging of A, of B
+  int ga;            // A: output row of element 0 (identity operands)
+  int ma;            // A: rows of the output (identity operands)
+};
+
+template <class C>
+__device__ inline void segk_setup(SegLoadK<C> &L, const GSeg &sg, const Bases &bases, const GOut &o, int row0,
+                                  int col0, int tid) {
+  constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK, RA = SegLoadK<C>::RA, RB = SegLoadK<C>::RB;
+  const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB;
+  const float *A = reinterpret_cast<const float *>(bases.p[sg.a_slot]) + sg.a_off;
+  const float *B = reinterpret_cast<const float *>(bases.p[sg.b_slot]) + sg.b_off;
+  L.idA = sg.flags & SEG_AID;
+  L.alpha = float(sg.alpha);
+  L.k = sg.k;
+  L.ma = o.m;
+  // op(A) element (i, kk) of step s sits at A[(row0+i)*lda + s*TK+kk] (row-major, K-contiguous)
+  // or A[(s*TK+kk)*lda + row0+i] (transposed, M-contiguous)
+  L.pa = tA;
+  L.ia = tA ? tid % BM : tid / TK;
+  L.dia = tA ? 0 : NT / TK;
+  L.ka = tA ? (tid / BM) * RA : tid % TK;
+  L.dka = tA ? 1 : 0;
+  L.ga = row0 + L.ia;
+  L.A = reinterpret_cast<const char *>(tA ? A + row0 : A + int64_t(row0) * sg.lda);
+  L.da = 4 * (tA ? int64_t(TK) * sg.lda : int64_t(TK));
 #pragma unroll
-  for (int it = 0; it < L.EA; ++it) {
-    const int kk = L.ka0 + L.dka * it;
-    const bool ok = (oka >> it) & 1;
-    float v;
-    if (L.idA)
-      v = (ok && L.ia0 + L.dia * it == k0 + kk) ? L.alpha : 0.f;
-    else
-      v = ok ? L.alpha * ra[it] : 0.f;
-    split_parts<NP>(v, Ap, (i0 + di * it) * (C::TK + 8) + kk);
+  for (int it = 0; it < RA; ++it) {
+    const int i = L.ia + L.dia * it, kk = L.ka + L.dka * it;
+    L.oa[it] = row0 + i < o.m ? 4 * (tA ? kk * sg.lda + i : i * sg.lda + kk) : kOffOut;
+  }
+  // op(B) element (kk, j) sits at B[(s*TK+kk)*ldb + col0+j] (row-major, N-contiguous)
+  // or B[(col0+j)*ldb + s*TK+kk] (transposed, K-contiguous)
+  L.pb = !tB;
+  L.jb = tB ? tid / TK : tid % BN;
+  L.djb = tB ? NT / TK : 0;
+  L.kb = tB ? tid % TK : (tid / BN) * RB;
+  L.dkb = tB ? 0 : 1;
+  L.B = reinterpret_cast<const char *>(tB ? B + int64_t(col0) * sg.ldb : B + col0);
+  L.db = 4 * (tB ? int64_t(TK) : int64_t(TK) * sg.ldb);
+#pragma unroll
+  for (int it = 0; it < RB; ++it) {
+    const int j = L.jb + L.djb * it, kk = L.kb + L.dkb * it;
+    L.ob[it] = col0 + j < o.n ? 4 * (tB ? j * sg.ldb + kk : kk * sg.ldb + j) : kOffOut;
+  }
+}
+
+// Loads of one K step.  EDGE: the step may reach past K (only a segment's
+// last step can), and the offsets of positions past K are replaced by
+// kOffOut; other steps load at the segment's fixed offsets.
+template <bool EDGE, class C>
+__device__ inline void segk_fetch(const SegLoadK<C> &L, int step, float (&ra)[SegLoadK<C>::RA],
+                                  float (&rb)[SegLoadK<C>::RB]) {
+  constexpr int RA = SegLoadK<C>::RA, RB = SegLoadK<C>::RB;
+  const int k0 = step * C::TK;
+  const __amdgpu_buffer_rsrc_t rA = buf_rsrc(L.A + step * L.da), rB = buf_rsrc(L.B + step * L.db);
+  if (!L.idA) {
+#pragma unroll
+    for (int it = 0; it < RA; ++it)
+      ra[it] = buf_load<float>(rA, !EDGE || k0 + L.ka + L.dka * it < L.k ? L.oa[it] : kOffOut);
   }
 #pragma unroll
-  for (int it = 0; it < L.EB; ++it)
-    split_parts<NP>(((okb >> it) & 1) ? rb[it] : 0.f, Bp, (j0 + dj * it) * (C::TK + 8) + L.kb0 + L.dkb * it);
+  for (int it = 0; it < RB; ++it) rb[it] = buf_load<float>(rB, !EDGE || k0 + L.kb + L.dkb * it < L.k ? L.ob[it] : kOffOut);
+}
+
+// R consecutive BF16 values of one part, written as one LDS access
+template <int R>
+struct Packed;
+template <>
+struct Packed<1> {
+  typedef __bf16 bf_t;
+  typedef float f_t;
+};
+template <>
+struct Packed<2> {
+  typedef __bf16 bf_t __attribute__((ext_vector_type(2)));
+  typedef float f_t __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Packed<4> {
+  typedef __bf16 bf_t __attribute__((ext_vector_type(4)));
+  typedef float f_t __attribute__((ext_vector_type(4)));
+};
+
+// Split R values into NP parts (NP = 2: hi = RNE(v), lo = RNE(v - hi);
+// NP = 3: hi, mid = RNE(v - hi), lo = RNE(v - hi - mid); every difference is
+// exact in FP32) and write part q to P[q][e .. e+R).
+template <int NP, int R, int LEN>
+__device__ inline void split_store(const float (&v)[R], __bf16 (&P)[NP][LEN], int e) {
+  typedef typename Packed<R>::bf_t bf_t;
+  typedef typename Packed<R>::f_t f_t;
+  f_t x;
+  if constexpr (R == 1) {
+    x = v[0];
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = v[r];
+  }
+  bf_t part[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    if constexpr (R == 1)
+      part[q] = __bf16(x);
+    else
+      part[q] = __builtin_convertvector(x, bf_t);
+    if (q + 1 < NP) {
+      if constexpr (R == 1)
+        x = x - float(part[q]);
+      else
+        x = x - __builtin_convertvector(part[q], f_t);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) *reinterpret_cast<bf_t *>(&P[q][e]) = part[q];
+}
+
+// Write one fetched K step to an LDS stage of NP part arrays ([row][k] for
+// A, [column][k] for B, rows of TK + 8): alpha folded into A, identity
+// factors generated, then the split.
+template <class C, int NP>
+__device__ inline void segk_store(const SegLoadK<C> &L, int step, const float (&ra)[SegLoadK<C>::RA],
+                                  const float (&rb)[SegLoadK<C>::RB], StageA<C, NP> &Ap, StageB<C, NP> &Bp) {
+  constexpr int RA = SegLoadK<C>::RA, RB = SegLoadK<C>::RB, LD = C::TK + 8;
+  const int k0 = step * C::TK;
+  float va[RA];
+  if (L.idA) {
+#pragma unroll
+    for (int it = 0; it < RA; ++it) {
+      const int g = L.ga + L.dia * it, kk = k0 + L.ka + L.dka * it;
+      va[it] = (g < L.ma && kk < L.k && g == kk) ? L.alpha : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < RA; ++it) va[it] = L.alpha * ra[it];
+  }
+  if (L.pa) {
+    split_store<NP>(va, Ap, L.ia * LD + L.ka);
+  } else {
+#pragma unroll
+    for (int it = 0; it < RA; ++it) {
+      const float v1[1] = {va[it]};
+      split_store<NP>(v1, Ap, (L.ia + L.dia * it) * LD + L.ka);
+    }
+  }
+  if (L.pb) {
+    split_store<NP>(rb, Bp, L.jb * LD + L.kb);
+  } else {
+#pragma unroll
+    for (int it = 0; it < RB; ++it) {
+      const float v1[1] = {rb[it]};
+      split_store<NP>(v1, Bp, (L.jb + L.djb * it) * LD + L.kb);
+    }
+  }
 }
 
 // One 16-deep K step of BF16 products: NP = 2: hi*lo + lo*hi + hi*hi;
@@ -657,10 +804,14 @@ __device__ inline void seg_store_bfs(const SegLoad<float, C> &L, int tid, int st
 // ones).
 template <class C, int NP>
 __device__ inline void tile_mfma_bfs(const StageA<C, NP> &Ap, const StageB<C, NP> &Bp, int wm, int wn, int lr,
-                                     int lk, bool full, int qm, int qn, v4f (&acc)[C::MI][C::NI]) {
+                                     int lk, int qm, int qn, v4f (&acc)[C::MI][C::NI]) {
   constexpr int MI = C::MI, NI = C::NI;
   static_assert(C::TK == 16, "one MFMA K step per staged step");
-  if (!full && !(qm > 0 && qn > 0)) return;
+  // a wave whose block lies wholly outside the output skips the step; a
+  // partly covered block runs every MFMA (rows and columns outside the
+  // output are staged as zeros and their accumulators are never stored),
+  // which keeps the step free of per-tile branches
+  if (qm <= 0 || qn <= 0) return;
   v4s a[NP][MI], b[NP][NI];
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
@@ -675,18 +826,17 @@ __device__ inline void tile_mfma_bfs(const StageA<C, NP> &Ap, const StageB<C, NP
 #pragma unroll
   for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < NI; ++ni)
-      if (full || (qm > 16 * mi && qn > 16 * ni)) {
-        v4f c = acc[mi][ni];
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[Lo][ni], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[Lo][mi], b[H][ni], c, 0, 0, 0);
-        if constexpr (NP == 3) {
-          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[M][mi], b[M][ni], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[M][ni], c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[M][mi], b[H][ni], c, 0, 0, 0);
-        }
-        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[H][ni], c, 0, 0, 0);
+    for (int ni = 0; ni < NI; ++ni) {
+      v4f c = acc[mi][ni];
+      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[Lo][ni], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[Lo][mi], b[H][ni], c, 0, 0, 0);
+      if constexpr (NP == 3) {
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[M][mi], b[M][ni], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[M][ni], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[M][mi], b[H][ni], c, 0, 0, 0);
       }
+      acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[H][ni], c, 0, 0, 0);
+    }
 }
 
 // Same tile walk as gemm_tile (FP32 data in HBM, FP32 accumulators and
@@ -696,7 +846,7 @@ template <class C, int NP>
 __device__ inline void gemm_tile_bfs(const GTile *__restrict__ tiles, const GOut *__restrict__ outs,
                                      const GSeg *__restrict__ segs, const Bases &bases) {
   constexpr int BM = C::BM, BN = C::BN, MI = C::MI, NI = C::NI, TK = C::TK;
-  typedef SegLoad<float, C> SL;
+  typedef SegLoadK<C> SL;
   __shared__ __attribute__((aligned(16))) StageA<C, NP> As[2];
   __shared__ __attribute__((aligned(16))) StageB<C, NP> Bs[2];
   const GTile tl = tiles[blockIdx.x];
@@ -707,32 +857,39 @@ __device__ inline void gemm_tile_bfs(const GTile *__restrict__ tiles, const GOut
   const int wm = (wave / C::WX) * (BM / C::WY), wn = (wave % C::WX) * (BN / C::WX);
   const int lr = lane & 15, lk = lane >> 4;
   const int qm = o.m - (row0 + wm), qn = o.n - (col0 + wn);
-  const bool full = qm >= BM / C::WY && qn >= BN / C::WX;
   v4f acc[MI][NI];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[i][j] = v4f{0, 0, 0, 0};
   SL L;
-  float ra[SL::EA], rb[SL::EB];
-  uint32_t oka, okb;
+  float ra[SL::RA], rb[SL::RB];
   for (int si = 0; si < o.seg_count; ++si) {
-    seg_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
+    segk_setup(L, segs[o.seg_begin + si], bases, o, row0, col0, tid);
     const int nsteps = (L.k + TK - 1) / TK;
     if (nsteps == 0) continue;
+    // double-buffered LDS, one step of register prefetch; steps 0 .. nsteps-2
+    // are whole, the last one may end past K
     int buf = 0;
-    seg_fetch(L, 0, ra, rb, oka, okb);
-    seg_store_bfs<C, NP>(L, tid, 0, ra, rb, oka, okb, As[buf], Bs[buf]);
+    segk_fetch<true>(L, 0, ra, rb);
+    segk_store<C, NP>(L, 0, ra, rb, As[buf], Bs[buf]);
     __syncthreads();
-    for (int step = 0; step + 1 < nsteps; ++step) {
-      seg_fetch(L, step + 1, ra, rb, oka, okb);
-      tile_mfma_bfs<C, NP>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
+    for (int step = 1; step + 1 < nsteps; ++step) {
+      segk_fetch<false>(L, step, ra, rb);
+      tile_mfma_bfs<C, NP>(As[buf], Bs[buf], wm, wn, lr, lk, qm, qn, acc);
       buf ^= 1;
-      seg_store_bfs<C, NP>(L, tid, step + 1, ra, rb, oka, okb, As[buf], Bs[buf]);
+      segk_store<C, NP>(L, step, ra, rb, As[buf], Bs[buf]);
       __syncthreads();
     }
-    tile_mfma_bfs<C, NP>(As[buf], Bs[buf], wm, wn, lr, lk, full, qm, qn, acc);
-    __syncthreads();
+    if (nsteps > 1) {
+      segk_fetch<true>(L, nsteps - 1, ra, rb);
+      tile_mfma_bfs<C, NP>(As[buf], Bs[buf], wm, wn, lr, lk, qm, qn, acc);
+      buf ^= 1;
+      segk_store<C, NP>(L, nsteps - 1, ra, rb, As[buf], Bs[buf]);
+      __syncthreads();
+    }
+    tile_mfma_bfs<C, NP>(As[buf], Bs[buf], wm, wn, lr, lk, qm, qn, acc);
+    __syncthreads();  // the next segment's first store reuses the stages
   }
   float *Cp = reinterpret_cast<float *>(bases.p[o.c_slot]) + o.c_off;
 #pragma unroll
@@ -805,8 +962,8 @@ static void launch_variant(int v, hipStream_t st, const DevPlan *p, const Bases 
 // Range limits of the kernels' 32-bit element and tile arithmetic, checked
 // on the host for every output and segment of a plan.
 static void plan_check(const GemmPlan &plan) {
-  // the 64x64 kernel keeps per-thread 32-bit element offsets inside one K
-  // step of an operand block: rows x ld (+ the K step) must stay below 2^31
+  // the kernels keep 32-bit offsets: element offsets inside an operand
+  // block below 2^31, byte offsets inside one tile's K step below 2^30
   for (const GOut &o : plan.outs) {
     // tile origins and row / column indices inside the kernel are 32-bit
     MDMRG_REQUIRE(o.m >= 1 && o.n >= 1 && o.m < (1 << 30) && o.n < (1 << 30), -6,
@@ -817,6 +974,12 @@ static void plan_check(const GemmPlan &plan) {
       const int64_t ext_b = (g.flags & SEG_TB) ? int64_t(o.n) * g.ldb + kTKmax : int64_t(kTKmax) * g.ldb + o.n;
       MDMRG_REQUIRE(ext_a < (int64_t(1) << 31) && ext_b < (int64_t(1) << 31), -6,
                     "grouped GEMM: operand block too large for 32-bit element offsets");
+      // buffer-load byte offsets inside one tile's K step (128 x 128 tiles at
+      // most, 8-byte elements) stay below 2^30, under the buffer range
+      const int64_t tile_a = (g.flags & SEG_TA) ? int64_t(kTKmax) * g.lda + 128 : int64_t(128) * g.lda + kTKmax;
+      const int64_t tile_b = (g.flags & SEG_TB) ? int64_t(128) * g.ldb + kTKmax : int64_t(kTKmax) * g.ldb + 128;
+      MDMRG_REQUIRE(8 * tile_a < (int64_t(1) << 30) && 8 * tile_b < (int64_t(1) << 30), -6,
+                    "grouped GEMM: leading dimension too large for 32-bit tile offsets");
     }
   }
 }
