@@ -160,20 +160,23 @@ def cpu_baseline(mdmrg, budget_s):
                       f'{os.environ.get("OMP_NUM_THREADS", "default")}'}
 
 
-SPLIT_FORMS = (('fp32', 'FP32', 'graph32'), ('bf16x3', 'BF16X3', 'graphbf3'), ('bf16x6', 'BF16X6', 'graphbf6'))
+# (name, precision form of the split products, graph statistics key, ladder):
+# ladder 1 runs an FP32 stage between the 3xBF16 stage and the FP64 refinement
+SPLIT_FORMS = (('fp32', 'FP32', 'graph32', 0), ('bf16x3', 'BF16X3', 'graphbf3', 0), ('bf16x6', 'BF16X6', 'graphbf6', 0),
+               ('bf16x3_fp32', 'BF16X3', None, 1))
 
 
 def split_compare(ctx, x0, torch, args):
     """Davidson s/step at fixed dE: the plain FP64 form against the mixed
-    precision forms (FP32, 3xBF16 or 6xBF16 products, then FP64 refinement),
-    launched eagerly and replayed from captured graphs (the precision +
+    precision forms (FP32, 3xBF16 or 6xBF16 products, or 3xBF16 then FP32
+    products, then FP64 refinement), launched eagerly and replayed from captured graphs (the precision +
     batched form), all from the same start vector at the current bond.
     E_ref = FP64 solve to |r| <= 1e-10; dE = 1e-9 |E_ref|.  Every form is
     warmed up at the bond before any timed solve (tile-variant trials of each
     plan, FP32 operator copies, graph capture), so all timed solves start from
     the same tuned state."""
     from paper_2311_14106_amd import mdmrg
-    forms = [(name, getattr(mdmrg, const), tag) for name, const, tag in SPLIT_FORMS]
+    forms = [(name, getattr(mdmrg, const), tag, lad) for name, const, tag, lad in SPLIT_FORMS]
 
     def solve(fn):
         x = x0.clone()
@@ -185,7 +188,7 @@ def split_compare(ctx, x0, torch, args):
 
     def warm(n=6):
         y = torch.empty_like(x0)
-        for prec in [mdmrg.FP64] + [p for _, p, _ in forms]:
+        for prec in [mdmrg.FP64] + sorted({p for _, p, _, _ in forms}):
             for _ in range(n):
                 ctx.heff_apply(x0, y, prec=prec)
         torch.cuda.synchronize()
@@ -193,9 +196,15 @@ def split_compare(ctx, x0, torch, args):
     def plain(x):
         return ctx.davidson(x, tol=args.split_tol, max_iter=600)
 
-    def mixed(prec):
-        return lambda x: ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol, prec_split=prec,
-                                            max_iter=600)
+    def mixed(prec, ladder=0):
+        def run(x):
+            ctx.set_option(mdmrg.OPT_MIXED_LADDER, ladder)
+            try:
+                return ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol, prec_split=prec,
+                                          max_iter=600)
+            finally:
+                ctx.set_option(mdmrg.OPT_MIXED_LADDER, 0)
+        return run
 
     def entry(sol, t, name):
         e, r, n64, ns, _ = sol
@@ -222,25 +231,26 @@ def split_compare(ctx, x0, torch, args):
     frac = {'fp64': tfl['fp64'] / PEAK_FP64_TFLOPS if ms64 > 0 else None}
     line = [f'FP64 {t64:.2f}s {n64} products dE={abs(e64 - e_ref):.1e}']
     times = {}
-    for name, prec, _ in forms:
+    for name, prec, _, lad in forms:
         a = ctx.stats()
-        sol, t = solve(mixed(prec))
+        sol, t = solve(mixed(prec, lad))
         b = ctx.stats()
         ms = (b['split_gemm_ms'] - a['split_gemm_ms']) / max(1.0, b['n_matvec_split'] - a['n_matvec_split'])
         res['mixed_' + name] = entry(sol, t, name)
-        res['gemm_ms_per_product'][name] = ms
-        tfl[name] = fl / (ms * 1e9) if ms > 0 else None
-        if name == 'fp32':
-            frac[name] = tfl[name] / PEAK_FP32_TFLOPS if ms > 0 else None
-        else:
-            frac[name + '_issued'] = int(name[-1]) * tfl[name] / PEAK_BF16_TFLOPS if ms > 0 else None
+        if not lad:
+            res['gemm_ms_per_product'][name] = ms
+            tfl[name] = fl / (ms * 1e9) if ms > 0 else None
+            if name == 'fp32':
+                frac[name] = tfl[name] / PEAK_FP32_TFLOPS if ms > 0 else None
+            else:
+                frac[name + '_issued'] = int(name[-1]) * tfl[name] / PEAK_BF16_TFLOPS if ms > 0 else None
         times['mixed_' + name] = t
         line.append(f'mixed {name} {t:.2f}s {sol[3]} + {sol[2]} FP64 products dE={abs(sol[0] - e_ref):.1e}')
     log(f'[bench] fixed-dE: ref E={e_ref:.12f} ({n_ref} products); ' + '; '.join(line))
     res['gemm_tflops'] = tfl
     res['gemm_frac_of_peak'] = frac
     res['speedup'] = t64 / times['mixed_fp32'] if times['mixed_fp32'] > 0 else None
-    for name, _, _ in forms[1:]:
+    for name, _, _, _ in forms[1:]:
         res['speedup_' + name] = t64 / times['mixed_' + name] if times['mixed_' + name] > 0 else None
     if args.batched:
         # precision + batched form: the same solves with every product
@@ -259,13 +269,14 @@ def split_compare(ctx, x0, torch, args):
                              'ok': abs(e64g - e_ref) <= de}
         gms = {'fp64': per(g0, g1, 'graph64')}
         gtimes = {}
-        for name, prec, tag in forms:
+        for name, prec, tag, lad in forms:
             a = ctx.stats()
-            sol, t = solve(mixed(prec))
+            sol, t = solve(mixed(prec, lad))
             b = ctx.stats()
             res[f'mixed_{name}_graph'] = entry(sol, t, name)
             res[f'speedup_{name}_graph'] = t64 / t if t > 0 else None
-            gms[name] = per(a, b, tag)
+            if tag:
+                gms[name] = per(a, b, tag)
             gtimes[f'mixed_{name}_graph'] = t
         ctx.set_option(mdmrg.OPT_GRAPH, 0)
         # the precision + batched form is the fastest graph-replayed mixed

@@ -621,8 +621,9 @@ using StageB = __bf16[NP][C::BN * (C::TK + 8)];
 //   consecutive rows (columns) and a thread holds R consecutive K positions
 //   of its row, so each BF16 part goes to LDS as one packed write of R values;
 // * an operand stored K-contiguous: consecutive threads take consecutive K
-//   positions of a row and a thread's elements lie NT/TK rows apart, each
-//   part written as single values.
+//   positions of a row and a thread holds R consecutive rows; neighbouring
+//   lanes exchange values (pair_store) so that each BF16 part again goes to
+//   LDS as packed K pairs.
 // Element `it` of a thread is at row r0 + dr*it and K position k0 + dk*it of
 // the staged tile.  Loads are buffer loads from a workgroup-uniform base
 // (the tile's first row / column at the step's first K position, advanced
@@ -651,7 +652,7 @@ struct SegLoadK {
 template <class C>
 __device__ inline void segk_setup(SegLoadK<C> &L, const GSeg &sg, const Bases &bases, const GOut &o, int row0,
                                   int col0, int tid) {
-  constexpr int BM = C::BM, BN = C::BN, NT = C::NT, TK = C::TK, RA = SegLoadK<C>::RA, RB = SegLoadK<C>::RB;
+  constexpr int BM = C::BM, BN = C::BN, TK = C::TK, RA = SegLoadK<C>::RA, RB = SegLoadK<C>::RB;
   const bool tA = sg.flags & SEG_TA, tB = sg.flags & SEG_TB;
   const float *A = reinterpret_cast<const float *>(bases.p[sg.a_slot]) + sg.a_off;
   const float *B = reinterpret_cast<const float *>(bases.p[sg.b_slot]) + sg.b_off;
@@ -662,8 +663,8 @@ __device__ inline void segk_setup(SegLoadK<C> &L, const GSeg &sg, const Bases &b
   // op(A) element (i, kk) of step s sits at A[(row0+i)*lda + s*TK+kk] (row-major, K-contiguous)
   // or A[(s*TK+kk)*lda + row0+i] (transposed, M-contiguous)
   L.pa = tA;
-  L.ia = tA ? tid % BM : tid / TK;
-  L.dia = tA ? 0 : NT / TK;
+  L.ia = tA ? tid % BM : RA * (tid / TK);
+  L.dia = tA ? 0 : 1;
   L.ka = tA ? (tid / BM) * RA : tid % TK;
   L.dka = tA ? 1 : 0;
   L.ga = row0 + L.ia;
@@ -677,8 +678,8 @@ __device__ inline void segk_setup(SegLoadK<C> &L, const GSeg &sg, const Bases &b
   // op(B) element (kk, j) sits at B[(s*TK+kk)*ldb + col0+j] (row-major, N-contiguous)
   // or B[(col0+j)*ldb + s*TK+kk] (transposed, K-contiguous)
   L.pb = !tB;
-  L.jb = tB ? tid / TK : tid % BN;
-  L.djb = tB ? NT / TK : 0;
+  L.jb = tB ? RB * (tid / TK) : tid % BN;
+  L.djb = tB ? 1 : 0;
   L.kb = tB ? tid % TK : (tid / BN) * RB;
   L.dkb = tB ? 0 : 1;
   L.B = reinterpret_cast<const char *>(tB ? B + int64_t(col0) * sg.ldb : B + col0);
@@ -759,6 +760,32 @@ __device__ inline void split_store(const float (&v)[R], __bf16 (&P)[NP][LEN], in
   for (int q = 0; q < NP; ++q) *reinterpret_cast<bf_t *>(&P[q][e]) = part[q];
 }
 
+// Staging of a K-contiguous operand: the thread holds R values of R
+// consecutive rows at K position kk, and so does its neighbour lane at
+// kk ^ 1.  The two exchange half of their values (one DPP lane swap per
+// pair) so that the even lane holds the first R/2 rows and the odd lane the
+// last R/2 at K positions (kk & ~1, kk | 1); each part is then written as
+// one packed pair per row.  With rows of TK + 8 BF16 the 64 lanes of such a
+// write cover the 64 LDS banks once.
+template <int NP, int R, int LEN>
+__device__ inline void pair_store(const float (&v)[R], __bf16 (&P)[NP][LEN], int row, int kk, int ld) {
+  if constexpr (R == 1) {
+    split_store<NP>(v, P, row * ld + kk);
+  } else {
+    constexpr int H = R / 2;
+    const bool odd = kk & 1;
+#pragma unroll
+    for (int p = 0; p < H; ++p) {
+      const float send = odd ? v[p] : v[H + p];
+      // quad_perm [1, 0, 3, 2]: every lane receives the value of lane ^ 1
+      const float recv =
+          __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, send), 0xB1, 0xF, 0xF, false));
+      const float pr[2] = {odd ? recv : v[p], odd ? v[H + p] : recv};
+      split_store<NP>(pr, P, (row + (odd ? H : 0) + p) * ld + (kk & ~1));
+    }
+  }
+}
+
 // Write one fetched K step to an LDS stage of NP part arrays ([row][k] for
 // A, [column][k] for B, rows of TK + 8): alpha folded into A, identity
 // factors generated, then the split.
@@ -778,24 +805,14 @@ __device__ inline void segk_store(const SegLoadK<C> &L, int step, const float (&
 #pragma unroll
     for (int it = 0; it < RA; ++it) va[it] = L.alpha * ra[it];
   }
-  if (L.pa) {
+  if (L.pa)
     split_store<NP>(va, Ap, L.ia * LD + L.ka);
-  } else {
-#pragma unroll
-    for (int it = 0; it < RA; ++it) {
-      const float v1[1] = {va[it]};
-      split_store<NP>(v1, Ap, (L.ia + L.dia * it) * LD + L.ka);
-    }
-  }
-  if (L.pb) {
+  else
+    pair_store<NP>(va, Ap, L.ia, L.ka, LD);
+  if (L.pb)
     split_store<NP>(rb, Bp, L.jb * LD + L.kb);
-  } else {
-#pragma unroll
-    for (int it = 0; it < RB; ++it) {
-      const float v1[1] = {rb[it]};
-      split_store<NP>(v1, Bp, (L.jb + L.djb * it) * LD + L.kb);
-    }
-  }
+  else
+    pair_store<NP>(rb, Bp, L.jb, L.kb, LD);
 }
 
 // One 16-deep K step of BF16 products: NP = 2: hi*lo + lo*hi + hi*hi;
