@@ -202,10 +202,15 @@ enum {
                                   FP32 stage (to tol_split or its own noise floor)
                                   between the 3xBF16 and the FP64 stages; 0 (default):
                                   3xBF16 then FP64 */
-  MDMRG_OPT_MIXED_HANDOVER = 10 /* 1..16: each stage of a mixed solve after the first
+  MDMRG_OPT_MIXED_HANDOVER = 10, /* 1..16: each stage of a mixed solve after the first
                                   starts from this many lowest Ritz vectors of the
                                   previous stage (one product each in its own precision);
                                   1 (default): from the eigenvector estimate alone */
+  MDMRG_OPT_MIXED_CORRECT = 11  /* 1 (default): when the split stages of a mixed solve
+                                  stop with an FP64 residual above 4 tol, up to two
+                                  defect-corrected split stages follow (see
+                                  mdmrg_davidson_mixed) before the FP64 Davidson
+                                  stage; 0: FP64 Davidson directly */
 };
 /* Set a context option (EINVAL for unknown options or bad values).
  * With the environment variable MDMRG_VERBOSE set, the library prints
@@ -286,16 +291,24 @@ int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max
 
 /* Mixed-precision Davidson (the products beyond the FP64 ceiling of Sec. IV
  * and Fig. 2, with the final eigenpair held to FP64 accuracy): a Davidson
- * solve whose products use the split
- * form prec_split (MDMRG_FP32, MDMRG_BF16X3 or MDMRG_BF16X6) until its
- * residual reaches
- * tol_split or stops decreasing (no 10% gain over 4 products once within
- * 2f, over 24 within 20f, over 64 elsewhere), then (MDMRG_OPT_MIXED_LADDER,
- * 3xBF16 only) an FP32 stage the same way, then an FP64 Davidson from that
- * vector until the FP64 residual <= tol.  f is the noise floor of the split operator, measured
- * with one split and one FP64 product of the normalised start vector x0:
- * f = |(H_split - H) x0| / |H x0| * |x0.H x0|.  *n_mv64 and *n_mv_split
- * count the products of each kind (the floor probe included). */
+ * solve whose products use the split form prec_split (MDMRG_FP32,
+ * MDMRG_BF16X3 or MDMRG_BF16X6) until its residual reaches tol_split or
+ * stops decreasing (no 10% gain over 4 products once within 2f, over 24
+ * within 20f, over 64 elsewhere), then (MDMRG_OPT_MIXED_LADDER, 3xBF16
+ * only) an FP32 stage the same way.  f is the noise floor of the split
+ * operator, measured with one split and one FP64 product of the normalised
+ * start vector v: f = |(H_split - H) v| / |H v| * |v.H v|.
+ * Then (MDMRG_OPT_MIXED_CORRECT, default) up to two defect-corrected
+ * rounds: one FP64 product of the current vector x0 gives its FP64
+ * residual -- if <= tol the solve ends there, with the FP64 Rayleigh
+ * quotient x0.H x0 as the energy -- and, with one split product, the defect
+ * d = H x0 - H_split x0; a split Davidson on H_split + d x0^T + x0 d^T -
+ * (x0.d) x0 x0^T (which reproduces H x0 exactly) then runs to tol / 2.
+ * Once the FP64 residual is within 4 tol (or after two rounds), an FP64
+ * Davidson from that vector, reusing its FP64 product, until the FP64
+ * residual <= tol (without the option: directly after the split stages).
+ * *n_mv64 and *n_mv_split count the products of each kind (the floor probe
+ * included). */
 int mdmrg_davidson_mixed(mdmrg_ctx ctx, double *x, double tol, int prec_split, double tol_split,
                          int max_iter, int m_max, double *energy, double *resid, int *n_mv64,
                          int *n_mv_split);

@@ -259,6 +259,9 @@ int mdmrg_set_option(mdmrg_ctx ctx, int option, int64_t value) {
       case MDMRG_OPT_MIXED_LADDER:
         c.mixed_ladder = value != 0;
         break;
+      case MDMRG_OPT_MIXED_CORRECT:
+        c.mixed_correct = value != 0;
+        break;
       case MDMRG_OPT_MIXED_HANDOVER:
         MDMRG_REQUIRE(value >= 1 && value <= 16, MDMRG_EINVAL, "set_option: hand-over size must be 1..16");
         c.mixed_handover = int(value);

@@ -286,7 +286,7 @@ void dev_zero(Device *d, void *dst, size_t bytes) {
 // C[l/16 + 4r][l%16] for FP64 and C[4(l/16) + r][l%16] for FP32.
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int kTKmax = 32;  // largest K step of the grouped kernel
+constexpr int kTKmax = 16;  // largest K step of the grouped kernel (checked against every TileCfg)
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 
 // one MFMA 16x16x4 step in the element type of the kernel: FP64
@@ -366,6 +366,10 @@ using Cfg64q = TileCfg<64, 64, 2, 2, KStep<T>::small>;  // variant 2, k_gemm_w4:
 // 32.7 -> 23.3 ms).
 template <class T>
 using Cfg128 = TileCfg<128, 128, 2, 4, KStep<T>::small>;
+static_assert(KStep<double>::small <= kTKmax && KStep<double>::wide <= kTKmax && KStep<float>::small <= kTKmax &&
+                  KStep<float>::wide <= kTKmax && KStep<Bf16x3>::small <= kTKmax && KStep<Bf16x3>::wide <= kTKmax &&
+                  KStep<Bf16x6>::small <= kTKmax && KStep<Bf16x6>::wide <= kTKmax,
+              "a K step exceeds kTKmax, which bounds the offsets the host checks");
 constexpr int kTileM = 64, kTileN = 64;  // output tile of variants 0-2 (variant 3: 128 x 128)
 constexpr int kPad = 2;  // LDS row padding (doubles) of the staged A / B tiles
 
@@ -792,7 +796,7 @@ __device__ inline void pair_store(const float (&v)[R], __bf16 (&P)[NP][LEN], int
 template <class C, int NP>
 __device__ inline void segk_store(const SegLoadK<C> &L, int step, const float (&ra)[SegLoadK<C>::RA],
                                   const float (&rb)[SegLoadK<C>::RB], StageA<C, NP> &Ap, StageB<C, NP> &Bp) {
-  constexpr int RA = SegLoadK<C>::RA, RB = SegLoadK<C>::RB, LD = C::TK + 8;
+  constexpr int RA = SegLoadK<C>::RA, LD = C::TK + 8;
   const int k0 = step * C::TK;
   float va[RA];
   if (L.idA) {
@@ -992,7 +996,8 @@ static void plan_check(const GemmPlan &plan) {
       MDMRG_REQUIRE(ext_a < (int64_t(1) << 31) && ext_b < (int64_t(1) << 31), -6,
                     "grouped GEMM: operand block too large for 32-bit element offsets");
       // buffer-load byte offsets inside one tile's K step (128 x 128 tiles at
-      // most, 8-byte elements) stay below 2^30, under the buffer range
+      // most, K steps of at most kTKmax, 8-byte elements) stay below 2^30,
+      // under the buffer range
       const int64_t tile_a = (g.flags & SEG_TA) ? int64_t(kTKmax) * g.lda + 128 : int64_t(128) * g.lda + kTKmax;
       const int64_t tile_b = (g.flags & SEG_TB) ? int64_t(128) * g.ldb + kTKmax : int64_t(kTKmax) * g.ldb + 128;
       MDMRG_REQUIRE(8 * tile_a < (int64_t(1) << 30) && 8 * tile_b < (int64_t(1) << 30), -6,

@@ -128,6 +128,17 @@ DevPlan *dev_plan_upload(Device *, const GemmPlan &plan) {
   dp->outs = new GOut[std::max<size_t>(1, plan.outs.size())];
   std::copy(plan.segs.begin(), plan.segs.end(), dp->segs);
   std::copy(plan.outs.begin(), plan.outs.end(), dp->outs);
+  // the device kernels' 32-bit offset limits (plan_check of the HIP layer):
+  // buffer-load byte offsets inside one 128 x 128 tile's K step of at most
+  // 16, for 8-byte elements, below 2^30
+  for (const GOut &o : plan.outs)
+    for (int q = 0; q < o.seg_count; ++q) {
+      const GSeg &g = plan.segs[o.seg_begin + q];
+      const int64_t ta = (g.flags & SEG_TA) ? int64_t(16) * g.lda + 128 : int64_t(128) * g.lda + 16;
+      const int64_t tb = (g.flags & SEG_TB) ? int64_t(128) * g.ldb + 16 : int64_t(16) * g.ldb + 128;
+      MDMRG_REQUIRE(8 * ta < (int64_t(1) << 30) && 8 * tb < (int64_t(1) << 30), -6,
+                    "grouped GEMM: leading dimension too large for 32-bit tile offsets");
+    }
   for (const GOut &o : plan.outs) {
     dp->n_tiles += int64_t((o.m + 63) / 64) * ((o.n + 63) / 64);
     dp->n_tiles128 += int64_t((o.m + 127) / 128) * ((o.n + 127) / 128);

@@ -1750,9 +1750,27 @@ static void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w, std
   V = V2;
 }
 
+// One product of a Davidson solve: H_eff v in form prec, plus, for a split
+// form while a defect correction is set (davidson_mixed), the symmetric
+// rank-2 term C v = d (x0.v) + x0 (d.v) - gamma x0 (x0.v).  Since
+// d = H x0 - H_split x0 is the FP64 defect of the split operator at the
+// normalised vector x0, the corrected operator reproduces H x0 exactly and
+// differs from H, near x0, only by the split rounding of the difference
+// (first order in |x - x0|).
+void Context::davidson_product(const double *v, double *w, int prec) {
+  heff_apply(v, w, prec);
+  if (corr && prec != 0) {
+    const int64_t N = psi.n_elem;
+    double ab[2];  // x0.v, d.v
+    dev_multidot(dev, corr, N, 2, v, N, ab);
+    const double c[2] = {ab[1] - corr_gamma * ab[0], ab[0]};
+    dev_lincomb(dev, corr, N, 2, c, 1.0, w, N);
+  }
+}
+
 int Context::davidson(double *x, double tol, int max_iter, int m_max, double *energy, double *resid,
                       int *n_mv, int prec, double stall_floor, const double *V0, int k0, double *Vout, int kout,
-                      int *k_written) {
+                      int *k_written, const double *hx_start) {
   MDMRG_REQUIRE(cur >= 0, -4, "davidson: no current bond");
   MDMRG_REQUIRE(m_max >= 3 && m_max <= 60, -1, "davidson: m_max must be in [3, 60]");
   const bool verbose = std::getenv("MDMRG_VERBOSE") != nullptr;
@@ -1778,8 +1796,13 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
   }
   dev_d2d(dev, V, x, sizeof(double) * N);
   dev_scale(dev, 1.0 / std::sqrt(nrm), V, N);
-  heff_apply(V, AV, prec);
-  int nmv = 1, nv = 1;
+  // hx_start: the product of the (normalised) start vector, already formed
+  // by the caller in this form and counted there
+  if (hx_start)
+    dev_d2d(dev, AV, hx_start, sizeof(double) * N);
+  else
+    davidson_product(V, AV, prec);
+  int nmv = hx_start ? 0 : 1, nv = 1;
   double best_r = 1e300;
   int best_at = 0;
   floor_checks = 0;
@@ -1804,7 +1827,7 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
     dev_multidot(dev, t, 0, 1, t, N, &tn);
     if (!(tn > 1e-20)) continue;
     dev_scale(dev, 1.0 / std::sqrt(tn), t, N);
-    heff_apply(t, AV + int64_t(nv) * N, prec);
+    davidson_product(t, AV + int64_t(nv) * N, prec);
     ++nmv;
     std::vector<double> col(nv + 1);
     dev_multidot(dev, V, N, nv + 1, AV + int64_t(nv) * N, N, col.data());
@@ -1934,7 +1957,7 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
       }
     }
     dev_scale(dev, 1.0 / std::sqrt(tn), t, N);
-    heff_apply(t, AV + int64_t(nv) * N, prec);
+    davidson_product(t, AV + int64_t(nv) * N, prec);
     ++nmv;
     std::vector<double> col(nv + 1);
     dev_multidot(dev, V, N, nv + 1, AV + int64_t(nv) * N, N, col.data());
@@ -2032,9 +2055,66 @@ int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_sp
     if (verbose)
       fprintf(stderr, "[mdmrg] mixed: FP32 stage %d products, |r| = %.3e (floor %.3e)\n", n32, r, floor32);
   }
-  const int st = davidson(x, tol, max_iter, m_max, &e, &r, &n64, 0, -1.0, Vk, kw);
-  ns += probe + (floor32 > 0.0 ? 1 : 0);
-  n64 += probe + checks;
+  // Defect correction (MDMRG_OPT_MIXED_CORRECT): one FP64 product of the
+  // current vector x0 gives its FP64 residual (done if within tol, with the
+  // FP64 Rayleigh quotient as the energy) and, with one split product, the
+  // defect d = H x0 - H_split x0.  A split stage on H_split + C (C the
+  // symmetric rank-2 term of davidson_product, so that (H_split + C) x0 =
+  // H x0) then carries the residual below the split form's own noise
+  // floor: what remains of the rounding acts on x - x0 only.  Two such
+  // rounds at most; once the FP64 residual is within 4 tol the plain FP64
+  // stage finishes from the vector and its FP64 product.
+  int n64c = 0, nc = 0, st64 = 0;
+  bool done = false;
+  if (mixed_correct) {
+    const int64_t N = psi.n_elem;
+    DevVecs cw(dev);
+    double *xd = cw.get(2 * N), *hs = cw.get(N);
+    struct Reset {
+      const double *&p;
+      ~Reset() { p = nullptr; }
+    } reset{corr};
+    for (int round = 0;; ++round) {
+      dev_d2d(dev, xd, x, sizeof(double) * N);  // x is normalised by davidson()
+      heff_apply(xd, xd + N, 0);
+      ++n64c;
+      double th = 0.0, r2 = 0.0;
+      dev_multidot(dev, xd, 0, 1, xd + N, N, &th);
+      dev_d2d(dev, hs, xd + N, sizeof(double) * N);
+      dev_axpy(dev, -th, xd, hs, N);
+      dev_multidot(dev, hs, 0, 1, hs, N, &r2);
+      MDMRG_REQUIRE(std::isfinite(r2) && std::isfinite(th), -3, "davidson_mixed: NaN in residual");
+      const double r64 = std::sqrt(r2);
+      if (verbose) fprintf(stderr, "[mdmrg] mixed: FP64 residual %.3e at round %d\n", r64, round);
+      if (r64 <= tol) {
+        e = th;
+        r = r64;
+        done = true;
+        break;
+      }
+      if (round == 2 || r64 <= 4.0 * tol) {
+        // close to tol (or two rounds spent): the FP64 stage, from this
+        // vector and its FP64 product
+        st64 = davidson(x, tol, max_iter, m_max, &e, &r, &n64, 0, -1.0, nullptr, 0, nullptr, 0, nullptr, xd + N);
+        done = true;
+        break;
+      }
+      heff_apply(xd, hs, prec_split);
+      ++nc;
+      dev_axpy(dev, -1.0, hs, xd + N, N);  // d = H x0 - H_split x0
+      dev_multidot(dev, xd, 0, 1, xd + N, N, &corr_gamma);
+      corr = xd;
+      int nci = 0;
+      davidson(x, 0.5 * tol, max_iter, m_max, &e, &r, &nci, prec_split, 0.5 * tol);
+      corr = nullptr;
+      nc += nci;
+      checks += floor_checks;
+      if (verbose) fprintf(stderr, "[mdmrg] mixed: corrected stage %d products, |r| = %.3e\n", nci, r);
+    }
+  }
+  const int st = done ? st64 : davidson(x, tol, max_iter, m_max, &e, &r, &n64, 0, -1.0, Vk, kw);
+  ns += probe + (floor32 > 0.0 ? 1 : 0) + nc;
+  n64 += probe + checks + n64c;
   if (energy) *energy = e;
   if (resid) *resid = r;
   if (n_mv64) *n_mv64 = n64;

@@ -192,11 +192,19 @@ struct Context {
   // Ritz vectors kept at a thick restart of the Davidson subspace
   // (MDMRG_OPT_DAVIDSON_KEEP)
   int davidson_keep = 2;
-  bool davidson_olsen = false;
+  bool davidson_olsen = false;  // Olsen correction vector (MDMRG_OPT_DAVIDSON_OLSEN)
   int floor_checks = 0;  // FP64 floor-check products of the last split Davidson
-  int mixed_handover = 1;  // Ritz vectors handed from one mixed stage to the next  // Olsen correction (MDMRG_OPT_DAVIDSON_OLSEN)
+  int mixed_handover = 1;  // Ritz vectors handed from one mixed stage to the next
   // 3xBF16 mixed solves pass through an FP32 stage (MDMRG_OPT_MIXED_LADDER)
   bool mixed_ladder = false;
+  // a mixed solve whose split stage stops above the FP64 tolerance continues
+  // with split stages on the defect-corrected operator (MDMRG_OPT_MIXED_CORRECT)
+  bool mixed_correct = true;
+  // defect correction of the split products of davidson(): w += C v with
+  // C = d x0^T + x0 d^T - gamma x0 x0^T, gamma = x0.d; corr = [x0 | d]
+  const double *corr = nullptr;
+  double corr_gamma = 0.0;
+  void davidson_product(const double *v, double *w, int prec);
   int keep_envs = 1;  // blocks kept per bond (MDMRG_OPT_KEEP_ENVS): 1 all, 0/2/3 see prepare()
   bool compress = true;    // interpolative compression of the N^L x C^R products
   // graph replay of the H_eff product (MDMRG_OPT_GRAPH): captured per bond and
@@ -230,7 +238,8 @@ struct Context {
   // their number in *k_written
   int davidson(double *x, double tol, int max_iter, int m_max, double *energy, double *resid, int *n_mv,
                int prec = 0, double stall_floor = -1.0, const double *V0 = nullptr, int k0 = 0,
-               double *Vout = nullptr, int kout = 0, int *k_written = nullptr);
+               double *Vout = nullptr, int kout = 0, int *k_written = nullptr,
+               const double *hx_start = nullptr);
   // split-precision Davidson to tol_split, then FP64 Davidson to tol
   int davidson_mixed(double *x, double tol, int prec_split, double tol_split, int max_iter, int m_max,
                      double *energy, double *resid, int *n_mv64, int *n_mv_split);

@@ -19,7 +19,7 @@ SPINLESS, HUBBARD = 0, 1
 REAL, MOMENTUM = 0, 1
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 OPT_KEEP_ENVS, OPT_SCRATCH_LIMIT, OPT_GRAPH, OPT_COMPRESS, OPT_GEMM_VARIANT, OPT_MEMORY_BUDGET = 1, 2, 3, 4, 5, 6
-OPT_DAVIDSON_KEEP, OPT_DAVIDSON_OLSEN, OPT_MIXED_LADDER, OPT_MIXED_HANDOVER = 7, 8, 9, 10
+OPT_DAVIDSON_KEEP, OPT_DAVIDSON_OLSEN, OPT_MIXED_LADDER, OPT_MIXED_HANDOVER, OPT_MIXED_CORRECT = 7, 8, 9, 10, 11
 
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)
 _c_i32_p = ctypes.POINTER(ctypes.c_int32)

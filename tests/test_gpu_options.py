@@ -6,9 +6,11 @@
   block rebuild it with the same plans; every tile variant accumulates in
   the same order).
 * Davidson and mixed-precision options (restart size, Olsen correction, the
-  FP32 stage between 3xBF16 and FP64, the Ritz-vector hand-over): every
-  combination reaches the FP64 residual tolerance 1e-7 and the energy of a
-  tight FP64 solve (1e-10) to 1e-9 relative, the split-precision target
+  FP32 stage between 3xBF16 and FP64, the Ritz-vector hand-over, the
+  defect-corrected split stages): every combination reaches the FP64
+  residual tolerance 1e-7 (checked with an FP64 product of the returned
+  vector) and the energy of a tight FP64 solve (1e-10) to 1e-9 relative,
+  the split-precision target
   (Sec. II.A: the eigenpair is the FP64 one whatever precision carried the
   iterations).
 
@@ -84,18 +86,25 @@ def test_davidson_and_mixed_options_reach_the_fp64_energy():
         print(f'[options] FP64 option {opt}={val}: {n} products, E={e:.12f}', flush=True)
         assert ok and r <= tol and abs(e - e_ref) <= 1e-9 * abs(e_ref)
         ctx.set_option(opt, 2 if opt == mdmrg.OPT_DAVIDSON_KEEP else 0)
-    for ladder, hand, olsen in ((0, 1, 0), (1, 1, 0), (0, 4, 0), (1, 3, 1)):
+    for ladder, hand, olsen, corr in ((0, 1, 0, 1), (0, 1, 0, 0), (1, 1, 0, 1), (0, 4, 0, 0), (1, 3, 1, 1)):
         ctx.set_option(mdmrg.OPT_MIXED_LADDER, ladder)
         ctx.set_option(mdmrg.OPT_MIXED_HANDOVER, hand)
         ctx.set_option(mdmrg.OPT_DAVIDSON_OLSEN, olsen)
-        for prec in (mdmrg.FP32, mdmrg.BF16X3):
+        ctx.set_option(mdmrg.OPT_MIXED_CORRECT, corr)
+        for prec in (mdmrg.FP32, mdmrg.BF16X3, mdmrg.BF16X6):
             x = x0.clone()
             e, r, n64, ns, ok = ctx.davidson_mixed(x, tol=tol, tol_split=tol, prec_split=prec, max_iter=800)
-            print(f'[options] mixed prec={prec} ladder={ladder} handover={hand} olsen={olsen}: '
+            print(f'[options] mixed prec={prec} ladder={ladder} handover={hand} olsen={olsen} correct={corr}: '
                   f'{ns} split + {n64} FP64 products, E={e:.12f}', flush=True)
-            assert ok and r <= tol, (prec, ladder, hand, olsen, r)
-            assert abs(e - e_ref) <= 1e-9 * abs(e_ref), (prec, ladder, hand, olsen, e, e_ref)
+            assert ok and r <= tol, (prec, ladder, hand, olsen, corr, r)
+            assert abs(e - e_ref) <= 1e-9 * abs(e_ref), (prec, ladder, hand, olsen, corr, e, e_ref)
             assert n64 >= 1
+            # the returned vector meets tol on the FP64 operator
+            hx = torch.empty_like(x)
+            ctx.heff_apply(x, hx)
+            th = float(torch.dot(x, hx))
+            assert float(torch.linalg.vector_norm(hx - th * x)) <= 1.01 * tol
+    ctx.set_option(mdmrg.OPT_MIXED_CORRECT, 1)
     for opt in (mdmrg.OPT_MIXED_HANDOVER, mdmrg.OPT_DAVIDSON_KEEP):
         with pytest.raises(mdmrg.MdmrgError):
             ctx.set_option(opt, 0)
