@@ -206,11 +206,11 @@ enum {
                                   starts from this many lowest Ritz vectors of the
                                   previous stage (one product each in its own precision);
                                   1 (default): from the eigenvector estimate alone */
-  MDMRG_OPT_MIXED_CORRECT = 11  /* 1 (default): when the split stages of a mixed solve
-                                  stop with an FP64 residual above 4 tol, up to two
+  MDMRG_OPT_MIXED_CORRECT = 11  /* 1: when the split stages of a mixed solve stop with
+                                  an FP64 residual above 4 tol, up to four
                                   defect-corrected split stages follow (see
                                   mdmrg_davidson_mixed) before the FP64 Davidson
-                                  stage; 0: FP64 Davidson directly */
+                                  stage; 0 (default): FP64 Davidson directly */
 };
 /* Set a context option (EINVAL for unknown options or bad values).
  * With the environment variable MDMRG_VERBOSE set, the library prints
@@ -298,13 +298,14 @@ int mdmrg_davidson(mdmrg_ctx ctx, double *x, double tol, int max_iter, int m_max
  * only) an FP32 stage the same way.  f is the noise floor of the split
  * operator, measured with one split and one FP64 product of the normalised
  * start vector v: f = |(H_split - H) v| / |H v| * |v.H v|.
- * Then (MDMRG_OPT_MIXED_CORRECT, default) up to two defect-corrected
+ * Then (MDMRG_OPT_MIXED_CORRECT; off by default) up to four defect-corrected
  * rounds: one FP64 product of the current vector x0 gives its FP64
  * residual -- if <= tol the solve ends there, with the FP64 Rayleigh
  * quotient x0.H x0 as the energy -- and, with one split product, the defect
  * d = H x0 - H_split x0; a split Davidson on H_split + d x0^T + x0 d^T -
- * (x0.d) x0 x0^T (which reproduces H x0 exactly) then runs to tol / 2.
- * Once the FP64 residual is within 4 tol (or after two rounds), an FP64
+ * (x0.d) x0 x0^T (which reproduces H x0 exactly) then runs to tol / 2 or
+ * until 8 products bring no 10% gain.
+ * Once the FP64 residual is within 4 tol (or after four rounds), an FP64
  * Davidson from that vector, reusing its FP64 product, until the FP64
  * residual <= tol (without the option: directly after the split stages).
  * *n_mv64 and *n_mv_split count the products of each kind (the floor probe

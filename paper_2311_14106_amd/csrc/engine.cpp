@@ -1870,11 +1870,14 @@ int Context::davidson(double *x, double tol, int max_iter, int m_max, double *en
       // twice the measured floor, over 24 within 20 times it, and over 64
       // elsewhere (far above the floor a plateau is slow convergence, e.g.
       // after a restart, not the floor)
-      const int window = rn <= 2.0 * stall_floor ? 4 : rn <= 20.0 * stall_floor ? 24 : 64;
+      // (a defect-corrected stage stops after 8 products without a 10% gain,
+      // without floor checks: a new defect round re-centres the correction)
+      const int window = corr ? 8 : rn <= 2.0 * stall_floor ? 4 : rn <= 20.0 * stall_floor ? 24 : 64;
       if (rn < 0.9 * best_r) {
         best_r = rn;
         best_at = nmv;
       } else if (nmv - best_at >= window) {
+        if (corr) break;
         // the floor, or slow convergence (a plateau after a restart)?  One
         // FP64 product of the Ritz vector decides: an FP64 residual close to
         // the split one means the split operator's rounding is not what
@@ -2061,9 +2064,11 @@ int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_sp
   // defect d = H x0 - H_split x0.  A split stage on H_split + C (C the
   // symmetric rank-2 term of davidson_product, so that (H_split + C) x0 =
   // H x0) then carries the residual below the split form's own noise
-  // floor: what remains of the rounding acts on x - x0 only.  Two such
-  // rounds at most; once the FP64 residual is within 4 tol the plain FP64
-  // stage finishes from the vector and its FP64 product.
+  // floor: what remains of the rounding acts on x - x0 only.  A corrected
+  // stage that stalls (8 products without a 10% gain) ends its round; the
+  // next round re-centres the correction at the new vector.  Four rounds at
+  // most; once the FP64 residual is within 4 tol the plain FP64 stage
+  // finishes from the vector and its FP64 product.
   int n64c = 0, nc = 0, st64 = 0;
   bool done = false;
   if (mixed_correct) {
@@ -2092,7 +2097,7 @@ int Context::davidson_mixed(double *x, double tol, int prec_split, double tol_sp
         done = true;
         break;
       }
-      if (round == 2 || r64 <= 4.0 * tol) {
+      if (round == 4 || r64 <= 4.0 * tol) {
         // close to tol (or two rounds spent): the FP64 stage, from this
         // vector and its FP64 product
         st64 = davidson(x, tol, max_iter, m_max, &e, &r, &n64, 0, -1.0, nullptr, 0, nullptr, 0, nullptr, xd + N);

@@ -199,7 +199,7 @@ struct Context {
   bool mixed_ladder = false;
   // a mixed solve whose split stage stops above the FP64 tolerance continues
   // with split stages on the defect-corrected operator (MDMRG_OPT_MIXED_CORRECT)
-  bool mixed_correct = true;
+  bool mixed_correct = false;
   // defect correction of the split products of davidson(): w += C v with
   // C = d x0^T + x0 d^T - gamma x0 x0^T, gamma = x0.d; corr = [x0 | d]
   const double *corr = nullptr;

@@ -104,7 +104,7 @@ def test_davidson_and_mixed_options_reach_the_fp64_energy():
             ctx.heff_apply(x, hx)
             th = float(torch.dot(x, hx))
             assert float(torch.linalg.vector_norm(hx - th * x)) <= 1.01 * tol
-    ctx.set_option(mdmrg.OPT_MIXED_CORRECT, 1)
+    ctx.set_option(mdmrg.OPT_MIXED_CORRECT, 0)
     for opt in (mdmrg.OPT_MIXED_HANDOVER, mdmrg.OPT_DAVIDSON_KEEP):
         with pytest.raises(mdmrg.MdmrgError):
             ctx.set_option(opt, 0)
