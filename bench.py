@@ -160,23 +160,27 @@ def cpu_baseline(mdmrg, budget_s):
                       f'{os.environ.get("OMP_NUM_THREADS", "default")}'}
 
 
-# (name, precision form of the split products, graph statistics key, ladder):
-# ladder 1 runs an FP32 stage between the 3xBF16 stage and the FP64 refinement
-SPLIT_FORMS = (('fp32', 'FP32', 'graph32', 0), ('bf16x3', 'BF16X3', 'graphbf3', 0), ('bf16x6', 'BF16X6', 'graphbf6', 0),
-               ('bf16x3_fp32', 'BF16X3', None, 1))
+# (name, precision form of the split products, graph statistics key, ladder,
+# defect correction): ladder 1 runs an FP32 stage between the 3xBF16 stage and
+# the FP64 refinement; correction 1 runs defect-corrected split stages before
+# it (MDMRG_OPT_MIXED_CORRECT)
+SPLIT_FORMS = (('fp32', 'FP32', 'graph32', 0, 0), ('bf16x3', 'BF16X3', 'graphbf3', 0, 0),
+               ('bf16x6', 'BF16X6', 'graphbf6', 0, 0), ('bf16x3_fp32', 'BF16X3', None, 1, 0),
+               ('bf16x3_corr', 'BF16X3', None, 0, 1))
 
 
 def split_compare(ctx, x0, torch, args):
     """Davidson s/step at fixed dE: the plain FP64 form against the mixed
-    precision forms (FP32, 3xBF16 or 6xBF16 products, or 3xBF16 then FP32
-    products, then FP64 refinement), launched eagerly and replayed from captured graphs (the precision +
+    precision forms (FP32, 3xBF16 or 6xBF16 products, 3xBF16 then FP32
+    products, or 3xBF16 then defect-corrected 3xBF16 products, then FP64
+    refinement), launched eagerly and replayed from captured graphs (the precision +
     batched form), all from the same start vector at the current bond.
     E_ref = FP64 solve to |r| <= 1e-10; dE = 1e-9 |E_ref|.  Every form is
     warmed up at the bond before any timed solve (tile-variant trials of each
     plan, FP32 operator copies, graph capture), so all timed solves start from
     the same tuned state."""
     from paper_2311_14106_amd import mdmrg
-    forms = [(name, getattr(mdmrg, const), tag, lad) for name, const, tag, lad in SPLIT_FORMS]
+    forms = [(name, getattr(mdmrg, const), tag, (lad, cor)) for name, const, tag, lad, cor in SPLIT_FORMS]
 
     def solve(fn):
         x = x0.clone()
@@ -196,14 +200,16 @@ def split_compare(ctx, x0, torch, args):
     def plain(x):
         return ctx.davidson(x, tol=args.split_tol, max_iter=600)
 
-    def mixed(prec, ladder=0):
+    def mixed(prec, opts=(0, 0)):
         def run(x):
-            ctx.set_option(mdmrg.OPT_MIXED_LADDER, ladder)
+            ctx.set_option(mdmrg.OPT_MIXED_LADDER, opts[0])
+            ctx.set_option(mdmrg.OPT_MIXED_CORRECT, opts[1])
             try:
                 return ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol, prec_split=prec,
                                           max_iter=600)
             finally:
                 ctx.set_option(mdmrg.OPT_MIXED_LADDER, 0)
+                ctx.set_option(mdmrg.OPT_MIXED_CORRECT, 0)
         return run
 
     def entry(sol, t, name):
@@ -237,7 +243,7 @@ def split_compare(ctx, x0, torch, args):
         b = ctx.stats()
         ms = (b['split_gemm_ms'] - a['split_gemm_ms']) / max(1.0, b['n_matvec_split'] - a['n_matvec_split'])
         res['mixed_' + name] = entry(sol, t, name)
-        if not lad:
+        if not any(lad):
             res['gemm_ms_per_product'][name] = ms
             tfl[name] = fl / (ms * 1e9) if ms > 0 else None
             if name == 'fp32':
