@@ -819,10 +819,28 @@ __device__ inline void segk_store(const SegLoadK<C> &L, int step, const float (&
     pair_store<NP>(rb, Bp, L.jb, L.kb, LD);
 }
 
-// One 16-deep K step of BF16 products: NP = 2: hi*lo + lo*hi + hi*hi;
-// NP = 3: hi*lo + lo*hi + mid*mid + hi*mid + mid*hi + hi*hi (smallest
-// terms first, so that the FP32 accumulator rounds them before the large
-// ones).
+// One 16-deep K step of BF16 products.  Pairs of products go into one
+// v_mfma_f32_16x16x32_bf16 (the full-rate gfx950 instruction): a lane's 8
+// operand values are the 4 of part X followed by the 4 of part Y at the same
+// K positions, for A and B alike, so the 32-deep product is X_A.X_B +
+// Y_A.Y_B over the step's 16 K positions.  NP = 2: (hi*lo + lo*hi), then
+// (hi*hi + 0); NP = 3: (hi*lo + mid*mid), (lo*hi + hi*mid), (mid*hi + hi*hi)
+// -- smallest terms first, so that the FP32 accumulator rounds them before
+// the large ones.  Every product of a chain on one accumulator is the same
+// instruction: a 16-deep v_mfma_f32_16x16x16_bf16 issued straight after a
+// 32-deep one on the same accumulator (the 16x16-per-wave split, where no
+// other MFMA sits between them) gave results without the cross terms in the
+// kernel test against the product model, as if it had read the
+// accumulator before the 32-deep product was written.  The 16-deep
+// instruction runs at half the rate of the 32-deep one on gfx950, so the
+// zero half costs nothing.
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+__device__ inline v4f mfma32(v4s ax, v4s ay, v4s bx, v4s by, v4f c) {
+  const v8s a = __builtin_shufflevector(ax, ay, 0, 1, 2, 3, 4, 5, 6, 7);
+  const v8s b = __builtin_shufflevector(bx, by, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
 template <class C, int NP>
 __device__ inline void tile_mfma_bfs(const StageA<C, NP> &Ap, const StageB<C, NP> &Bp, int wm, int wn, int lr,
                                      int lk, int qm, int qn, v4f (&acc)[C::MI][C::NI]) {
@@ -844,19 +862,20 @@ __device__ inline void tile_mfma_bfs(const StageA<C, NP> &Ap, const StageB<C, NP
       b[q][ni] = *reinterpret_cast<const v4s *>(Bp[q] + (wn + 16 * ni + lr) * (C::TK + 8) + 4 * lk);
   }
   constexpr int H = 0, M = 1, Lo = NP - 1;  // part indices (M unused for NP = 2)
+  const v4s z = {0, 0, 0, 0};
 #pragma unroll
   for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
     for (int ni = 0; ni < NI; ++ni) {
       v4f c = acc[mi][ni];
-      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[Lo][ni], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[Lo][mi], b[H][ni], c, 0, 0, 0);
-      if constexpr (NP == 3) {
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[M][mi], b[M][ni], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[M][ni], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[M][mi], b[H][ni], c, 0, 0, 0);
+      if constexpr (NP == 2) {
+        c = mfma32(a[H][mi], a[Lo][mi], b[Lo][ni], b[H][ni], c);
+        acc[mi][ni] = mfma32(a[H][mi], z, b[H][ni], z, c);
+      } else {
+        c = mfma32(a[H][mi], a[M][mi], b[Lo][ni], b[M][ni], c);
+        c = mfma32(a[Lo][mi], a[H][mi], b[H][ni], b[M][ni], c);
+        acc[mi][ni] = mfma32(a[M][mi], a[H][mi], b[H][ni], b[H][ni], c);
       }
-      acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[H][mi], b[H][ni], c, 0, 0, 0);
     }
 }
 
@@ -960,7 +979,7 @@ __global__ __launch_bounds__(Cfg64q<T>::NT) void k_gemm_w4(const GTile *__restri
 // 128x128 tiles: 118 (FP64), 92 (FP32) and 115 (3xBF16) registers per lane,
 // 33 KB (FP64, FP32) and 48 KB (3xBF16) of LDS stages per workgroup.
 template <class T>
-__global__ __launch_bounds__(Cfg128<T>::NT) void k_gemm_t128(const GTile *__restrict__ tiles,
+__global__ __launch_bounds__(Cfg128<T>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_t128(const GTile *__restrict__ tiles,
                                                           const GOut *__restrict__ outs,
                                                           const GSeg *__restrict__ segs, Bases bases) {
   gemm_any<T, Cfg128<T>>(tiles, outs, segs, bases);
