@@ -205,7 +205,8 @@ def split_compare(ctx, x0, torch, args):
             ctx.set_option(mdmrg.OPT_MIXED_LADDER, opts[0])
             ctx.set_option(mdmrg.OPT_MIXED_CORRECT, opts[1])
             try:
-                return ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol, prec_split=prec,
+                return ctx.davidson_mixed(x, tol=args.split_tol, tol_split=args.split_tol * args.split_inner,
+                                          prec_split=prec,
                                           max_iter=600)
             finally:
                 ctx.set_option(mdmrg.OPT_MIXED_LADDER, 0)
@@ -228,6 +229,7 @@ def split_compare(ctx, x0, torch, args):
         1.0, s1['n_matvec'] - s0['n_matvec'])
     fl = ctx.heff_cost()['flop']
     res = {'dE_target': de, 'E_ref': e_ref, 'residual_tol': args.split_tol,
+           'residual_tol_split': args.split_tol * args.split_inner,
            'fp64': {'davidson_s': t64, 'products': n64, 'dE': abs(e64 - e_ref), 'ok': abs(e64 - e_ref) <= de},
            'gemm_ms_per_product': {'fp64': ms64}}
     # GEMM throughput of one product (algorithmic FLOP, 2mnk) against the
@@ -383,6 +385,8 @@ def main():
                     help='skip the graph-replayed (precision + batched) solves of the fixed-dE comparison')
     ap.add_argument('--drift-steps', type=int, default=3,
                     help='steps of the per-step energy-error segment of the split forms (0: skip)')
+    ap.add_argument('--split-inner', type=float, default=1.0,
+                    help='residual target of the split stages of the mixed solves, as a fraction of --split-tol')
     ap.add_argument('--split-tol', type=float, default=1e-5,
                     help='FP64 residual tolerance of the fixed-dE Davidson comparison')
     args = ap.parse_args()
