@@ -66,8 +66,8 @@ static hipEvent_t ev_get(Device *d) {
 }
 
 // Process-wide totals of the grouped kernel per precision form (0 FP64,
-// 1 FP32, 2 3xBF16) and tile variant, summed over every device context of the
-// process, including destroyed ones.
+// 1 FP32, 2 3xBF16, 3 6xBF16) and tile variant, summed over every device
+// context of the process, including destroyed ones.
 static std::mutex g_timing_mu;
 static double g_ms[kPrecs][kGemmVariants], g_launches[kPrecs][kGemmVariants], g_flop[kPrecs][kGemmVariants];
 
@@ -331,11 +331,11 @@ struct TileCfg {
 // faster on split-K H_eff products) and 16 in the 16-wave split, which keeps
 // the unsplit long-K case; FP32 stages 16 everywhere (32, the same LDS bytes
 // per stage as FP64 at 16, measured slower).
-// The 3xBF16 form stages 16 columns per step: one v_mfma_f32_16x16x16_bf16
-// step (a 32-column step on v_mfma_f32_16x16x32_bf16 holds twice the LDS and
-// measured 25% slower).
-struct Bf16x3 {};  // element-type tag: FP32 data, products as 3 BF16 MFMAs
-struct Bf16x6 {};  // element-type tag: FP32 data, three BF16 parts, 6 BF16 MFMAs
+// The BF16 forms stage 16 columns per step (a 32-column step holds twice
+// the LDS and measured 25% slower); their products go in pairs into
+// v_mfma_f32_16x16x32_bf16 (tile_mfma_bfs).
+struct Bf16x3 {};  // element-type tag: FP32 data, two BF16 parts, 3 products
+struct Bf16x6 {};  // element-type tag: FP32 data, three BF16 parts, 6 products
 template <class T>
 struct KStep {  // FP32
   static constexpr int small = 16, wide = 16;
@@ -598,17 +598,18 @@ __device__ inline void gemm_tile(const GTile *__restrict__ tiles, const GOut *__
       }
 }
 
-// ---------------------------------------------- 3xBF16 split products
-// Every FP32 operand element x is split when it is staged to LDS into
-// hi = RNE_bf16(x) and lo = RNE_bf16(x - hi) (x - hi is exact in FP32), and
-// a product is formed as hi*lo + lo*hi + hi*hi with FP32 accumulation on
-// v_mfma_f32_16x16x16_bf16 (lo*lo is dropped): about 16 significant bits
-// per operand instead of FP32's 24, at BF16 MFMA rate.  The staged tiles are
+// ---------------------------------------------- BF16 split products
+// Every FP32 operand element x is split when it is staged to LDS.  3xBF16:
+// hi = RNE_bf16(x), lo = RNE_bf16(x - hi) (x - hi is exact in FP32); a
+// product is hi*lo + lo*hi + hi*hi with FP32 accumulation (lo*lo dropped):
+// about 16 significant bits per operand instead of FP32's 24, at BF16 MFMA
+// rate.  6xBF16 adds a middle part (hi, mid, lo) and the terms mid*mid,
+// hi*mid, mid*hi: about 24 bits per operand.  The staged tiles are
 // K-contiguous ([row][k] for A, [column][k] for B, rows of TK + 8 BF16), so
-// a lane's 4 operand values of one MFMA are one 8-byte LDS read; the
-// instruction takes from lane l the values of row / column l % 16 at K
-// positions fixed by l / 16, the same for both operands, so the staged K
-// order is the product's K order.
+// a lane's 4 values of one part are one 8-byte LDS read; the MFMA takes
+// from lane l the values of row / column l % 16 at K positions fixed by
+// l / 16, the same for both operands, so any staged K order is a valid
+// product order.
 typedef short v4s __attribute__((ext_vector_type(4)));  // 4 BF16 bit patterns
 
 
@@ -976,8 +977,10 @@ __global__ __launch_bounds__(Cfg64q<T>::NT) void k_gemm_w4(const GTile *__restri
   gemm_any<T, Cfg64q<T>>(tiles, outs, segs, bases);
 }
 
-// 128x128 tiles: 118 (FP64), 92 (FP32) and 115 (3xBF16) registers per lane,
-// 33 KB (FP64, FP32) and 48 KB (3xBF16) of LDS stages per workgroup.
+// 128x128 tiles: 116 (FP64), 90 (FP32), 114 (3xBF16) and 128 (6xBF16)
+// registers per lane, 33 KB (FP64, FP32), 48 KB (3xBF16) and 72 KB (6xBF16)
+// of LDS stages per workgroup; held at 4 waves per SIMD (two workgroups of
+// 8 waves per CU).
 template <class T>
 __global__ __launch_bounds__(Cfg128<T>::NT) __attribute__((amdgpu_waves_per_eu(4))) void k_gemm_t128(const GTile *__restrict__ tiles,
                                                           const GOut *__restrict__ outs,
