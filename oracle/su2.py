@@ -27,11 +27,19 @@ On top of them, for explicit Fock-space blocks of spin-1/2 fermions:
   [A^k1 x B^k2]^k from those of A and B through one 6j symbol (the
   recoupling a spin-adapted renormalisation applies to composite operators).
 
+* ``ninej``, ``reduced_matrix``, ``singlet_product_factor`` and
+  ``two_block_singlet_hubbard``: the spin-adapted superblock Hamiltonian of
+  a Hubbard model on two blocks (the structure a spin-adapted DMRG step
+  diagonalises), built from the blocks' multiplets, reduced creation and
+  annihilation operators and the two-block singlet recoupling.
+
 Tests check these against orthogonality sums, closed forms, brute-force
-diagonalisation of S^2 and the matrix elements of the plain Fock-space
-operators (``tests/test_oracle_su2.py``).
+diagonalisation of S^2, the matrix elements of the plain Fock-space
+operators and the exact ground energies of the plain Fock-space
+diagonalisation (``tests/test_oracle_su2.py``).
 """
 from fractions import Fraction
+from functools import lru_cache
 from math import factorial, sqrt
 
 import numpy as np
@@ -273,3 +281,147 @@ def coupled_reduced(redA, redB, tk1, tk2, tk, a, b, mults):
             continue
         tot += ph * sqrt(tk + 1) * float(six) * redA(a, c) * redB(c, b)
     return tot
+
+
+def ninej(ta, tb, tc, td, te, tf, tg, th, ti):
+    """Wigner 9j symbol {a b c; d e f; g h i} from the sum over products of
+    three 6j symbols (Edmonds 6.4.3):
+        sum_x (-1)^(2x) (2x+1) {a b c; f i x} {d e f; b x h} {g h i; x a d};
+    exact 6j factors, the sum in FP64."""
+    lo = max(abs(ta - ti), abs(th - td), abs(tb - tf))
+    hi = min(ta + ti, th + td, tb + tf)
+    tot = 0.0
+    for tx in range(lo, hi + 1, 2):
+        s1 = sixj(ta, tb, tc, tf, ti, tx)
+        s2 = sixj(td, te, tf, tb, tx, th)
+        s3 = sixj(tg, th, ti, tx, ta, td)
+        if s1.sign == 0 or s2.sign == 0 or s3.sign == 0:
+            continue
+        tot += (-1) ** tx * (tx + 1) * float(s1) * float(s2) * float(s3)
+    return tot
+
+
+@lru_cache(maxsize=None)
+def cg_float(tj1, tm1, tj2, tm2, tJ, tM):
+    """float(cg(...)), memoised."""
+    return float(cg(tj1, tm1, tj2, tm2, tJ, tM))
+
+
+def reduced_matrix(bra, ket, comps, tk, dN=None):
+    """<a||T^k||b> for every multiplet a of `bra` and b of `ket` (lists of
+    ``multiplet_basis``), from one component each: the bra at its top weight
+    M' = S' and the first component q with a nonzero Clebsch-Gordan
+    coefficient (the Wigner-Eckart theorem, pinned on small blocks by
+    ``reduced_element``, makes the choice irrelevant).  comps[tq] are dense
+    Fock matrices of the block; dN, if given, is the change of particle
+    number the operator makes (other pairs are zero and skipped)."""
+    R = np.zeros((len(bra), len(ket)))
+    for ib, (Nb, tSb, Vb) in enumerate(ket):
+        for ia, (Na, tSa, Va) in enumerate(bra):
+            if not triangle(tSb, tk, tSa) or (dN is not None and Na - Nb != dN):
+                continue
+            for tq in range(-tk, tk + 1, 2):
+                tMb = tSa - tq
+                if abs(tMb) > tSb or (tSb - tMb) % 2:
+                    continue
+                c = cg_float(tSb, tMb, tk, tq, tSa, tSa)
+                if c == 0.0:
+                    continue
+                me = Va[:, 0] @ (comps[tq] @ Vb[:, (tSb - tMb) // 2])
+                R[ia, ib] = me * sqrt(tSa + 1) / c
+                break
+    return R
+
+
+def singlet_product_factor(tSp, tS, tk):
+    """Matrix element of [X^k (block 1) x Y^k (block 2)]^0 between the total
+    singlets |(S' S')0> and |(S S)0> of two blocks, per unit reduced elements
+    <S'||X||S> <S'||Y||S> (the convention of the module docstring), by the
+    explicit sum over magnetic quantum numbers of the Clebsch-Gordan
+    couplings: the two-block recoupling coefficient of a spin-adapted
+    superblock Hamiltonian."""
+    tot = 0.0
+    for tM in range(-tS, tS + 1, 2):
+        c0 = float(cg(tS, tM, tS, -tM, 0, 0))
+        for tq in range(-tk, tk + 1, 2):
+            tMp = tM + tq
+            if abs(tMp) > tSp:
+                continue
+            tot += (c0 * float(cg(tSp, tMp, tSp, -tMp, 0, 0)) * float(cg(tk, tq, tk, -tq, 0, 0)) *
+                    float(cg(tS, tM, tk, tq, tSp, tMp)) * float(cg(tS, -tM, tk, -tq, tSp, -tMp)) / (tSp + 1))
+    return tot
+
+
+def _block_hubbard(Tsp, U):
+    """Dense Fock matrix of a Hubbard block: hopping Tsp (sites x sites,
+    spin-diagonal) and on-site U n_up n_dn; spin-orbital p = 2 site + sigma."""
+    nb = Tsp.shape[0]
+    nso = 2 * nb
+    H = np.zeros((1 << nso, 1 << nso))
+    for i in range(nb):
+        for j in range(nb):
+            if Tsp[i, j] != 0.0:
+                for s in (0, 1):
+                    H += Tsp[i, j] * fock_op(nso, [(2 * i + s, 1), (2 * j + s, 0)])
+        H += U * fock_op(nso, [(2 * i, 1), (2 * i, 0), (2 * i + 1, 1), (2 * i + 1, 0)])
+    return H
+
+
+def two_block_singlet_hubbard(Tsp, U, n_left, n_elec):
+    """Spin-adapted superblock Hamiltonian of a Hubbard model (spatial
+    hopping Tsp, on-site U) on sites [0, n_left) + [n_left, n) in the basis of
+    total singlets |(a b) S=0> of a left multiplet a and a right multiplet b
+    (S_a = S_b, N_a + N_b = n_elec): the block Hamiltonians act within a
+    block (scalars); a hopping t_ij across the blocks is
+    sum_sigma c+_i,sigma c_j,sigma = -sqrt(2) [c+_i x c~_j]^0 (c~ the rank-1/2
+    annihilator, components (c_dn, -c_up)), whose singlet matrix elements are
+    (-1)^N_a F(S_a', S_a) <a'||c+_i||a> <b'||c~_j||b> with F the two-block
+    recoupling factor (the fermion sign moves c~_j past the N_a electrons of
+    the left block in the ket), plus its transpose.  Returns (H, basis)."""
+    n = Tsp.shape[0]
+    nL, nR = n_left, n - n_left
+    mL, mR = multiplet_basis(nL), multiplet_basis(nR)
+    basis = [(ia, ib) for ia, (Na, tSa, _) in enumerate(mL) for ib, (Nb, tSb, _) in enumerate(mR)
+             if tSa == tSb and Na + Nb == n_elec]
+    index = {p: k for k, p in enumerate(basis)}
+    HL, HR = _block_hubbard(Tsp[:nL, :nL], U), _block_hubbard(Tsp[nL:, nL:], U)
+    top = lambda m: np.array([v[:, 0] for _, _, v in m]).T  # top-weight vectors
+    TL, TR = top(mL), top(mR)
+    hL, hR = TL.T @ HL @ TL, TR.T @ HR @ TR  # scalar blocks: equal in every M
+    # <a'||H_L||a> between multiplets of equal (N, S), times delta_b'b; same for R
+    A = np.array([p[0] for p in basis])
+    B = np.array([p[1] for p in basis])
+    keyL = np.array([mL[a][0] * 1000 + mL[a][1] for a in A])
+    keyR = np.array([mR[b][0] * 1000 + mR[b][1] for b in B])
+    H = hL[np.ix_(A, A)] * ((B[:, None] == B[None, :]) & (keyL[:, None] == keyL[None, :]))
+    H += hR[np.ix_(B, B)] * ((A[:, None] == A[None, :]) & (keyR[:, None] == keyR[None, :]))
+    nsoL, nsoR = 2 * nL, 2 * nR
+    F = {}
+    Ys = {}
+    for i in range(nL):
+        if not np.any(Tsp[i, nL:]):
+            continue
+        Xc = reduced_matrix(mL, mL, {1: fock_op(nsoL, [(2 * i, 1)]), -1: fock_op(nsoL, [(2 * i + 1, 1)])}, 1,
+                            dN=1)
+        for j in range(nR):
+            t = Tsp[i, nL + j]
+            if t == 0.0:
+                continue
+            if j not in Ys:
+                Ys[j] = reduced_matrix(mR, mR, {1: fock_op(nsoR, [(2 * j + 1, 0)]),
+                                                -1: -fock_op(nsoR, [(2 * j, 0)])}, 1, dN=-1)
+            Yc = Ys[j]
+            C = np.zeros_like(H)
+            for kk, (ia, ib) in enumerate(basis):  # ket
+                Na, tS = mL[ia][0], mL[ia][1]
+                for ja in np.flatnonzero(Xc[:, ia]):
+                    tSp = mL[ja][1]
+                    for jb in np.flatnonzero(Yc[:, ib]):
+                        k = index.get((int(ja), int(jb)))
+                        if k is None:
+                            continue
+                        if (tSp, tS) not in F:
+                            F[(tSp, tS)] = singlet_product_factor(tSp, tS, 1)
+                        C[k, kk] += (-1) ** Na * F[(tSp, tS)] * Xc[ja, ia] * Yc[jb, ib]
+            H += t * (-sqrt(2.0)) * (C + C.T)
+    return H, basis
