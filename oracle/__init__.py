@@ -20,13 +20,18 @@ The oracle is deliberately slow and literal:
   Lanczos ``eigsh`` otherwise); the library's Davidson (Sec. II.A names
   Lanczos or Davidson) is compared with that eigenvalue, not with another
   Davidson.
-* ``split``      -- the split-precision product model (FP32 and 3xBF16
-  hi/lo products) evaluated in FP64, for the kernel tests of those forms.
+* ``split``      -- the split-precision product models (FP32, 3xBF16
+  hi/lo and 6xBF16 hi/mid/lo products) evaluated in FP64, for the kernel
+  tests of those forms.
 * ``su2``        -- Clebsch-Gordan coefficients and 6j symbols in exact
-  rational arithmetic (Racah formulas), SU(2) multiplet bases of small
-  spin-1/2 fermion blocks, Wigner-Eckart reduced elements and the 6j
-  product rule of coupled operators (the algebra of the spin-adapted form,
+  rational arithmetic (Racah formulas), 9j symbols, SU(2) multiplet bases
+  of small spin-1/2 fermion blocks, Wigner-Eckart reduced elements, the 6j
+  product rule of coupled operators and the spin-adapted two-block
+  superblock of a Hubbard model (the algebra of the spin-adapted form,
   Sec. IV).
+* ``rdm``        -- one- and two-particle reduced density matrices of an
+  explicit Fock-space state, the energy of Eq. (1) from them and the
+  charge-density-wave order parameter (Sec. II.B, III.C).
 
 Pins (closed forms, brute force on tiny inputs, basis invariance) live in
 ``tests/test_oracle_*.py``.
