@@ -32,6 +32,9 @@ The oracle is deliberately slow and literal:
 * ``rdm``        -- one- and two-particle reduced density matrices of an
   explicit Fock-space state, the energy of Eq. (1) from them and the
   charge-density-wave order parameter (Sec. II.B, III.C).
+* ``modeopt``    -- mode rotations of an explicit Fock-space state (the
+  exponential of the one-body generator), the half-Renyi entropy of a
+  bipartition and the two-mode micro-iteration that lowers it (Sec. II.B).
 
 Pins (closed forms, brute force on tiny inputs, basis invariance) live in
 ``tests/test_oracle_*.py``.
