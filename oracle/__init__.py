@@ -35,6 +35,10 @@ The oracle is deliberately slow and literal:
 * ``modeopt``    -- mode rotations of an explicit Fock-space state (the
   exponential of the one-body generator), the half-Renyi entropy of a
   bipartition and the two-mode micro-iteration that lowers it (Sec. II.B).
+* ``mutual``     -- one- and two-mode entropies, mutual information, total
+  correlation and correlation distance, natural modes, the Fiedler
+  ordering, the DEAS order and the HF reference taken after the last sweep
+  (Sec. II.B).
 
 Pins (closed forms, brute force on tiny inputs, basis invariance) live in
 ``tests/test_oracle_*.py``.
