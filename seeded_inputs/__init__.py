@@ -46,7 +46,6 @@ def bond_profile(n_sites, spinful, target, D, weight_power=1.0):
     Returns ``bonds``: list over bonds 0..n of [(qn, dim), ...].
     """
     target = tuple(target)
-    d = 4 if spinful else 2
     bonds = []
     for i in range(n_sites + 1):
         cand = {}
@@ -74,31 +73,7 @@ def bond_profile(n_sites, spinful, target, D, weight_power=1.0):
                     cand[Q] += 1
                     rem -= 1
         bonds.append({Q: m for Q, m in cand.items() if m > 0})
-    # consistency passes
-    changed = True
-    while changed:
-        changed = False
-        for i in range(n_sites):
-            L, R = bonds[i], bonds[i + 1]
-            for Qr in list(R):
-                avail = sum(L.get((Qr[0] - local_qn(s, spinful)[0], Qr[1] - local_qn(s, spinful)[1]), 0)
-                            for s in range(d))
-                if R[Qr] > avail:
-                    R[Qr] = avail
-                    changed = True
-                if R[Qr] == 0:
-                    del R[Qr]
-        for i in range(n_sites - 1, -1, -1):
-            L, R = bonds[i], bonds[i + 1]
-            for Ql in list(L):
-                avail = sum(R.get((Ql[0] + local_qn(s, spinful)[0], Ql[1] + local_qn(s, spinful)[1]), 0)
-                            for s in range(d))
-                if L[Ql] > avail:
-                    L[Ql] = avail
-                    changed = True
-                if L[Ql] == 0:
-                    del L[Ql]
-    return [sorted(b.items()) for b in bonds]
+    return _consistent(bonds, n_sites, spinful)
 
 
 def _consistent(bonds, n_sites, spinful):
