@@ -441,6 +441,75 @@ int mdmrg_gemm_grouped_split(mdmrg_ctx ctx, int prec, int n_bases, const float *
  * replayed from a captured graph (MDMRG_OPT_GRAPH). */
 int mdmrg_get_stats(mdmrg_ctx ctx, double *out);
 
+/* ------------------------------------------- mode analysis (host only) */
+/*
+ * The quantities computed at the end of the last sweep to set up the next
+ * mode-transformation macro-iteration (Sec. II.B): one- and two-mode
+ * entropies, mutual information, total correlation, correlation distance,
+ * the one-particle density matrix, occupations and natural modes, the
+ * Fiedler ordering, the DEAS order and the HF reference.  They run on the
+ * host from plain arrays (no context, no GPU); a failure returns
+ * MDMRG_EINVAL (MDMRG_ENOMEM for host memory) with the message in
+ * mdmrg_last_error(NULL).  A mode is a site: one spin-orbital (spinless) or
+ * the pair 2i, 2i+1 (spin_half); d = 2 or 4 local states, bit t of a local
+ * state = spin-orbital t of the site occupied.
+ */
+
+/* Reduced density operators of single modes and of mode pairs of the MPS
+ * given in the exchange format (site tensors of mdmrg_get_mps, sector lists
+ * of mdmrg_get_bond; the state need not be normalised), and from them:
+ *   s_one[n]       s_i = -Tr rho_i ln rho_i;
+ *   s_two[n*n]     s_ij of the pair (symmetric; s_two[i*n+i] = s_i);
+ * and, each optional (NULL to skip):
+ *   rho_one[n*d*d] rho_i, local state index;
+ *   rho_two[n*n*d^4] rho_ij for i != j in the representation with the
+ *                  spin-orbitals of i moved to the front, then those of j
+ *                  (the Jordan-Wigner sign of that reordering included),
+ *                  local index c_i + d*c_j; the diagonal blocks are not
+ *                  written;
+ *   gamma[nso*nso] gamma_pq = <a+_p a_q> over spin-orbitals p = ns*i + t;
+ *   occ[nso]       <n_p>.
+ * The contraction costs about n^2 d^2 / 2 block-sparse transfers of a
+ * bond operator over one site and uses the host's hardware threads.  EINVAL for a layout that
+ * does not add up to n_data, sectors out of order or a zero state. */
+int mdmrg_mode_analysis(int n_sites, int spin_half, const int32_t *n_sect, const int32_t *sect_qn,
+                        const int32_t *sect_dim, const double *data, int64_t n_data, double *s_one,
+                        double *s_two, double *rho_one, double *rho_two, double *gamma, double *occ);
+
+/* Mutual information I_ij = s_i + s_j - s_ij (I_ii = 0) into I[n*n],
+ * *i_tot = sum_i s_i and *i_dist = sum_{i,j} I_ij (pos(i) - pos(j))^2 over
+ * the positions pos(order[k]) = k of the modes along the chain (order NULL:
+ * index order).  i_tot, i_dist may be NULL.  EINVAL if order is not a
+ * permutation. */
+int mdmrg_mutual_information(int n, const double *s_one, const double *s_two, const int32_t *order,
+                             double *I, double *i_tot, double *i_dist);
+
+/* Mode ordering from the Fiedler vector (the eigenvector of the second-
+ * smallest eigenvalue of the Laplacian diag(sum_j I_ij) - I of the graph
+ * weighted by the symmetrised I[n*n]): order[n] lists the modes by
+ * ascending entry.  The vector's sign is the one that correlates non-
+ * negatively with the current positions; ties keep index order.  EINVAL if
+ * the graph is disconnected (the second eigenvalue vanishes) or I holds a
+ * non-finite value. */
+int mdmrg_fiedler_order(int n, const double *I, int32_t *order);
+
+/* Complete-active-space vector of the DEAS warm-up: order[n] = the modes by
+ * decreasing one-mode entropy s_one, ties in index order. */
+int mdmrg_deas_order(int n, const double *s_one, int32_t *order);
+
+/* HF reference configuration from the spin-orbital occupations occ[nso]:
+ * config[nso] (0/1) fills the target_a most occupied spin-orbitals
+ * (spin_half: the target_a most occupied up and target_b most occupied
+ * down ones), ties to the lower index.  EINVAL for a target outside
+ * [0, n_sites]. */
+int mdmrg_hf_reference(int n_sites, int spin_half, const double *occ, int target_a, int target_b,
+                       int8_t *config);
+
+/* Natural occupation numbers occupation[nso] (descending) and natural modes
+ * (the columns of modes[nso*nso], row-major; NULL to skip) of the
+ * symmetrised one-particle density matrix gamma[nso*nso]. */
+int mdmrg_natural_orbitals(int nso, const double *gamma, double *occupation, double *modes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, 'libmdmrg.so')
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 CXX = os.environ.get('CXX', 'g++')
 
-SOURCES = ['device.hip', 'model.cpp', 'engine.cpp', 'capi.cpp']
+SOURCES = ['device.hip', 'model.cpp', 'engine.cpp', 'capi.cpp', 'modes.cpp']
 COMMON = ['-O3', '-fPIC', '-std=c++17', '-Wall', '-Wno-unused-result', '-pthread']
 HIP_FLAGS = ['-x', 'hip', '--offload-arch=gfx950',
              '-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops']
@@ -47,7 +47,7 @@ def build(verbose=False):
 
 
 CHECK_OUT = os.path.join(HERE, 'libmdmrg_check.so')
-CHECK_SOURCES = ['device_check.cpp', 'model.cpp', 'engine.cpp', 'capi.cpp']
+CHECK_SOURCES = ['device_check.cpp', 'model.cpp', 'engine.cpp', 'capi.cpp', 'modes.cpp']
 
 
 def build_check(verbose=False):

@@ -29,7 +29,11 @@ static int guarded(mdmrg_ctx ctx, F &&f) {
   }
 }
 
-static thread_local std::string g_err;
+// Message of the last failed call that has no context (creation, the host
+// analysis functions); per thread.
+namespace mdmrg {
+thread_local std::string g_err;
+}
 
 extern "C" {
 

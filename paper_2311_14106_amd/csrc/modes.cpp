@@ -1,0 +1,605 @@
+// Host analysis of a matrix product state at the end of a sweep (Sec. II.B):
+// the one- and two-mode reduced density operators and their von Neumann
+// entropies, the one-particle density matrix and occupations, the mutual
+// information with the total correlation and correlation distance, the
+// natural modes, the Fiedler ordering, the DEAS order and the HF reference
+// configuration that set up the next mode-transformation macro-iteration.
+//
+// Everything here runs on the host from the MPS exchange arrays (the format
+// of mdmrg_set_mps / mdmrg_get_mps); no context and no GPU are involved.
+//
+// Mode density operators.  The MPS amplitude of the local configurations
+// (s_0 .. s_{n-1}) is the coefficient of the Fock state with the creation
+// operators in chain order.  For modes i < j the density operator in the
+// representation with the modes' spin-orbitals moved to the front (i's first)
+// is
+//   rho[(c,e),(c',e')] = sum_rest psi(..c..e..) psi(..c'..e'..) (-1)^{P}
+// where P = (N(e) + N(e')) * (particles on the sites strictly between i and
+// j): the Jordan-Wigner string of the reordering.  It is contracted left to
+// right: the left environment E_L[i] (sum over the configurations of sites
+// < i), the pair (c, c') at site i, the transfer over sites i+1 .. j-1 (with
+// the parity of each site's state when N(c) + N(c') is odd), the pair
+// (e, e') at site j and the right environment E_R[j+1].  Every operator
+// between two bonds maps a bra sector to one ket sector (its quantum-number
+// shift is fixed), so it is stored as one dense block per bra sector.
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <exception>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/mdmrg.h"
+
+namespace mdmrg {
+extern thread_local std::string g_err;  // read by mdmrg_last_error(NULL)
+}
+
+namespace {
+
+struct BadInput : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+struct Mps {
+  int n = 0, ns = 1, d = 2;
+  std::vector<std::vector<std::array<int, 2>>> qn;  // per bond
+  std::vector<std::vector<int>> dim;                // per bond
+  // per site: block of (l, s) -> (r, offset) or r = -1
+  std::vector<std::vector<int>> blk_r;
+  std::vector<std::vector<int64_t>> blk_off;
+  const double *data = nullptr;
+
+  std::array<int, 2> q(int s) const {
+    return ns == 2 ? std::array<int, 2>{s & 1, (s >> 1) & 1} : std::array<int, 2>{s & 1, 0};
+  }
+  int find(int bond, std::array<int, 2> Q) const {
+    const auto &v = qn[bond];
+    auto it = std::lower_bound(v.begin(), v.end(), Q);
+    return (it != v.end() && *it == Q) ? int(it - v.begin()) : -1;
+  }
+};
+
+void parse(Mps &m, int n_sites, int spin_half, const int32_t *n_sect, const int32_t *sect_qn,
+           const int32_t *sect_dim, const double *data, int64_t n_data) {
+  m.n = n_sites;
+  m.ns = spin_half ? 2 : 1;
+  m.d = 1 << m.ns;
+  m.data = data;
+  m.qn.resize(n_sites + 1);
+  m.dim.resize(n_sites + 1);
+  int64_t k = 0;
+  for (int b = 0; b <= n_sites; ++b) {
+    if (n_sect[b] < 1) throw BadInput("a bond has no sectors");
+    for (int t = 0; t < n_sect[b]; ++t, ++k) {
+      std::array<int, 2> Q{sect_qn[2 * k], sect_qn[2 * k + 1]};
+      if (sect_dim[k] < 1) throw BadInput("a sector has dimension < 1");
+      if (t > 0 && !(m.qn[b].back() < Q)) throw BadInput("sectors not in ascending order");
+      m.qn[b].push_back(Q);
+      m.dim[b].push_back(sect_dim[k]);
+    }
+  }
+  if (m.qn[0].size() != 1 || m.qn[0][0] != std::array<int, 2>{0, 0} || m.dim[0][0] != 1 ||
+      m.qn[n_sites].size() != 1 || m.dim[n_sites][0] != 1)
+    throw BadInput("bond 0 must be {(0,0): 1} and bond n a single sector of dimension 1");
+  int64_t off = 0;
+  m.blk_r.resize(n_sites);
+  m.blk_off.resize(n_sites);
+  for (int i = 0; i < n_sites; ++i) {
+    const int nl = int(m.qn[i].size());
+    m.blk_r[i].assign(size_t(nl) * m.d, -1);
+    m.blk_off[i].assign(size_t(nl) * m.d, -1);
+    for (int l = 0; l < nl; ++l)
+      for (int s = 0; s < m.d; ++s) {
+        const auto qs = m.q(s);
+        const int r = m.find(i + 1, {m.qn[i][l][0] + qs[0], m.qn[i][l][1] + qs[1]});
+        if (r < 0) continue;
+        m.blk_r[i][size_t(l) * m.d + s] = r;
+        m.blk_off[i][size_t(l) * m.d + s] = off;
+        off += int64_t(m.dim[i][l]) * m.dim[i + 1][r];
+      }
+  }
+  if (off != n_data) throw BadInput("n_data does not match the sector layout");
+}
+
+// An operator between the bra and ket copies of one bond: per bra sector
+// the ket sector (-1: none) and a dense m_bra x m_ket block, row-major.
+struct Op {
+  std::vector<int> ket;
+  std::vector<std::vector<double>> mat;
+};
+
+Op identity_op(const Mps &m, int bond, double scale = 1.0) {
+  Op o;
+  const int ns = int(m.qn[bond].size());
+  o.ket.resize(ns);
+  o.mat.resize(ns);
+  for (int t = 0; t < ns; ++t) {
+    o.ket[t] = t;
+    const int md = m.dim[bond][t];
+    o.mat[t].assign(size_t(md) * md, 0.0);
+    for (int a = 0; a < md; ++a) o.mat[t][size_t(a) * md + a] = scale;
+  }
+  return o;
+}
+
+// X' = sum A^{sb T} X A^{sk} over site i: (sb, sk) fixed when sb >= 0,
+// otherwise summed over s = sb = sk with the sign (-1)^{N(s)} when parity.
+Op apply_site(const Mps &m, int i, const Op &X, int sb, int sk, bool parity) {
+  const int nr = int(m.qn[i + 1].size());
+  Op out;
+  out.ket.assign(nr, -1);
+  out.mat.resize(nr);
+  std::vector<double> tmp;
+  const int nl = int(m.qn[i].size());
+  for (int l = 0; l < nl; ++l) {
+    const int lk = X.ket[l];
+    if (lk < 0) continue;
+    const int s0 = sb >= 0 ? sb : 0, s1 = sb >= 0 ? sb + 1 : m.d;
+    for (int s = s0; s < s1; ++s) {
+      const int sK = sb >= 0 ? sk : s;
+      const int r = m.blk_r[i][size_t(l) * m.d + s];
+      const int rk = m.blk_r[i][size_t(lk) * m.d + sK];
+      if (r < 0 || rk < 0) continue;
+      const double sign = (parity && (__builtin_popcount(unsigned(s)) & 1)) ? -1.0 : 1.0;
+      const int ml = m.dim[i][l], mlk = m.dim[i][lk], mr = m.dim[i + 1][r], mrk = m.dim[i + 1][rk];
+      const double *A = m.data + m.blk_off[i][size_t(l) * m.d + s];     // ml x mr
+      const double *B = m.data + m.blk_off[i][size_t(lk) * m.d + sK];   // mlk x mrk
+      const std::vector<double> &Xl = X.mat[l];                          // ml x mlk
+      tmp.assign(size_t(ml) * mrk, 0.0);                                 // X B
+      for (int a = 0; a < ml; ++a)
+        for (int b = 0; b < mlk; ++b) {
+          const double x = Xl[size_t(a) * mlk + b];
+          if (x == 0.0) continue;
+          const double *Br = B + size_t(b) * mrk;
+          double *T = tmp.data() + size_t(a) * mrk;
+          for (int c = 0; c < mrk; ++c) T[c] += x * Br[c];
+        }
+      if (out.ket[r] < 0) {
+        out.ket[r] = rk;
+        out.mat[r].assign(size_t(mr) * mrk, 0.0);
+      } else if (out.ket[r] != rk) {
+        throw std::logic_error("operator sector shift is not fixed");
+      }
+      double *O = out.mat[r].data();
+      for (int a = 0; a < ml; ++a) {
+        const double *Ar = A + size_t(a) * mr;
+        const double *T = tmp.data() + size_t(a) * mrk;
+        for (int r1 = 0; r1 < mr; ++r1) {
+          const double x = sign * Ar[r1];
+          if (x == 0.0) continue;
+          double *Orow = O + size_t(r1) * mrk;
+          for (int c = 0; c < mrk; ++c) Orow[c] += x * T[c];
+        }
+      }
+    }
+  }
+  return out;
+}
+
+// Y' = sum_s A^s Y A^{s T} over site i (right environments; identity form).
+Op apply_site_right(const Mps &m, int i, const Op &Y) {
+  const int nl = int(m.qn[i].size());
+  Op out;
+  out.ket.assign(nl, -1);
+  out.mat.resize(nl);
+  std::vector<double> tmp;
+  for (int l = 0; l < nl; ++l)
+    for (int s = 0; s < m.d; ++s) {
+      const int r = m.blk_r[i][size_t(l) * m.d + s];
+      if (r < 0 || Y.ket[r] != r) continue;  // identity environments are sector-diagonal
+      const int ml = m.dim[i][l], mr = m.dim[i + 1][r];
+      const double *A = m.data + m.blk_off[i][size_t(l) * m.d + s];  // ml x mr
+      const std::vector<double> &Yr = Y.mat[r];                       // mr x mr
+      tmp.assign(size_t(ml) * mr, 0.0);                               // A Y
+      for (int a = 0; a < ml; ++a)
+        for (int b = 0; b < mr; ++b) {
+          const double x = A[size_t(a) * mr + b];
+          if (x == 0.0) continue;
+          for (int c = 0; c < mr; ++c) tmp[size_t(a) * mr + c] += x * Yr[size_t(b) * mr + c];
+        }
+      if (out.ket[l] < 0) {
+        out.ket[l] = l;
+        out.mat[l].assign(size_t(ml) * ml, 0.0);
+      }
+      double *O = out.mat[l].data();
+      for (int a = 0; a < ml; ++a)
+        for (int b = 0; b < ml; ++b) {
+          double acc = 0.0;
+          for (int c = 0; c < mr; ++c) acc += tmp[size_t(a) * mr + c] * A[size_t(b) * mr + c];
+          O[size_t(a) * ml + b] += acc;
+        }
+    }
+  return out;
+}
+
+// sum_{r,r'} X[r][r'] E[r][r'] over the bra sectors where both map to the
+// same ket sector.
+double frob(const Op &X, const Op &E) {
+  double acc = 0.0;
+  for (size_t r = 0; r < X.ket.size(); ++r) {
+    if (X.ket[r] < 0 || X.ket[r] != E.ket[r]) continue;
+    const auto &a = X.mat[r], &b = E.mat[r];
+    for (size_t k = 0; k < a.size(); ++k) acc += a[k] * b[k];
+  }
+  return acc;
+}
+
+// W = A^e E A^{e2 T} at bond j (E the sector-diagonal right environment of
+// bond j+1): closing an operator Y of bond j with the pair (e, e2) at site
+// j is frob(Y, W).
+Op close_op(const Mps &m, int j, int e, int e2, const Op &E) {
+  const int nl = int(m.qn[j].size());
+  Op out;
+  out.ket.assign(nl, -1);
+  out.mat.resize(nl);
+  std::vector<double> tmp;
+  for (int l = 0; l < nl; ++l) {
+    const int r = m.blk_r[j][size_t(l) * m.d + e];
+    if (r < 0 || E.ket[r] != r) continue;
+    const auto qe2 = m.q(e2);
+    const int lk = m.find(j, {m.qn[j + 1][r][0] - qe2[0], m.qn[j + 1][r][1] - qe2[1]});
+    if (lk < 0) continue;
+    const int ml = m.dim[j][l], mlk = m.dim[j][lk], mr = m.dim[j + 1][r];
+    const double *A = m.data + m.blk_off[j][size_t(l) * m.d + e];     // ml x mr
+    const double *B = m.data + m.blk_off[j][size_t(lk) * m.d + e2];   // mlk x mr
+    const std::vector<double> &Er = E.mat[r];                          // mr x mr
+    tmp.assign(size_t(ml) * mr, 0.0);                                  // A E
+    for (int a = 0; a < ml; ++a)
+      for (int b = 0; b < mr; ++b) {
+        const double x = A[size_t(a) * mr + b];
+        if (x == 0.0) continue;
+        for (int c = 0; c < mr; ++c) tmp[size_t(a) * mr + c] += x * Er[size_t(b) * mr + c];
+      }
+    out.ket[l] = lk;
+    out.mat[l].assign(size_t(ml) * mlk, 0.0);
+    for (int a = 0; a < ml; ++a)
+      for (int b = 0; b < mlk; ++b) {
+        double acc = 0.0;
+        for (int c = 0; c < mr; ++c) acc += tmp[size_t(a) * mr + c] * B[size_t(b) * mr + c];
+        out.mat[l][size_t(a) * mlk + b] = acc;
+      }
+  }
+  return out;
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (row-major):
+// eigenvalues ascending in w, eigenvectors as the columns of V when wanted.
+void jacobi(int n, std::vector<double> A, std::vector<double> &w, std::vector<double> *V) {
+  if (V) {
+    V->assign(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) (*V)[size_t(i) * n + i] = 1.0;
+  }
+  double norm = 0.0;
+  for (double x : A) norm += x * x;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[size_t(p) * n + q] * A[size_t(p) * n + q];
+    if (off <= 1e-32 * norm || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[size_t(p) * n + q];
+        if (apq == 0.0) continue;
+        const double app = A[size_t(p) * n + p], aqq = A[size_t(q) * n + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = A[size_t(k) * n + p], akq = A[size_t(k) * n + q];
+          A[size_t(k) * n + p] = c * akp - s * akq;
+          A[size_t(k) * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = A[size_t(p) * n + k], aqk = A[size_t(q) * n + k];
+          A[size_t(p) * n + k] = c * apk - s * aqk;
+          A[size_t(q) * n + k] = s * apk + c * aqk;
+        }
+        if (V)
+          for (int k = 0; k < n; ++k) {
+            double *Vr = V->data() + size_t(k) * n;
+            const double vkp = Vr[p], vkq = Vr[q];
+            Vr[p] = c * vkp - s * vkq;
+            Vr[q] = s * vkp + c * vkq;
+          }
+      }
+  }
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](int a, int b) { return A[size_t(a) * n + a] < A[size_t(b) * n + b]; });
+  w.resize(n);
+  for (int k = 0; k < n; ++k) w[k] = A[size_t(idx[k]) * n + idx[k]];
+  if (V) {
+    std::vector<double> W(size_t(n) * n);
+    for (int r = 0; r < n; ++r)
+      for (int k = 0; k < n; ++k) W[size_t(r) * n + k] = (*V)[size_t(r) * n + idx[k]];
+    *V = std::move(W);
+  }
+}
+
+double vn_entropy(int n, const std::vector<double> &rho) {
+  std::vector<double> S(rho);
+  for (int a = 0; a < n; ++a)
+    for (int b = a + 1; b < n; ++b) {
+      const double x = 0.5 * (S[size_t(a) * n + b] + S[size_t(b) * n + a]);
+      S[size_t(a) * n + b] = S[size_t(b) * n + a] = x;
+    }
+  std::vector<double> w;
+  jacobi(n, S, w, nullptr);
+  double s = 0.0;
+  for (double x : w)
+    if (x > 1e-300) s -= x * std::log(x);
+  return s;
+}
+
+// <a+_p a_q> on the local Fock space of k spin-orbitals (bit t of a local
+// configuration = spin-orbital t, creation operators in bit order):
+// matrix element <out|a+_p a_q|in> as (out, sign) or out = -1.
+int hop_local(int in, int p, int q, double &sign) {
+  if (!((in >> q) & 1)) return -1;
+  sign = (__builtin_popcount(unsigned(in) & ((1u << q) - 1u)) & 1) ? -1.0 : 1.0;
+  int mid = in ^ (1 << q);
+  if ((mid >> p) & 1) return -1;
+  if (__builtin_popcount(unsigned(mid) & ((1u << p) - 1u)) & 1) sign = -sign;
+  return mid | (1 << p);
+}
+
+// Runs task(0..n-1) on the host's hardware threads; rethrows the first
+// exception a task raised.
+template <class F>
+void run_parallel(int n, F &&task) {
+  const int nt = std::max(1, std::min<int>(n, int(std::thread::hardware_concurrency())));
+  std::atomic<int> next{0};
+  std::exception_ptr err;
+  std::mutex mu;
+  auto worker = [&] {
+    for (int k; (k = next.fetch_add(1)) < n;) {
+      try {
+        task(k);
+      } catch (...) {
+        std::lock_guard<std::mutex> g(mu);
+        if (!err) err = std::current_exception();
+        next.store(n);
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto &t : pool) t.join();
+  if (err) std::rethrow_exception(err);
+}
+
+template <class F>
+int guarded_host(F &&f) {
+  try {
+    mdmrg::g_err.clear();
+    return f();
+  } catch (const std::bad_alloc &) {
+    mdmrg::g_err = "host allocation failed";
+    return MDMRG_ENOMEM;
+  } catch (const std::exception &e) {
+    mdmrg::g_err = e.what();
+    return MDMRG_EINVAL;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mdmrg_mode_analysis(int n_sites, int spin_half, const int32_t *n_sect, const int32_t *sect_qn,
+                        const int32_t *sect_dim, const double *data, int64_t n_data, double *s_one,
+                        double *s_two, double *rho_one, double *rho_two, double *gamma, double *occ) {
+  if (n_sites < 1 || !n_sect || !sect_qn || !sect_dim || (!data && n_data > 0) || !s_one || !s_two)
+    return MDMRG_EINVAL;
+  return guarded_host([&] {
+    Mps m;
+    parse(m, n_sites, spin_half, n_sect, sect_qn, sect_dim, data, n_data);
+    const int n = m.n, d = m.d, ns = m.ns, nso = n * ns, d2 = d * d;
+    // identity environments and the closing operators of every site
+    std::vector<Op> EL(n + 1), ER(n + 1);
+    EL[0] = identity_op(m, 0);
+    for (int i = 0; i < n; ++i) EL[i + 1] = apply_site(m, i, EL[i], -1, -1, false);
+    ER[n] = identity_op(m, n);
+    for (int i = n - 1; i >= 0; --i) ER[i] = apply_site_right(m, i, ER[i + 1]);
+    const double Z = frob(EL[n], ER[n]);
+    if (!(Z > 0.0) || !std::isfinite(Z)) throw BadInput("the state has no norm");
+    std::vector<Op> W(size_t(n) * d * d);
+    for (int j = 0; j < n; ++j)
+      for (int e = 0; e < d; ++e)
+        for (int e2 = 0; e2 < d; ++e2) W[(size_t(j) * d + e) * d + e2] = close_op(m, j, e, e2, ER[j + 1]);
+    if (gamma) std::fill(gamma, gamma + size_t(nso) * nso, 0.0);
+
+    // one site i per task: rho_i, then rho_ij for every j > i
+    auto site_task = [&](int i) {
+      std::vector<double> r1(size_t(d) * d);
+      for (int c = 0; c < d; ++c)
+        for (int c2 = 0; c2 < d; ++c2) r1[size_t(c) * d + c2] = frob(EL[i], W[(size_t(i) * d + c) * d + c2]) / Z;
+      s_one[i] = vn_entropy(d, r1);
+      s_two[size_t(i) * n + i] = s_one[i];
+      if (rho_one) std::copy(r1.begin(), r1.end(), rho_one + size_t(i) * d * d);
+      if (occ)
+        for (int t = 0; t < ns; ++t) {
+          double o = 0.0;
+          for (int c = 0; c < d; ++c)
+            if ((c >> t) & 1) o += r1[size_t(c) * d + c];
+          occ[size_t(i) * ns + t] = o;
+        }
+      if (gamma)  // same-site elements <a+_p a_q> = sum_in sign rho[in][out]
+        for (int p = 0; p < ns; ++p)
+          for (int q = 0; q < ns; ++q) {
+            double g = 0.0, sg;
+            for (int a = 0; a < d; ++a) {
+              const int b = hop_local(a, p, q, sg);
+              if (b >= 0) g += sg * r1[size_t(a) * d + b];
+            }
+            gamma[size_t(i * ns + p) * nso + i * ns + q] = g;
+          }
+      if (i + 1 >= n) return;
+      // blocks of rho_ij for all j > i, local index c + d*e (modes i, j)
+      std::vector<double> blks(size_t(n - i - 1) * d2 * d2);
+      for (int c = 0; c < d; ++c)
+        for (int c2 = 0; c2 < d; ++c2) {
+          const bool parity = (__builtin_popcount(unsigned(c)) + __builtin_popcount(unsigned(c2))) & 1;
+          Op Y = apply_site(m, i, EL[i], c, c2, false);
+          for (int j = i + 1; j < n; ++j) {
+            double *blk = blks.data() + size_t(j - i - 1) * d2 * d2;
+            for (int e = 0; e < d; ++e)
+              for (int e2 = 0; e2 < d; ++e2)
+                blk[(size_t(c) + size_t(d) * e) * d2 + size_t(c2) + size_t(d) * e2] =
+                    frob(Y, W[(size_t(j) * d + e) * d + e2]) / Z;
+            if (j + 1 < n) Y = apply_site(m, j, Y, -1, -1, parity);
+          }
+        }
+      for (int j = i + 1; j < n; ++j) {
+        const double *blk = blks.data() + size_t(j - i - 1) * d2 * d2;
+        const double sij = vn_entropy(d2, std::vector<double>(blk, blk + size_t(d2) * d2));
+        s_two[size_t(i) * n + j] = s_two[size_t(j) * n + i] = sij;
+        if (rho_two) {
+          std::copy(blk, blk + size_t(d2) * d2, rho_two + (size_t(i) * n + j) * d2 * d2);
+          // modes listed (j, i): local index e + d*c and the reordering sign
+          // (-1)^{N(c)N(e) + N(c')N(e')}
+          double *out = rho_two + (size_t(j) * n + i) * d2 * d2;
+          for (int c = 0; c < d; ++c)
+            for (int e = 0; e < d; ++e)
+              for (int c2 = 0; c2 < d; ++c2)
+                for (int e2 = 0; e2 < d; ++e2) {
+                  const int sg = (__builtin_popcount(unsigned(c)) * __builtin_popcount(unsigned(e)) +
+                                  __builtin_popcount(unsigned(c2)) * __builtin_popcount(unsigned(e2))) & 1;
+                  const double v = blk[(size_t(c) + size_t(d) * e) * d2 + size_t(c2) + size_t(d) * e2];
+                  out[(size_t(e) + size_t(d) * c) * d2 + size_t(e2) + size_t(d) * c2] = sg ? -v : v;
+                }
+        }
+        if (gamma)  // <a+_p a_q> with p and q on different sites of the pair
+          for (int p = 0; p < 2 * ns; ++p)
+            for (int q = 0; q < 2 * ns; ++q) {
+              if ((p < ns) == (q < ns)) continue;
+              double g = 0.0, sg;
+              for (int a = 0; a < d2; ++a) {
+                const int b = hop_local(a, p, q, sg);
+                if (b >= 0) g += sg * blk[size_t(a) * d2 + b];
+              }
+              const int gp = p < ns ? i * ns + p : j * ns + (p - ns);
+              const int gq = q < ns ? i * ns + q : j * ns + (q - ns);
+              gamma[size_t(gp) * nso + gq] = g;
+            }
+      }
+    };
+    run_parallel(n, site_task);
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_mutual_information(int n, const double *s_one, const double *s_two, const int32_t *order,
+                             double *I, double *i_tot, double *i_dist) {
+  if (n < 1 || !s_one || !s_two || !I) return MDMRG_EINVAL;
+  return guarded_host([&] {
+    std::vector<int> pos(n);
+    std::iota(pos.begin(), pos.end(), 0);
+    if (order) {
+      std::vector<int> seen(n, 0);
+      for (int k = 0; k < n; ++k) {
+        if (order[k] < 0 || order[k] >= n || seen[order[k]]++) throw BadInput("order is not a permutation");
+        pos[order[k]] = k;
+      }
+    }
+    double tot = 0.0, dist = 0.0;
+    for (int i = 0; i < n; ++i) {
+      tot += s_one[i];
+      for (int j = 0; j < n; ++j) {
+        const double v = i == j ? 0.0 : s_one[i] + s_one[j] - s_two[size_t(i) * n + j];
+        I[size_t(i) * n + j] = v;
+        const double dd = double(pos[i] - pos[j]);
+        dist += v * dd * dd;
+      }
+    }
+    if (i_tot) *i_tot = tot;
+    if (i_dist) *i_dist = dist;
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_fiedler_order(int n, const double *I, int32_t *order) {
+  if (n < 2 || !I || !order) return MDMRG_EINVAL;
+  return guarded_host([&] {
+    std::vector<double> L(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        if (i == j) continue;
+        const double w = 0.5 * (I[size_t(i) * n + j] + I[size_t(j) * n + i]);
+        if (!std::isfinite(w)) throw BadInput("non-finite mutual information");
+        L[size_t(i) * n + j] = -w;
+        L[size_t(i) * n + i] += w;
+      }
+    std::vector<double> w, V;
+    jacobi(n, L, w, &V);
+    if (!(w[1] > 1e-12 * std::max(w[n - 1], 1e-300))) throw BadInput("the graph is disconnected");
+    std::vector<double> v(n);
+    double corr = 0.0;
+    for (int i = 0; i < n; ++i) {
+      v[i] = V[size_t(i) * n + 1];
+      corr += v[i] * (i - 0.5 * (n - 1));
+    }
+    if (corr < 0)
+      for (double &x : v) x = -x;
+    std::vector<int> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return v[a] < v[b]; });
+    for (int k = 0; k < n; ++k) order[k] = idx[k];
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_deas_order(int n, const double *s_one, int32_t *order) {
+  if (n < 1 || !s_one || !order) return MDMRG_EINVAL;
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return s_one[a] > s_one[b]; });
+  for (int k = 0; k < n; ++k) order[k] = idx[k];
+  return MDMRG_OK;
+}
+
+int mdmrg_hf_reference(int n_sites, int spin_half, const double *occ, int target_a, int target_b,
+                       int8_t *config) {
+  const int ns = spin_half ? 2 : 1;
+  if (n_sites < 1 || !occ || !config || target_a < 0 || target_a > n_sites ||
+      (spin_half && (target_b < 0 || target_b > n_sites)))
+    return MDMRG_EINVAL;
+  std::fill(config, config + size_t(n_sites) * ns, int8_t(0));
+  for (int sigma = 0; sigma < ns; ++sigma) {
+    const int k = sigma == 0 ? target_a : target_b;
+    std::vector<int> so(n_sites);
+    for (int i = 0; i < n_sites; ++i) so[i] = i * ns + sigma;
+    std::stable_sort(so.begin(), so.end(), [&](int a, int b) { return occ[a] > occ[b]; });
+    for (int t = 0; t < k; ++t) config[so[t]] = 1;
+  }
+  return MDMRG_OK;
+}
+
+int mdmrg_natural_orbitals(int nso, const double *gamma, double *occupation, double *modes) {
+  if (nso < 1 || !gamma || !occupation) return MDMRG_EINVAL;
+  return guarded_host([&] {
+    std::vector<double> G(size_t(nso) * nso);
+    for (int a = 0; a < nso; ++a)
+      for (int b = 0; b < nso; ++b)
+        G[size_t(a) * nso + b] = 0.5 * (gamma[size_t(a) * nso + b] + gamma[size_t(b) * nso + a]);
+    std::vector<double> w, V;
+    jacobi(nso, G, w, modes ? &V : nullptr);
+    for (int k = 0; k < nso; ++k) occupation[k] = w[nso - 1 - k];  // descending
+    if (modes)
+      for (int r = 0; r < nso; ++r)
+        for (int k = 0; k < nso; ++k) modes[size_t(r) * nso + k] = V[size_t(r) * nso + nso - 1 - k];
+    return MDMRG_OK;
+  });
+}
+
+}  // extern "C"

@@ -70,6 +70,16 @@ EXPORTS = {
                                                 _c_i64_p, ctypes.c_int64, _c_i64_p, _c_dbl_p]),
     'mdmrg_get_mps': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     'mdmrg_get_stats': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p]),
+    'mdmrg_mode_analysis': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_i32_p, _c_i32_p, _c_i32_p, _c_dbl_p,
+                                           ctypes.c_int64, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p,
+                                           _c_dbl_p]),
+    'mdmrg_mutual_information': (ctypes.c_int, [ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_i32_p, _c_dbl_p, _c_dbl_p,
+                                                _c_dbl_p]),
+    'mdmrg_fiedler_order': (ctypes.c_int, [ctypes.c_int, _c_dbl_p, _c_i32_p]),
+    'mdmrg_deas_order': (ctypes.c_int, [ctypes.c_int, _c_dbl_p, _c_i32_p]),
+    'mdmrg_hf_reference': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_dbl_p, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int8)]),
+    'mdmrg_natural_orbitals': (ctypes.c_int, [ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
 }
 
 
@@ -149,6 +159,104 @@ def rotate_modes(R, T, V, spin_half, L=None):
     if st:
         raise MdmrgError(st, L.mdmrg_last_error(None).decode())
     return T, V
+
+
+def _host_check(L, st):
+    if st:
+        raise MdmrgError(st, L.mdmrg_last_error(None).decode())
+
+
+def mode_analysis(n_sect, sect_qn, sect_dim, data, spin_half, rho=False, L=None):
+    """One- and two-mode entropies, gamma and occupations of an MPS in the
+    exchange format (mdmrg_mode_analysis); with rho=True also the mode
+    density operators.  Returns a dict of numpy arrays."""
+    L = L or lib()
+    n_sect = np.ascontiguousarray(n_sect, dtype=np.int32)
+    sect_qn = np.ascontiguousarray(sect_qn, dtype=np.int32)
+    sect_dim = np.ascontiguousarray(sect_dim, dtype=np.int32)
+    data = np.ascontiguousarray(data, dtype=np.float64)
+    n = len(n_sect) - 1
+    S = int(n_sect.sum())
+    if n < 1 or sect_qn.size != 2 * S or sect_dim.size != S:
+        raise MdmrgError(EINVAL, 'sector arrays do not match n_sect')
+    ns = 2 if spin_half else 1
+    d = 1 << ns
+    out = {'s_one': np.zeros(n), 's_two': np.zeros((n, n)), 'gamma': np.zeros((n * ns, n * ns)),
+           'occ': np.zeros(n * ns)}
+    if rho:
+        out['rho_one'] = np.zeros((n, d, d))
+        out['rho_two'] = np.zeros((n, n, d * d, d * d))
+    st = L.mdmrg_mode_analysis(n, int(bool(spin_half)), _ip(n_sect), _ip(sect_qn), _ip(sect_dim), _dp(data),
+                               data.size, _dp(out['s_one']), _dp(out['s_two']),
+                               _dp(out['rho_one']) if rho else None, _dp(out['rho_two']) if rho else None,
+                               _dp(out['gamma']), _dp(out['occ']))
+    _host_check(L, st)
+    return out
+
+
+def mutual_information(s_one, s_two, order=None, L=None):
+    """(I, I_tot, I_dist) from one- and two-mode entropies."""
+    L = L or lib()
+    s_one = np.ascontiguousarray(s_one, dtype=np.float64)
+    s_two = np.ascontiguousarray(s_two, dtype=np.float64)
+    n = s_one.size
+    if s_two.shape != (n, n):
+        raise MdmrgError(EINVAL, 's_two must be n x n')
+    if order is not None:
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        if order.size != n:
+            raise MdmrgError(EINVAL, 'order must list n modes')
+    Imat = np.zeros((n, n))
+    tot, dist = ctypes.c_double(), ctypes.c_double()
+    st = L.mdmrg_mutual_information(n, _dp(s_one), _dp(s_two), _ip(order) if order is not None else None,
+                                    _dp(Imat), ctypes.byref(tot), ctypes.byref(dist))
+    _host_check(L, st)
+    return Imat, tot.value, dist.value
+
+
+def fiedler_order(Imat, L=None):
+    L = L or lib()
+    Imat = np.ascontiguousarray(Imat, dtype=np.float64)
+    n = Imat.shape[0]
+    if Imat.shape != (n, n):
+        raise MdmrgError(EINVAL, 'I must be square')
+    order = np.zeros(n, dtype=np.int32)
+    _host_check(L, L.mdmrg_fiedler_order(n, _dp(Imat), _ip(order)))
+    return order
+
+
+def deas_order(s_one, L=None):
+    L = L or lib()
+    s_one = np.ascontiguousarray(s_one, dtype=np.float64)
+    order = np.zeros(s_one.size, dtype=np.int32)
+    _host_check(L, L.mdmrg_deas_order(s_one.size, _dp(s_one), _ip(order)))
+    return order
+
+
+def hf_reference(occ, n_sites, spin_half, target, L=None):
+    """0/1 occupation of every spin-orbital of the HF reference."""
+    L = L or lib()
+    occ = np.ascontiguousarray(occ, dtype=np.float64)
+    ns = 2 if spin_half else 1
+    if occ.size != n_sites * ns:
+        raise MdmrgError(EINVAL, 'occ must hold one value per spin-orbital')
+    config = np.zeros(n_sites * ns, dtype=np.int8)
+    _host_check(L, L.mdmrg_hf_reference(n_sites, int(bool(spin_half)), _dp(occ), int(target[0]), int(target[1]),
+                                        config.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))))
+    return config
+
+
+def natural_orbitals(gamma, L=None):
+    """(occupation numbers descending, natural modes as columns)."""
+    L = L or lib()
+    gamma = np.ascontiguousarray(gamma, dtype=np.float64)
+    nso = gamma.shape[0]
+    if gamma.shape != (nso, nso):
+        raise MdmrgError(EINVAL, 'gamma must be square')
+    w = np.zeros(nso)
+    V = np.zeros((nso, nso))
+    _host_check(L, L.mdmrg_natural_orbitals(nso, _dp(gamma), _dp(w), _dp(V)))
+    return w, V
 
 
 class Context:
