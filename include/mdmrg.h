@@ -510,6 +510,35 @@ int mdmrg_hf_reference(int n_sites, int spin_half, const double *occ, int target
  * symmetrised one-particle density matrix gamma[nso*nso]. */
 int mdmrg_natural_orbitals(int nso, const double *gamma, double *occupation, double *modes);
 
+/* The two-mode micro-iteration of the mode optimisation (Sec. II.B) at a
+ * bond: the two modes of the bond (the sites of s1 and s2, first and
+ * second) are rotated by the angle theta, i.e. the new modes d are related
+ * to the old ones by c_1 = cos(theta) d_1 - sin(theta) d_2,
+ * c_2 = sin(theta) d_1 + cos(theta) d_2 (both spin components alike; on
+ * Fock space U = exp(theta sum_sigma (a+_1s a_2s - a+_2s a_1s))), which is
+ * the Givens matrix R of mdmrg_rotate_modes for these two modes, and the
+ * half-Renyi entropy S_1/2 = 2 ln Tr sqrt(rho) of the bipartition
+ * (a, s1 | s2, b) of the rotated two-site wave function is evaluated (rho
+ * normalised to trace 1; its eigenvalues are the squared singular values of
+ * the bipartition matrix, computed per sector by one-sided Jacobi so that
+ * small ones keep their accuracy).  The blocks of psi are given as by mdmrg_psi_layout (8 int32
+ * per block: a, s1, s2, b, m_a, m_b, offset_lo, offset_hi; every
+ * (a, s1, s2, b) of the sector rule present, so that the rotation maps the
+ * layout onto itself), psi on the host (n_elem doubles; the left and right
+ * blocks are taken as orthonormal, as in the canonical form around the
+ * bond).
+ *   n_theta > 0: S_1/2 at theta[k] into s_half[k], and the best angle is
+ *                searched on that grid;  n_theta = 0: on 64 angles
+ *                covering [-pi/2, pi/2);
+ * then refined by golden-section search within one grid step of the best
+ * grid point: *theta_best, *s_best.  psi_rotated (NULL to skip, n_elem
+ * doubles, not aliasing psi) receives the wave function rotated by
+ * theta_best.  EINVAL for a descriptor outside n_elem, repeated blocks, a
+ * layout that the rotation leaves, or a zero psi. */
+int mdmrg_two_mode_rotation(int spin_half, int n_blk, const int32_t *desc, const double *psi, int64_t n_elem,
+                            int n_theta, const double *theta, double *s_half, double *theta_best,
+                            double *s_best, double *psi_rotated);
+
 #ifdef __cplusplus
 }
 #endif

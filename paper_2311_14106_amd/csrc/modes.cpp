@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstdint>
 #include <exception>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -392,6 +393,251 @@ int guarded_host(F &&f) {
   }
 }
 
+
+// Singular values of the m x n matrix whose n columns are the contiguous
+// length-m vectors of X (overwritten), n <= m: one-sided Jacobi (Hestenes)
+// -- pairs of columns are rotated until all are mutually orthogonal; the
+// singular values are then the column norms, small ones to full accuracy.
+std::vector<double> singular_values(int m, int n, std::vector<double> &X) {
+  auto col = [&](int j) { return X.data() + size_t(j) * m; };
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double *xp = col(p), *xq = col(q);
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int i = 0; i < m; ++i) {
+          a += xp[i] * xp[i];
+          b += xq[i] * xq[i];
+          g += xp[i] * xq[i];
+        }
+        if (g == 0.0 || std::fabs(g) <= 1e-15 * std::sqrt(a * b)) continue;
+        rotated = true;
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+        for (int i = 0; i < m; ++i) {
+          const double u = xp[i], v = xq[i];
+          xp[i] = c * u - sn * v;
+          xq[i] = sn * u + c * v;
+        }
+      }
+    if (!rotated) break;
+  }
+  std::vector<double> sv(n);
+  for (int j = 0; j < n; ++j) {
+    double a = 0.0;
+    for (int i = 0; i < m; ++i) a += col(j)[i] * col(j)[i];
+    sv[j] = std::sqrt(a);
+  }
+  return sv;
+}
+
+// Generator of the two-mode rotation on the local space of two adjacent
+// sites (bits 0..ns-1 the first site's spin-orbitals, ns..2ns-1 the
+// second's): K0 = sum_sigma (a+_{1 sigma} a_{2 sigma} - a+_{2 sigma} a_{1 sigma}),
+// and U = exp(theta K0) by scaling and squaring of its Taylor series.
+std::vector<double> two_mode_unitary(int ns, double theta) {
+  const int D = 1 << (2 * ns);
+  std::vector<double> K(size_t(D) * D, 0.0);
+  for (int sg = 0; sg < ns; ++sg)
+    for (int t = 0; t < D; ++t) {
+      double sign;
+      int o = hop_local(t, sg, ns + sg, sign);
+      if (o >= 0) K[size_t(o) * D + t] += theta * sign;
+      o = hop_local(t, ns + sg, sg, sign);
+      if (o >= 0) K[size_t(o) * D + t] -= theta * sign;
+    }
+  int sq = 0;
+  double nrm = std::fabs(theta) * 2.0 * ns;
+  while (nrm > 0.25) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  const double f = std::ldexp(1.0, -sq);
+  for (double &x : K) x *= f;
+  std::vector<double> U(size_t(D) * D, 0.0), term(size_t(D) * D, 0.0), nxt(size_t(D) * D);
+  for (int i = 0; i < D; ++i) U[size_t(i) * D + i] = term[size_t(i) * D + i] = 1.0;
+  for (int k = 1; k <= 24; ++k) {
+    std::fill(nxt.begin(), nxt.end(), 0.0);
+    for (int i = 0; i < D; ++i)
+      for (int l = 0; l < D; ++l) {
+        const double x = K[size_t(i) * D + l];
+        if (x == 0.0) continue;
+        for (int j = 0; j < D; ++j) nxt[size_t(i) * D + j] += x * term[size_t(l) * D + j] / k;
+      }
+    term.swap(nxt);
+    for (size_t q = 0; q < U.size(); ++q) U[q] += term[q];
+  }
+  for (int r = 0; r < sq; ++r) {
+    std::fill(nxt.begin(), nxt.end(), 0.0);
+    for (int i = 0; i < D; ++i)
+      for (int l = 0; l < D; ++l) {
+        const double x = U[size_t(i) * D + l];
+        if (x == 0.0) continue;
+        for (int j = 0; j < D; ++j) nxt[size_t(i) * D + j] += x * U[size_t(l) * D + j];
+      }
+    U.swap(nxt);
+  }
+  return U;
+}
+
+// The two-site wave function of a bond as blocks (a, s1, s2, b) of
+// m_a x m_b doubles (row-major) at given offsets.
+struct TwoSite {
+  int ns = 1, d = 2, nblk = 0;
+  std::vector<std::array<int, 6>> blk;  // a, s1, s2, b, m_a, m_b
+  std::vector<int64_t> off;
+  // per (a, b): the block index of every local pair t = s1 + d*s2 (-1: none)
+  std::vector<std::pair<std::pair<int, int>, std::vector<int>>> ab;
+  // bipartition components: rows (a, s1), columns (s2, b)
+  std::vector<std::vector<int>> comp_blocks;
+};
+
+void parse_two_site(TwoSite &w, int spin_half, int n_blk, const int32_t *desc, int64_t n_elem) {
+  w.ns = spin_half ? 2 : 1;
+  w.d = 1 << w.ns;
+  w.nblk = n_blk;
+  std::vector<std::pair<std::pair<int, int>, std::pair<int, int>>> keys;  // ((a,b),(t,k))
+  for (int k = 0; k < n_blk; ++k) {
+    const int32_t *q = desc + 8 * size_t(k);
+    const int64_t off = int64_t(uint32_t(q[6])) | (int64_t(q[7]) << 32);
+    if (q[0] < 0 || q[3] < 0 || q[1] < 0 || q[1] >= w.d || q[2] < 0 || q[2] >= w.d || q[4] < 1 || q[5] < 1 ||
+        off < 0 || off + int64_t(q[4]) * q[5] > n_elem)
+      throw BadInput("a block descriptor is out of range");
+    w.blk.push_back({q[0], q[1], q[2], q[3], q[4], q[5]});
+    w.off.push_back(off);
+    keys.push_back({{q[0], q[3]}, {q[1] + w.d * q[2], k}});
+  }
+  std::sort(keys.begin(), keys.end());
+  for (size_t k = 0; k < keys.size(); ++k) {
+    if (k > 0 && keys[k].first == keys[k - 1].first && keys[k].second.first == keys[k - 1].second.first)
+      throw BadInput("two blocks share (a, s1, s2, b)");
+    if (w.ab.empty() || w.ab.back().first != keys[k].first)
+      w.ab.push_back({keys[k].first, std::vector<int>(size_t(w.d) * w.d, -1)});
+    w.ab.back().second[keys[k].second.first] = keys[k].second.second;
+  }
+  // union-find over rows (a, s1) and columns (s2, b) joined by blocks
+  std::vector<std::pair<int, int>> rows, cols;
+  for (auto &b : w.blk) {
+    rows.push_back({b[0], b[1]});
+    cols.push_back({b[2], b[3]});
+  }
+  std::sort(rows.begin(), rows.end());
+  rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+  std::sort(cols.begin(), cols.end());
+  cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+  std::vector<int> parent(rows.size() + cols.size());
+  std::iota(parent.begin(), parent.end(), 0);
+  std::function<int(int)> root = [&](int x) { return parent[x] == x ? x : parent[x] = root(parent[x]); };
+  std::vector<int> brow(n_blk);
+  for (int k = 0; k < n_blk; ++k) {
+    const auto &b = w.blk[k];
+    const int r = int(std::lower_bound(rows.begin(), rows.end(), std::make_pair(b[0], b[1])) - rows.begin());
+    const int c = int(std::lower_bound(cols.begin(), cols.end(), std::make_pair(b[2], b[3])) - cols.begin());
+    brow[k] = r;
+    parent[root(r)] = root(int(rows.size()) + c);
+  }
+  std::vector<int> label(parent.size(), -1);
+  for (int k = 0; k < n_blk; ++k) {
+    const int r = root(brow[k]);
+    if (label[r] < 0) {
+      label[r] = int(w.comp_blocks.size());
+      w.comp_blocks.emplace_back();
+    }
+    w.comp_blocks[label[r]].push_back(k);
+  }
+}
+
+// psi' = (U (x) 1) psi on the local pair of every (a, b).
+void rotate_two_site(const TwoSite &w, const std::vector<double> &U, const double *psi, double *out) {
+  const int D = w.d * w.d;
+  for (const auto &e : w.ab) {
+    const auto &idx = e.second;
+    for (int t2 = 0; t2 < D; ++t2) {
+      const int k2 = idx[t2];
+      if (k2 < 0) continue;
+      const int64_t sz = int64_t(w.blk[k2][4]) * w.blk[k2][5];
+      double *o = out + w.off[k2];
+      std::fill(o, o + sz, 0.0);
+      for (int t = 0; t < D; ++t) {
+        const double u = U[size_t(t2) * D + t];
+        if (u == 0.0) continue;
+        const int k = idx[t];
+        if (k < 0) throw BadInput("the layout is not closed under the rotation");
+        const double *x = psi + w.off[k];
+        for (int64_t q = 0; q < sz; ++q) o[q] += u * x[q];
+      }
+    }
+  }
+}
+
+// S_1/2 = 2 ln sum_k sqrt(p_k) of the bipartition (a, s1 | s2, b), p_k the
+// squared singular values (Schmidt weights) normalised to sum 1.
+// The sectors run on the host's threads when `threads` is set.
+double half_renyi_two_site(const TwoSite &w, const double *psi, bool threads) {
+  const int nc = int(w.comp_blocks.size());
+  std::vector<double> part_s(nc, 0.0), part_s2(nc, 0.0);
+  auto sector = [&](int ic) {
+    const auto &cb = w.comp_blocks[ic];
+    // rows (a, s1) and columns (s2, b) of this component
+    std::vector<std::pair<int, int>> rows, cols;
+    for (int k : cb) {
+      rows.push_back({w.blk[k][0], w.blk[k][1]});
+      cols.push_back({w.blk[k][2], w.blk[k][3]});
+    }
+    std::sort(rows.begin(), rows.end());
+    rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    auto row_of = [&](int k) {
+      return int(std::lower_bound(rows.begin(), rows.end(), std::make_pair(w.blk[k][0], w.blk[k][1])) - rows.begin());
+    };
+    auto col_of = [&](int k) {
+      return int(std::lower_bound(cols.begin(), cols.end(), std::make_pair(w.blk[k][2], w.blk[k][3])) - cols.begin());
+    };
+    std::vector<int> roff(rows.size() + 1, 0), coff(cols.size() + 1, 0), rdim(rows.size()), cdim(cols.size());
+    for (int k : cb) {
+      rdim[row_of(k)] = w.blk[k][4];
+      cdim[col_of(k)] = w.blk[k][5];
+    }
+    for (size_t r = 0; r < rows.size(); ++r) roff[r + 1] = roff[r] + rdim[r];
+    for (size_t c = 0; c < cols.size(); ++c) coff[c + 1] = coff[c] + cdim[c];
+    const int R = roff.back(), C = coff.back();
+    // the component matrix with its shorter side as the column count: X holds
+    // min(R, C) contiguous vectors of length max(R, C)
+    const bool cols_short = C <= R;
+    const int m = cols_short ? R : C, n = cols_short ? C : R;
+    std::vector<double> X(size_t(m) * n, 0.0);
+    for (int k : cb) {
+      const int r0 = roff[row_of(k)], c0 = coff[col_of(k)];
+      const int ma = w.blk[k][4], mb = w.blk[k][5];
+      const double *x = psi + w.off[k];
+      for (int i = 0; i < ma; ++i)
+        for (int j = 0; j < mb; ++j) {
+          const double v = x[size_t(i) * mb + j];
+          if (cols_short) X[size_t(c0 + j) * m + r0 + i] = v;
+          else X[size_t(r0 + i) * m + c0 + j] = v;
+        }
+    }
+    for (double sv : singular_values(m, n, X)) {
+      part_s[ic] += sv;
+      part_s2[ic] += sv * sv;
+    }
+  };
+  if (threads) {
+    run_parallel(nc, sector);
+  } else {
+    for (int ic = 0; ic < nc; ++ic) sector(ic);
+  }
+  double sum_s = 0.0, sum_s2 = 0.0;
+  for (int ic = 0; ic < nc; ++ic) {
+    sum_s += part_s[ic];
+    sum_s2 += part_s2[ic];
+  }
+  if (!(sum_s2 > 0.0)) throw BadInput("the wave function is zero");
+  return 2.0 * std::log(sum_s / std::sqrt(sum_s2));
+}
 }  // namespace
 
 extern "C" {
@@ -598,6 +844,66 @@ int mdmrg_natural_orbitals(int nso, const double *gamma, double *occupation, dou
     if (modes)
       for (int r = 0; r < nso; ++r)
         for (int k = 0; k < nso; ++k) modes[size_t(r) * nso + k] = V[size_t(r) * nso + nso - 1 - k];
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_two_mode_rotation(int spin_half, int n_blk, const int32_t *desc, const double *psi, int64_t n_elem,
+                            int n_theta, const double *theta, double *s_half, double *theta_best,
+                            double *s_best, double *psi_rotated) {
+  if (n_blk < 1 || !desc || !psi || n_elem < 1 || n_theta < 0 || (n_theta > 0 && (!theta || !s_half)) ||
+      !theta_best || !s_best)
+    return MDMRG_EINVAL;
+  return guarded_host([&] {
+    TwoSite w;
+    parse_two_site(w, spin_half, n_blk, desc, n_elem);
+    const int ns = w.ns;
+    std::vector<double> buf(n_elem, 0.0);
+    auto eval = [&](double th) {  // one angle, sectors on the threads
+      rotate_two_site(w, two_mode_unitary(ns, th), psi, buf.data());
+      return half_renyi_two_site(w, buf.data(), true);
+    };
+    // the given angles, else 64 points on [-pi/2, pi/2)
+    std::vector<double> grid;
+    if (n_theta > 0) {
+      grid.assign(theta, theta + n_theta);
+    } else {
+      for (int k = 0; k < 64; ++k) grid.push_back(-0.5 * M_PI + M_PI * k / 64.0);
+    }
+    // the grid: one angle per thread, each with its own rotated copy
+    std::vector<double> val(grid.size());
+    run_parallel(int(grid.size()), [&](int k) {
+      std::vector<double> mine(n_elem, 0.0);
+      rotate_two_site(w, two_mode_unitary(ns, grid[k]), psi, mine.data());
+      val[k] = half_renyi_two_site(w, mine.data(), false);
+    });
+    if (n_theta > 0) std::copy(val.begin(), val.end(), s_half);
+    const size_t kb = size_t(std::min_element(val.begin(), val.end()) - val.begin());
+    double best_t = grid[kb], best_v = val[kb];
+    // golden-section refinement within one grid step of the best angle
+    double step = 0.0;
+    for (size_t k = 1; k < grid.size(); ++k) step = std::max(step, std::fabs(grid[k] - grid[k - 1]));
+    if (grid.size() > 1 && step > 0.0) {
+      const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+      double a = best_t - step, b = best_t + step;
+      double x1 = b - g * (b - a), x2 = a + g * (b - a);
+      double f1 = eval(x1), f2 = eval(x2);
+      for (int it = 0; it < 80 && b - a > 1e-12; ++it) {
+        if (f1 < f2) {
+          b = x2; x2 = x1; f2 = f1; x1 = b - g * (b - a); f1 = eval(x1);
+        } else {
+          a = x1; x1 = x2; f1 = f2; x2 = a + g * (b - a); f2 = eval(x2);
+        }
+      }
+      const double xm = f1 < f2 ? x1 : x2, fm = std::min(f1, f2);
+      if (fm < best_v) {
+        best_v = fm;
+        best_t = xm;
+      }
+    }
+    *theta_best = best_t;
+    *s_best = best_v;
+    if (psi_rotated) rotate_two_site(w, two_mode_unitary(ns, best_t), psi, psi_rotated);
     return MDMRG_OK;
   });
 }

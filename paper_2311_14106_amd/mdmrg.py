@@ -80,6 +80,8 @@ EXPORTS = {
     'mdmrg_hf_reference': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_dbl_p, ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_int8)]),
     'mdmrg_natural_orbitals': (ctypes.c_int, [ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
+    'mdmrg_two_mode_rotation': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_i32_p, _c_dbl_p, ctypes.c_int64,
+                                               ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
 }
 
 
@@ -257,6 +259,26 @@ def natural_orbitals(gamma, L=None):
     V = np.zeros((nso, nso))
     _host_check(L, L.mdmrg_natural_orbitals(nso, _dp(gamma), _dp(w), _dp(V)))
     return w, V
+
+
+def two_mode_rotation(desc, psi, spin_half, thetas=None, rotated=False, L=None):
+    """Two-mode micro-iteration at a bond (mdmrg_two_mode_rotation): desc is
+    the (n_blk, 8) int32 layout of mdmrg_psi_layout, psi the host vector.
+    Returns (theta_best, s_best, s_half at thetas or None, rotated psi or
+    None)."""
+    L = L or lib()
+    desc = np.ascontiguousarray(desc, dtype=np.int32).reshape(-1, 8)
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    th = None if thetas is None else np.ascontiguousarray(thetas, dtype=np.float64)
+    sh = None if th is None else np.zeros(th.size)
+    out = np.zeros_like(psi) if rotated else None
+    tb, sb = ctypes.c_double(), ctypes.c_double()
+    st = L.mdmrg_two_mode_rotation(int(bool(spin_half)), desc.shape[0], _ip(desc), _dp(psi), psi.size,
+                                   0 if th is None else th.size, None if th is None else _dp(th),
+                                   None if sh is None else _dp(sh), ctypes.byref(tb), ctypes.byref(sb),
+                                   None if out is None else _dp(out))
+    _host_check(L, st)
+    return tb.value, sb.value, sh, out
 
 
 class Context:

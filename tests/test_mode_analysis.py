@@ -20,6 +20,18 @@ blocks for every bitstring of the particle-number sector), normalised.
 * malformed layouts, a zero state, a disconnected graph, a non-permutation
   order and an impossible target are refused with EINVAL and a message.
 
+The two-mode micro-iteration (mdmrg_two_mode_rotation) on the two-site
+blocks of the same kind of MPS (centre at bond k, isometric elsewhere, so
+the blocks carry the whole state), against the oracle's mode rotation of
+the Fock vector (oracle/modeopt.py): S_1/2 of the bond's bipartition at 25
+angles to 1e-9, the rotated blocks equal to the rotated Fock vector to
+1e-12, the minimum of the oracle's micro-iteration on the same grid, and a
+second pass from the optimum finding nothing lower.  The optimum of these
+states sits on the cusp where the bond's Schmidt rank drops (theta = 0),
+which the singular values by one-sided Jacobi resolve.  Bad layouts (a block
+outside the vector, a repeated block, a block the rotation needs missing, a
+zero vector) are refused.
+
 Host code only: no GPU is used.
 """
 import numpy as np
@@ -168,3 +180,125 @@ def test_bad_inputs_are_refused(L):
     assert 'permutation' in str(e.value)
     with pytest.raises(mdmrg.MdmrgError):
         mdmrg.hf_reference(np.zeros(6), 3, True, (4, 1), L=L)
+
+
+# ---- the two-mode micro-iteration (mdmrg_two_mode_rotation) ----------------
+def _two_site(bonds, tensors, spinful, k):
+    """Two-site blocks (a, s1, s2, b) at bond (k, k+1) in the packed
+    lexicographic layout: psi = sum_r A_k[a, s1, r] A_{k+1}[r, s2, b]."""
+    d = 4 if spinful else 2
+    mid = {Q: r for r, (Q, m) in enumerate(bonds[k + 1])}
+    desc, chunks, off = [], [], 0
+    for a, (Qa, ma) in enumerate(bonds[k]):
+        for s1 in range(d):
+            q1 = si.local_qn(s1, spinful)
+            Qm = (Qa[0] + q1[0], Qa[1] + q1[1])
+            for s2 in range(d):
+                q2 = si.local_qn(s2, spinful)
+                for b, (Qb, mb) in enumerate(bonds[k + 2]):
+                    if (Qm[0] + q2[0], Qm[1] + q2[1]) != Qb:
+                        continue
+                    blk = np.zeros((ma, mb))
+                    r = mid.get(Qm)
+                    if r is not None and (a, s1, r) in tensors[k] and (r, s2, b) in tensors[k + 1]:
+                        blk = tensors[k][(a, s1, r)] @ tensors[k + 1][(r, s2, b)]
+                    desc.append([a, s1, s2, b, ma, mb, off & 0xFFFFFFFF, off >> 32])
+                    chunks.append(blk.ravel())
+                    off += ma * mb
+    return np.array(desc, dtype=np.int64).astype(np.int32), np.concatenate(chunks)
+
+
+def _fock_from_two_site(bonds, tensors, spinful, k, desc, psi2, target):
+    """Fock amplitudes of the state with the two-site blocks psi2 at (k, k+1)
+    and the MPS tensors elsewhere."""
+    n = len(bonds) - 1
+    ns = 2 if spinful else 1
+    d = 1 << ns
+    basis = ed.sector_basis(n * ns, target[0] + target[1], spinful, target[0] if spinful else None)
+    index = [{Q: j for j, (Q, m) in enumerate(b)} for b in bonds]
+    blocks = {(int(q[0]), int(q[1]), int(q[2]), int(q[3])):
+              psi2[int(q[6]) | (int(q[7]) << 32):][:int(q[4]) * int(q[5])].reshape(int(q[4]), int(q[5]))
+              for q in desc}
+    out = np.zeros(len(basis))
+    for t, f in enumerate(basis):
+        s = [(int(f) >> (ns * i)) & (d - 1) for i in range(n)]
+        v, Q, l = np.ones((1, 1)), (0, 0), 0
+        ok = True
+        for i in range(n):
+            q = si.local_qn(s[i], spinful)
+            if i == k:
+                q2 = si.local_qn(s[k + 1], spinful)
+                Qb = (Q[0] + q[0] + q2[0], Q[1] + q[1] + q2[1])
+                b = index[k + 2].get(Qb)
+                blk = blocks.get((l, s[k], s[k + 1], b))
+            elif i == k + 1:
+                continue
+            else:
+                Qb = (Q[0] + q[0], Q[1] + q[1])
+                b = index[i + 1].get(Qb)
+                blk = tensors[i].get((l, s[i], b)) if b is not None else None
+            if blk is None:
+                ok = False
+                break
+            v, Q, l = v @ blk, Qb, b
+        out[t] = v[0, 0] if ok else 0.0
+    return out, basis
+
+
+TWO_MODE_CASES = [(8, False, (4, 0), 6, 4, 3), (5, True, (2, 2), 8, 2, 1), (6, True, (3, 2), 8, 2, 2)]
+
+
+@pytest.mark.parametrize('n,spinful,target,D,k,seed', TWO_MODE_CASES)
+def test_two_mode_rotation_matches_the_oracle(L, n, spinful, target, D, k, seed):
+    from oracle import modeopt
+    bonds = si.bond_profile(n, spinful, target, D)
+    tensors = si.random_mps(bonds, spinful, seed, k)
+    desc, psi2 = _two_site(bonds, tensors, spinful, k)
+    psi, basis = _fock_vector(bonds, tensors, spinful, target)
+    # the two-site blocks carry the whole state (isometric left and right)
+    again, _ = _fock_from_two_site(bonds, tensors, spinful, k, desc, psi2, target)
+    assert np.allclose(again, psi, atol=1e-13)
+    ns = 2 if spinful else 1
+    cut = ns * (k + 1)
+    thetas = np.linspace(-np.pi / 2, np.pi / 2, 25, endpoint=False)
+
+    def oracle_s(th):
+        return modeopt.half_renyi(modeopt.rotate_state(psi, basis, modeopt.givens(n, k, k + 1, th), spinful),
+                                  basis, cut)
+    tb, sb, sh, rot = mdmrg.two_mode_rotation(desc, psi2, spinful, thetas, rotated=True, L=L)
+    ref = np.array([oracle_s(th) for th in thetas])
+    assert np.allclose(sh, ref, atol=1e-9, rtol=0), np.abs(sh - ref).max()
+    assert np.ptp(ref) > 0.05  # the angle matters
+    # the rotated blocks are the oracle's rotated state
+    rot_fock, _ = _fock_from_two_site(bonds, tensors, spinful, k, desc, rot, target)
+    ref_rot = modeopt.rotate_state(psi, basis, modeopt.givens(n, k, k + 1, tb), spinful)
+    assert np.allclose(rot_fock, ref_rot, atol=1e-12 * np.abs(psi).max())
+    assert abs(oracle_s(tb) - sb) < 1e-9
+    # the same minimum as the oracle's micro-iteration on the same grid
+    t_or, s_or = modeopt.best_two_mode_angle(psi, basis, n, k, k + 1, cut, thetas, spinful)
+    assert sb <= s_or + 1e-9 and sb >= s_or - 1e-6, (sb, s_or)
+    assert sb <= ref.min() + 1e-12
+    # rotating the optimum again finds nothing better
+    tb2, sb2, _, _ = mdmrg.two_mode_rotation(desc, rot, spinful, L=L)
+    assert abs(sb2 - sb) < 1e-8
+
+
+def test_two_mode_rotation_refuses_bad_layouts(L):
+    bonds = si.bond_profile(8, False, (4, 0), 6)
+    tensors = si.random_mps(bonds, False, 3, 4)
+    desc, psi2 = _two_site(bonds, tensors, False, 4)
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        mdmrg.two_mode_rotation(desc, psi2[:-1], False, L=L)
+    assert 'out of range' in str(e.value)
+    # drop one block of a pair that the rotation mixes
+    t = desc[:, 1] + 2 * desc[:, 2]
+    k = int(np.nonzero(t == 1)[0][0])
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        mdmrg.two_mode_rotation(np.delete(desc, k, axis=0), psi2, False, L=L)
+    assert 'closed' in str(e.value)
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        mdmrg.two_mode_rotation(np.concatenate([desc, desc[:1]]), psi2, False, L=L)
+    assert 'share' in str(e.value)
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        mdmrg.two_mode_rotation(desc, np.zeros_like(psi2), False, L=L)
+    assert 'zero' in str(e.value)
