@@ -468,13 +468,24 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out);
  *                  local index c_i + d*c_j; the diagonal blocks are not
  *                  written;
  *   gamma[nso*nso] gamma_pq = <a+_p a_q> over spin-orbitals p = ns*i + t;
- *   occ[nso]       <n_p>.
+ *   occ[nso]       <n_p>;
+ *   nn[n*n]        <n_i n_j>, n_i the particle number of mode i (both
+ *                  spins), the density correlations of the CDW order
+ *                  parameter (Sec. III.C).
  * The contraction costs about n^2 d^2 / 2 block-sparse transfers of a
  * bond operator over one site and uses the host's hardware threads.  EINVAL for a layout that
  * does not add up to n_data, sectors out of order or a zero state. */
 int mdmrg_mode_analysis(int n_sites, int spin_half, const int32_t *n_sect, const int32_t *sect_qn,
                         const int32_t *sect_dim, const double *data, int64_t n_data, double *s_one,
-                        double *s_two, double *rho_one, double *rho_two, double *gamma, double *occ);
+                        double *s_two, double *rho_one, double *rho_two, double *gamma, double *occ,
+                        double *nn);
+
+/* Charge-density-wave order parameter (Sec. III.C) in the current modes:
+ * C_CDW = <(sum_i s_i n_i)^2> / N^2 = sum_ij s_i s_j nn[i*n+j] / sum_ij nn,
+ * with the mode signs sign[n] (+1 on one sublattice, -1 on the other, for a
+ * real-space ordering) and nn from mdmrg_mode_analysis (sum_ij <n_i n_j> =
+ * N^2 in a fixed-N state).  EINVAL if nn sums to zero. */
+int mdmrg_cdw_order(int n, const double *nn, const double *sign, double *c_cdw);
 
 /* Mutual information I_ij = s_i + s_j - s_ij (I_ii = 0) into I[n*n],
  * *i_tot = sum_i s_i and *i_dist = sum_{i,j} I_ij (pos(i) - pos(j))^2 over

@@ -644,7 +644,8 @@ extern "C" {
 
 int mdmrg_mode_analysis(int n_sites, int spin_half, const int32_t *n_sect, const int32_t *sect_qn,
                         const int32_t *sect_dim, const double *data, int64_t n_data, double *s_one,
-                        double *s_two, double *rho_one, double *rho_two, double *gamma, double *occ) {
+                        double *s_two, double *rho_one, double *rho_two, double *gamma, double *occ,
+                        double *nn) {
   if (n_sites < 1 || !n_sect || !sect_qn || !sect_dim || (!data && n_data > 0) || !s_one || !s_two)
     return MDMRG_EINVAL;
   return guarded_host([&] {
@@ -680,6 +681,14 @@ int mdmrg_mode_analysis(int n_sites, int spin_half, const int32_t *n_sect, const
             if ((c >> t) & 1) o += r1[size_t(c) * d + c];
           occ[size_t(i) * ns + t] = o;
         }
+      if (nn) {  // <n_i^2>, n_i the particle number of the mode
+        double o = 0.0;
+        for (int c = 0; c < d; ++c) {
+          const int nc = __builtin_popcount(unsigned(c));
+          o += r1[size_t(c) * d + c] * nc * nc;
+        }
+        nn[size_t(i) * n + i] = o;
+      }
       if (gamma)  // same-site elements <a+_p a_q> = sum_in sign rho[in][out]
         for (int p = 0; p < ns; ++p)
           for (int q = 0; q < ns; ++q) {
@@ -710,6 +719,15 @@ int mdmrg_mode_analysis(int n_sites, int spin_half, const int32_t *n_sect, const
         const double *blk = blks.data() + size_t(j - i - 1) * d2 * d2;
         const double sij = vn_entropy(d2, std::vector<double>(blk, blk + size_t(d2) * d2));
         s_two[size_t(i) * n + j] = s_two[size_t(j) * n + i] = sij;
+        if (nn) {  // <n_i n_j> from the diagonal of rho_ij
+          double o = 0.0;
+          for (int c = 0; c < d; ++c)
+            for (int e = 0; e < d; ++e) {
+              const size_t t = size_t(c) + size_t(d) * e;
+              o += blk[t * d2 + t] * __builtin_popcount(unsigned(c)) * __builtin_popcount(unsigned(e));
+            }
+          nn[size_t(i) * n + j] = nn[size_t(j) * n + i] = o;
+        }
         if (rho_two) {
           std::copy(blk, blk + size_t(d2) * d2, rho_two + (size_t(i) * n + j) * d2 * d2);
           // modes listed (j, i): local index e + d*c and the reordering sign
@@ -741,6 +759,21 @@ int mdmrg_mode_analysis(int n_sites, int spin_half, const int32_t *n_sect, const
       }
     };
     run_parallel(n, site_task);
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_cdw_order(int n, const double *nn, const double *sign, double *c_cdw) {
+  if (n < 1 || !nn || !sign || !c_cdw) return MDMRG_EINVAL;
+  return guarded_host([&] {
+    double num = 0.0, n2 = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        num += sign[i] * sign[j] * nn[size_t(i) * n + j];
+        n2 += nn[size_t(i) * n + j];
+      }
+    if (!(n2 > 0.0)) throw BadInput("the state holds no particles");
+    *c_cdw = num / n2;
     return MDMRG_OK;
   });
 }

@@ -72,7 +72,8 @@ EXPORTS = {
     'mdmrg_get_stats': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p]),
     'mdmrg_mode_analysis': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_i32_p, _c_i32_p, _c_i32_p, _c_dbl_p,
                                            ctypes.c_int64, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p,
-                                           _c_dbl_p]),
+                                           _c_dbl_p, _c_dbl_p]),
+    'mdmrg_cdw_order': (ctypes.c_int, [ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
     'mdmrg_mutual_information': (ctypes.c_int, [ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_i32_p, _c_dbl_p, _c_dbl_p,
                                                 _c_dbl_p]),
     'mdmrg_fiedler_order': (ctypes.c_int, [ctypes.c_int, _c_dbl_p, _c_i32_p]),
@@ -184,16 +185,29 @@ def mode_analysis(n_sect, sect_qn, sect_dim, data, spin_half, rho=False, L=None)
     ns = 2 if spin_half else 1
     d = 1 << ns
     out = {'s_one': np.zeros(n), 's_two': np.zeros((n, n)), 'gamma': np.zeros((n * ns, n * ns)),
-           'occ': np.zeros(n * ns)}
+           'occ': np.zeros(n * ns), 'nn': np.zeros((n, n))}
     if rho:
         out['rho_one'] = np.zeros((n, d, d))
         out['rho_two'] = np.zeros((n, n, d * d, d * d))
     st = L.mdmrg_mode_analysis(n, int(bool(spin_half)), _ip(n_sect), _ip(sect_qn), _ip(sect_dim), _dp(data),
                                data.size, _dp(out['s_one']), _dp(out['s_two']),
                                _dp(out['rho_one']) if rho else None, _dp(out['rho_two']) if rho else None,
-                               _dp(out['gamma']), _dp(out['occ']))
+                               _dp(out['gamma']), _dp(out['occ']), _dp(out['nn']))
     _host_check(L, st)
     return out
+
+
+def cdw_order(nn, signs, L=None):
+    """C_CDW from the density correlations of mode_analysis."""
+    L = L or lib()
+    nn = np.ascontiguousarray(nn, dtype=np.float64)
+    signs = np.ascontiguousarray(signs, dtype=np.float64)
+    n = signs.size
+    if nn.shape != (n, n):
+        raise MdmrgError(EINVAL, 'nn must be n x n')
+    c = ctypes.c_double()
+    _host_check(L, L.mdmrg_cdw_order(n, _dp(nn), _dp(signs), ctypes.byref(c)))
+    return c.value
 
 
 def mutual_information(s_one, s_two, order=None, L=None):

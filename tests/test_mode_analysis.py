@@ -13,6 +13,8 @@ blocks for every bitstring of the particle-number sector), normalised.
 
 * entropies s_i, s_ij, every one- and two-mode density operator (both
   orientations of each pair), gamma and occupations to 1e-12;
+* <n_i n_j> against the oracle's 2-RDM and C_CDW against both the oracle's
+  value from the RDMs and its direct evaluation on the Fock amplitudes;
 * I, I_tot and I_dist (random chain order), the Fiedler ordering of that
   I and of shuffled weighted paths, the DEAS order, the HF reference and
   the natural occupations and modes;
@@ -103,6 +105,16 @@ def test_entropies_rdms_and_gamma_match_the_oracle(L, n, spinful, target, D, see
     assert np.allclose(out['gamma'], g, atol=1e-12, rtol=0)
     assert np.allclose(out['occ'], np.diag(g), atol=1e-12, rtol=0)
     assert abs(out['occ'].sum() - sum(target)) < 1e-12
+    # density correlations and C_CDW against the oracle's 2-RDM
+    G = rdm.two_rdm(psi, basis, n * ns)
+    nn_so = rdm.density_correlation(g, G)  # over spin-orbitals
+    fold = np.kron(np.eye(n), np.ones((1, ns)))  # mode <- its spin-orbitals
+    assert np.allclose(out['nn'], fold @ nn_so @ fold.T, atol=1e-12, rtol=0)
+    signs = np.array([(-1.0) ** i for i in range(n)])
+    c = mdmrg.cdw_order(out['nn'], signs, L=L)
+    assert abs(c - rdm.cdw_order(g, G, np.repeat(signs, ns))) < 1e-12
+    m = np.array([sum(signs[i] * ((int(f) >> (ns * i)) & (2 ** ns - 1)).bit_count() for i in range(n)) for f in basis])
+    assert abs(c - float(np.sum(psi ** 2 * m ** 2)) / sum(target) ** 2) < 1e-12
 
 
 def test_norm_does_not_matter(L):
