@@ -27,6 +27,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <exception>
 #include <functional>
 #include <mutex>
@@ -353,11 +354,22 @@ int hop_local(int in, int p, int q, double &sign) {
   return mid | (1 << p);
 }
 
-// Runs task(0..n-1) on the host's hardware threads; rethrows the first
-// exception a task raised.
+// Host threads for the analysis: OMP_NUM_THREADS when set, else the
+// hardware threads, at most 64.
+int host_threads() {
+  int nt = int(std::thread::hardware_concurrency());
+  if (const char *env = std::getenv("OMP_NUM_THREADS")) {
+    const int v = std::atoi(env);
+    if (v > 0) nt = v;
+  }
+  return std::max(1, std::min(nt, 64));
+}
+
+// Runs task(0..n-1) on host_threads() threads; rethrows the first exception
+// a task raised.
 template <class F>
 void run_parallel(int n, F &&task) {
-  const int nt = std::max(1, std::min<int>(n, int(std::thread::hardware_concurrency())));
+  const int nt = std::max(1, std::min(n, host_threads()));
   std::atomic<int> next{0};
   std::exception_ptr err;
   std::mutex mu;
