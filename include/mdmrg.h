@@ -457,7 +457,13 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out);
 
 /* Reduced density operators of single modes and of mode pairs of the MPS
  * given in the exchange format (site tensors of mdmrg_get_mps, sector lists
- * of mdmrg_get_bond; the state need not be normalised), and from them:
+ * of mdmrg_get_bond; the state need not be normalised).  With centre >= 0
+ * the state is the one whose sites centre and centre+1 are the two-site
+ * wave function psi (n_psi doubles on the host, n_blk blocks described as
+ * by mdmrg_psi_layout over the sectors of bonds centre and centre+2): the
+ * form of the library's own state during and after a sweep, whose centre
+ * lives in the Davidson vector; the exchange data of those two sites is
+ * then ignored.  From the state:
  *   s_one[n]       s_i = -Tr rho_i ln rho_i;
  *   s_two[n*n]     s_ij of the pair (symmetric; s_two[i*n+i] = s_i);
  * and, each optional (NULL to skip):
@@ -480,7 +486,8 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out);
 int mdmrg_mode_analysis(int n_sites, int spin_half, const int32_t *n_sect, const int32_t *sect_qn,
                         const int32_t *sect_dim, const double *data, int64_t n_data, double *s_one,
                         double *s_two, double *rho_one, double *rho_two, double *gamma, double *occ,
-                        double *nn);
+                        double *nn, int centre, int n_blk, const int32_t *desc, const double *psi,
+                        int64_t n_psi);
 
 /* Charge-density-wave order parameter (Sec. III.C) in the current modes:
  * C_CDW = <(sum_i s_i n_i)^2> / N^2 = sum_ij s_i s_j nn[i*n+j] / sum_ij nn,

@@ -57,6 +57,7 @@ struct Mps {
   // per site: block of (l, s) -> (r, offset) or r = -1
   std::vector<std::vector<int>> blk_r;
   std::vector<std::vector<int64_t>> blk_off;
+  std::vector<int64_t> site_off;  // data of site i: [site_off[i], site_off[i+1])
   const double *data = nullptr;
 
   std::array<int, 2> q(int s) const {
@@ -94,7 +95,9 @@ void parse(Mps &m, int n_sites, int spin_half, const int32_t *n_sect, const int3
   int64_t off = 0;
   m.blk_r.resize(n_sites);
   m.blk_off.resize(n_sites);
+  m.site_off.assign(n_sites + 1, 0);
   for (int i = 0; i < n_sites; ++i) {
+    m.site_off[i] = off;
     const int nl = int(m.qn[i].size());
     m.blk_r[i].assign(size_t(nl) * m.d, -1);
     m.blk_off[i].assign(size_t(nl) * m.d, -1);
@@ -108,6 +111,7 @@ void parse(Mps &m, int n_sites, int spin_half, const int32_t *n_sect, const int3
         off += int64_t(m.dim[i][l]) * m.dim[i + 1][r];
       }
   }
+  m.site_off[n_sites] = off;
   if (off != n_data) throw BadInput("n_data does not match the sector layout");
 }
 
@@ -650,6 +654,115 @@ double half_renyi_two_site(const TwoSite &w, const double *psi, bool threads) {
   if (!(sum_s2 > 0.0)) throw BadInput("the wave function is zero");
   return 2.0 * std::log(sum_s / std::sqrt(sum_s2));
 }
+
+// Exchange arrays of the state whose sites l and l+1 are replaced by the
+// two-site wave function psi at bond l (blocks (a, s1, s2, b) over the
+// sectors of bonds l and l+2).  It is factored exactly, without an SVD, as
+// psi = M * 1: bond l+1 gets one sector per middle quantum number
+// Q = Q_a + q(s1), of dimension C_Q = sum of m_b over the (s2, b) with
+// Q_b = Q + q(s2); site l holds the rows of M (block (a, s1, Q): psi's
+// blocks side by side in (s2, b) order) and site l+1 the identity slices
+// (block (Q, s2, b): C_Q x m_b with ones on the columns of (s2, b)).
+void merge_centre(const Mps &m, int l, const TwoSite &w, const double *psi, std::vector<int32_t> &n_sect,
+                  std::vector<int32_t> &sqn, std::vector<int32_t> &sdim, std::vector<double> &data) {
+  const int d = m.d;
+  if (l < 0 || l + 2 > m.n) throw BadInput("the centre bond is not a bond of two sites");
+  // the blocks of psi by (a, s1, s2, b), checked against the sector lists
+  std::vector<int> blk_at(size_t(m.qn[l].size()) * d * d * m.qn[l + 2].size(), -1);
+  auto key = [&](int a, int s1, int s2, int b) { return ((size_t(a) * d + s1) * d + s2) * m.qn[l + 2].size() + b; };
+  for (int k = 0; k < w.nblk; ++k) {
+    const auto &b = w.blk[k];
+    if (b[0] >= int(m.qn[l].size()) || b[3] >= int(m.qn[l + 2].size()) || b[4] != m.dim[l][b[0]] ||
+        b[5] != m.dim[l + 2][b[3]])
+      throw BadInput("a centre block does not match the sectors of its bonds");
+    const auto q1 = m.q(b[1]), q2 = m.q(b[2]);
+    const auto &Qa = m.qn[l][b[0]], &Qb = m.qn[l + 2][b[3]];
+    if (Qa[0] + q1[0] + q2[0] != Qb[0] || Qa[1] + q1[1] + q2[1] != Qb[1])
+      throw BadInput("a centre block breaks the quantum-number rule");
+    blk_at[key(b[0], b[1], b[2], b[3])] = k;
+  }
+  // middle sectors and their column layout
+  std::vector<std::array<int, 2>> mids;
+  for (size_t a = 0; a < m.qn[l].size(); ++a)
+    for (int s1 = 0; s1 < d; ++s1) {
+      const auto q1 = m.q(s1);
+      mids.push_back({m.qn[l][a][0] + q1[0], m.qn[l][a][1] + q1[1]});
+    }
+  std::sort(mids.begin(), mids.end());
+  mids.erase(std::unique(mids.begin(), mids.end()), mids.end());
+  std::vector<std::array<int, 2>> qmid;
+  std::vector<std::vector<std::array<int, 3>>> colmap;  // per middle sector: (s2, b, column offset)
+  std::vector<int> cdim;
+  for (const auto &Q : mids) {
+    std::vector<std::array<int, 3>> cols;
+    int c = 0;
+    for (int s2 = 0; s2 < d; ++s2) {
+      const auto q2 = m.q(s2);
+      const int b = m.find(l + 2, {Q[0] + q2[0], Q[1] + q2[1]});
+      if (b < 0) continue;
+      cols.push_back({s2, b, c});
+      c += m.dim[l + 2][b];
+    }
+    if (c == 0) continue;
+    qmid.push_back(Q);
+    colmap.push_back(cols);
+    cdim.push_back(c);
+  }
+  if (qmid.empty()) throw BadInput("the centre has no middle sector");
+  // sector lists
+  n_sect.clear();
+  sqn.clear();
+  sdim.clear();
+  for (int b = 0; b <= m.n; ++b) {
+    if (b == l + 1) {
+      n_sect.push_back(int32_t(qmid.size()));
+      for (size_t t = 0; t < qmid.size(); ++t) {
+        sqn.push_back(qmid[t][0]);
+        sqn.push_back(qmid[t][1]);
+        sdim.push_back(cdim[t]);
+      }
+    } else {
+      n_sect.push_back(int32_t(m.qn[b].size()));
+      for (size_t t = 0; t < m.qn[b].size(); ++t) {
+        sqn.push_back(m.qn[b][t][0]);
+        sqn.push_back(m.qn[b][t][1]);
+        sdim.push_back(m.dim[b][t]);
+      }
+    }
+  }
+  // site data: sites < l, the two new sites, sites > l+1
+  data.assign(m.data + m.site_off[0], m.data + m.site_off[l]);
+  for (size_t a = 0; a < m.qn[l].size(); ++a)
+    for (int s1 = 0; s1 < d; ++s1) {
+      const auto q1 = m.q(s1);
+      const std::array<int, 2> Q{m.qn[l][a][0] + q1[0], m.qn[l][a][1] + q1[1]};
+      const auto it = std::lower_bound(qmid.begin(), qmid.end(), Q);
+      if (it == qmid.end() || *it != Q) continue;
+      const size_t t = size_t(it - qmid.begin());
+      const int ma = m.dim[l][a], C = cdim[t];
+      const size_t base = data.size();
+      data.resize(base + size_t(ma) * C, 0.0);
+      for (const auto &cm : colmap[t]) {
+        const int k = blk_at[key(int(a), s1, cm[0], cm[1])];
+        if (k < 0) continue;  // absent block: zero
+        const int mb = m.dim[l + 2][cm[1]];
+        const double *x = psi + w.off[k];
+        for (int i = 0; i < ma; ++i)
+          for (int j = 0; j < mb; ++j) data[base + size_t(i) * C + cm[2] + j] = x[size_t(i) * mb + j];
+      }
+    }
+  for (size_t t = 0; t < qmid.size(); ++t)
+    for (int s2 = 0; s2 < d; ++s2)
+      for (const auto &cm : colmap[t]) {
+        if (cm[0] != s2) continue;
+        const int mb = m.dim[l + 2][cm[1]], C = cdim[t];
+        const size_t base = data.size();
+        data.resize(base + size_t(C) * mb, 0.0);
+        for (int j = 0; j < mb; ++j) data[base + size_t(cm[2] + j) * mb + j] = 1.0;
+      }
+  data.insert(data.end(), m.data + m.site_off[l + 2], m.data + m.site_off[m.n]);
+}
+
 }  // namespace
 
 extern "C" {
@@ -657,12 +770,24 @@ extern "C" {
 int mdmrg_mode_analysis(int n_sites, int spin_half, const int32_t *n_sect, const int32_t *sect_qn,
                         const int32_t *sect_dim, const double *data, int64_t n_data, double *s_one,
                         double *s_two, double *rho_one, double *rho_two, double *gamma, double *occ,
-                        double *nn) {
-  if (n_sites < 1 || !n_sect || !sect_qn || !sect_dim || (!data && n_data > 0) || !s_one || !s_two)
+                        double *nn, int centre, int n_blk, const int32_t *desc, const double *psi,
+                        int64_t n_psi) {
+  if (n_sites < 1 || !n_sect || !sect_qn || !sect_dim || (!data && n_data > 0) || !s_one || !s_two ||
+      (centre >= 0 && (n_blk < 1 || !desc || !psi || n_psi < 1)))
     return MDMRG_EINVAL;
   return guarded_host([&] {
     Mps m;
     parse(m, n_sites, spin_half, n_sect, sect_qn, sect_dim, data, n_data);
+    std::vector<int32_t> c_sect, c_qn, c_dim;
+    std::vector<double> c_data;
+    if (centre >= 0) {  // the state with its two-site centre at bond `centre`
+      TwoSite w;
+      parse_two_site(w, spin_half, n_blk, desc, n_psi);
+      merge_centre(m, centre, w, psi, c_sect, c_qn, c_dim, c_data);
+      m = Mps();
+      parse(m, n_sites, spin_half, c_sect.data(), c_qn.data(), c_dim.data(), c_data.data(),
+            int64_t(c_data.size()));
+    }
     const int n = m.n, d = m.d, ns = m.ns, nso = n * ns, d2 = d * d;
     // identity environments and the closing operators of every site
     std::vector<Op> EL(n + 1), ER(n + 1);

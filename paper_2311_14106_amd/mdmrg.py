@@ -72,7 +72,8 @@ EXPORTS = {
     'mdmrg_get_stats': (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p]),
     'mdmrg_mode_analysis': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_i32_p, _c_i32_p, _c_i32_p, _c_dbl_p,
                                            ctypes.c_int64, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p,
-                                           _c_dbl_p, _c_dbl_p]),
+                                           _c_dbl_p, _c_dbl_p, ctypes.c_int, ctypes.c_int, _c_i32_p, _c_dbl_p,
+                                           ctypes.c_int64]),
     'mdmrg_cdw_order': (ctypes.c_int, [ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
     'mdmrg_mutual_information': (ctypes.c_int, [ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_i32_p, _c_dbl_p, _c_dbl_p,
                                                 _c_dbl_p]),
@@ -164,15 +165,30 @@ def rotate_modes(R, T, V, spin_half, L=None):
     return T, V
 
 
+def _raw_desc(desc):
+    """The (n_blk, 8) int32 block descriptors of mdmrg_psi_layout, from
+    either that array or the block list of Context.psi_layout (tuples
+    (a, s1, s2, b, offset, m_a, m_b))."""
+    if isinstance(desc, np.ndarray):
+        return np.ascontiguousarray(desc, dtype=np.int32).reshape(-1, 8)
+    out = np.zeros((len(desc), 8), dtype=np.int64)
+    for k, (a, s1, s2, b, off, ma, mb) in enumerate(desc):
+        out[k] = (a, s1, s2, b, ma, mb, off & 0xFFFFFFFF, off >> 32)
+    return out.astype(np.uint32).view(np.int32) if out.size else out.astype(np.int32)
+
+
 def _host_check(L, st):
     if st:
         raise MdmrgError(st, L.mdmrg_last_error(None).decode())
 
 
-def mode_analysis(n_sect, sect_qn, sect_dim, data, spin_half, rho=False, L=None):
-    """One- and two-mode entropies, gamma and occupations of an MPS in the
-    exchange format (mdmrg_mode_analysis); with rho=True also the mode
-    density operators.  Returns a dict of numpy arrays."""
+def mode_analysis(n_sect, sect_qn, sect_dim, data, spin_half, rho=False, centre=None, L=None):
+    """One- and two-mode entropies, gamma, occupations and density
+    correlations of an MPS in the exchange format (mdmrg_mode_analysis);
+    with rho=True also the mode density operators.  centre = (bond, desc,
+    psi) replaces the sites bond and bond+1 by the two-site vector psi
+    (host array) with the (n_blk, 8) layout desc of psi_layout.  Returns a
+    dict of numpy arrays."""
     L = L or lib()
     n_sect = np.ascontiguousarray(n_sect, dtype=np.int32)
     sect_qn = np.ascontiguousarray(sect_qn, dtype=np.int32)
@@ -189,10 +205,19 @@ def mode_analysis(n_sect, sect_qn, sect_dim, data, spin_half, rho=False, L=None)
     if rho:
         out['rho_one'] = np.zeros((n, d, d))
         out['rho_two'] = np.zeros((n, n, d * d, d * d))
+    cb, cdesc, cpsi = -1, None, None
+    if centre is not None:
+        cb = int(centre[0])
+        cdesc = _raw_desc(centre[1])
+        cpsi = np.ascontiguousarray(centre[2], dtype=np.float64)
+        if cb < 0:
+            raise MdmrgError(EINVAL, 'the centre bond must be >= 0')
     st = L.mdmrg_mode_analysis(n, int(bool(spin_half)), _ip(n_sect), _ip(sect_qn), _ip(sect_dim), _dp(data),
                                data.size, _dp(out['s_one']), _dp(out['s_two']),
                                _dp(out['rho_one']) if rho else None, _dp(out['rho_two']) if rho else None,
-                               _dp(out['gamma']), _dp(out['occ']), _dp(out['nn']))
+                               _dp(out['gamma']), _dp(out['occ']), _dp(out['nn']), cb,
+                               0 if cdesc is None else cdesc.shape[0], None if cdesc is None else _ip(cdesc),
+                               None if cpsi is None else _dp(cpsi), 0 if cpsi is None else cpsi.size)
     _host_check(L, st)
     return out
 
@@ -277,11 +302,12 @@ def natural_orbitals(gamma, L=None):
 
 def two_mode_rotation(desc, psi, spin_half, thetas=None, rotated=False, L=None):
     """Two-mode micro-iteration at a bond (mdmrg_two_mode_rotation): desc is
-    the (n_blk, 8) int32 layout of mdmrg_psi_layout, psi the host vector.
+    the layout of psi_layout (raw (n_blk, 8) array or block list), psi the
+    host vector.
     Returns (theta_best, s_best, s_half at thetas or None, rotated psi or
     None)."""
     L = L or lib()
-    desc = np.ascontiguousarray(desc, dtype=np.int32).reshape(-1, 8)
+    desc = _raw_desc(desc)
     psi = np.ascontiguousarray(psi, dtype=np.float64)
     th = None if thetas is None else np.ascontiguousarray(thetas, dtype=np.float64)
     sh = None if th is None else np.zeros(th.size)

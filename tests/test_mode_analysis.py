@@ -19,6 +19,10 @@ blocks for every bitstring of the particle-number sector), normalised.
   I and of shuffled weighted paths, the DEAS order, the HF reference and
   the natural occupations and modes;
 * the result does not depend on the norm of the state;
+* a state given as isometries plus a generic two-site centre (the form of
+  the library's own DMRG state, whose centre lives in the Davidson vector)
+  matches the oracle on its Fock vector, and a product centre reproduces
+  the plain MPS;
 * malformed layouts, a zero state, a disconnected graph, a non-permutation
   order and an impossible target are refused with EINVAL and a message.
 
@@ -314,3 +318,43 @@ def test_two_mode_rotation_refuses_bad_layouts(L):
     with pytest.raises(mdmrg.MdmrgError) as e:
         mdmrg.two_mode_rotation(desc, np.zeros_like(psi2), False, L=L)
     assert 'zero' in str(e.value)
+
+
+@pytest.mark.parametrize('n,spinful,target,D,k,seed', TWO_MODE_CASES)
+def test_analysis_of_a_state_with_a_two_site_centre(L, n, spinful, target, D, k, seed):
+    """The state of a DMRG step: isometries left and right and a generic
+    two-site vector at bond k (random blocks, not a product of site
+    tensors; the exchange data of sites k and k+1 is ignored)."""
+    bonds = si.bond_profile(n, spinful, target, D)
+    tensors = si.random_mps(bonds, spinful, seed, k)
+    desc, prod = _two_site(bonds, tensors, spinful, k)
+    psi2 = np.random.default_rng(seed + 100).standard_normal(prod.size)
+    psi, basis = _fock_from_two_site(bonds, tensors, spinful, k, desc, psi2, target)
+    psi = psi / np.linalg.norm(psi)
+    arrays = si.flatten_mps(bonds, tensors, spinful)
+    out = mdmrg.mode_analysis(*arrays, spinful, rho=True, centre=(k, desc, psi2), L=L)
+    ns = 2 if spinful else 1
+    assert np.allclose(out['s_one'], mutual.one_mode_entropies(psi, basis, n, spinful), atol=1e-12, rtol=0)
+    assert np.allclose(out['s_two'], mutual.two_mode_entropies(psi, basis, n, spinful), atol=1e-12, rtol=0)
+    for i, j in ((k, k + 1), (0, n - 1), (k + 1, 0), (k, n - 1)):
+        assert np.allclose(out['rho_two'][i, j], mutual.mode_rdm(psi, basis, [i, j], spinful), atol=1e-12,
+                           rtol=0), (i, j)
+    assert np.allclose(out['gamma'], rdm.one_rdm(psi, basis, n * ns), atol=1e-12, rtol=0)
+    # the block-list form of the layout (Context.psi_layout) is accepted too
+    blocks = [(int(q[0]), int(q[1]), int(q[2]), int(q[3]), int(q[6]) | (int(q[7]) << 32), int(q[4]), int(q[5]))
+              for q in desc]
+    c = mdmrg.mode_analysis(*arrays, spinful, centre=(k, blocks, psi2), L=L)
+    assert np.array_equal(c['s_two'], out['s_two'])
+    # the product centre reproduces the plain MPS
+    a = mdmrg.mode_analysis(*arrays, spinful, centre=(k, desc, prod), L=L)
+    b = mdmrg.mode_analysis(*arrays, spinful, L=L)
+    for key in ('s_one', 's_two', 'gamma', 'nn'):
+        assert np.allclose(a[key], b[key], atol=1e-12, rtol=0), key
+    # refusals: a block of the wrong shape, a centre past the chain
+    bad = desc.copy()
+    bad[0, 4] += 1
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        mdmrg.mode_analysis(*arrays, spinful, centre=(k, bad, np.zeros(psi2.size + 64)), L=L)
+    assert 'match' in str(e.value)
+    with pytest.raises(mdmrg.MdmrgError):
+        mdmrg.mode_analysis(*arrays, spinful, centre=(n - 1, desc, psi2), L=L)
