@@ -525,6 +525,19 @@ void parse_two_site(TwoSite &w, int spin_half, int n_blk, const int32_t *desc, i
     w.off.push_back(off);
     keys.push_back({{q[0], q[3]}, {q[1] + w.d * q[2], k}});
   }
+  // every block of a left sector a has the same row count, every block of
+  // a right sector b the same column count
+  std::vector<std::pair<int, int>> ra, cb;
+  for (auto &b : w.blk) {
+    ra.push_back({b[0], b[4]});
+    cb.push_back({b[3], b[5]});
+  }
+  for (auto *v : {&ra, &cb}) {
+    std::sort(v->begin(), v->end());
+    for (size_t k = 1; k < v->size(); ++k)
+      if ((*v)[k].first == (*v)[k - 1].first && (*v)[k].second != (*v)[k - 1].second)
+        throw BadInput("blocks of one sector disagree on its dimension");
+  }
   std::sort(keys.begin(), keys.end());
   for (size_t k = 0; k < keys.size(); ++k) {
     if (k > 0 && keys[k].first == keys[k - 1].first && keys[k].second.first == keys[k - 1].second.first)
@@ -1022,7 +1035,7 @@ int mdmrg_two_mode_rotation(int spin_half, int n_blk, const int32_t *desc, const
                             int n_theta, const double *theta, double *s_half, double *theta_best,
                             double *s_best, double *psi_rotated) {
   if (n_blk < 1 || !desc || !psi || n_elem < 1 || n_theta < 0 || (n_theta > 0 && (!theta || !s_half)) ||
-      !theta_best || !s_best)
+      !theta_best || !s_best || psi_rotated == psi)
     return MDMRG_EINVAL;
   return guarded_host([&] {
     TwoSite w;

@@ -318,6 +318,14 @@ def test_two_mode_rotation_refuses_bad_layouts(L):
     with pytest.raises(mdmrg.MdmrgError) as e:
         mdmrg.two_mode_rotation(desc, np.zeros_like(psi2), False, L=L)
     assert 'zero' in str(e.value)
+    # one block claiming fewer rows than the others of its left sector
+    bad = desc.copy()
+    a0 = bad[0, 0]
+    k2 = int(np.nonzero(bad[:, 0] == a0)[0][1])
+    bad[k2, 4] = max(1, bad[k2, 4] - 1) if bad[k2, 4] > 1 else bad[k2, 4] + 1
+    with pytest.raises(mdmrg.MdmrgError) as e:
+        mdmrg.two_mode_rotation(bad, np.zeros(psi2.size + 64), False, L=L)
+    assert 'disagree' in str(e.value)
 
 
 @pytest.mark.parametrize('n,spinful,target,D,k,seed', TWO_MODE_CASES)
@@ -352,9 +360,9 @@ def test_analysis_of_a_state_with_a_two_site_centre(L, n, spinful, target, D, k,
         assert np.allclose(a[key], b[key], atol=1e-12, rtol=0), key
     # refusals: a block of the wrong shape, a centre past the chain
     bad = desc.copy()
-    bad[0, 4] += 1
+    bad[bad[:, 0] == desc[0, 0], 4] += 1  # every block of one left sector
     with pytest.raises(mdmrg.MdmrgError) as e:
-        mdmrg.mode_analysis(*arrays, spinful, centre=(k, bad, np.zeros(psi2.size + 64)), L=L)
+        mdmrg.mode_analysis(*arrays, spinful, centre=(k, bad, np.zeros(psi2.size + 4096)), L=L)
     assert 'match' in str(e.value)
     with pytest.raises(mdmrg.MdmrgError):
         mdmrg.mode_analysis(*arrays, spinful, centre=(n - 1, desc, psi2), L=L)
