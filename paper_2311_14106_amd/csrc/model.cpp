@@ -3,7 +3,10 @@
 // engine partitions at every bond.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <numeric>
+#include <thread>
+#include <vector>
 
 #include "model.h"
 
@@ -87,6 +90,25 @@ void build_lattice(int model, int basis, int Lx, int Ly, double t, double u, dou
       }
 }
 
+// Runs f(0..n-1) in contiguous chunks on OMP_NUM_THREADS host threads
+// (default: the hardware threads; at most 64).
+template <class F>
+static void parallel_rows(int64_t n, F &&f) {
+  int nt = int(std::thread::hardware_concurrency());
+  if (const char *env = std::getenv("OMP_NUM_THREADS")) {
+    const int v = std::atoi(env);
+    if (v > 0) nt = v;
+  }
+  nt = int(std::max<int64_t>(1, std::min<int64_t>({int64_t(nt), int64_t(64), n})));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&, t] {
+      const int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+      for (int64_t k = lo; k < hi; ++k) f(k);
+    });
+  for (auto &th : pool) th.join();
+}
+
 void rotate_modes(int n, int spin_half, const double *R, double *T, double *V) {
   // orthogonality check
   double err = 0.0;
@@ -117,20 +139,53 @@ void rotate_modes(int n, int spin_half, const double *R, double *T, double *V) {
       for (int j = 0; j < m; ++j) T2[int64_t(i) * m + j] += r * tmp[int64_t(a) * m + j];
     }
   std::copy(T2.begin(), T2.end(), T);
-  // V: four one-index transforms, each V'[..i..] = sum_a R[a,i] V[..a..]
-  const int64_t m2 = int64_t(m) * m, m3 = m2 * m, m4 = m3 * m;
+  // V: four one-index transforms.  With V viewed as [alpha, a, beta]
+  // (alpha the indices before the transformed one, beta those after),
+  // W[alpha, i, :] = sum_a R[a,i] V[alpha, a, :], a ascending: contiguous
+  // rows of length m^(3-axis), one (alpha, i) row per work item on the host
+  // threads (the last axis, whose rows have length 1, one alpha per item).
+  const int64_t m4 = int64_t(m) * m * m * m;
   std::vector<double> W(m4);
+  std::vector<char> nz;
   for (int axis = 0; axis < 4; ++axis) {
-    std::fill(W.begin(), W.end(), 0.0);
-    const int64_t stride = (axis == 0) ? m3 : (axis == 1) ? m2 : (axis == 2) ? m : 1;
-    for (int64_t e = 0; e < m4; ++e) {
-      const double v = V[e];
-      if (v == 0.0) continue;
-      const int a = int((e / stride) % m);
-      const int64_t base = e - int64_t(a) * stride;
-      const double *Ra = &Rs[int64_t(a) * m];
-      for (int i = 0; i < m; ++i)
-        if (Ra[i] != 0.0) W[base + int64_t(i) * stride] += Ra[i] * v;
+    int64_t B = 1, A = 1;
+    for (int k = 0; k < 3 - axis; ++k) B *= m;
+    for (int k = 0; k < axis; ++k) A *= m;
+    // rows V[alpha, a, :] that are entirely zero are skipped
+    nz.assign(size_t(A) * m, 0);
+    for (int64_t r = 0; r < A * m; ++r) {
+      const double *v = V + r * B;
+      for (int64_t q = 0; q < B; ++q)
+        if (v[q] != 0.0) {
+          nz[r] = 1;
+          break;
+        }
+    }
+    if (B > 1) {
+      parallel_rows(A * m, [&](int64_t item) {
+        const int64_t alpha = item / m;
+        const int i = int(item % m);
+        double *w = W.data() + item * B;
+        std::fill(w, w + B, 0.0);
+        for (int a = 0; a < m; ++a) {
+          const double c = Rs[int64_t(a) * m + i];
+          if (c == 0.0 || !nz[alpha * m + a]) continue;
+          const double *v = V + (alpha * m + a) * B;
+          for (int64_t q = 0; q < B; ++q) w[q] += c * v[q];
+        }
+      });
+    } else {
+      parallel_rows(A, [&](int64_t alpha) {
+        double *w = W.data() + alpha * m;
+        std::fill(w, w + m, 0.0);
+        for (int a = 0; a < m; ++a) {
+          const double v = V[alpha * m + a];
+          if (v == 0.0) continue;
+          const double *Ra = &Rs[int64_t(a) * m];
+          for (int i = 0; i < m; ++i)
+            if (Ra[i] != 0.0) w[i] += Ra[i] * v;
+        }
+      });
     }
     std::copy(W.begin(), W.end(), V);
   }
