@@ -34,7 +34,10 @@ angles to 1e-9, the rotated blocks equal to the rotated Fock vector to
 1e-12, the minimum of the oracle's micro-iteration on the same grid, and a
 second pass from the optimum finding nothing lower.  The optimum of these
 states sits on the cusp where the bond's Schmidt rank drops (theta = 0),
-which the singular values by one-sided Jacobi resolve.  Bad layouts (a block
+which the singular values by one-sided Jacobi resolve.  Independently of
+the oracle, a particle shared by the two modes follows the closed form
+S_1/2(theta) = 2 ln(|cos(theta - phi)| + |sin(theta - phi)|) and is
+disentangled at theta = phi.  Bad layouts (a block
 outside the vector, a repeated block, a block the rotation needs missing, a
 zero vector) are refused.
 
@@ -366,3 +369,24 @@ def test_analysis_of_a_state_with_a_two_site_centre(L, n, spinful, target, D, k,
     assert 'match' in str(e.value)
     with pytest.raises(mdmrg.MdmrgError):
         mdmrg.mode_analysis(*arrays, spinful, centre=(n - 1, desc, psi2), L=L)
+
+
+@pytest.mark.parametrize('spinful', [False, True])
+def test_two_mode_rotation_closed_form_of_a_shared_particle(L, spinful):
+    """One particle (spin up for spin-1/2) shared by the bond's two modes,
+    cos(phi) |1 0> + sin(phi) |0 1>, one-dimensional outer sectors: the
+    rotation by theta turns the pair into cos(theta - phi) |1 0> -
+    sin(theta - phi) |0 1>, so S_1/2(theta) = 2 ln(|cos(theta - phi)| +
+    |sin(theta - phi)|), zero at theta = phi (mod pi/2)."""
+    phi = 0.37
+    up = 1  # local state of one particle (spin up) on a site
+    desc = np.array([[0, up, 0, 0, 1, 1, 0, 0], [0, 0, up, 0, 1, 1, 1, 0]], dtype=np.int32)
+    psi2 = np.array([np.cos(phi), np.sin(phi)])
+    thetas = np.linspace(-np.pi / 2, np.pi / 2, 16, endpoint=False)
+    tb, sb, sh, rot = mdmrg.two_mode_rotation(desc, psi2, spinful, thetas, rotated=True, L=L)
+    ref = 2 * np.log(np.abs(np.cos(thetas - phi)) + np.abs(np.sin(thetas - phi)))
+    assert np.allclose(sh, ref, atol=1e-13, rtol=0)
+    assert abs(sb) < 1e-12
+    assert min(abs((tb - phi) - k * np.pi / 2) for k in range(-2, 3)) < 1e-6
+    # the rotated pair is a single configuration
+    assert np.sort(np.abs(rot)) == pytest.approx([0.0, 1.0], abs=1e-6)
