@@ -35,6 +35,9 @@ The oracle is deliberately slow and literal:
 * ``modeopt``    -- mode rotations of an explicit Fock-space state (the
   exponential of the one-body generator), the half-Renyi entropy of a
   bipartition and the two-mode micro-iteration that lowers it (Sec. II.B).
+* ``ozaki``      -- FP64 products from exact integer products of 8-bit
+  slices with per-row and per-column exponents (the model of an
+  FP64-accurate split form on the integer matrix units; not in the paper).
 * ``mutual``     -- one- and two-mode entropies, mutual information, total
   correlation and correlation distance, natural modes, the Fiedler
   ordering, the DEAS order and the HF reference taken after the last sweep
