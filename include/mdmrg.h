@@ -481,8 +481,9 @@ int mdmrg_get_stats(mdmrg_ctx ctx, double *out);
  * The contraction costs about n^2 d^2 / 2 block-sparse transfers of a
  * bond operator over one site and runs on OMP_NUM_THREADS host threads
  * (default: the hardware threads; at most 64), as does the angle search of
- * mdmrg_two_mode_rotation.  EINVAL for a layout that
- * does not add up to n_data, sectors out of order or a zero state. */
+ * mdmrg_two_mode_rotation.  EINVAL for a layout that does not add up to
+ * n_data, sectors out of order, centre blocks that do not match the sectors
+ * of their bonds or break the quantum-number rule, or a zero state. */
 int mdmrg_mode_analysis(int n_sites, int spin_half, const int32_t *n_sect, const int32_t *sect_qn,
                         const int32_t *sect_dim, const double *data, int64_t n_data, double *s_one,
                         double *s_two, double *rho_one, double *rho_two, double *gamma, double *occ,
