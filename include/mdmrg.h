@@ -560,6 +560,24 @@ int mdmrg_two_mode_rotation(int spin_half, int n_blk, const int32_t *desc, const
                             int n_theta, const double *theta, double *s_half, double *theta_best,
                             double *s_best, double *psi_rotated);
 
+/* A sweep of two-mode micro-iterations through the chain (Sec. II.B: the
+ * mode transformation built from two-mode rotations while sweeping through
+ * the network).  The state is given as by mdmrg_mode_analysis with its
+ * two-site centre at bond 0 (desc/psi as there; sites 2..n-1 of the
+ * exchange data right isometries, sites 0 and 1 ignored).  For k = 0 .. n-2
+ * the modes k, k+1 are rotated by the angle that minimises S_1/2 at bond k
+ * (as mdmrg_two_mode_rotation, on the grid theta_grid[n_theta] or, with
+ * n_theta = 0, on 64 angles over [-pi/2, pi/2)), then the centre moves to
+ * bond k+1 by an exact factorisation (no truncation).  Outputs:
+ * theta[n-1] the angles, s_half[n-1] S_1/2 of bond k after its rotation,
+ * R[n*n] = G_0 G_1 ... G_{n-2} (row-major) with G_k the Givens matrix of
+ * mdmrg_two_mode_rotation for modes k, k+1: mdmrg_rotate_modes(R) gives
+ * the integrals in the new modes.  EINVAL as for mdmrg_mode_analysis. */
+int mdmrg_rotation_sweep(int n_sites, int spin_half, const int32_t *n_sect, const int32_t *sect_qn,
+                         const int32_t *sect_dim, const double *data, int64_t n_data, int n_blk,
+                         const int32_t *desc, const double *psi, int64_t n_psi, int n_theta,
+                         const double *theta_grid, double *theta, double *s_half, double *R);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,7 @@
 #include <cstdlib>
 #include <exception>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -776,6 +777,135 @@ void merge_centre(const Mps &m, int l, const TwoSite &w, const double *psi, std:
   data.insert(data.end(), m.data + m.site_off[l + 2], m.data + m.site_off[m.n]);
 }
 
+
+// Angles to search: the given ones, else 64 covering [-pi/2, pi/2).
+std::vector<double> angle_grid(int n_theta, const double *theta) {
+  std::vector<double> grid;
+  if (n_theta > 0) {
+    grid.assign(theta, theta + n_theta);
+  } else {
+    for (int k = 0; k < 64; ++k) grid.push_back(-0.5 * M_PI + M_PI * k / 64.0);
+  }
+  return grid;
+}
+
+// The two-mode micro-iteration on a two-site vector: S_1/2 on the grid (one
+// angle per thread), then golden-section search within one grid step of the
+// best grid angle (sectors on the threads).
+void best_angle(const TwoSite &w, const double *psi, int64_t n_elem, const std::vector<double> &grid,
+                double *s_grid, double *theta_best, double *s_best) {
+  std::vector<double> buf(n_elem, 0.0);
+  auto eval = [&](double th) {
+    rotate_two_site(w, two_mode_unitary(w.ns, th), psi, buf.data());
+    return half_renyi_two_site(w, buf.data(), true);
+  };
+  std::vector<double> val(grid.size());
+  run_parallel(int(grid.size()), [&](int k) {
+    std::vector<double> mine(n_elem, 0.0);
+    rotate_two_site(w, two_mode_unitary(w.ns, grid[k]), psi, mine.data());
+    val[k] = half_renyi_two_site(w, mine.data(), false);
+  });
+  if (s_grid) std::copy(val.begin(), val.end(), s_grid);
+  const size_t kb = size_t(std::min_element(val.begin(), val.end()) - val.begin());
+  double best_t = grid[kb], best_v = val[kb];
+  double step = 0.0;
+  for (size_t k = 1; k < grid.size(); ++k) step = std::max(step, std::fabs(grid[k] - grid[k - 1]));
+  if (grid.size() > 1 && step > 0.0) {
+    const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+    double a = best_t - step, b = best_t + step;
+    double x1 = b - g * (b - a), x2 = a + g * (b - a);
+    double f1 = eval(x1), f2 = eval(x2);
+    for (int it = 0; it < 80 && b - a > 1e-12; ++it) {
+      if (f1 < f2) {
+        b = x2; x2 = x1; f2 = f1; x1 = b - g * (b - a); f1 = eval(x1);
+      } else {
+        a = x1; x1 = x2; f1 = f2; x2 = a + g * (b - a); f2 = eval(x2);
+      }
+    }
+    const double xm = f1 < f2 ? x1 : x2, fm = std::min(f1, f2);
+    if (fm < best_v) {
+      best_v = fm;
+      best_t = xm;
+    }
+  }
+  *theta_best = best_t;
+  *s_best = best_v;
+}
+
+// Exact factorisation M = L C of an R x Cn matrix (row-major): one-sided
+// Jacobi on the shorter side's vectors.  L (R x r) has orthonormal columns,
+// C = S V^T (r x Cn); singular values at or below 1e-15 of the largest are
+// dropped (rank r).  Returns r.
+int factor_lc(int R, int Cn, const std::vector<double> &M, std::vector<double> &L, std::vector<double> &C) {
+  const bool cols_short = Cn <= R;
+  const int m = cols_short ? R : Cn, n = cols_short ? Cn : R;
+  std::vector<double> X(size_t(m) * n), J(size_t(n) * n, 0.0);
+  for (int i = 0; i < R; ++i)
+    for (int j = 0; j < Cn; ++j) {
+      if (cols_short) X[size_t(j) * m + i] = M[size_t(i) * Cn + j];
+      else X[size_t(i) * m + j] = M[size_t(i) * Cn + j];
+    }
+  for (int i = 0; i < n; ++i) J[size_t(i) * n + i] = 1.0;  // J[col q][row p]: vector q of J
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double *xp = X.data() + size_t(p) * m, *xq = X.data() + size_t(q) * m;
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int i = 0; i < m; ++i) {
+          a += xp[i] * xp[i];
+          b += xq[i] * xq[i];
+          g += xp[i] * xq[i];
+        }
+        if (g == 0.0 || std::fabs(g) <= 1e-15 * std::sqrt(a * b)) continue;
+        rotated = true;
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
+        for (int i = 0; i < m; ++i) {
+          const double u = xp[i], v = xq[i];
+          xp[i] = c * u - sn * v;
+          xq[i] = sn * u + c * v;
+        }
+        double *jp = J.data() + size_t(p) * n, *jq = J.data() + size_t(q) * n;
+        for (int i = 0; i < n; ++i) {
+          const double u = jp[i], v = jq[i];
+          jp[i] = c * u - sn * v;
+          jq[i] = sn * u + c * v;
+        }
+      }
+    if (!rotated) break;
+  }
+  // X_q = (A J)_q with A the matrix whose columns were rotated; sigma_q = |X_q|
+  std::vector<double> sig(n);
+  double smax = 0.0;
+  for (int q = 0; q < n; ++q) {
+    double a = 0.0;
+    for (int i = 0; i < m; ++i) a += X[size_t(q) * m + i] * X[size_t(q) * m + i];
+    sig[q] = std::sqrt(a);
+    smax = std::max(smax, sig[q]);
+  }
+  std::vector<int> keep;
+  for (int q = 0; q < n; ++q)
+    if (sig[q] > 1e-15 * smax && sig[q] > 0.0) keep.push_back(q);
+  const int r = int(keep.size());
+  L.assign(size_t(R) * r, 0.0);
+  C.assign(size_t(r) * Cn, 0.0);
+  for (int t = 0; t < r; ++t) {
+    const int q = keep[t];
+    if (cols_short) {
+      // M J = X (R x n): M = X J^T; L = X_q / sigma_q, C row t = sigma_q J_q^T
+      for (int i = 0; i < R; ++i) L[size_t(i) * r + t] = X[size_t(q) * m + i] / sig[q];
+      for (int j = 0; j < Cn; ++j) C[size_t(t) * Cn + j] = sig[q] * J[size_t(q) * n + j];
+    } else {
+      // M^T J = X (Cn x n): M = J X^T; L column t = J_q, C row t = X_q^T
+      for (int i = 0; i < R; ++i) L[size_t(i) * r + t] = J[size_t(q) * n + i];
+      for (int j = 0; j < Cn; ++j) C[size_t(t) * Cn + j] = X[size_t(q) * m + j];
+    }
+  }
+  return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1040,53 +1170,165 @@ int mdmrg_two_mode_rotation(int spin_half, int n_blk, const int32_t *desc, const
   return guarded_host([&] {
     TwoSite w;
     parse_two_site(w, spin_half, n_blk, desc, n_elem);
-    const int ns = w.ns;
-    std::vector<double> buf(n_elem, 0.0);
-    auto eval = [&](double th) {  // one angle, sectors on the threads
-      rotate_two_site(w, two_mode_unitary(ns, th), psi, buf.data());
-      return half_renyi_two_site(w, buf.data(), true);
+    const std::vector<double> grid = angle_grid(n_theta, theta);
+    best_angle(w, psi, n_elem, grid, n_theta > 0 ? s_half : nullptr, theta_best, s_best);
+    if (psi_rotated) rotate_two_site(w, two_mode_unitary(w.ns, *theta_best), psi, psi_rotated);
+    return MDMRG_OK;
+  });
+}
+
+int mdmrg_rotation_sweep(int n_sites, int spin_half, const int32_t *n_sect, const int32_t *sect_qn,
+                         const int32_t *sect_dim, const double *data, int64_t n_data, int n_blk,
+                         const int32_t *desc, const double *psi, int64_t n_psi, int n_theta,
+                         const double *theta_grid, double *theta, double *s_half, double *R) {
+  if (n_sites < 2 || !n_sect || !sect_qn || !sect_dim || (!data && n_data > 0) || n_blk < 1 || !desc || !psi ||
+      n_psi < 1 || n_theta < 0 || (n_theta > 0 && !theta_grid) || !theta || !s_half || !R)
+    return MDMRG_EINVAL;
+  return guarded_host([&] {
+    Mps m;
+    parse(m, n_sites, spin_half, n_sect, sect_qn, sect_dim, data, n_data);
+    const int n = m.n, d = m.d;
+    const std::vector<double> grid = angle_grid(n_theta, theta_grid);
+    // the centre at bond k: sectors of bond k (left) and k+2 (right), blocks
+    // for every (a, s1, s2, b) of the sector rule, packed in that order
+    std::vector<std::array<int, 2>> lq(m.qn[0]);
+    std::vector<int> ld(m.dim[0]);
+    std::vector<int32_t> cdesc;
+    std::vector<double> cpsi;
+    auto layout = [&](int k) {  // cdesc for the current left sectors, bond k+2 on the right
+      cdesc.clear();
+      int64_t off = 0;
+      for (size_t a = 0; a < lq.size(); ++a)
+        for (int s1 = 0; s1 < d; ++s1)
+          for (int s2 = 0; s2 < d; ++s2) {
+            const auto q1 = m.q(s1), q2 = m.q(s2);
+            const int b = m.find(k + 2, {lq[a][0] + q1[0] + q2[0], lq[a][1] + q1[1] + q2[1]});
+            if (b < 0) continue;
+            const int mb = m.dim[k + 2][b];
+            const int32_t v[8] = {int32_t(a), s1, s2, b, ld[a], mb, int32_t(off & 0xFFFFFFFF), int32_t(off >> 32)};
+            cdesc.insert(cdesc.end(), v, v + 8);
+            off += int64_t(ld[a]) * mb;
+          }
+      return off;
     };
-    // the given angles, else 64 points on [-pi/2, pi/2)
-    std::vector<double> grid;
-    if (n_theta > 0) {
-      grid.assign(theta, theta + n_theta);
-    } else {
-      for (int k = 0; k < 64; ++k) grid.push_back(-0.5 * M_PI + M_PI * k / 64.0);
+    // the given centre, copied into the packed layout of bond 0
+    {
+      const int64_t ne = layout(0);
+      TwoSite w0;
+      parse_two_site(w0, spin_half, n_blk, desc, n_psi);
+      cpsi.assign(ne, 0.0);
+      TwoSite wl;
+      parse_two_site(wl, spin_half, int(cdesc.size() / 8), cdesc.data(), ne);
+      for (int k = 0; k < w0.nblk; ++k) {
+        const auto &b = w0.blk[k];
+        if (b[0] >= int(lq.size()) || b[3] >= int(m.qn[2].size()) || b[4] != ld[b[0]] || b[5] != m.dim[2][b[3]])
+          throw BadInput("a centre block does not match the sectors of its bonds");
+        int found = -1;
+        for (int t = 0; t < wl.nblk && found < 0; ++t)
+          if (wl.blk[t][0] == b[0] && wl.blk[t][1] == b[1] && wl.blk[t][2] == b[2] && wl.blk[t][3] == b[3]) found = t;
+        if (found < 0) throw BadInput("a centre block breaks the quantum-number rule");
+        std::copy(psi + w0.off[k], psi + w0.off[k] + int64_t(b[4]) * b[5], cpsi.begin() + wl.off[found]);
+      }
     }
-    // the grid: one angle per thread, each with its own rotated copy
-    std::vector<double> val(grid.size());
-    run_parallel(int(grid.size()), [&](int k) {
-      std::vector<double> mine(n_elem, 0.0);
-      rotate_two_site(w, two_mode_unitary(ns, grid[k]), psi, mine.data());
-      val[k] = half_renyi_two_site(w, mine.data(), false);
-    });
-    if (n_theta > 0) std::copy(val.begin(), val.end(), s_half);
-    const size_t kb = size_t(std::min_element(val.begin(), val.end()) - val.begin());
-    double best_t = grid[kb], best_v = val[kb];
-    // golden-section refinement within one grid step of the best angle
-    double step = 0.0;
-    for (size_t k = 1; k < grid.size(); ++k) step = std::max(step, std::fabs(grid[k] - grid[k - 1]));
-    if (grid.size() > 1 && step > 0.0) {
-      const double g = 0.5 * (std::sqrt(5.0) - 1.0);
-      double a = best_t - step, b = best_t + step;
-      double x1 = b - g * (b - a), x2 = a + g * (b - a);
-      double f1 = eval(x1), f2 = eval(x2);
-      for (int it = 0; it < 80 && b - a > 1e-12; ++it) {
-        if (f1 < f2) {
-          b = x2; x2 = x1; f2 = f1; x1 = b - g * (b - a); f1 = eval(x1);
-        } else {
-          a = x1; x1 = x2; f1 = f2; x2 = a + g * (b - a); f2 = eval(x2);
+    for (int i = 0; i < n * n; ++i) R[i] = (i % (n + 1) == 0) ? 1.0 : 0.0;
+    for (int k = 0; k + 1 < n; ++k) {
+      const int64_t ne = int64_t(cpsi.size());
+      TwoSite w;
+      parse_two_site(w, spin_half, int(cdesc.size() / 8), cdesc.data(), ne);
+      double th, sv;
+      best_angle(w, cpsi.data(), ne, grid, nullptr, &th, &sv);
+      theta[k] = th;
+      s_half[k] = sv;
+      std::vector<double> rot(ne, 0.0);
+      rotate_two_site(w, two_mode_unitary(w.ns, th), cpsi.data(), rot.data());
+      std::map<std::array<int, 4>, int> where;  // (a, s1, s2, b) -> block
+      for (int t = 0; t < w.nblk; ++t) where[{w.blk[t][0], w.blk[t][1], w.blk[t][2], w.blk[t][3]}] = t;
+      const double c = std::cos(th), sn = std::sin(th);  // R <- R G_k
+      for (int r = 0; r < n; ++r) {
+        const double x = R[size_t(r) * n + k], y = R[size_t(r) * n + k + 1];
+        R[size_t(r) * n + k] = c * x + sn * y;
+        R[size_t(r) * n + k + 1] = -sn * x + c * y;
+      }
+      if (k + 2 >= n) break;
+      // move the centre: per middle sector Q, rows (a, s1) | columns (s2, b)
+      // factored exactly as L C (L orthonormal columns, C = S V^T), rank kept
+      std::vector<std::array<int, 2>> nq;
+      std::vector<int> nd;
+      std::vector<std::vector<double>> Cq;                   // r x (columns) per new sector
+      std::vector<std::vector<std::array<int, 3>>> colsq;    // (s2, b, column offset)
+      for (const auto &Q : [&] {
+             std::vector<std::array<int, 2>> v;
+             for (size_t a = 0; a < lq.size(); ++a)
+               for (int s1 = 0; s1 < d; ++s1) v.push_back({lq[a][0] + m.q(s1)[0], lq[a][1] + m.q(s1)[1]});
+             std::sort(v.begin(), v.end());
+             v.erase(std::unique(v.begin(), v.end()), v.end());
+             return v;
+           }()) {
+        std::vector<std::array<int, 3>> rows, cols;  // (a, s1, row offset), (s2, b, column offset)
+        int Rn = 0, Cn = 0;
+        for (size_t a = 0; a < lq.size(); ++a)
+          for (int s1 = 0; s1 < d; ++s1)
+            if (lq[a][0] + m.q(s1)[0] == Q[0] && lq[a][1] + m.q(s1)[1] == Q[1]) {
+              rows.push_back({int(a), s1, Rn});
+              Rn += ld[a];
+            }
+        for (int s2 = 0; s2 < d; ++s2) {
+          const int b = m.find(k + 2, {Q[0] + m.q(s2)[0], Q[1] + m.q(s2)[1]});
+          if (b < 0) continue;
+          cols.push_back({s2, b, Cn});
+          Cn += m.dim[k + 2][b];
+        }
+        if (Rn == 0 || Cn == 0) continue;
+        std::vector<double> M(size_t(Rn) * Cn, 0.0);
+        for (const auto &rw : rows)
+          for (const auto &cl : cols) {
+            const auto it = where.find({rw[0], rw[1], cl[0], cl[1]});
+            if (it == where.end()) continue;
+            const auto &bk = w.blk[it->second];
+            const double *x = rot.data() + w.off[it->second];
+            for (int i = 0; i < bk[4]; ++i)
+              for (int j = 0; j < bk[5]; ++j) M[size_t(rw[2] + i) * Cn + cl[2] + j] = x[size_t(i) * bk[5] + j];
+          }
+        std::vector<double> L, C;
+        const int r = factor_lc(Rn, Cn, M, L, C);
+        if (r == 0) continue;
+        // the new site tensor (L) is not needed for the angles; C carries on
+        nq.push_back(Q);
+        nd.push_back(r);
+        Cq.push_back(std::move(C));
+        colsq.push_back(cols);
+        (void)L;
+      }
+      if (nq.empty()) throw BadInput("the state vanished while moving the centre");
+      // the next centre: psi'(mid, s2, s3, c) = sum_b C(mid; s2, b) A_{k+2}(b, s3, c)
+      lq = nq;
+      ld = nd;
+      const int64_t ne2 = layout(k + 1);
+      cpsi.assign(ne2, 0.0);
+      TwoSite wn;
+      parse_two_site(wn, spin_half, int(cdesc.size() / 8), cdesc.data(), ne2);
+      for (int t = 0; t < wn.nblk; ++t) {
+        const auto &bk = wn.blk[t];  // (mid, s2, s3, c)
+        const int mid = bk[0], s2 = bk[1], s3 = bk[2], cc = bk[3];
+        const int r = nd[mid], mc = bk[5];
+        for (const auto &cl : colsq[mid]) {
+          if (cl[0] != s2) continue;
+          const int b = cl[1];
+          if (m.blk_r[k + 2][size_t(b) * d + s3] != cc) continue;
+          const int mb = m.dim[k + 2][b];
+          const double *A = m.data + m.blk_off[k + 2][size_t(b) * d + s3];  // mb x mc
+          const std::vector<double> &Cm = Cq[mid];                          // r x Cn
+          const int Cn = int(Cm.size() / size_t(r));
+          double *o = cpsi.data() + wn.off[t];
+          for (int i = 0; i < r; ++i)
+            for (int j = 0; j < mb; ++j) {
+              const double x = Cm[size_t(i) * Cn + cl[2] + j];
+              if (x == 0.0) continue;
+              for (int q = 0; q < mc; ++q) o[size_t(i) * mc + q] += x * A[size_t(j) * mc + q];
+            }
         }
       }
-      const double xm = f1 < f2 ? x1 : x2, fm = std::min(f1, f2);
-      if (fm < best_v) {
-        best_v = fm;
-        best_t = xm;
-      }
     }
-    *theta_best = best_t;
-    *s_best = best_v;
-    if (psi_rotated) rotate_two_site(w, two_mode_unitary(ns, best_t), psi, psi_rotated);
     return MDMRG_OK;
   });
 }

@@ -84,6 +84,9 @@ EXPORTS = {
     'mdmrg_natural_orbitals': (ctypes.c_int, [ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
     'mdmrg_two_mode_rotation': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_i32_p, _c_dbl_p, ctypes.c_int64,
                                                ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
+    'mdmrg_rotation_sweep': (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_i32_p, _c_i32_p, _c_i32_p, _c_dbl_p,
+                                            ctypes.c_int64, ctypes.c_int, _c_i32_p, _c_dbl_p, ctypes.c_int64,
+                                            ctypes.c_int, _c_dbl_p, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
 }
 
 
@@ -319,6 +322,32 @@ def two_mode_rotation(desc, psi, spin_half, thetas=None, rotated=False, L=None):
                                    None if out is None else _dp(out))
     _host_check(L, st)
     return tb.value, sb.value, sh, out
+
+
+def rotation_sweep(n_sect, sect_qn, sect_dim, data, spin_half, desc, psi, thetas=None, L=None):
+    """Sweep of two-mode micro-iterations from a state with its centre at
+    bond 0 (mdmrg_rotation_sweep).  Returns (angles, S_1/2 per bond, R)."""
+    L = L or lib()
+    n_sect = np.ascontiguousarray(n_sect, dtype=np.int32)
+    sect_qn = np.ascontiguousarray(sect_qn, dtype=np.int32)
+    sect_dim = np.ascontiguousarray(sect_dim, dtype=np.int32)
+    data = np.ascontiguousarray(data, dtype=np.float64)
+    n = len(n_sect) - 1
+    S = int(n_sect.sum())
+    if n < 2 or sect_qn.size != 2 * S or sect_dim.size != S:
+        raise MdmrgError(EINVAL, 'sector arrays do not match n_sect')
+    desc = _raw_desc(desc)
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    th = None if thetas is None else np.ascontiguousarray(thetas, dtype=np.float64)
+    theta = np.zeros(n - 1)
+    s_half = np.zeros(n - 1)
+    R = np.zeros((n, n))
+    st = L.mdmrg_rotation_sweep(n, int(bool(spin_half)), _ip(n_sect), _ip(sect_qn), _ip(sect_dim), _dp(data),
+                                data.size, desc.shape[0], _ip(desc), _dp(psi), psi.size,
+                                0 if th is None else th.size, None if th is None else _dp(th), _dp(theta),
+                                _dp(s_half), _dp(R))
+    _host_check(L, st)
+    return theta, s_half, R
 
 
 class Context:

@@ -37,12 +37,22 @@ states sits on the cusp where the bond's Schmidt rank drops (theta = 0),
 which the singular values by one-sided Jacobi resolve.  Independently of
 the oracle, a particle shared by the two modes follows the closed form
 S_1/2(theta) = 2 ln(|cos(theta - phi)| + |sin(theta - phi)|) and is
-disentangled at theta = phi.  Bad layouts (a block
+disentangled at theta = phi.
+
+The sweep of micro-iterations (mdmrg_rotation_sweep) from a full-rank state
+with its centre at bond 0: at every bond the library's angle and S_1/2
+equal the oracle's micro-iteration on the Fock vector of the state the
+library has there; R is the product of the Givens matrices in the order
+applied; through the library's integral transformation with R the rotated
+state keeps the energy of the original (random integrals, spinless and
+spin-1/2).  Bad layouts (a block
 outside the vector, a repeated block, a block the rotation needs missing, a
 zero vector) are refused.
 
 Host code only: no GPU is used.
 """
+import itertools
+
 import numpy as np
 import pytest
 
@@ -390,3 +400,62 @@ def test_two_mode_rotation_closed_form_of_a_shared_particle(L, spinful):
     assert min(abs((tb - phi) - k * np.pi / 2) for k in range(-2, 3)) < 1e-6
     # the rotated pair is a single configuration
     assert np.sort(np.abs(rot)) == pytest.approx([0.0, 1.0], abs=1e-6)
+
+
+@pytest.mark.parametrize('n,spinful,target,D,seed', [(6, False, (3, 0), 8, 1), (4, True, (2, 1), 16, 2)])
+def test_rotation_sweep_matches_sequential_micro_iterations(L, n, spinful, target, D, seed):
+    """mdmrg_rotation_sweep from a full-rank state with its centre at bond 0
+    against the oracle applying best_two_mode_angle and rotate_state bond by
+    bond on the Fock vector: the same angles and S_1/2, and R equal to the
+    product of the oracle's Givens matrices.  Fed to the library's integral
+    transformation, R leaves the energy of the rotated state equal to that
+    of the original state in the original integrals."""
+    from oracle import modeopt
+    bonds = si.bond_profile(n, spinful, target, D)
+    tensors = si.random_mps(bonds, spinful, seed, 0)
+    desc, psi2 = _two_site(bonds, tensors, spinful, 0)
+    arrays = si.flatten_mps(bonds, tensors, spinful)
+    grid = np.linspace(-np.pi / 2, np.pi / 2, 24, endpoint=False)
+    th, sh, R = mdmrg.rotation_sweep(*arrays, spinful, desc, psi2, grid, L=L)
+    psi, basis = _fock_vector(bonds, tensors, spinful, target)
+    psi = psi / np.linalg.norm(psi)
+    ns = 2 if spinful else 1
+    # the oracle's micro-iteration at every bond, from the state the library
+    # has there (the oracle state follows the library's angles, so that the
+    # optimisers' last digits do not accumulate along the chain)
+    po, Ro = psi.copy(), np.eye(n)
+    for k in range(n - 1):
+        before = modeopt.half_renyi(po, basis, ns * (k + 1))
+        t, s_ = modeopt.best_two_mode_angle(po, basis, n, k, k + 1, ns * (k + 1), grid, spinful)
+        # minima of S_1/2 are often cusps (a Schmidt value reaching zero), where
+        # S moves linearly with the optimisers' last digits of the angle
+        assert abs(th[k] - t) < 1e-6 and abs(sh[k] - s_) < 1e-8, (k, th[k], t, sh[k], s_)
+        assert sh[k] <= before + 1e-12
+        G = modeopt.givens(n, k, k + 1, th[k])
+        po = modeopt.rotate_state(po, basis, G, spinful)
+        assert abs(modeopt.half_renyi(po, basis, ns * (k + 1)) - sh[k]) < 1e-10
+        Ro = Ro @ G
+    assert np.allclose(R, Ro, atol=1e-13)
+    assert np.allclose(R @ R.T, np.eye(n), atol=1e-13)
+    # R composes the rotations in the order they were applied
+    assert np.allclose(modeopt.rotate_state(psi, basis, Ro, spinful), po, atol=1e-12)
+    # energy invariance through the library's integral transformation
+    rng = np.random.default_rng(seed)
+    nso = n * ns
+    T = rng.standard_normal((n, n))
+    T = T + T.T
+    W = rng.standard_normal((n, n, n, n)) * 0.3
+    W = W + W.transpose(3, 2, 1, 0)  # Hermitian: V_pqrs = V_srqp
+    if spinful:
+        T = np.kron(T, np.eye(2))
+        W2 = np.zeros((nso,) * 4)
+        for p_, q_, r_, s_ in itertools.product(range(n), repeat=4):
+            for a_ in range(2):
+                for b_ in range(2):
+                    W2[2 * p_ + a_, 2 * q_ + b_, 2 * r_ + b_, 2 * s_ + a_] = W[p_, q_, r_, s_]
+        W = W2
+    Tr, Wr = mdmrg.rotate_modes(R, T, W, spinful, L=L)
+    e0 = rdm.energy(T, W, rdm.one_rdm(psi, basis, nso), rdm.two_rdm(psi, basis, nso))
+    pr = modeopt.rotate_state(psi, basis, R, spinful)
+    e1 = rdm.energy(Tr, Wr, rdm.one_rdm(pr, basis, nso), rdm.two_rdm(pr, basis, nso))
+    assert abs(e1 - e0) < 1e-11 * max(1.0, abs(e0)), (e0, e1)
