@@ -459,3 +459,23 @@ def test_rotation_sweep_matches_sequential_micro_iterations(L, n, spinful, targe
     pr = modeopt.rotate_state(psi, basis, R, spinful)
     e1 = rdm.energy(Tr, Wr, rdm.one_rdm(pr, basis, nso), rdm.two_rdm(pr, basis, nso))
     assert abs(e1 - e0) < 1e-11 * max(1.0, abs(e0)), (e0, e1)
+
+
+def test_rotation_sweep_of_two_modes_is_one_micro_iteration(L):
+    """Two modes sharing one particle, cos(phi)|10> + sin(phi)|01>: the
+    sweep is the single micro-iteration at bond 0, theta = phi (mod pi/2),
+    S_1/2 = 0 and R the Givens matrix of that angle."""
+    phi = -0.52
+    n_sect = np.array([1, 2, 1], dtype=np.int32)
+    sect_qn = np.array([0, 0, 0, 0, 1, 0, 1, 0], dtype=np.int32)  # bond 1: N=0 and N=1
+    sect_dim = np.array([1, 1, 1, 1], dtype=np.int32)
+    # exchange data (ignored for the centre sites but laid out): site 0 blocks
+    # (l=0,s=0,r=0), (l=0,s=1,r=1); site 1 blocks (l=0,s=1,r=0), (l=1,s=0,r=0)
+    data = np.ones(4)
+    desc = np.array([[0, 0, 1, 0, 1, 1, 0, 0], [0, 1, 0, 0, 1, 1, 1, 0]], dtype=np.int32)
+    psi2 = np.array([np.sin(phi), np.cos(phi)])  # (s1, s2) = (0, 1), then (1, 0)
+    th, sh, R = mdmrg.rotation_sweep(n_sect, sect_qn, sect_dim, data, False, desc, psi2, L=L)
+    assert th.shape == (1,) and abs(sh[0]) < 1e-12
+    assert min(abs((th[0] - phi) - k * np.pi / 2) for k in range(-2, 3)) < 1e-6
+    c, s = np.cos(th[0]), np.sin(th[0])
+    assert np.allclose(R, [[c, -s], [s, c]], atol=1e-15)
