@@ -45,7 +45,9 @@ equal the oracle's micro-iteration on the Fock vector of the state the
 library has there; R is the product of the Givens matrices in the order
 applied; through the library's integral transformation with R the rotated
 state keeps the energy of the original (random integrals, spinless and
-spin-1/2).  Bad layouts (a block
+spin-1/2).  A new mode order goes through the same transformation as a
+permutation matrix and is the exact relabelling of the integrals.  Bad
+layouts (a block
 outside the vector, a repeated block, a block the rotation needs missing, a
 zero vector) are refused.
 
@@ -479,3 +481,20 @@ def test_rotation_sweep_of_two_modes_is_one_micro_iteration(L):
     assert min(abs((th[0] - phi) - k * np.pi / 2) for k in range(-2, 3)) < 1e-6
     c, s = np.cos(th[0]), np.sin(th[0])
     assert np.allclose(R, [[c, -s], [s, c]], atol=1e-15)
+
+
+@pytest.mark.parametrize('spinful', [False, True])
+def test_reordering_is_a_permutation_rotation(L, spinful):
+    """A new mode order (e.g. the Fiedler order) applied through
+    mdmrg_rotate_modes with the permutation matrix P[order[i], i] = 1 is the
+    plain relabelling of the integrals, exactly."""
+    model = mdmrg.HUBBARD if spinful else mdmrg.SPINLESS
+    T, V = mdmrg.build_lattice(model, mdmrg.MOMENTUM, 3, 3, 1.0, 2.0, L=L)
+    n = 9
+    order = np.random.default_rng(8).permutation(n)
+    P = np.zeros((n, n))
+    P[order, np.arange(n)] = 1.0
+    Tr, Vr = mdmrg.rotate_modes(P, T, V, spinful, L=L)
+    so = np.array([2 * o + s for o in order for s in range(2)]) if spinful else order
+    assert np.array_equal(Tr, T[np.ix_(so, so)])
+    assert np.array_equal(Vr, V[np.ix_(so, so, so, so)])
