@@ -655,3 +655,28 @@ def test_rotation_sweep_lowers_the_entropy_of_the_hubbard_3x3_ground_state(L, hu
         po = modeopt.rotate_state(po, basis, modeopt.givens(9, k, k + 1, th[k]), True)
         assert abs(modeopt.half_renyi(po, basis, 2 * (k + 1)) - sh[k]) < 1e-10
     assert sh.sum() < sum(before) - 0.1
+
+
+def test_results_do_not_depend_on_the_thread_count(L, monkeypatch):
+    """Every parallel task writes its own outputs and partial sums are added
+    in a fixed order: 1 and 5 host threads give the same bits."""
+    import os
+    n, spinful, target, D, k, seed = TWO_MODE_CASES[1]
+    bonds = si.bond_profile(n, spinful, target, D)
+    tensors = si.random_mps(bonds, spinful, seed, 0)
+    desc, psi2 = _two_site(bonds, tensors, spinful, 0)
+    arrays = si.flatten_mps(bonds, tensors, spinful)
+    T, V = mdmrg.build_lattice(mdmrg.HUBBARD, mdmrg.MOMENTUM, 3, 3, 1.0, 4.0, L=L)
+    R = si.random_orthogonal(9, 4)
+    runs = []
+    for threads in ('1', '5'):
+        monkeypatch.setenv('OMP_NUM_THREADS', threads)
+        a = mdmrg.mode_analysis(*arrays, spinful, rho=True, L=L)
+        b = mdmrg.rotation_sweep(*arrays, spinful, desc, psi2, L=L)
+        c = mdmrg.rotate_modes(R, T, V, True, L=L)
+        runs.append((a, b, c))
+    (a1, b1, c1), (a5, b5, c5) = runs
+    for key in a1:
+        assert np.array_equal(a1[key], a5[key]), key
+    for x, y in zip(b1 + c1, b5 + c5):
+        assert np.array_equal(x, y)
