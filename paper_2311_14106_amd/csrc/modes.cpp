@@ -1,9 +1,13 @@
 // Host analysis of a matrix product state at the end of a sweep (Sec. II.B):
 // the one- and two-mode reduced density operators and their von Neumann
-// entropies, the one-particle density matrix and occupations, the mutual
+// entropies, the one-particle density matrix, occupations and density
+// correlations (with the CDW order parameter of Sec. III.C), the mutual
 // information with the total correlation and correlation distance, the
 // natural modes, the Fiedler ordering, the DEAS order and the HF reference
-// configuration that set up the next mode-transformation macro-iteration.
+// configuration that set up the next mode-transformation macro-iteration;
+// and the two-mode micro-iterations that build the mode transformation
+// (the S_1/2-minimising rotation of a bond's two modes, and a sweep of them
+// through the chain with the composite rotation).
 //
 // Everything here runs on the host from the MPS exchange arrays (the format
 // of mdmrg_set_mps / mdmrg_get_mps); no context and no GPU are involved.
