@@ -56,7 +56,9 @@ dimensions up to 242, built from the ED vector by Schmidt decompositions in
 the test) of the 3x3 Hubbard ground state in the momentum basis: the
 analysis equals the oracle's on the ED vector, and the sweep of
 micro-iterations follows the oracle bond by bond and lowers the summed
-S_1/2 of the cuts (16.64 to 16.29).
+S_1/2 of the cuts (16.64 to 16.29); over repeated sweeps no cut's S_1/2
+rises (a rotation of modes k, k+1 changes only the cut between them), and
+the values a sweep reports are those of the state it leaves.
 
 Host code only: no GPU is used.
 """
@@ -680,3 +682,26 @@ def test_results_do_not_depend_on_the_thread_count(L, monkeypatch):
         assert np.array_equal(a1[key], a5[key]), key
     for x, y in zip(b1 + c1, b5 + c5):
         assert np.array_equal(x, y)
+
+
+def test_repeated_rotation_sweeps_never_raise_a_cut_entropy(L, hubbard33):
+    """A rotation of modes k and k+1 changes only the cut between them, and
+    the micro-iteration never raises that cut's S_1/2 (theta = 0 is on the
+    grid): over three successive sweeps on the 3x3 Hubbard ground state every
+    cut's S_1/2 is non-increasing.  Between sweeps the state is rotated by
+    the sweep's R with the oracle and rebuilt as an exact MPS."""
+    from oracle import modeopt
+    psi, basis, arrays, desc, psi2, bonds = hubbard33
+    grid = np.linspace(-np.pi / 2, np.pi / 2, 16, endpoint=False)
+    assert np.any(grid == 0.0)
+    prev = np.array([modeopt.half_renyi(psi, basis, 2 * (k + 1)) for k in range(8)])
+    state = psi.copy()
+    for sweep in range(3):
+        bnd, tens, cen = _exact_mps_centre0(state, basis, 9, True, (4, 4))
+        dsc, p2 = _centre_layout(bnd, cen, True)
+        th, sh, R = mdmrg.rotation_sweep(*si.flatten_mps(bnd, tens, True), True, dsc, p2, grid, L=L)
+        assert np.all(sh <= prev + 1e-10), (sweep, sh - prev)
+        state = modeopt.rotate_state(state, basis, R, True)
+        now = np.array([modeopt.half_renyi(state, basis, 2 * (k + 1)) for k in range(8)])
+        assert np.allclose(now, sh, atol=1e-9)  # the reported values are the state's
+        prev = sh
